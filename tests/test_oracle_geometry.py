@@ -1,0 +1,76 @@
+"""Bookkeeping pins against the numbers printed in the paper's tables."""
+import math
+
+import numpy as np
+
+from conftest import read_golden
+from oracle import geometry
+
+
+def test_table2_sizes_and_padding_rule():
+    for row in read_golden("table2_sizes.txt"):
+        ell, sx, sy, nz, m, n, npad = (int(v) for v in row[:7])
+        five_digits = len(row) > 7 and row[7] == "~"
+        (gsx, gsy, gnz), (dx, dy, dz) = geometry.ladder_size(ell)
+        assert (gsx, gsy, gnz) == (sx, sy, nz)
+        assert np.allclose((dx * sx, dy * sy, dz * nz), (2000.0, 1200.0, 400.0), rtol=1e-15)
+        gm, gn, gnp = geometry.ladder_counts(ell)
+        assert (gm, gn) == (m, n)
+        if five_digits:
+            assert float(f"{gnp:.4e}") == float(f"{npad:.4e}")
+        else:
+            assert gnp == npad
+
+
+def test_padding_uses_round_half_away_from_zero():
+    # l = 6: s_x = 150 -> 0.05 * 150 = 7.5 must round to 8 (banker's rounding gives 8
+    # too), s_y = 90 -> 4.5 must round to 5 (banker's rounding gives 4 and misses Table 2)
+    assert geometry.padding_cells(90, 0.05) == 5
+    assert geometry.padding_cells(150, 0.05) == 8
+    assert geometry.padding_cells(250, 0.05) == 13   # 12.5 -> 13 (l = 10)
+
+
+def test_subspace_sizes_from_tables():
+    for row in read_golden("subspace_sizes.txt"):
+        m, s, t, tp = (int(v) for v in row)
+        assert geometry.subspace_sizes(m, s) == (t, tp)
+
+
+def test_basis_memory_is_binary_gigabytes():
+    for row in read_golden("memory_nt.txt"):
+        n, tp, printed = int(row[0]), int(row[1]), float(row[2])
+        assert round(n * tp * 8 / 2 ** 30, 1) == printed
+
+
+def test_table3_field_geometry():
+    blocks = 72 * 72
+    assert 62 + 2 * 5 == 72
+    for row in read_golden("table3_fielddata.txt"):
+        n, nz, dz = int(row[0]), int(row[1]), int(row[2])
+        assert n == blocks * nz
+        assert math.floor(2000.0 / nz) == dz
+
+
+def test_alpha1_scaling_matches_table3():
+    # eq. (eq:alpha1) scales alpha^(1) with (n/m)^3.5 for a fixed survey: with m = 3844
+    # the printed alpha^(1) of Table 3 divided by (n/m)^3.5 must be nearly constant
+    # across the nine depth discretizations (the ratio is sigma_1 / mean(sigma)).
+    from oracle import solvers
+    m = 62 * 62
+    ratios = []
+    for row in read_golden("table3_fielddata.txt"):
+        n, a1 = int(row[0]), float(row[3])
+        unit = solvers.alpha_one(n, m, np.array([1.0, 1.0]))   # s_1 / mean = 1
+        ratios.append(a1 / unit)
+    ratios = np.array(ratios)
+    assert ratios.max() / ratios.min() < 1.1
+    # a wrong exponent (3 instead of 3.5) would spread the ratios by a factor > 3
+    assert 4.0 < ratios.mean() < 5.0
+
+
+def test_geometry_coordinates():
+    g = geometry.uniform_geometry(4, 3, 2, 20.0, 30.0, 10.0, pad=(1, 2, 0, 1))
+    assert (g.nx, g.ny, g.m, g.n) == (7, 4, 12, 56)
+    a, b = g.station_xy(0, 0)
+    assert (a, b) == (30.0, 15.0)        # centre of surface cell (1, 0)
+    assert g.cell_bounds(1, 0, 1)[:6] == (20.0, 40.0, 0.0, 30.0, 10.0, 20.0)

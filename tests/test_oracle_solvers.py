@@ -1,0 +1,124 @@
+"""Pins of the oracle's GKB, RSVD and UPRE against dense linear algebra and statistics."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import geometry, irls, operator as op, solvers
+
+
+def small_problem(kernel="gravity", seed=0):
+    g = geometry.uniform_geometry(8, 8, 2, 25.0, 25.0, 25.0, kernel=kernel, incl_deg=45.0,
+                                  decl_deg=45.0)
+    G = op.dense_G(g)
+    rng = np.random.default_rng(seed)
+    wd = 1.0 / (0.05 + rng.random(g.m))
+    winv = 0.5 + rng.random(g.n)          # W^{-1}
+    Gt = wd[:, None] * G * winv[None, :]
+    r = rng.standard_normal(g.m) * 3.0
+    return g, G, wd, winv, Gt, r
+
+
+def ops(Gt):
+    return (lambda x: Gt @ x), (lambda y: Gt.T @ y)
+
+
+@pytest.mark.parametrize("kernel", ["gravity", "magnetic"])
+def test_gkb_full_space_equals_tikhonov(kernel):
+    g, G, wd, winv, Gt, r = small_problem(kernel)
+    alpha = 0.3 * np.linalg.svd(Gt, compute_uv=False)[5]
+    y, a, S = solvers.gkb(*ops(Gt), r, g.n, g.m, g.m, "fixed", alpha)
+    ref = solvers.tikhonov_z(Gt, r, alpha)
+    assert np.linalg.norm(y - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def test_gkb_factorization_relations():
+    g, G, wd, winv, Gt, r = small_problem()
+    tp = 30
+    y, a, S, F = solvers.gkb(*ops(Gt), r, g.n, 20, tp, "fixed", 1.0, return_factors=True)
+    A, H, B = F["A"], F["H"], F["B"]
+    assert np.linalg.norm(Gt @ A - H @ B) <= 1e-12 * np.linalg.norm(B)
+    assert np.abs(A.T @ A - np.eye(tp)).max() <= 1e-12
+    assert np.abs(H.T @ H - np.eye(tp + 1)).max() <= 1e-12
+    # B is lower bidiagonal: diagonal gamma_i, subdiagonal beta_{i+1}
+    assert np.count_nonzero(np.triu(B, 1)) == 0 and np.count_nonzero(np.tril(B, -2)) == 0
+    # leading singular values of the projected problem converge to those of G~
+    s_true = np.linalg.svd(Gt, compute_uv=False)
+    assert np.allclose(S[:3], s_true[:3], rtol=1e-10)
+
+
+@pytest.mark.parametrize("kernel", ["gravity", "magnetic"])
+def test_rsvd_full_space_equals_tikhonov(kernel):
+    g, G, wd, winv, Gt, r = small_problem(kernel)
+    alpha = 0.3 * np.linalg.svd(Gt, compute_uv=False)[5]
+    omega = np.random.default_rng(9).standard_normal((g.m, g.m))
+    y, a, S = solvers.rsvd(*ops(Gt), r, g.n, g.m, g.m, omega, "fixed", alpha)
+    ref = solvers.tikhonov_z(Gt, r, alpha)
+    assert np.linalg.norm(y - ref) <= 1e-8 * np.linalg.norm(ref)
+    assert np.allclose(S, np.linalg.svd(Gt, compute_uv=False), rtol=1e-8)
+
+
+def test_rsvd_power_iteration_captures_dominant_space():
+    g, G, wd, winv, Gt, r = small_problem()
+    omega = np.random.default_rng(10).standard_normal((24, g.m))
+    y, a, S, F = solvers.rsvd(*ops(Gt), r, g.n, 16, 24, omega, "fixed", 1.0, return_factors=True)
+    s_true = np.linalg.svd(Gt, compute_uv=False)
+    assert np.allclose(S[:4], s_true[:4], rtol=1e-4)
+    Q = F["Q"]
+    assert np.abs(Q.T @ Q - np.eye(24)).max() <= 1e-12
+
+
+def test_upre_is_unbiased_for_predictive_risk():
+    # For c = diag(s) xi + e with e ~ N(0, I): E[U(alpha)] equals E[||A(x_alpha - x)||^2]
+    # exactly (Vogel's UPRE).  A dropped factor or a wrong sign breaks the equality.
+    rng = np.random.default_rng(4)
+    s = np.sort(rng.random(40) * 10)[::-1] + 1e-3
+    xi = rng.standard_normal(40) / (1 + np.arange(40))
+    for alpha in (0.05, 0.5, 3.0):
+        phi = s * s / (s * s + alpha * alpha)
+        U, P = [], []
+        for _ in range(4000):
+            c = s * xi + rng.standard_normal(40)
+            U.append(solvers.upre(alpha, s, c))
+            P.append(np.sum((phi * c - s * xi) ** 2))
+        U, P = np.array(U), np.array(P)
+        se = math.sqrt(np.var(U - P) / len(U))
+        assert abs(U.mean() - P.mean()) < 5 * se
+
+
+def test_upre_minimizer_against_brute_force():
+    rng = np.random.default_rng(6)
+    for trial in range(5):
+        s = np.sort(np.exp(rng.uniform(-6, 2, 60)))[::-1]
+        c = s * rng.standard_normal(60) * 3 + rng.standard_normal(60)
+        a = solvers.upre_alpha(s, c)
+        grid = np.exp(np.linspace(np.log(s[-1] * 1e-3), np.log(s[0]), 10000))
+        brute = min(solvers.upre(g, s, c) for g in grid)
+        assert solvers.upre(a, s, c) <= brute + 1e-9 * abs(brute)
+
+
+def test_irls_step_matches_dense_closed_form():
+    # One step with fixed alpha and a full projected space equals eq. (constantWL) with
+    # m_apr -> m^(k-1), W = W_z W_L^(k), followed by the bound restriction.
+    g = geometry.uniform_geometry(6, 5, 3, 30.0, 30.0, 30.0)
+    G = op.dense_G(g)
+    rng = np.random.default_rng(12)
+    m_true = np.zeros(g.n)
+    m_true[rng.choice(g.n, 10, replace=False)] = 1.0
+    d_obs = G @ m_true + 0.01 * rng.standard_normal(g.m)
+    wd = np.full(g.m, 1.0 / 0.01)
+    m_prev = np.clip(rng.random(g.n) * 0.5, 0, 1)
+    m_prev2 = np.clip(rng.random(g.n) * 0.5, 0, 1)
+    p = irls.IrlsParams(solver="gkb", t=g.m, tp=g.m, lam=0.0, beta_depth=0.8, alpha_fixed=0.7,
+                        m_min=-10.0, m_max=10.0)
+    m_new, alpha, chi2, _ = irls.irls_step(g, p, 3, d_obs, wd, m_prev, m_prev2, G_dense=G)
+    Wz = irls.depth_weights(g, 0.8)
+    WL = irls.focusing_weights(m_prev, m_prev2, 0.0, 1e-9, 3)
+    Wm = Wz * WL
+    Wd = np.diag(wd)
+    lhs = G.T @ Wd.T @ Wd @ G + alpha ** 2 * np.diag(Wm * Wm)
+    rhs = G.T @ Wd.T @ Wd @ (d_obs - G @ m_prev)
+    ref = m_prev + np.linalg.solve(lhs, rhs)
+    assert np.linalg.norm(m_new - ref) <= 1e-7 * np.linalg.norm(ref)
+    res = wd * (G @ m_new - d_obs)
+    assert abs(chi2 - res @ res / (g.m + math.sqrt(2 * g.m))) <= 1e-12 * chi2
