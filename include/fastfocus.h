@@ -1,0 +1,176 @@
+/*
+ * fastfocus.h -- C ABI of the MI355X (gfx950) layered-BTTB sensitivity operator and the
+ * focusing inversion built on it.
+ *
+ * Method (Renaut, Hogue & Vatankhah, arXiv 2004.13904):
+ *   Sec. 2.1, eq. (blockG): G = [G^(1) ... G^(nz)], one BTTB block per depth layer, each
+ *     entry the prism integral of the gravity (g_z) or magnetic (total-field anomaly) kernel.
+ *   Appendix A: every G^(r) is embedded in a BCCB matrix; G x and G^T y are computed with
+ *     2-D FFTs of the precomputed kernel spectra.
+ *   Sec. 2.3, Algorithms 1 and 2: GKB and RSVD projected solves of the normal equations
+ *     eq. (normalequations) with the UPRE regularization parameter; Sec. 2.2-2.3 the IRLS
+ *     focusing iteration.
+ *
+ * Conventions for every entry point
+ *   - Model vectors (length n = nx*ny*nz) are ordered (layer r, row q, column p), p fastest;
+ *     data vectors (length m = sx*sy) are ordered (row j, column i), i fastest.  Layer 0 is
+ *     the top layer, z grows downward from the station plane z = 0.
+ *   - Station (i, j) sits at the centre of surface cell (i + pad_xl, j + pad_yl).
+ *   - All vector / matrix pointers are DEVICE pointers on the device the handle was built on,
+ *     unless marked "host".  The caller owns them.  Buffers must not alias unless stated.
+ *   - All work is enqueued asynchronously on `stream` (a hipStream_t; NULL = the null
+ *     stream).  Argument validation is synchronous and happens before any launch.
+ *   - Return value: FF_OK (0) or a negative ff_status.  No exception crosses the ABI.  The
+ *     message of the last failure on the calling thread is returned by ff_last_error().
+ *   - A handle owns device workspace for its operator passes: concurrent calls that use the
+ *     same handle on different streams race; serialize them (one stream per handle).
+ *   - Units: gravity entries in mGal per g/cc, magnetic entries in nT per SI susceptibility.
+ */
+#ifndef FASTFOCUS_H
+#define FASTFOCUS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ff_status;
+#define FF_OK        0
+#define FF_EINVAL   (-1)   /* bad argument value or NULL pointer                          */
+#define FF_ESHAPE   (-2)   /* sizes inconsistent with the handle, or embedding too small   */
+#define FF_EDTYPE   (-3)   /* unsupported dtype for this call                              */
+#define FF_ENOMEM   (-4)   /* device allocation failed, or workspace too small             */
+#define FF_EHIP     (-5)   /* a HIP runtime / launch error                                 */
+#define FF_EDEVICE  (-6)   /* pointer or stream on another device than the handle          */
+#define FF_ENOTIMPL (-7)   /* configuration not implemented                                */
+
+#define FF_GRAVITY_GZ   0  /* vertical attraction g_z of a unit-density prism            */
+#define FF_MAGNETIC_TFA 1  /* total-field anomaly of a unit-susceptibility prism, induced  */
+
+#define FF_F32 0           /* FP32 operator: complex64 spectra, float vectors              */
+#define FF_F64 1           /* FP64 operator: complex128 spectra, double vectors            */
+
+typedef void *ff_stream;   /* hipStream_t */
+
+/* Survey and volume geometry (Sec. 2.1, Fig. 1).  z_edges is a HOST array of nz + 1
+   increasing depths with z_edges[0] == 0 (the station plane).  nx = sx + pad_xl + pad_xr,
+   ny = sy + pad_yl + pad_yr.  The magnetic kernel uses induced magnetization parallel to
+   the inducing field of inclination incl_deg, declination decl_deg (x = north, y = east,
+   z = down) and intensity field_nT.  nfft_x / nfft_y choose the BCCB embedding size; 0
+   picks the smallest power of two >= sx + nx - 1 (resp. sy + ny - 1).  Any size >= that
+   bound gives the same product (Appendix A); smaller sizes are rejected (FF_ESHAPE).
+   Supported embedding sizes: powers of two from 8 to 2048. */
+typedef struct {
+    int32_t sx, sy, nz;
+    int32_t pad_xl, pad_xr, pad_yl, pad_yr;
+    double dx, dy;
+    const double *z_edges;
+    int32_t kernel;
+    double incl_deg, decl_deg, field_nT;
+    int32_t nfft_x, nfft_y;
+} ff_geometry;
+
+typedef struct ff_spectra_s *ff_spectra;
+
+/* Appendix A ("the 2DFFT of T is precomputed"): evaluates the per-offset kernel table
+   t_r(u, v) of every layer from the prism formulas in FP64, places it in the circulant
+   array of the embedding and stores its 2-D DFT (scaled by 1/(nfft_x*nfft_y)) on the
+   current device, as complex64 (dtype FF_F32) or complex128 (FF_F64).  Also allocates the
+   handle's pass workspace.  Blocks until the spectra are built.  *out receives the handle;
+   free it with ff_free_spectra. */
+ff_status build_spectra(const ff_geometry *geom, int32_t dtype, ff_stream stream, ff_spectra *out);
+ff_status ff_free_spectra(ff_spectra h);
+
+/* Sizes of a handle (host outputs, any may be NULL). */
+ff_status ff_spectra_info(ff_spectra h, int64_t *m, int64_t *n, int32_t *nfft_x,
+                          int32_t *nfft_y, int32_t *dtype);
+
+/* Writes the FP64 kernel table t_r(u, v) (Sec. 2.1: entry of G^(r) for station-to-prism
+   offsets u = i + pad_xl - p, v = j + pad_yl - q) to the DEVICE array `table` of
+   nz * (sy + ny - 1) * (sx + nx - 1) doubles, indexed [r][v - v0][u - u0] with
+   u0 = pad_xl - nx + 1, v0 = pad_yl - ny + 1.  For verification of the prism kernels. */
+ff_status ff_kernel_table(ff_spectra h, double *table, ff_stream stream);
+
+/* Appendix A, eq. (costGx): d = w_post .* G (w_pre .* x).  x: n values, d: m values, both of
+   the handle's dtype (float or double).  w_pre (n) and w_post (m) are optional diagonal
+   weights of the same dtype (NULL = identity); with w_pre = W^{-1} and w_post = W_d this is
+   the weighted operator G~ of eq. (forwardmult).  Layer contributions are summed in the
+   frequency domain, so one call costs nz forward 2-D FFTs and one inverse. */
+ff_status apply_G(ff_spectra h, const void *x, void *d, const void *w_pre, const void *w_post,
+                  ff_stream stream);
+
+/* Appendix A: x = w_post .* G^T (w_pre .* d).  d: m values, x: n values, w_pre (m), w_post
+   (n), same dtype conventions as apply_G.  One forward 2-D FFT and nz inverse. */
+ff_status apply_GT(ff_spectra h, const void *d, void *x, const void *w_pre, const void *w_post,
+                   ff_stream stream);
+
+/* Sec. 2.4 ("matrix products are loops over columns") and Appendix A (cost of G X):
+   Y = w_post .* G (w_pre .* X) for transpose = 0, Y = w_post .* G^T (w_pre .* X) for
+   transpose = 1, for k column vectors.  X is column-major with leading dimension ldx
+   (>= n, or >= m when transposed), Y likewise with ldy.  The weights apply to every column.
+   Vectors are processed in batched launches that read each spectrum tile once per batch. */
+ff_status apply_G_block(ff_spectra h, int32_t transpose, int64_t k, const void *X, int64_t ldx,
+                        void *Y, int64_t ldy, const void *w_pre, const void *w_post,
+                        ff_stream stream);
+
+/* ---------------------------------------------------------------------------------------
+   Projected solvers and IRLS (Sec. 2.3).  All vectors below are FP64 device arrays; the
+   operator applications inside run in the handle's dtype.  `workspace` is a caller-owned
+   device buffer of at least ff_workspace_size(...) bytes (it holds the n x t_p basis). */
+
+#define FF_WS_GKB  0
+#define FF_WS_RSVD 1
+#define FF_WS_IRLS 2
+ff_status ff_workspace_size(ff_spectra h, int32_t which, int32_t solver, int32_t tp,
+                            size_t *bytes);
+
+/* Algorithm 1: GKB factorization G~ A = H B of G~ = diag(wd) G diag(winv) with
+   reorthogonalization of A and H, SVD of the (tp+1) x tp bidiagonal B, and the solution
+   y = ||r~|| A V Gamma(alpha, Sigma) U(1,:)^T.  Inputs r_tilde (m), wd (m), winv (n).
+   alpha_mode: 0 = UPRE over the first t singular values, 1 = alpha^(1) of eq. (eq:alpha1),
+   2 = fixed (*alpha on input).  Outputs y (n, standard form: the model update is
+   winv .* y), *alpha (host), sigma (tp, device, descending).  1 <= t <= tp <= m. */
+ff_status gkb_project(ff_spectra h, const double *r_tilde, const double *wd, const double *winv,
+                      int32_t t, int32_t tp, int32_t alpha_mode, double *y, double *alpha,
+                      double *sigma, void *workspace, size_t ws_bytes, ff_stream stream);
+
+/* Algorithm 2: randomized SVD with one power iteration of G~ (same weights as above),
+   Omega given as a tp x m FP64 device matrix (row-major, i.e. m-vectors stored one after
+   another), eigen-decomposition of the symmetrized B^T B, UPRE over t values, solution
+   y = Q V~ Gamma U~^T (B^T r~).  Outputs as gkb_project; sigma holds all tp values. */
+ff_status rsvd_project(ff_spectra h, const double *r_tilde, const double *wd, const double *winv,
+                       int32_t t, int32_t tp, const double *omega, int32_t alpha_mode,
+                       double *y, double *alpha, double *sigma, void *workspace,
+                       size_t ws_bytes, ff_stream stream);
+
+/* Parameters of one IRLS step (Sec. 2.2-2.3, Sec. 3.1). */
+typedef struct {
+    int32_t solver;      /* 0 = GKB, 1 = RSVD                                             */
+    int32_t t, tp;       /* truncation and projected sizes                                */
+    int32_t k;           /* 1-based IRLS iteration index                                  */
+    double lambda;       /* eq. (WLdefn): 1 = L1-like, 0 = minimum support, 2 = smooth     */
+    double eps2;         /* focusing parameter epsilon^2                                  */
+    double beta_depth;   /* depth weighting exponent (0.8 gravity, 1.4 magnetic)          */
+    double m_min, m_max; /* bound constraints                                             */
+    double alpha_fixed;  /* > 0: use this alpha; otherwise eq. (eq:alpha1) at k = 1, UPRE after */
+} ff_irls_params;
+
+/* One IRLS step: W = W_z W_L^(k) with (W_L^(k))_ii = ((m_prev - m_prev2)_i^2 + eps2)^((lambda-2)/4)
+   (identity at k = 1), r~ = wd .* (d_obs - G m_prev), projected solve (GKB or RSVD with
+   `omega` tp x m when solver = 1), m_new = clip(m_prev + W^{-1} y, m_min, m_max) and the
+   scaled chi^2 of eq. (scaledchi2).  d_obs, wd: m; m_prev, m_prev2, m_new: n (FP64 device).
+   *alpha and *chi2_scaled are host outputs; the call synchronizes `stream` once at the end. */
+ff_status irls_step(ff_spectra h, const ff_irls_params *p, const double *d_obs, const double *wd,
+                    const double *m_prev, const double *m_prev2, const double *omega,
+                    double *m_new, double *alpha, double *chi2_scaled, void *workspace,
+                    size_t ws_bytes, ff_stream stream);
+
+/* Thread-local message of the last failure ("" if none).  Valid until the next call. */
+const char *ff_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FASTFOCUS_H */

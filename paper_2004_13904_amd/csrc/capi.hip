@@ -1,0 +1,224 @@
+// C ABI entry points: argument validation, handle lifetime and error reporting.  Every
+// failure is reported as a negative status plus a thread-local message; nothing throws
+// across the boundary.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "common.h"
+
+namespace ff {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+ff_status fail(ff_status code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+ff_status hip_fail(hipError_t e, const char *what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return FF_EHIP;
+}
+
+size_t csize(int dtype) { return dtype == FF_F64 ? sizeof(double2) : sizeof(float2); }
+
+namespace {
+
+int next_pow2(int64_t v) {
+  int p = 8;
+  while (p < v) p *= 2;
+  return p;
+}
+
+void free_handle(ff_spectra h) {
+  if (!h) return;
+  int cur = 0;
+  hipGetDevice(&cur);
+  hipSetDevice(h->device);
+  hipFree(h->spec);
+  hipFree(h->tw_x);
+  hipFree(h->tw_y);
+  hipFree(h->z_dev);
+  hipFree(h->ws_rows);
+  hipFree(h->ws_cols);
+  hipSetDevice(cur);
+  delete h;
+}
+
+ff_status check_device(ff_spectra h) {
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(FF_EHIP, "hipGetDevice failed");
+  if (cur != h->device) return fail(FF_EDEVICE, "current device differs from the handle's device");
+  return FF_OK;
+}
+
+template <typename T> ff_status upload_twiddles(int N, void **dst) {
+  std::vector<cplx<T>> tw(N);
+  for (int e = 0; e < N; ++e) {
+    // exp(-2 pi i e / N) evaluated in double and rounded once
+    const double a = 2.0 * M_PI * (double)e / (double)N;
+    tw[e] = mk<T>((T)std::cos(a), (T)-std::sin(a));
+  }
+  if (hipMalloc(dst, sizeof(cplx<T>) * N) != hipSuccess) return fail(FF_ENOMEM, "twiddle table allocation failed");
+  if (hipMemcpy(*dst, tw.data(), sizeof(cplx<T>) * N, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(FF_EHIP, "twiddle table upload failed");
+  return FF_OK;
+}
+
+int column_blocks(int H, int NY) {
+  const int tpf = NY / 8;
+  const int cpb = tpf >= 64 ? 1 : 64 / tpf;
+  return (H + cpb - 1) / cpb;
+}
+
+}  // namespace
+}  // namespace ff
+
+using namespace ff;
+
+extern "C" {
+
+const char *ff_last_error(void) { return g_err.c_str(); }
+
+ff_status build_spectra(const ff_geometry *g, int32_t dtype, ff_stream stream, ff_spectra *out) {
+  if (!g || !out) return fail(FF_EINVAL, "build_spectra: NULL geometry or output");
+  *out = nullptr;
+  if (dtype != FF_F32 && dtype != FF_F64) return fail(FF_EDTYPE, "build_spectra: dtype must be FF_F32 or FF_F64");
+  if (g->sx < 1 || g->sy < 1 || g->nz < 1) return fail(FF_ESHAPE, "build_spectra: sx, sy, nz must be >= 1");
+  if (g->pad_xl < 0 || g->pad_xr < 0 || g->pad_yl < 0 || g->pad_yr < 0)
+    return fail(FF_ESHAPE, "build_spectra: negative padding");
+  if (!(g->dx > 0) || !(g->dy > 0) || !std::isfinite(g->dx) || !std::isfinite(g->dy))
+    return fail(FF_EINVAL, "build_spectra: dx, dy must be positive and finite");
+  if (!g->z_edges) return fail(FF_EINVAL, "build_spectra: z_edges is NULL");
+  if (g->z_edges[0] != 0.0) return fail(FF_EINVAL, "build_spectra: z_edges[0] must be 0 (station plane)");
+  for (int r = 0; r < g->nz; ++r)
+    if (!(g->z_edges[r + 1] > g->z_edges[r]) || !std::isfinite(g->z_edges[r + 1]))
+      return fail(FF_EINVAL, "build_spectra: z_edges must increase strictly");
+  if (g->kernel != FF_GRAVITY_GZ && g->kernel != FF_MAGNETIC_TFA)
+    return fail(FF_EINVAL, "build_spectra: unknown kernel");
+  if (g->kernel == FF_MAGNETIC_TFA &&
+      (!std::isfinite(g->incl_deg) || !std::isfinite(g->decl_deg) || !std::isfinite(g->field_nT)))
+    return fail(FF_EINVAL, "build_spectra: magnetic field parameters must be finite");
+  const int64_t nx = (int64_t)g->sx + g->pad_xl + g->pad_xr;
+  const int64_t ny = (int64_t)g->sy + g->pad_yl + g->pad_yr;
+  const int64_t minx = g->sx + nx - 1, miny = g->sy + ny - 1;
+  if (minx > 2048 || miny > 2048) return fail(FF_ENOTIMPL, "build_spectra: embedding would exceed 2048");
+  int NX = g->nfft_x, NY = g->nfft_y;
+  if (NX == 0) NX = next_pow2(minx);
+  if (NY == 0) NY = next_pow2(miny);
+  if (!is_pow2(NX) || !is_pow2(NY) || NX < 8 || NY < 8 || NX > 2048 || NY > 2048)
+    return fail(FF_ENOTIMPL, "build_spectra: embedding sizes must be powers of two in [8, 2048]");
+  if (NX < minx || NY < miny)
+    return fail(FF_ESHAPE, "build_spectra: embedding smaller than s + n - 1 would wrap around");
+
+  ff_spectra h = new (std::nothrow) ff_spectra_s();
+  if (!h) return fail(FF_ENOMEM, "build_spectra: host allocation failed");
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return fail(FF_EHIP, "build_spectra: no HIP device");
+  }
+  h->dtype = dtype;
+  h->sx = g->sx; h->sy = g->sy; h->nz = g->nz;
+  h->pxl = g->pad_xl; h->pxr = g->pad_xr; h->pyl = g->pad_yl; h->pyr = g->pad_yr;
+  h->nx = (int)nx; h->ny = (int)ny;
+  h->dx = g->dx; h->dy = g->dy;
+  h->incl = g->incl_deg; h->decl = g->decl_deg; h->field = g->field_nT;
+  h->kernel = g->kernel;
+  h->z_edges.assign(g->z_edges, g->z_edges + g->nz + 1);
+  h->NX = NX; h->NY = NY; h->H = NX / 2 + 1;
+  h->m = (int64_t)g->sx * g->sy;
+  h->n = nx * ny * g->nz;
+  const int cb = column_blocks(h->H, NY);
+  auto groups = [&](int target) {
+    int lg = (target + cb - 1) / cb;
+    if (lg < 1) lg = 1;
+    if (lg > h->nz) lg = h->nz;
+    return lg;
+  };
+  h->lg_G = groups(1024);
+  h->lg_GT = groups(1024);
+
+  const size_t cs = csize(dtype);
+  const int64_t rows = ny > g->sy ? ny : g->sy;
+  h->ws_rows_bytes = cs * (size_t)kMaxBatch * h->nz * h->H * rows;
+  const int lgmax = h->lg_G > 1 ? h->lg_G : 1;
+  h->ws_cols_bytes = cs * (size_t)kMaxBatch * lgmax * h->H * g->sy;
+  ff_status st = FF_OK;
+  if (hipMalloc(&h->spec, cs * (size_t)h->nz * h->H * NY) != hipSuccess ||
+      hipMalloc(&h->ws_rows, h->ws_rows_bytes) != hipSuccess ||
+      hipMalloc(&h->ws_cols, h->ws_cols_bytes) != hipSuccess ||
+      hipMalloc((void **)&h->z_dev, sizeof(double) * (h->nz + 1)) != hipSuccess) {
+    free_handle(h);
+    return fail(FF_ENOMEM, "build_spectra: device allocation failed");
+  }
+  if (hipMemcpy(h->z_dev, g->z_edges, sizeof(double) * (h->nz + 1), hipMemcpyHostToDevice) != hipSuccess) {
+    free_handle(h);
+    return fail(FF_EHIP, "build_spectra: z_edges upload failed");
+  }
+  st = dtype == FF_F32 ? upload_twiddles<float>(NX, &h->tw_x) : upload_twiddles<double>(NX, &h->tw_x);
+  if (st == FF_OK) st = dtype == FF_F32 ? upload_twiddles<float>(NY, &h->tw_y) : upload_twiddles<double>(NY, &h->tw_y);
+  if (st == FF_OK) st = make_spectra(h, (hipStream_t)stream);
+  if (st != FF_OK) {
+    std::string msg = g_err;
+    free_handle(h);
+    return fail(st, msg);
+  }
+  *out = h;
+  return FF_OK;
+}
+
+ff_status ff_free_spectra(ff_spectra h) {
+  if (!h) return fail(FF_EINVAL, "ff_free_spectra: NULL handle");
+  free_handle(h);
+  return FF_OK;
+}
+
+ff_status ff_spectra_info(ff_spectra h, int64_t *m, int64_t *n, int32_t *nfft_x, int32_t *nfft_y,
+                          int32_t *dtype) {
+  if (!h) return fail(FF_EINVAL, "ff_spectra_info: NULL handle");
+  if (m) *m = h->m;
+  if (n) *n = h->n;
+  if (nfft_x) *nfft_x = h->NX;
+  if (nfft_y) *nfft_y = h->NY;
+  if (dtype) *dtype = h->dtype;
+  return FF_OK;
+}
+
+ff_status ff_kernel_table(ff_spectra h, double *table, ff_stream stream) {
+  if (!h || !table) return fail(FF_EINVAL, "ff_kernel_table: NULL argument");
+  ff_status st = check_device(h);
+  if (st != FF_OK) return st;
+  return kernel_table(h, table, (hipStream_t)stream);
+}
+
+ff_status apply_G(ff_spectra h, const void *x, void *d, const void *w_pre, const void *w_post, ff_stream stream) {
+  if (!h || !x || !d) return fail(FF_EINVAL, "apply_G: NULL argument");
+  ff_status st = check_device(h);
+  if (st != FF_OK) return st;
+  return op_apply(h, 0, 1, x, h->n, d, h->m, w_pre, w_post, h->dtype, (hipStream_t)stream);
+}
+
+ff_status apply_GT(ff_spectra h, const void *d, void *x, const void *w_pre, const void *w_post, ff_stream stream) {
+  if (!h || !x || !d) return fail(FF_EINVAL, "apply_GT: NULL argument");
+  ff_status st = check_device(h);
+  if (st != FF_OK) return st;
+  return op_apply(h, 1, 1, d, h->m, x, h->n, w_pre, w_post, h->dtype, (hipStream_t)stream);
+}
+
+ff_status apply_G_block(ff_spectra h, int32_t transpose, int64_t k, const void *X, int64_t ldx, void *Y,
+                        int64_t ldy, const void *w_pre, const void *w_post, ff_stream stream) {
+  if (!h || !X || !Y) return fail(FF_EINVAL, "apply_G_block: NULL argument");
+  if (transpose != 0 && transpose != 1) return fail(FF_EINVAL, "apply_G_block: transpose must be 0 or 1");
+  if (k < 0) return fail(FF_ESHAPE, "apply_G_block: k < 0");
+  const int64_t rin = transpose ? h->m : h->n, rout = transpose ? h->n : h->m;
+  if (ldx < rin || ldy < rout) return fail(FF_ESHAPE, "apply_G_block: leading dimension too small");
+  ff_status st = check_device(h);
+  if (st != FF_OK) return st;
+  if (k == 0) return FF_OK;
+  return op_apply(h, transpose, k, X, ldx, Y, ldy, w_pre, w_post, h->dtype, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,114 @@
+// Internal declarations shared by the HIP translation units of libfastfocus.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fastfocus.h"
+
+namespace ff {
+
+// ---------------------------------------------------------------------------------------
+// Complex scalars: float2 / double2 so that one element is one vector load.
+template <typename T> struct CT;
+template <> struct CT<float> { using type = float2; };
+template <> struct CT<double> { using type = double2; };
+template <typename T> using cplx = typename CT<T>::type;
+
+template <typename T> __host__ __device__ __forceinline__ cplx<T> mk(T re, T im) {
+  cplx<T> c;
+  c.x = re;
+  c.y = im;
+  return c;
+}
+template <typename T> __device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <typename T> __device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+template <typename T> __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+template <typename T> __device__ __forceinline__ cplx<T> cmulc(cplx<T> a, cplx<T> b) {
+  return mk<T>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <typename T> __device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return mk<T>(a.x, -a.y); }
+template <typename T> __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+
+// ---------------------------------------------------------------------------------------
+// Error reporting: the C ABI returns a status and keeps a thread-local message.
+void set_error(const std::string &msg);
+ff_status fail(ff_status code, const std::string &msg);
+ff_status hip_fail(hipError_t e, const char *what);
+
+#define FF_HIP(call)                                                \
+  do {                                                              \
+    hipError_t e_ = (call);                                         \
+    if (e_ != hipSuccess) return ::ff::hip_fail(e_, #call);         \
+  } while (0)
+
+#define FF_LAUNCH_CHECK(what)                                       \
+  do {                                                              \
+    hipError_t e_ = hipGetLastError();                              \
+    if (e_ != hipSuccess) return ::ff::hip_fail(e_, what);          \
+  } while (0)
+
+// Dispatch a runtime embedding size to a compile-time constant NN.
+#define FF_SWITCH_N(N, ...)                                   \
+  switch (N) {                                                 \
+    case 8: { constexpr int NN = 8; __VA_ARGS__; } break;             \
+    case 16: { constexpr int NN = 16; __VA_ARGS__; } break;           \
+    case 32: { constexpr int NN = 32; __VA_ARGS__; } break;           \
+    case 64: { constexpr int NN = 64; __VA_ARGS__; } break;           \
+    case 128: { constexpr int NN = 128; __VA_ARGS__; } break;         \
+    case 256: { constexpr int NN = 256; __VA_ARGS__; } break;         \
+    case 512: { constexpr int NN = 512; __VA_ARGS__; } break;         \
+    case 1024: { constexpr int NN = 1024; __VA_ARGS__; } break;       \
+    case 2048: { constexpr int NN = 2048; __VA_ARGS__; } break;       \
+    default: return ::ff::fail(FF_ENOTIMPL, "unsupported embedding size"); \
+  }
+
+
+inline bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Largest number of vectors one batched operator launch processes (the handle's pass
+// workspace is sized for it).
+constexpr int kMaxBatch = 16;
+
+}  // namespace ff
+
+// ---------------------------------------------------------------------------------------
+// The spectra handle.
+struct ff_spectra_s {
+  int device = 0;
+  int dtype = FF_F32;
+  // geometry
+  int sx = 0, sy = 0, nz = 0, pxl = 0, pxr = 0, pyl = 0, pyr = 0, nx = 0, ny = 0;
+  double dx = 0, dy = 0, incl = 0, decl = 0, field = 0;
+  int kernel = 0;
+  std::vector<double> z_edges;
+  // embedding
+  int NX = 0, NY = 0, H = 0;         // H = NX/2 + 1 half-spectrum columns
+  int64_t m = 0, n = 0;
+  // device memory
+  void *spec = nullptr;              // [nz][H][NY] complex (float2 or double2), scaled by 1/(NX NY)
+  void *tw_x = nullptr, *tw_y = nullptr;   // twiddle tables exp(-2 pi i e / N), e in [0, N)
+  double *z_dev = nullptr;           // z_edges on the device
+  void *ws_rows = nullptr;           // batch x nz x H x max(ny, sy) complex: row-pass <-> column-pass
+  void *ws_cols = nullptr;           // batch x LG x H x max(sy, ...) complex: column-pass partials / D1
+  size_t ws_rows_bytes = 0, ws_cols_bytes = 0;
+  int lg_G = 1;                      // layer groups of the G column pass (partial sums)
+  int lg_GT = 1;                     // layer groups of the G^T column pass
+};
+
+namespace ff {
+size_t csize(int dtype);
+// operator passes (apply.hip)
+ff_status op_apply(ff_spectra h, int transpose, int64_t k, const void *X, int64_t ldx, void *Y,
+                   int64_t ldy, const void *w_pre, const void *w_post, int io_dtype,
+                   hipStream_t s);
+// spectra construction (spectra.hip)
+ff_status make_spectra(ff_spectra h, hipStream_t s);
+ff_status kernel_table(ff_spectra h, double *table, hipStream_t s);
+}  // namespace ff

@@ -1,0 +1,147 @@
+// Radix-8 (+ a final radix-4 or radix-2) Stockham FFT held in registers, one FFT per group
+// of N/8 threads, exchanged between stages through LDS.
+//
+// Data distribution (the same on entry and on exit, so transforms chain without shuffles):
+// thread j of the group holds the 8 elements with natural indices j + u*(N/8), u = 0..7.
+// A stage of radix R with Ns points already combined takes, for butterfly b, the R inputs
+// a[b + t*N/R], multiplies input t by w^(t*(b mod Ns)) with w = exp(-+2 pi i/(Ns*R)), does an
+// R-point DFT and writes output s to position (b/Ns)*Ns*R + (b mod Ns) + s*Ns (Stockham
+// autosort).  In the last stage Ns = N/R, so the outputs land at b + s*N/R: natural order
+// in the thread's own registers.  Twiddles come from a table exp(-2 pi i e / N), e in [0, N),
+// built on the host in FP64 and rounded once to T.
+//
+// Every FFT group of a block must call run() together (block-wide barriers inside).
+#pragma once
+
+#include "common.h"
+
+namespace ff {
+
+template <typename T> struct Consts;
+template <> struct Consts<float> { static constexpr float r2 = 0.70710678118654752440f; };
+template <> struct Consts<double> { static constexpr double r2 = 0.70710678118654752440; };
+
+// multiply by w4 = -i (forward) or +i (inverse)
+template <bool INV, typename T> __device__ __forceinline__ cplx<T> mul_w4(cplx<T> a) {
+  return INV ? mk<T>(-a.y, a.x) : mk<T>(a.y, -a.x);
+}
+// multiply by w8 = (1 -+ i)/sqrt2
+template <bool INV, typename T> __device__ __forceinline__ cplx<T> mul_w8(cplx<T> a) {
+  const T c = Consts<T>::r2;
+  return INV ? mk<T>((a.x - a.y) * c, (a.x + a.y) * c) : mk<T>((a.x + a.y) * c, (a.y - a.x) * c);
+}
+// multiply by w8^3 = (-1 -+ i)/sqrt2
+template <bool INV, typename T> __device__ __forceinline__ cplx<T> mul_w83(cplx<T> a) {
+  const T c = Consts<T>::r2;
+  return INV ? mk<T>((-a.x - a.y) * c, (a.x - a.y) * c) : mk<T>((a.y - a.x) * c, (-a.x - a.y) * c);
+}
+
+template <bool INV, typename T>
+__device__ __forceinline__ void dft2(cplx<T> &a0, cplx<T> &a1) {
+  cplx<T> t = a0;
+  a0 = cadd<T>(t, a1);
+  a1 = csub<T>(t, a1);
+}
+
+template <bool INV, typename T>
+__device__ __forceinline__ void dft4(cplx<T> &a0, cplx<T> &a1, cplx<T> &a2, cplx<T> &a3) {
+  cplx<T> t0 = cadd<T>(a0, a2), t1 = csub<T>(a0, a2);
+  cplx<T> t2 = cadd<T>(a1, a3), t3 = mul_w4<INV, T>(csub<T>(a1, a3));
+  a0 = cadd<T>(t0, t2);
+  a2 = csub<T>(t0, t2);
+  a1 = cadd<T>(t1, t3);
+  a3 = csub<T>(t1, t3);
+}
+
+// in-place 8-point DFT of a[0..7]
+template <bool INV, typename T> __device__ __forceinline__ void dft8(cplx<T> *a) {
+  cplx<T> e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
+  cplx<T> o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
+  dft4<INV, T>(e0, e1, e2, e3);
+  dft4<INV, T>(o0, o1, o2, o3);
+  o1 = mul_w8<INV, T>(o1);
+  o2 = mul_w4<INV, T>(o2);
+  o3 = mul_w83<INV, T>(o3);
+  a[0] = cadd<T>(e0, o0);
+  a[4] = csub<T>(e0, o0);
+  a[1] = cadd<T>(e1, o1);
+  a[5] = csub<T>(e1, o1);
+  a[2] = cadd<T>(e2, o2);
+  a[6] = csub<T>(e2, o2);
+  a[3] = cadd<T>(e3, o3);
+  a[7] = csub<T>(e3, o3);
+}
+
+template <bool INV, typename T>
+__device__ __forceinline__ cplx<T> twiddle(cplx<T> v, const cplx<T> *__restrict__ tw, int e) {
+  cplx<T> w = tw[e];
+  return INV ? cmulc<T>(v, w) : cmul<T>(v, w);
+}
+
+constexpr int ilog8(int n) { return n < 8 ? 0 : 1 + ilog8(n / 8); }
+constexpr int ipow8(int k) { return k == 0 ? 1 : 8 * ipow8(k - 1); }
+
+template <typename T, int N, bool INV> struct FFT {
+  static_assert(N >= 8 && (N & (N - 1)) == 0, "N must be a power of two >= 8");
+  static constexpr int TPF = N / 8;                // threads per transform
+  static constexpr int L8 = ilog8(N);              // radix-8 stages
+  static constexpr int REM = N / ipow8(L8);        // 1, 2 or 4: final radix
+  static constexpr int LDS = 2 * N;                // complex elements of LDS per transform
+
+  // v[u] = x[j + u*TPF] on entry, X[j + u*TPF] on exit.  buf: this group's 2N LDS elements.
+  __device__ static void run(cplx<T> (&v)[8], int j, cplx<T> *buf, const cplx<T> *__restrict__ tw) {
+    int Ns = 1;
+    bool used_lds = false;
+#pragma unroll
+    for (int st = 0; st < L8; ++st) {
+      const bool last = (st == L8 - 1) && REM == 1;
+      // radix-8 butterfly b = j on slots 0..7 (a[b + t*N/8] = slot t)
+      const int k = j % Ns;
+      const int step = k * (N / (Ns * 8));
+      if (st > 0) {
+#pragma unroll
+        for (int t = 1; t < 8; ++t) v[t] = twiddle<INV, T>(v[t], tw, step * t);
+      }
+      dft8<INV, T>(v);
+      if (!last) {
+        cplx<T> *dst = buf + (st & 1) * N;
+        const int base = (j / Ns) * Ns * 8 + k;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) dst[base + s * Ns] = v[s];
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = dst[j + u * TPF];
+        used_lds = true;
+      }
+      Ns *= 8;
+    }
+    if (REM == 4) {
+      // two radix-4 butterflies: b = j (slots 0,2,4,6) and b = j + N/8 (slots 1,3,5,7)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int b = j + c * TPF;
+        const int k = b % Ns;
+        const int step = k * (N / (Ns * 4));
+        if (Ns > 1) {
+#pragma unroll
+          for (int t = 1; t < 4; ++t) v[c + 2 * t] = twiddle<INV, T>(v[c + 2 * t], tw, step * t);
+        }
+        dft4<INV, T>(v[c], v[c + 2], v[c + 4], v[c + 6]);
+      }
+    } else if (REM == 2) {
+      // four radix-2 butterflies b = j + c*N/8 on slots c, c+4
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int b = j + c * TPF;
+        const int k = b % Ns;
+        const int step = k * (N / (Ns * 2));
+        if (Ns > 1) v[c + 4] = twiddle<INV, T>(v[c + 4], tw, step);
+        dft2<INV, T>(v[c], v[c + 4]);
+      }
+    }
+    // A later call (or the caller's own LDS use) may overwrite the buffers this call read.
+    if (used_lds) __syncthreads();
+  }
+};
+
+}  // namespace ff

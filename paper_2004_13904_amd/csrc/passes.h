@@ -1,0 +1,278 @@
+// Pass kernels of the BCCB-embedded layered operator (Appendix A of the paper).
+//
+//   G x   : [row R2C along x of every model row, zero-padded to NX]            (pass 1)
+//           [per column kx: FFT along y, multiply by the layer spectrum, sum the
+//            layers in the frequency domain, inverse FFT along y, keep the station rows] (pass 2)
+//           [row C2R along x of every station row, keep the station columns]    (pass 3)
+//   G^T y : pass 1 on the data rows (embedded at the station offset), pass 2 with the
+//           conjugate spectra and one inverse per layer, pass 3 on every model row.
+//
+// Intermediate layout between the passes is column-major per half-spectrum column
+// ([batch][kx][row], rows contiguous) so that the column pass reads and writes whole
+// contiguous columns and the row passes transpose through LDS.
+#pragma once
+
+#include "fft.h"
+
+namespace ff {
+
+template <typename T, int N> struct RowCfg {
+  static constexpr int CS = (int)sizeof(cplx<T>);
+  static constexpr int byLds = 32768 / (N * CS);       // 2N complex per FFT within 64 KB
+  static constexpr int byThr = 8192 / N;               // <= 1024 threads
+  static constexpr int m1 = byLds < byThr ? byLds : byThr;
+  static constexpr int m2 = m1 < 8 ? m1 : 8;
+  static constexpr int NF = m2 < 1 ? 1 : m2;           // FFTs (row pairs) per block
+  static constexpr int ROWS = 2 * NF;
+  static constexpr int THREADS = NF * (N / 8);
+  static constexpr int TS = ROWS + 1;                  // padded tile stride (bank conflicts)
+  static constexpr int H = N / 2 + 1;
+  static_assert(H * TS <= NF * 2 * N, "tile must fit in the FFT buffers");
+};
+
+template <int NY> struct ColCfg {
+  static constexpr int TPF = NY / 8;
+  static constexpr int CPB = TPF >= 64 ? 1 : 64 / TPF;  // columns per block
+  static constexpr int THREADS = CPB * TPF;
+};
+
+// Strides of a 3-level index (vector v, batch b within the vector, row) -> element offset.
+struct Idx3 {
+  int64_t v, b, row;
+  __device__ __forceinline__ int64_t at(int64_t vv, int64_t bb, int64_t rr) const {
+    return vv * v + bb * b + rr * row;
+  }
+};
+
+// ---------------------------------------------------------------------------------------
+// Pass 1: real rows -> half spectra along x, written transposed.
+// Input row (vec, b, row) holds `len` values that sit at x = off .. off+len-1 of the length-N
+// embedding (zero elsewhere); `pre` (optional) multiplies them (indexed without the vector
+// stride).  Output element (vec, b, kx, row) at out[o.at(vec, b, row) + kx*out_kx].
+// Grid: (ceil(nrows/ROWS), nb, nvec).
+template <typename T, typename TI, int N>
+__global__ void __launch_bounds__((RowCfg<T, N>::THREADS))
+k_row_r2c(const TI *__restrict__ in, Idx3 ii, const TI *__restrict__ pre, Idx3 pi, int nrows, int len,
+          int off, cplx<T> *__restrict__ out, Idx3 oi, int64_t out_kx,
+          const cplx<T> *__restrict__ tw) {
+  using C = RowCfg<T, N>;
+  using F = FFT<T, N, false>;
+  __shared__ cplx<T> sh[C::NF * 2 * N];
+  const int f = threadIdx.x / F::TPF, j = threadIdx.x % F::TPF;
+  const int64_t vec = blockIdx.z, b = blockIdx.y;
+  const int row0 = blockIdx.x * C::ROWS;
+  const int ra = row0 + 2 * f, rb = ra + 1;
+  cplx<T> v[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int c = j + u * F::TPF - off;
+    T a = 0, bv = 0;
+    if (c >= 0 && c < len) {
+      if (ra < nrows) {
+        a = (T)in[ii.at(vec, b, ra) + c];
+        if (pre) a *= (T)pre[pi.at(0, b, ra) + c];
+      }
+      if (rb < nrows) {
+        bv = (T)in[ii.at(vec, b, rb) + c];
+        if (pre) bv *= (T)pre[pi.at(0, b, rb) + c];
+      }
+    }
+    v[u] = mk<T>(a, bv);
+  }
+  F::run(v, j, sh + f * 2 * N, tw);
+  // separate the two packed real transforms: Xa = (Z_k + conj Z_{N-k})/2, Xb = (Z_k - conj Z_{N-k})/(2i)
+  cplx<T> *z = sh + f * 2 * N;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) z[j + u * F::TPF] = v[u];
+  __syncthreads();
+  cplx<T> xa[5], xb[5];
+#pragma unroll
+  for (int u = 0; u < 5; ++u) {
+    const int k = j + u * F::TPF;
+    if (u < 4 || j == 0) {
+      const cplx<T> zk = z[k], zr = z[(N - k) & (N - 1)];
+      xa[u] = mk<T>((zk.x + zr.x) * (T)0.5, (zk.y - zr.y) * (T)0.5);
+      xb[u] = mk<T>((zk.y + zr.y) * (T)0.5, (zr.x - zk.x) * (T)0.5);
+    }
+  }
+  __syncthreads();
+  cplx<T> *tile = sh;
+#pragma unroll
+  for (int u = 0; u < 5; ++u) {
+    const int k = j + u * F::TPF;
+    if (u < 4 || j == 0) {
+      tile[k * C::TS + 2 * f] = xa[u];
+      tile[k * C::TS + 2 * f + 1] = xb[u];
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < C::H * C::ROWS; idx += C::THREADS) {
+    const int k = idx / C::ROWS, rr = idx - k * C::ROWS;
+    const int row = row0 + rr;
+    if (row < nrows) out[oi.at(vec, b, row) + k * out_kx] = tile[k * C::TS + rr];
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Pass 3: half spectra (vec, b, kx, row), summed over P partial buffers `pstride` apart, ->
+// real rows; keeps x = off .. off+len-1, multiplies by `post` (optional, indexed without the
+// vector stride).  Grid: (ceil(nrows/ROWS), nb, nvec).
+template <typename T, typename TO, int N>
+__global__ void __launch_bounds__((RowCfg<T, N>::THREADS))
+k_row_c2r(const cplx<T> *__restrict__ in, Idx3 ii, int64_t in_kx, int64_t pstride, int P, int nrows,
+          TO *__restrict__ out, Idx3 oi, const TO *__restrict__ post, Idx3 qi, int len, int off,
+          const cplx<T> *__restrict__ tw) {
+  using C = RowCfg<T, N>;
+  using F = FFT<T, N, true>;
+  __shared__ cplx<T> sh[C::NF * 2 * N];
+  const int f = threadIdx.x / F::TPF, j = threadIdx.x % F::TPF;
+  const int64_t vec = blockIdx.z, b = blockIdx.y;
+  const int row0 = blockIdx.x * C::ROWS;
+  cplx<T> *tile = sh;
+  for (int idx = threadIdx.x; idx < C::H * C::ROWS; idx += C::THREADS) {
+    const int k = idx / C::ROWS, rr = idx - k * C::ROWS;
+    const int row = row0 + rr;
+    cplx<T> val = mk<T>(0, 0);
+    if (row < nrows) {
+      const cplx<T> *src = in + ii.at(vec, b, row) + k * in_kx;
+      for (int p = 0; p < P; ++p) val = cadd<T>(val, src[p * pstride]);
+    }
+    tile[k * C::TS + rr] = val;
+  }
+  __syncthreads();
+  cplx<T> v[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int k = j + u * F::TPF;
+    cplx<T> A, B;
+    if (k <= N / 2) {
+      A = tile[k * C::TS + 2 * f];
+      B = tile[k * C::TS + 2 * f + 1];
+      if (k == 0 || k == N / 2) {  // real signal: DC and Nyquist bins are real
+        A.y = 0;
+        B.y = 0;
+      }
+    } else {
+      A = cconj<T>(tile[(N - k) * C::TS + 2 * f]);
+      B = cconj<T>(tile[(N - k) * C::TS + 2 * f + 1]);
+    }
+    v[u] = mk<T>(A.x - B.y, A.y + B.x);  // Z = A + i B
+  }
+  __syncthreads();
+  F::run(v, j, sh + f * 2 * N, tw);
+  const int ra = row0 + 2 * f, rb = ra + 1;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int c = j + u * F::TPF - off;
+    if (c >= 0 && c < len) {
+      if (ra < nrows) {
+        T a = v[u].x;
+        if (post) a *= (T)post[qi.at(0, b, ra) + c];
+        out[oi.at(vec, b, ra) + c] = (TO)a;
+      }
+      if (rb < nrows) {
+        T bv = v[u].y;
+        if (post) bv *= (T)post[qi.at(0, b, rb) + c];
+        out[oi.at(vec, b, rb) + c] = (TO)bv;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Pass 2 of G: for each half-spectrum column kx and layer group g:
+//   acc = sum_{r in group} S_r[kx, :] .* FFT_y(X1[vec, r, kx, 0:ny]),
+//   out[vec, g, kx, j] = IFFT_y(acc)[pyl + j], j in [0, sy).
+// X1 rows are stored [vec][r][kx][y] (ld = ny); spectra [r][kx][ky].
+// Grid: (ceil(H/CPB), LG, nvec).
+template <typename T, int NY>
+__global__ void __launch_bounds__(ColCfg<NY>::THREADS)
+k_col_G(const cplx<T> *__restrict__ X1, int ny, int nz, int H, int LG,
+        const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ outp, int sy, int pyl,
+        const cplx<T> *__restrict__ tw) {
+  using CC = ColCfg<NY>;
+  using Ff = FFT<T, NY, false>;
+  using Fi = FFT<T, NY, true>;
+  __shared__ cplx<T> sh[CC::CPB * 2 * NY];
+  const int f = threadIdx.x / CC::TPF, j = threadIdx.x % CC::TPF;
+  const int kx = blockIdx.x * CC::CPB + f;
+  const bool ok = kx < H;
+  const int g = blockIdx.y;
+  const int64_t vec = blockIdx.z;
+  const int r0 = (int)((int64_t)g * nz / LG), r1 = (int)((int64_t)(g + 1) * nz / LG);
+  cplx<T> acc[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) acc[u] = mk<T>(0, 0);
+  for (int r = r0; r < r1; ++r) {
+    const cplx<T> *src = X1 + ((vec * nz + r) * H + kx) * (int64_t)ny;
+    cplx<T> v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int y = j + u * CC::TPF;
+      v[u] = (ok && y < ny) ? src[y] : mk<T>(0, 0);
+    }
+    Ff::run(v, j, sh + f * 2 * NY, tw);
+    if (ok) {
+      const cplx<T> *sp = spec + ((int64_t)r * H + kx) * NY;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const cplx<T> s = sp[j + u * CC::TPF];
+        acc[u] = cadd<T>(acc[u], cmul<T>(v[u], s));
+      }
+    }
+  }
+  Fi::run(acc, j, sh + f * 2 * NY, tw);
+  if (ok) {
+    cplx<T> *dst = outp + ((vec * LG + g) * H + kx) * (int64_t)sy;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int y = j + u * CC::TPF - pyl;
+      if (y >= 0 && y < sy) dst[y] = acc[u];
+    }
+  }
+}
+
+// Pass 2 of G^T: for each column kx: D = FFT_y(D1[vec, kx, :] placed at rows pyl..pyl+sy-1);
+// for each layer r of the group: X1[vec, r, kx, q] = IFFT_y(conj(S_r[kx, :]) .* D)[q], q < ny.
+// Grid: (ceil(H/CPB), LG, nvec).
+template <typename T, int NY>
+__global__ void __launch_bounds__(ColCfg<NY>::THREADS)
+k_col_GT(const cplx<T> *__restrict__ D1, int sy, int pyl, int nz, int H, int LG,
+         const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ X1, int ny,
+         const cplx<T> *__restrict__ tw) {
+  using CC = ColCfg<NY>;
+  using Ff = FFT<T, NY, false>;
+  using Fi = FFT<T, NY, true>;
+  __shared__ cplx<T> sh[CC::CPB * 2 * NY];
+  const int f = threadIdx.x / CC::TPF, j = threadIdx.x % CC::TPF;
+  const int kx = blockIdx.x * CC::CPB + f;
+  const bool ok = kx < H;
+  const int g = blockIdx.y;
+  const int64_t vec = blockIdx.z;
+  const int r0 = (int)((int64_t)g * nz / LG), r1 = (int)((int64_t)(g + 1) * nz / LG);
+  const cplx<T> *src = D1 + (vec * H + kx) * (int64_t)sy;
+  cplx<T> dh[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int y = j + u * CC::TPF - pyl;
+    dh[u] = (ok && y >= 0 && y < sy) ? src[y] : mk<T>(0, 0);
+  }
+  Ff::run(dh, j, sh + f * 2 * NY, tw);
+  for (int r = r0; r < r1; ++r) {
+    cplx<T> v[8];
+    const cplx<T> *sp = spec + ((int64_t)r * H + (ok ? kx : 0)) * NY;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = ok ? cmulc<T>(dh[u], sp[j + u * CC::TPF]) : mk<T>(0, 0);
+    Fi::run(v, j, sh + f * 2 * NY, tw);
+    if (ok) {
+      cplx<T> *dst = X1 + ((vec * nz + r) * H + kx) * (int64_t)ny;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int y = j + u * CC::TPF;
+        if (y < ny) dst[y] = v[u];
+      }
+    }
+  }
+}
+
+}  // namespace ff

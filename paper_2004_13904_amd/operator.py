@@ -1,0 +1,154 @@
+"""Torch-facing wrapper of the layered BTTB operator (argument marshalling only).
+
+``Operator(survey, dtype)`` builds the kernel spectra on the current HIP device; ``G``,
+``GT`` and ``G_block`` enqueue the hand-written HIP passes on torch's current stream.
+``GOp`` / ``GTOp`` are ``torch.autograd.Function``s whose backward is the adjoint HIP
+operator (G is linear, so no activations are kept: the context holds only the handle).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib as L
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Operator:
+    """G and G^T of one survey geometry on one device (see include/fastfocus.h)."""
+
+    def __init__(self, survey, dtype=torch.float32, nfft=(0, 0)):
+        if not torch.cuda.is_available():
+            raise L.FastFocusError("Operator", -6, "no HIP device available")
+        if dtype not in (torch.float32, torch.float64):
+            raise L.FastFocusError("Operator", -3, "dtype must be float32 or float64")
+        self.survey = dict(survey)
+        self.dtype = dtype
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        geom, self._keep = L.make_geometry(survey, nfft)
+        h = C.c_void_p()
+        dt = L.FF_F32 if dtype == torch.float32 else L.FF_F64
+        L.call("build_spectra", C.byref(geom), dt, _stream(), C.byref(h))
+        self.h = h
+        m, n, nfx, nfy, dti = C.c_int64(), C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32()
+        L.call("ff_spectra_info", h, C.byref(m), C.byref(n), C.byref(nfx), C.byref(nfy), C.byref(dti))
+        self.m, self.n, self.nfft = m.value, n.value, (nfx.value, nfy.value)
+        s = self.survey
+        self.nx = s["sx"] + s.get("pad_xl", 0) + s.get("pad_xr", 0)
+        self.ny = s["sy"] + s.get("pad_yl", 0) + s.get("pad_yr", 0)
+        self.nz = s["nz"]
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            L.load().ff_free_spectra(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- validation ------------------------------------------------------------------
+    def _vec(self, t, numel, name, dtype=None):
+        dtype = dtype or self.dtype
+        if t.device != self.device:
+            raise L.FastFocusError(name, -6, f"tensor on {t.device}, operator on {self.device}")
+        if t.dtype != dtype:
+            raise L.FastFocusError(name, -3, f"expected {dtype}, got {t.dtype}")
+        if not t.is_contiguous():
+            raise L.FastFocusError(name, -2, "tensor must be contiguous")
+        if t.numel() != numel:
+            raise L.FastFocusError(name, -2, f"expected {numel} values, got {t.numel()}")
+        return t
+
+    def _new(self, *shape):
+        return torch.empty(*shape, dtype=self.dtype, device=self.device)
+
+    # -- operator ----------------------------------------------------------------------
+    def G(self, x, out=None, w_pre=None, w_post=None, stream=None):
+        """d = w_post * G (w_pre * x); x has n values, returns m values."""
+        self._vec(x, self.n, "apply_G")
+        out = self._new(self.m) if out is None else self._vec(out, self.m, "apply_G")
+        if w_pre is not None:
+            self._vec(w_pre, self.n, "apply_G")
+        if w_post is not None:
+            self._vec(w_post, self.m, "apply_G")
+        L.call("apply_G", self.h, _ptr(x), _ptr(out), _ptr(w_pre), _ptr(w_post), _stream(stream))
+        return out
+
+    def GT(self, d, out=None, w_pre=None, w_post=None, stream=None):
+        """x = w_post * G^T (w_pre * d); d has m values, returns n values."""
+        self._vec(d, self.m, "apply_GT")
+        out = self._new(self.n) if out is None else self._vec(out, self.n, "apply_GT")
+        if w_pre is not None:
+            self._vec(w_pre, self.m, "apply_GT")
+        if w_post is not None:
+            self._vec(w_post, self.n, "apply_GT")
+        L.call("apply_GT", self.h, _ptr(d), _ptr(out), _ptr(w_pre), _ptr(w_post), _stream(stream))
+        return out
+
+    def G_block(self, X, transpose=False, out=None, w_pre=None, w_post=None, stream=None):
+        """Rows of X (k x n, or k x m when transposed) are the vectors; returns k x m (k x n)."""
+        rin, rout = (self.m, self.n) if transpose else (self.n, self.m)
+        if X.dim() != 2 or X.shape[1] != rin:
+            raise L.FastFocusError("apply_G_block", -2, f"expected (k, {rin}), got {tuple(X.shape)}")
+        k = X.shape[0]
+        self._vec(X, k * rin, "apply_G_block")
+        out = self._new(k, rout) if out is None else self._vec(out, k * rout, "apply_G_block")
+        if w_pre is not None:
+            self._vec(w_pre, rin, "apply_G_block")
+        if w_post is not None:
+            self._vec(w_post, rout, "apply_G_block")
+        L.call("apply_G_block", self.h, int(bool(transpose)), k, _ptr(X), rin, _ptr(out), rout,
+               _ptr(w_pre), _ptr(w_post), _stream(stream))
+        return out
+
+    def kernel_table(self, stream=None):
+        """FP64 kernel table t_r(u, v), shape (nz, sy + ny - 1, sx + nx - 1)."""
+        s = self.survey
+        t = torch.empty(self.nz, s["sy"] + self.ny - 1, s["sx"] + self.nx - 1, dtype=torch.float64,
+                        device=self.device)
+        L.call("ff_kernel_table", self.h, _ptr(t), _stream(stream))
+        return t
+
+
+class GOp(torch.autograd.Function):
+    """y = G x (x: (n,) or (k, n)); backward applies the hand-written G^T."""
+
+    @staticmethod
+    def forward(ctx, op, x):
+        ctx.op = op
+        x = x.contiguous()
+        return op.G_block(x) if x.dim() == 2 else op.G(x)
+
+    @staticmethod
+    def backward(ctx, g):
+        g = g.contiguous()
+        gx = ctx.op.G_block(g, transpose=True) if g.dim() == 2 else ctx.op.GT(g)
+        return None, gx
+
+
+class GTOp(torch.autograd.Function):
+    """x = G^T d; backward applies G."""
+
+    @staticmethod
+    def forward(ctx, op, d):
+        ctx.op = op
+        d = d.contiguous()
+        return op.G_block(d, transpose=True) if d.dim() == 2 else op.GT(d)
+
+    @staticmethod
+    def backward(ctx, g):
+        g = g.contiguous()
+        gd = ctx.op.G_block(g) if g.dim() == 2 else ctx.op.G(g)
+        return None, gd

@@ -1,0 +1,82 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared entry point, and
+rejects invalid geometries before touching a device (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "fastfocus.h")
+
+
+def _lib():
+    from paper_2004_13904_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        from paper_2004_13904_amd import build
+        build.build(verbose=False)
+    return L, L.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:ff_status|const char \*)\s*\**\s*(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("build_spectra", "apply_G", "apply_GT", "apply_G_block", "gkb_project",
+                     "rsvd_project", "irls_step"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    L, lib = _lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(L.EXPORTS) == set(declared_functions())
+
+
+def geom(L, **kw):
+    s = dict(sx=8, sy=8, nz=2, dx=20.0, dy=20.0, z_edges=(0.0, 20.0, 40.0), kernel="gravity")
+    s.update(kw)
+    return L.make_geometry(s)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(z_edges=(1.0, 20.0, 40.0)), -1),            # station plane must be z = 0
+    (dict(z_edges=(0.0, 20.0, 20.0)), -1),            # strictly increasing layers
+    (dict(dx=-1.0), -1),
+    (dict(sx=0), -2),
+])
+def test_invalid_geometry_is_rejected_on_the_host(kw, code):
+    L, lib = _lib()
+    g, keep = geom(L, **kw)
+    h = C.c_void_p()
+    rc = lib.build_spectra(C.byref(g), L.FF_F32, None, C.byref(h))
+    assert rc == code
+    assert lib.ff_last_error().decode()
+    assert not h.value
+
+
+def test_wraparound_embedding_is_rejected():
+    L, lib = _lib()
+    g, keep = geom(L)
+    g.nfft_x = 8            # s_x + n_x - 1 = 15 > 8: circular wrap-around
+    h = C.c_void_p()
+    assert lib.build_spectra(C.byref(g), L.FF_F32, None, C.byref(h)) == -2
+    g.nfft_x = 24           # not a power of two
+    assert lib.build_spectra(C.byref(g), L.FF_F32, None, C.byref(h)) == -7
+
+
+def test_bad_dtype_and_null_arguments():
+    L, lib = _lib()
+    g, keep = geom(L)
+    h = C.c_void_p()
+    assert lib.build_spectra(C.byref(g), 7, None, C.byref(h)) == -3
+    assert lib.build_spectra(None, 0, None, C.byref(h)) == -1
+    assert lib.apply_G(None, None, None, None, None, None) == -1
+    assert lib.ff_free_spectra(None) == -1

@@ -1,0 +1,184 @@
+"""Parity of the HIP operator (C ABI) with the CPU oracle, per the bars:
+FP64 operators within 1e-12 relative l2 of the dense / direct-sum definition, FP32 within 1e-5.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import announce, ogeom, otable, rel, to_dev, to_host
+from oracle import geometry, operator as op
+from paper_2004_13904_amd import workloads as W
+from paper_2004_13904_amd import _lib as L
+from paper_2004_13904_amd.operator import Operator
+
+pytestmark = pytest.mark.gpu
+
+F64, F32 = torch.float64, torch.float32
+TOL = {F64: 1e-12, F32: 1e-5}
+
+
+def survey(**kw):
+    s = W.survey(kw.pop("sx"), kw.pop("sy"), kw.pop("nz"), kw.pop("dx"), kw.pop("dy"), kw.pop("dz"),
+                 kernel=kw.pop("kernel", "gravity"), incl=kw.pop("incl", 90.0),
+                 decl=kw.pop("decl", 0.0), pad=kw.pop("pad", (0, 0, 0, 0)))
+    assert not kw
+    return s
+
+
+SMALL = {
+    "tiny": W.SURVEYS["tiny"],
+    "padded_ragged": survey(sx=9, sy=7, nz=3, dx=20, dy=25, dz=15, pad=(2, 1, 0, 3)),
+    "mag45": survey(sx=8, sy=6, nz=3, dx=20, dy=20, dz=20, kernel="magnetic", incl=45, decl=45),
+    "mag_padded": survey(sx=7, sy=9, nz=2, dx=20, dy=20, dz=30, kernel="magnetic", incl=60, decl=-20,
+                         pad=(1, 2, 3, 1)),
+    "wide_tail": survey(sx=37, sy=11, nz=5, dx=20, dy=20, dz=10, pad=(3, 0, 2, 2)),
+    "mag_many_layers": survey(sx=23, sy=19, nz=33, dx=25, dy=25, dz=12, kernel="magnetic", incl=70,
+                              decl=10),
+}
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_small_against_dense_G(name, dtype):
+    s = SMALL[name]
+    announce("dense", name, dtype)
+    g = ogeom(s)
+    G = op.dense_G(g)
+    rng = np.random.default_rng(0)
+    x = rng.random(g.n)
+    d = rng.standard_normal(g.m)
+    A = Operator(s, dtype)
+    dG = to_host(A.G(to_dev(x, dtype)))
+    xT = to_host(A.GT(to_dev(d, dtype)))
+    assert rel(dG, G @ x) <= TOL[dtype]
+    assert rel(xT, G.T @ d) <= TOL[dtype]
+    A.close()
+
+
+def test_tiny_fp64_adjoint_identity():
+    s = W.SURVEYS["tiny"]
+    A = Operator(s, F64)
+    x = W.uniform_model(s, 0)
+    d = W.gaussian_data(s, 1)
+    Gx = to_host(A.G(to_dev(x, F64)))
+    GTd = to_host(A.GT(to_dev(d, F64)))
+    assert abs(Gx @ d - x @ GTd) <= 1e-13 * np.linalg.norm(Gx) * np.linalg.norm(d)
+
+
+@pytest.mark.parametrize("name", ["tiny", "mag_padded", "gravity_l4", "magnetic_1m"])
+def test_kernel_table_matches_oracle(name):
+    s = SMALL.get(name) or W.SURVEYS[name]
+    announce("table", name)
+    A = Operator(s, F64)
+    t = to_host(A.kernel_table())
+    ref = otable(name) if name in W.SURVEYS else op.kernel_table(ogeom(s))
+    assert t.shape == ref.shape
+    # entries agree to the rounding of the 8-corner sums (far entries cancel; bounded by the
+    # largest entry of the table)
+    assert np.abs(t - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("nfft", [(32, 32), (64, 32), (32, 128)])
+def test_embedding_size_invariance(nfft):
+    s = W.SURVEYS["tiny"]
+    x = W.uniform_model(s, 0)
+    A = Operator(s, F64, nfft=nfft)
+    B = Operator(s, F64)
+    assert A.nfft == nfft and B.nfft == (32, 32)
+    a = to_host(A.G(to_dev(x, F64)))
+    b = to_host(B.G(to_dev(x, F64)))
+    assert rel(a, b) <= 1e-13
+
+
+def test_too_small_embedding_is_rejected():
+    with pytest.raises(L.FastFocusError) as e:
+        Operator(W.SURVEYS["tiny"], F64, nfft=(16, 32))
+    assert e.value.code == -2
+
+
+@pytest.mark.parametrize("name", ["gravity_l4", "gravity_diff", "gravity_rsvd", "magnetic_1m"])
+def test_full_size_fp32_against_direct_sums(name):
+    s = W.SURVEYS[name]
+    announce("full", name)
+    g = ogeom(s)
+    T = otable(name)
+    x = W.uniform_model(s, 0)
+    d = W.gaussian_data(s, 1)
+    A = Operator(s, F32)
+    dG = to_host(A.G(to_dev(x, F32)))
+    xT = to_host(A.GT(to_dev(d, F32)))
+    ref_d = op.apply_G(g, x, T)
+    ref_x = op.apply_GT(g, d, T)
+    assert rel(dG, ref_d) <= 1e-5
+    assert rel(xT, ref_x) <= 1e-5
+    # the embedding size, the spectra and both FFT directions are exercised by the adjoint
+    assert abs(dG @ d - x @ xT) <= 1e-5 * np.linalg.norm(dG) * np.linalg.norm(d)
+
+
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_weighted_operator(dtype):
+    s = SMALL["padded_ragged"]
+    g = ogeom(s)
+    G = op.dense_G(g)
+    rng = np.random.default_rng(2)
+    x, d = rng.random(g.n), rng.standard_normal(g.m)
+    wn, wm = 0.5 + rng.random(g.n), 0.5 + rng.random(g.m)
+    A = Operator(s, dtype)
+    out = to_host(A.G(to_dev(x, dtype), w_pre=to_dev(wn, dtype), w_post=to_dev(wm, dtype)))
+    assert rel(out, wm * (G @ (wn * x))) <= TOL[dtype]
+    out = to_host(A.GT(to_dev(d, dtype), w_pre=to_dev(wm, dtype), w_post=to_dev(wn, dtype)))
+    assert rel(out, wn * (G.T @ (wm * d))) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [F64, F32])
+@pytest.mark.parametrize("k", [1, 5, 16, 21])
+def test_block_apply_equals_vector_loop(dtype, k):
+    s = SMALL["wide_tail"]
+    g = ogeom(s)
+    G = op.dense_G(g)
+    rng = np.random.default_rng(k)
+    X = rng.standard_normal((k, g.n))
+    Y = rng.standard_normal((k, g.m))
+    A = Operator(s, dtype)
+    GX = A.G_block(to_dev(X, dtype))
+    GTY = A.G_block(to_dev(Y, dtype), transpose=True)
+    for c in range(k):
+        assert torch.equal(GX[c], A.G(to_dev(X[c], dtype)))
+        assert torch.equal(GTY[c], A.GT(to_dev(Y[c], dtype)))
+    assert rel(to_host(GX), X @ G.T) <= TOL[dtype]
+    assert rel(to_host(GTY), Y @ G) <= TOL[dtype]
+
+
+def test_zero_and_impulse_inputs():
+    s = SMALL["mag45"]
+    g = ogeom(s)
+    G = op.dense_G(g)
+    A = Operator(s, F64)
+    z = to_host(A.G(torch.zeros(g.n, dtype=F64, device="cuda")))
+    assert np.all(z == 0)
+    # G^T e_s is row s of G; G e_c is column c
+    for st in (0, g.m - 1, 13):
+        e = np.zeros(g.m)
+        e[st] = 1.0
+        assert rel(to_host(A.GT(to_dev(e, F64))), G[st]) <= 1e-12
+    for c in (0, g.n - 1, 77):
+        e = np.zeros(g.n)
+        e[c] = 1.0
+        assert rel(to_host(A.G(to_dev(e, F64))), G[:, c]) <= 1e-12
+
+
+def test_deterministic_repeats():
+    s = W.SURVEYS["gravity_l4"]
+    A = Operator(s, F32)
+    x = to_dev(W.uniform_model(s, 0), F32)
+    ref = A.G(x)
+    for _ in range(10):
+        assert torch.equal(A.G(x), ref)
+
+
+def test_wrong_tensor_arguments_raise():
+    A = Operator(W.SURVEYS["tiny"], F32)
+    with pytest.raises(L.FastFocusError):
+        A.G(torch.zeros(10, dtype=F32, device="cuda"))
+    with pytest.raises(L.FastFocusError):
+        A.G(torch.zeros(A.n, dtype=F64, device="cuda"))
