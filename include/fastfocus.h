@@ -167,6 +167,26 @@ ff_status irls_step(ff_spectra h, const ff_irls_params *p, const double *d_obs, 
                     double *m_new, double *alpha, double *chi2_scaled, void *workspace,
                     size_t ws_bytes, ff_stream stream);
 
+/* Launch tuning of a handle's column passes: the layers of every column are split over
+   lg_G (G) and lg_GT (G^T) groups of blocks (1 <= lg <= nz); the G partial sums of the groups
+   are added in the inverse row pass.  build_spectra picks values that fill the chip; an
+   autotuner may change them.  Results do not depend on them beyond rounding order. */
+typedef struct {
+    int32_t lg_G, lg_GT;
+} ff_tuning;
+ff_status ff_get_tuning(ff_spectra h, ff_tuning *t);
+ff_status ff_set_tuning(ff_spectra h, const ff_tuning *t);
+
+/* Pass profiling (instrumentation for benchmarks).  ff_profile_begin makes every following
+   operator call on this handle record a HIP event on its stream before pass 1 and after each of
+   its three passes, for at most max_ops calls.  ff_profile_end waits for those events and
+   writes the summed durations in milliseconds: ms[3*t + p] for transpose t (0 = G, 1 = G^T) and
+   pass p (0 = row transforms, 1 = column transforms with spectral products, 2 = inverse row
+   transforms), and the number of profiled calls per transpose in ops[t].  Block calls count
+   each batched launch group as one call. */
+ff_status ff_profile_begin(ff_spectra h, int32_t max_ops);
+ff_status ff_profile_end(ff_spectra h, double *ms, int64_t *ops);
+
 /* Thread-local message of the last failure ("" if none).  Valid until the next call. */
 const char *ff_last_error(void);
 

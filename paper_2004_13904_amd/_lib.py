@@ -20,7 +20,8 @@ STATUS = {0: "FF_OK", -1: "FF_EINVAL", -2: "FF_ESHAPE", -3: "FF_EDTYPE", -4: "FF
 
 EXPORTS = ["build_spectra", "ff_free_spectra", "ff_spectra_info", "ff_kernel_table", "apply_G",
            "apply_GT", "apply_G_block", "ff_workspace_size", "gkb_project", "rsvd_project",
-           "irls_step", "ff_last_error"]
+           "irls_step", "ff_get_tuning", "ff_set_tuning", "ff_profile_begin", "ff_profile_end",
+           "ff_last_error"]
 
 
 class FFGeometry(C.Structure):
@@ -36,6 +37,10 @@ class FFIrlsParams(C.Structure):
     _fields_ = [("solver", C.c_int32), ("t", C.c_int32), ("tp", C.c_int32), ("k", C.c_int32),
                 ("lam", C.c_double), ("eps2", C.c_double), ("beta_depth", C.c_double),
                 ("m_min", C.c_double), ("m_max", C.c_double), ("alpha_fixed", C.c_double)]
+
+
+class FFTuning(C.Structure):
+    _fields_ = [("lg_G", C.c_int32), ("lg_GT", C.c_int32)]
 
 
 class FastFocusError(RuntimeError):
@@ -71,6 +76,10 @@ def load(path=None):
         "rsvd_project": [vp, vp, vp, vp, i32, i32, vp, i32, vp, dp, vp, vp, C.c_size_t, vp],
         "irls_step": [vp, C.POINTER(FFIrlsParams), vp, vp, vp, vp, vp, vp, dp, dp, vp, C.c_size_t,
                       vp],
+        "ff_get_tuning": [vp, C.POINTER(FFTuning)],
+        "ff_set_tuning": [vp, C.POINTER(FFTuning)],
+        "ff_profile_begin": [vp, i32],
+        "ff_profile_end": [vp, dp, C.POINTER(i64)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

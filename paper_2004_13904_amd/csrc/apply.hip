@@ -6,6 +6,39 @@
 namespace ff {
 namespace {
 
+// Row-pass launch: full-size blocks (RowMax transforms, 2*NF rows, written back as 2*NF-row
+// contiguous segments) when the pass has at least 2048 rows, else one transform (two rows)
+// per block so that small passes still spread over the chip.
+template <typename T, typename TI, int N>
+void launch_r2c(int nrows, int nb, int kb, const TI *in, Idx3 ii, const TI *pre, Idx3 pi, int len, int off,
+                cplx<T> *out, Idx3 oi, int64_t out_kx, const cplx<T> *tw, hipStream_t s) {
+  constexpr int NFM = RowMax<T, N>::NF;
+  if (NFM == 1 || (int64_t)nrows * nb * kb >= 2048) {
+    using C = RowCfg<T, N, NFM>;
+    dim3 g((nrows + C::ROWS - 1) / C::ROWS, nb, kb);
+    k_row_r2c<T, TI, N, NFM><<<g, C::THREADS, 0, s>>>(in, ii, pre, pi, nrows, len, off, out, oi, out_kx, tw);
+  } else {
+    using C = RowCfg<T, N, 1>;
+    dim3 g((nrows + C::ROWS - 1) / C::ROWS, nb, kb);
+    k_row_r2c<T, TI, N, 1><<<g, C::THREADS, 0, s>>>(in, ii, pre, pi, nrows, len, off, out, oi, out_kx, tw);
+  }
+}
+
+template <typename T, typename TO, int N>
+void launch_c2r(int nrows, int nb, int kb, const cplx<T> *in, Idx3 ii, int64_t in_kx, int64_t pstride, int P,
+                TO *out, Idx3 oi, const TO *post, Idx3 qi, int len, int off, const cplx<T> *tw, hipStream_t s) {
+  constexpr int NFM = RowMax<T, N>::NF;
+  if (NFM == 1 || (int64_t)nrows * nb * kb >= 2048) {
+    using C = RowCfg<T, N, NFM>;
+    dim3 g((nrows + C::ROWS - 1) / C::ROWS, nb, kb);
+    k_row_c2r<T, TO, N, NFM><<<g, C::THREADS, 0, s>>>(in, ii, in_kx, pstride, P, nrows, out, oi, post, qi, len, off, tw);
+  } else {
+    using C = RowCfg<T, N, 1>;
+    dim3 g((nrows + C::ROWS - 1) / C::ROWS, nb, kb);
+    k_row_c2r<T, TO, N, 1><<<g, C::THREADS, 0, s>>>(in, ii, in_kx, pstride, P, nrows, out, oi, post, qi, len, off, tw);
+  }
+}
+
 template <typename T, typename TI, typename TO>
 ff_status run_G(ff_spectra h, int kb, const TI *X, int64_t ldx, TO *Y, int64_t ldy, const TI *pre,
                 const TO *post, hipStream_t s) {
@@ -15,26 +48,22 @@ ff_status run_G(ff_spectra h, int kb, const TI *X, int64_t ldx, TO *Y, int64_t l
   const cplx<T> *spec = (const cplx<T> *)h->spec;
   const cplx<T> *twx = (const cplx<T> *)h->tw_x, *twy = (const cplx<T> *)h->tw_y;
   const int64_t lay = (int64_t)ny * nx;
-  FF_SWITCH_N(h->NX, {
-    using C = RowCfg<T, NN>;
-    dim3 g((ny + C::ROWS - 1) / C::ROWS, nz, kb);
-    k_row_r2c<T, TI, NN><<<g, C::THREADS, 0, s>>>(X, Idx3{ldx, lay, nx}, pre, Idx3{0, lay, nx}, ny, nx, 0, X1,
-                                                   Idx3{(int64_t)nz * H * ny, (int64_t)H * ny, 1}, ny, twx);
-  });
+  prof_mark(h, 0, 0, s);
+  FF_SWITCH_N(h->NX, launch_r2c<T, TI, NN>(ny, nz, kb, X, Idx3{ldx, lay, nx}, pre, Idx3{0, lay, nx}, nx, 0, X1,
+                                           Idx3{(int64_t)nz * H * ny, (int64_t)H * ny, 1}, ny, twx, s));
   FF_LAUNCH_CHECK("G pass 1 (row transforms)");
+  prof_mark(h, 1, 0, s);
   FF_SWITCH_N(h->NY, {
-    using CC = ColCfg<NN>;
+    using CC = ColCfg<T, NN>;
     dim3 g((H + CC::CPB - 1) / CC::CPB, LG, kb);
-    k_col_G<T, NN><<<g, CC::THREADS, 0, s>>>(X1, ny, nz, H, LG, spec, Ap, sy, h->pyl, twy);
+    k_col_G<T, NN><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, nz, H, LG, spec, Ap, sy, h->pyl, twy);
   });
   FF_LAUNCH_CHECK("G pass 2 (column transforms and spectral products)");
-  FF_SWITCH_N(h->NX, {
-    using C = RowCfg<T, NN>;
-    dim3 g((sy + C::ROWS - 1) / C::ROWS, 1, kb);
-    k_row_c2r<T, TO, NN><<<g, C::THREADS, 0, s>>>(Ap, Idx3{(int64_t)LG * H * sy, 0, 1}, sy, (int64_t)H * sy, LG, sy,
-                                                   Y, Idx3{ldy, 0, sx}, post, Idx3{0, 0, sx}, sx, h->pxl, twx);
-  });
+  prof_mark(h, 2, 0, s);
+  FF_SWITCH_N(h->NX, launch_c2r<T, TO, NN>(sy, 1, kb, Ap, Idx3{(int64_t)LG * H * sy, 0, 1}, sy, (int64_t)H * sy, LG,
+                                           Y, Idx3{ldy, 0, sx}, post, Idx3{0, 0, sx}, sx, h->pxl, twx, s));
   FF_LAUNCH_CHECK("G pass 3 (inverse row transforms)");
+  prof_mark(h, 3, 0, s);
   return FF_OK;
 }
 
@@ -47,26 +76,22 @@ ff_status run_GT(ff_spectra h, int kb, const TI *X, int64_t ldx, TO *Y, int64_t 
   const cplx<T> *spec = (const cplx<T> *)h->spec;
   const cplx<T> *twx = (const cplx<T> *)h->tw_x, *twy = (const cplx<T> *)h->tw_y;
   const int64_t lay = (int64_t)ny * nx;
-  FF_SWITCH_N(h->NX, {
-    using C = RowCfg<T, NN>;
-    dim3 g((sy + C::ROWS - 1) / C::ROWS, 1, kb);
-    k_row_r2c<T, TI, NN><<<g, C::THREADS, 0, s>>>(X, Idx3{ldx, 0, sx}, pre, Idx3{0, 0, sx}, sy, sx, h->pxl, D1,
-                                                   Idx3{(int64_t)H * sy, 0, 1}, sy, twx);
-  });
+  prof_mark(h, 0, 1, s);
+  FF_SWITCH_N(h->NX, launch_r2c<T, TI, NN>(sy, 1, kb, X, Idx3{ldx, 0, sx}, pre, Idx3{0, 0, sx}, sx, h->pxl, D1,
+                                           Idx3{(int64_t)H * sy, 0, 1}, sy, twx, s));
   FF_LAUNCH_CHECK("G^T pass 1 (row transforms)");
+  prof_mark(h, 1, 1, s);
   FF_SWITCH_N(h->NY, {
-    using CC = ColCfg<NN>;
+    using CC = ColCfg<T, NN>;
     dim3 g((H + CC::CPB - 1) / CC::CPB, LG, kb);
-    k_col_GT<T, NN><<<g, CC::THREADS, 0, s>>>(D1, sy, h->pyl, nz, H, LG, spec, X1, ny, twy);
+    k_col_GT<T, NN><<<g, CC::THREADS * CC::WPB, 0, s>>>(D1, sy, h->pyl, nz, H, LG, spec, X1, ny, twy);
   });
   FF_LAUNCH_CHECK("G^T pass 2 (column transforms and spectral products)");
-  FF_SWITCH_N(h->NX, {
-    using C = RowCfg<T, NN>;
-    dim3 g((ny + C::ROWS - 1) / C::ROWS, nz, kb);
-    k_row_c2r<T, TO, NN><<<g, C::THREADS, 0, s>>>(X1, Idx3{(int64_t)nz * H * ny, (int64_t)H * ny, 1}, ny, 0, 1, ny,
-                                                   Y, Idx3{ldy, lay, nx}, post, Idx3{0, lay, nx}, nx, 0, twx);
-  });
+  prof_mark(h, 2, 1, s);
+  FF_SWITCH_N(h->NX, launch_c2r<T, TO, NN>(ny, nz, kb, X1, Idx3{(int64_t)nz * H * ny, (int64_t)H * ny, 1}, ny, 0, 1,
+                                           Y, Idx3{ldy, lay, nx}, post, Idx3{0, lay, nx}, nx, 0, twx, s));
   FF_LAUNCH_CHECK("G^T pass 3 (inverse row transforms)");
+  prof_mark(h, 3, 1, s);
   return FF_OK;
 }
 
@@ -86,6 +111,39 @@ ff_status run(ff_spectra h, int transpose, int64_t k, const void *X, int64_t ldx
 }
 
 }  // namespace
+
+int col_wave_groups(int dtype, int NY) {
+  int w = 1;
+  auto pick = [&](auto tag) {
+    using T = decltype(tag);
+    switch (NY) {
+      case 8: w = ColCfg<T, 8>::WPB; break;
+      case 16: w = ColCfg<T, 16>::WPB; break;
+      case 32: w = ColCfg<T, 32>::WPB; break;
+      case 64: w = ColCfg<T, 64>::WPB; break;
+      case 128: w = ColCfg<T, 128>::WPB; break;
+      case 256: w = ColCfg<T, 256>::WPB; break;
+      case 512: w = ColCfg<T, 512>::WPB; break;
+      case 1024: w = ColCfg<T, 1024>::WPB; break;
+      case 2048: w = ColCfg<T, 2048>::WPB; break;
+      default: w = 1;
+    }
+  };
+  if (dtype == FF_F64) pick(double(0)); else pick(float(0));
+  return w;
+}
+
+void prof_mark(ff_spectra h, int slot, int transpose, hipStream_t s) {
+  if (h->prof_cap == 0) return;
+  if (slot == 0) {
+    h->prof_cur = -1;
+    if (h->prof_n >= h->prof_cap) return;
+    h->prof_cur = h->prof_n++;
+    h->prof_kind[h->prof_cur] = transpose;
+  }
+  if (h->prof_cur < 0) return;
+  hipEventRecord(h->prof_ev[4 * h->prof_cur + slot], s);
+}
 
 ff_status op_apply(ff_spectra h, int transpose, int64_t k, const void *X, int64_t ldx, void *Y, int64_t ldy,
                    const void *w_pre, const void *w_post, int io_dtype, hipStream_t s) {

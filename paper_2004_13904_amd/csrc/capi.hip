@@ -33,11 +33,20 @@ int next_pow2(int64_t v) {
   return p;
 }
 
+void prof_release(ff_spectra h) {
+  for (hipEvent_t e : h->prof_ev) hipEventDestroy(e);
+  h->prof_ev.clear();
+  h->prof_kind.clear();
+  h->prof_cap = h->prof_n = 0;
+  h->prof_cur = -1;
+}
+
 void free_handle(ff_spectra h) {
   if (!h) return;
   int cur = 0;
   hipGetDevice(&cur);
   hipSetDevice(h->device);
+  prof_release(h);
   hipFree(h->spec);
   hipFree(h->tw_x);
   hipFree(h->tw_y);
@@ -131,21 +140,22 @@ ff_status build_spectra(const ff_geometry *g, int32_t dtype, ff_stream stream, f
   h->NX = NX; h->NY = NY; h->H = NX / 2 + 1;
   h->m = (int64_t)g->sx * g->sy;
   h->n = nx * ny * g->nz;
+  // Layer groups across blocks of the column passes: enough wavefronts to fill the chip
+  // (about 2048), while every group keeps at least one layer per wave group of its block.
   const int cb = column_blocks(h->H, NY);
-  auto groups = [&](int target) {
-    int lg = (target + cb - 1) / cb;
-    if (lg < 1) lg = 1;
-    if (lg > h->nz) lg = h->nz;
-    return lg;
-  };
-  h->lg_G = groups(1024);
-  h->lg_GT = groups(1024);
+  const int wpb = col_wave_groups(dtype, NY);
+  int lg = (2048 + cb * wpb - 1) / (cb * wpb);
+  const int lgmax_layers = h->nz / wpb > 0 ? h->nz / wpb : 1;
+  if (lg > lgmax_layers) lg = lgmax_layers;
+  if (lg < 1) lg = 1;
+  h->lg_G = lg;
+  h->lg_GT = lg;
 
   const size_t cs = csize(dtype);
   const int64_t rows = ny > g->sy ? ny : g->sy;
   h->ws_rows_bytes = cs * (size_t)kMaxBatch * h->nz * h->H * rows;
-  const int lgmax = h->lg_G > 1 ? h->lg_G : 1;
-  h->ws_cols_bytes = cs * (size_t)kMaxBatch * lgmax * h->H * g->sy;
+  // room for the G partial sums of up to nz layer groups (ff_set_tuning may raise lg_G)
+  h->ws_cols_bytes = cs * (size_t)kMaxBatch * h->nz * h->H * g->sy;
   ff_status st = FF_OK;
   if (hipMalloc(&h->spec, cs * (size_t)h->nz * h->H * NY) != hipSuccess ||
       hipMalloc(&h->ws_rows, h->ws_rows_bytes) != hipSuccess ||
@@ -219,6 +229,66 @@ ff_status apply_G_block(ff_spectra h, int32_t transpose, int64_t k, const void *
   if (st != FF_OK) return st;
   if (k == 0) return FF_OK;
   return op_apply(h, transpose, k, X, ldx, Y, ldy, w_pre, w_post, h->dtype, (hipStream_t)stream);
+}
+
+ff_status ff_get_tuning(ff_spectra h, ff_tuning *t) {
+  if (!h || !t) return fail(FF_EINVAL, "ff_get_tuning: NULL argument");
+  t->lg_G = h->lg_G;
+  t->lg_GT = h->lg_GT;
+  return FF_OK;
+}
+
+ff_status ff_set_tuning(ff_spectra h, const ff_tuning *t) {
+  if (!h || !t) return fail(FF_EINVAL, "ff_set_tuning: NULL argument");
+  if (t->lg_G < 1 || t->lg_G > h->nz || t->lg_GT < 1 || t->lg_GT > h->nz)
+    return fail(FF_EINVAL, "ff_set_tuning: layer groups must lie in [1, nz]");
+  h->lg_G = t->lg_G;
+  h->lg_GT = t->lg_GT;
+  return FF_OK;
+}
+
+ff_status ff_profile_begin(ff_spectra h, int32_t max_ops) {
+  if (!h || max_ops < 1) return fail(FF_EINVAL, "ff_profile_begin: NULL handle or max_ops < 1");
+  ff_status st = check_device(h);
+  if (st != FF_OK) return st;
+  prof_release(h);
+  h->prof_ev.resize(4 * (size_t)max_ops);
+  for (auto &e : h->prof_ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+      prof_release(h);
+      return fail(FF_EHIP, "ff_profile_begin: hipEventCreate failed");
+    }
+  }
+  h->prof_kind.assign(max_ops, 0);
+  h->prof_cap = max_ops;
+  return FF_OK;
+}
+
+ff_status ff_profile_end(ff_spectra h, double *ms, int64_t *ops) {
+  if (!h || !ms || !ops) return fail(FF_EINVAL, "ff_profile_end: NULL argument");
+  for (int i = 0; i < 6; ++i) ms[i] = 0.0;
+  ops[0] = ops[1] = 0;
+  ff_status st = FF_OK;
+  for (int c = 0; c < h->prof_n && st == FF_OK; ++c) {
+    hipEvent_t *e = &h->prof_ev[4 * c];
+    if (hipEventSynchronize(e[3]) != hipSuccess) {
+      st = fail(FF_EHIP, "ff_profile_end: event wait failed");
+      break;
+    }
+    const int t = h->prof_kind[c];
+    for (int p = 0; p < 3; ++p) {
+      float v = 0.f;
+      if (hipEventElapsedTime(&v, e[p], e[p + 1]) != hipSuccess) {
+        st = fail(FF_EHIP, "ff_profile_end: hipEventElapsedTime failed");
+        break;
+      }
+      ms[3 * t + p] += v;
+    }
+    ops[t] += 1;
+  }
+  prof_release(h);
+  return st;
 }
 
 }  // extern "C"

@@ -100,6 +100,10 @@ struct ff_spectra_s {
   size_t ws_rows_bytes = 0, ws_cols_bytes = 0;
   int lg_G = 1;                      // layer groups of the G column pass (partial sums)
   int lg_GT = 1;                     // layer groups of the G^T column pass
+  // pass profiling: 4 events per profiled call (before pass 1, after passes 1-3)
+  std::vector<hipEvent_t> prof_ev;
+  std::vector<int> prof_kind;        // transpose flag of each profiled call
+  int prof_cap = 0, prof_n = 0, prof_cur = -1;
 };
 
 namespace ff {
@@ -111,4 +115,8 @@ ff_status op_apply(ff_spectra h, int transpose, int64_t k, const void *X, int64_
 // spectra construction (spectra.hip)
 ff_status make_spectra(ff_spectra h, hipStream_t s);
 ff_status kernel_table(ff_spectra h, double *table, hipStream_t s);
+// wave groups per block of the column passes (layer split inside a block)
+int col_wave_groups(int dtype, int NY);
+// records profiling event `slot` (0..3) of the current profiled call, if profiling is on
+void prof_mark(ff_spectra h, int slot, int transpose, hipStream_t s);
 }  // namespace ff

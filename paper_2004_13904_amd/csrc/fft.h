@@ -10,7 +10,12 @@
 // in the thread's own registers.  Twiddles come from a table exp(-2 pi i e / N), e in [0, N),
 // built on the host in FP64 and rounded once to T.
 //
-// Every FFT group of a block must call run() together (block-wide barriers inside).
+// Transforms of N <= 512 live in one wavefront and synchronize with wavefront barriers, so
+// waves run their transforms independently.  Larger transforms span several waves and use
+// block-wide barriers: then every FFT group of the block must call run() together.
+//
+// LDS exchange buffers are padded by one element per 8 (index i -> i + i/8) so that the
+// strided Stockham writes spread over the banks.
 #pragma once
 
 #include "common.h"
@@ -78,6 +83,20 @@ __device__ __forceinline__ cplx<T> twiddle(cplx<T> v, const cplx<T> *__restrict_
   return INV ? cmulc<T>(v, w) : cmul<T>(v, w);
 }
 
+// Synchronization of one transform's LDS exchange: a wavefront barrier with LDS ordering
+// when the group fits in a wavefront, else a block barrier.
+template <int TPF> __device__ __forceinline__ void group_sync() {
+  if constexpr (TPF <= 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ int pad8(int i) { return i + (i >> 3); }
+
 constexpr int ilog8(int n) { return n < 8 ? 0 : 1 + ilog8(n / 8); }
 constexpr int ipow8(int k) { return k == 0 ? 1 : 8 * ipow8(k - 1); }
 
@@ -86,9 +105,15 @@ template <typename T, int N, bool INV> struct FFT {
   static constexpr int TPF = N / 8;                // threads per transform
   static constexpr int L8 = ilog8(N);              // radix-8 stages
   static constexpr int REM = N / ipow8(L8);        // 1, 2 or 4: final radix
-  static constexpr int LDS = 2 * N;                // complex elements of LDS per transform
+  static constexpr bool WAVE = TPF <= 64;          // one wavefront: wavefront barriers
+  static constexpr int HALF = N + N / 8;           // one padded exchange buffer
+  // complex elements of LDS per transform: one buffer (synchronized before and after each
+  // exchange) inside a wavefront or when two would exceed 32 KB, else two alternating
+  // buffers (one barrier per exchange)
+  static constexpr bool SINGLE = WAVE || 2 * HALF * (int)sizeof(cplx<T>) > 32768;
+  static constexpr int LDS = SINGLE ? HALF : 2 * HALF;
 
-  // v[u] = x[j + u*TPF] on entry, X[j + u*TPF] on exit.  buf: this group's 2N LDS elements.
+  // v[u] = x[j + u*TPF] on entry, X[j + u*TPF] on exit.  buf: this group's LDS elements.
   __device__ static void run(cplx<T> (&v)[8], int j, cplx<T> *buf, const cplx<T> *__restrict__ tw) {
     int Ns = 1;
     bool used_lds = false;
@@ -104,13 +129,14 @@ template <typename T, int N, bool INV> struct FFT {
       }
       dft8<INV, T>(v);
       if (!last) {
-        cplx<T> *dst = buf + (st & 1) * N;
+        cplx<T> *dst = SINGLE ? buf : buf + (st & 1) * HALF;
         const int base = (j / Ns) * Ns * 8 + k;
+        if (SINGLE) group_sync<TPF>();
 #pragma unroll
-        for (int s = 0; s < 8; ++s) dst[base + s * Ns] = v[s];
-        __syncthreads();
+        for (int s = 0; s < 8; ++s) dst[pad8(base + s * Ns)] = v[s];
+        group_sync<TPF>();
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = dst[j + u * TPF];
+        for (int u = 0; u < 8; ++u) v[u] = dst[pad8(j + u * TPF)];
         used_lds = true;
       }
       Ns *= 8;
@@ -140,7 +166,7 @@ template <typename T, int N, bool INV> struct FFT {
       }
     }
     // A later call (or the caller's own LDS use) may overwrite the buffers this call read.
-    if (used_lds) __syncthreads();
+    if (used_lds) group_sync<TPF>();
   }
 };
 

@@ -16,24 +16,37 @@
 
 namespace ff {
 
-template <typename T, int N> struct RowCfg {
+// Row-pass blocks: NF transforms (2 NF rows) per block.  NFMAX keeps the LDS of the
+// transforms within 64 KB and the block within 1024 threads.
+template <typename T, int N> struct RowMax {
   static constexpr int CS = (int)sizeof(cplx<T>);
-  static constexpr int byLds = 32768 / (N * CS);       // 2N complex per FFT within 64 KB
-  static constexpr int byThr = 8192 / N;               // <= 1024 threads
-  static constexpr int m1 = byLds < byThr ? byLds : byThr;
-  static constexpr int m2 = m1 < 8 ? m1 : 8;
-  static constexpr int NF = m2 < 1 ? 1 : m2;           // FFTs (row pairs) per block
+  static constexpr int H = N / 2 + 1;
+  static constexpr int LDSF = FFT<T, N, false>::LDS;
+  static constexpr bool fits(int nf) {
+    return nf * (N / 8) <= 1024 && (H * (2 * nf + 1) > nf * LDSF ? H * (2 * nf + 1) : nf * LDSF) * CS <= 65536;
+  }
+  static constexpr int NF = fits(8) ? 8 : fits(4) ? 4 : fits(2) ? 2 : 1;
+};
+
+template <typename T, int N, int NF_> struct RowCfg {
+  static constexpr int NF = NF_;
   static constexpr int ROWS = 2 * NF;
   static constexpr int THREADS = NF * (N / 8);
   static constexpr int TS = ROWS + 1;                  // padded tile stride (bank conflicts)
   static constexpr int H = N / 2 + 1;
-  static_assert(H * TS <= NF * 2 * N, "tile must fit in the FFT buffers");
+  static constexpr int LDSF = FFT<T, N, false>::LDS;   // per transform
+  static constexpr int SH = H * TS > NF * LDSF ? H * TS : NF * LDSF;   // transforms, then tile
 };
 
-template <int NY> struct ColCfg {
+// Column-pass wave groups: CPB columns per wave group (one wavefront for NY <= 512), WPB
+// wave groups per block splitting the layers (LDS of the block within 64 KB).
+template <typename T, int NY> struct ColCfg {
   static constexpr int TPF = NY / 8;
-  static constexpr int CPB = TPF >= 64 ? 1 : 64 / TPF;  // columns per block
-  static constexpr int THREADS = CPB * TPF;
+  static constexpr int CPB = TPF >= 64 ? 1 : 64 / TPF;  // columns per wave group
+  static constexpr int THREADS = CPB * TPF;             // threads per wave group
+  static constexpr int GLDS = CPB * FFT<T, NY, false>::LDS;   // LDS elements per wave group
+  static constexpr int byLds = 65536 / (GLDS * (int)sizeof(cplx<T>));
+  static constexpr int WPB = TPF > 64 ? 1 : (byLds < 8 ? byLds : 8);
 };
 
 // Strides of a 3-level index (vector v, batch b within the vector, row) -> element offset.
@@ -50,14 +63,14 @@ struct Idx3 {
 // embedding (zero elsewhere); `pre` (optional) multiplies them (indexed without the vector
 // stride).  Output element (vec, b, kx, row) at out[o.at(vec, b, row) + kx*out_kx].
 // Grid: (ceil(nrows/ROWS), nb, nvec).
-template <typename T, typename TI, int N>
-__global__ void __launch_bounds__((RowCfg<T, N>::THREADS))
+template <typename T, typename TI, int N, int NF>
+__global__ void __launch_bounds__((RowCfg<T, N, NF>::THREADS))
 k_row_r2c(const TI *__restrict__ in, Idx3 ii, const TI *__restrict__ pre, Idx3 pi, int nrows, int len,
           int off, cplx<T> *__restrict__ out, Idx3 oi, int64_t out_kx,
           const cplx<T> *__restrict__ tw) {
-  using C = RowCfg<T, N>;
+  using C = RowCfg<T, N, NF>;
   using F = FFT<T, N, false>;
-  __shared__ cplx<T> sh[C::NF * 2 * N];
+  __shared__ cplx<T> sh[C::SH];
   const int f = threadIdx.x / F::TPF, j = threadIdx.x % F::TPF;
   const int64_t vec = blockIdx.z, b = blockIdx.y;
   const int row0 = blockIdx.x * C::ROWS;
@@ -79,12 +92,12 @@ k_row_r2c(const TI *__restrict__ in, Idx3 ii, const TI *__restrict__ pre, Idx3 p
     }
     v[u] = mk<T>(a, bv);
   }
-  F::run(v, j, sh + f * 2 * N, tw);
+  F::run(v, j, sh + f * F::LDS, tw);
   // separate the two packed real transforms: Xa = (Z_k + conj Z_{N-k})/2, Xb = (Z_k - conj Z_{N-k})/(2i)
-  cplx<T> *z = sh + f * 2 * N;
+  cplx<T> *z = sh + f * F::LDS;
 #pragma unroll
   for (int u = 0; u < 8; ++u) z[j + u * F::TPF] = v[u];
-  __syncthreads();
+  group_sync<F::TPF>();
   cplx<T> xa[5], xb[5];
 #pragma unroll
   for (int u = 0; u < 5; ++u) {
@@ -117,14 +130,14 @@ k_row_r2c(const TI *__restrict__ in, Idx3 ii, const TI *__restrict__ pre, Idx3 p
 // Pass 3: half spectra (vec, b, kx, row), summed over P partial buffers `pstride` apart, ->
 // real rows; keeps x = off .. off+len-1, multiplies by `post` (optional, indexed without the
 // vector stride).  Grid: (ceil(nrows/ROWS), nb, nvec).
-template <typename T, typename TO, int N>
-__global__ void __launch_bounds__((RowCfg<T, N>::THREADS))
+template <typename T, typename TO, int N, int NF>
+__global__ void __launch_bounds__((RowCfg<T, N, NF>::THREADS))
 k_row_c2r(const cplx<T> *__restrict__ in, Idx3 ii, int64_t in_kx, int64_t pstride, int P, int nrows,
           TO *__restrict__ out, Idx3 oi, const TO *__restrict__ post, Idx3 qi, int len, int off,
           const cplx<T> *__restrict__ tw) {
-  using C = RowCfg<T, N>;
+  using C = RowCfg<T, N, NF>;
   using F = FFT<T, N, true>;
-  __shared__ cplx<T> sh[C::NF * 2 * N];
+  __shared__ cplx<T> sh[C::SH];
   const int f = threadIdx.x / F::TPF, j = threadIdx.x % F::TPF;
   const int64_t vec = blockIdx.z, b = blockIdx.y;
   const int row0 = blockIdx.x * C::ROWS;
@@ -159,7 +172,7 @@ k_row_c2r(const cplx<T> *__restrict__ in, Idx3 ii, int64_t in_kx, int64_t pstrid
     v[u] = mk<T>(A.x - B.y, A.y + B.x);  // Z = A + i B
   }
   __syncthreads();
-  F::run(v, j, sh + f * 2 * N, tw);
+  F::run(v, j, sh + f * F::LDS, tw);
   const int ra = row0 + 2 * f, rb = ra + 1;
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
@@ -184,49 +197,77 @@ k_row_c2r(const cplx<T> *__restrict__ in, Idx3 ii, int64_t in_kx, int64_t pstrid
 //   acc = sum_{r in group} S_r[kx, :] .* FFT_y(X1[vec, r, kx, 0:ny]),
 //   out[vec, g, kx, j] = IFFT_y(acc)[pyl + j], j in [0, sy).
 // X1 rows are stored [vec][r][kx][y] (ld = ny); spectra [r][kx][ky].
+// A block holds WPB wave groups on the same CPB columns; wave group w takes every WPB-th
+// layer of the group (loading the next layer while transforming the current one); the
+// partial sums meet in LDS and wave group 0 does the inverse transform.
 // Grid: (ceil(H/CPB), LG, nvec).
 template <typename T, int NY>
-__global__ void __launch_bounds__(ColCfg<NY>::THREADS)
+__global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
 k_col_G(const cplx<T> *__restrict__ X1, int ny, int nz, int H, int LG,
         const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ outp, int sy, int pyl,
         const cplx<T> *__restrict__ tw) {
-  using CC = ColCfg<NY>;
+  using CC = ColCfg<T, NY>;
   using Ff = FFT<T, NY, false>;
   using Fi = FFT<T, NY, true>;
-  __shared__ cplx<T> sh[CC::CPB * 2 * NY];
-  const int f = threadIdx.x / CC::TPF, j = threadIdx.x % CC::TPF;
+  constexpr int TPF = CC::TPF, WPB = CC::WPB;
+  __shared__ cplx<T> sh[WPB * CC::CPB * Ff::LDS];
+  const int w = threadIdx.x / CC::THREADS, lt = threadIdx.x % CC::THREADS;
+  const int f = lt / TPF, j = lt % TPF;
   const int kx = blockIdx.x * CC::CPB + f;
   const bool ok = kx < H;
+  const int kxs = ok ? kx : 0;
   const int g = blockIdx.y;
   const int64_t vec = blockIdx.z;
   const int r0 = (int)((int64_t)g * nz / LG), r1 = (int)((int64_t)(g + 1) * nz / LG);
-  cplx<T> acc[8];
+  cplx<T> *buf = sh + (w * CC::CPB + f) * Ff::LDS;
+  cplx<T> acc[8], xn[8], sn[8];
 #pragma unroll
   for (int u = 0; u < 8; ++u) acc[u] = mk<T>(0, 0);
-  for (int r = r0; r < r1; ++r) {
-    const cplx<T> *src = X1 + ((vec * nz + r) * H + kx) * (int64_t)ny;
-    cplx<T> v[8];
+  auto load = [&](int r) {
+    const cplx<T> *src = X1 + ((vec * nz + r) * H + kxs) * (int64_t)ny;
+    const cplx<T> *sp = spec + ((int64_t)r * H + kxs) * NY;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int y = j + u * CC::TPF;
-      v[u] = (ok && y < ny) ? src[y] : mk<T>(0, 0);
+      const int y = j + u * TPF;
+      xn[u] = (ok && y < ny) ? src[y] : mk<T>(0, 0);
+      sn[u] = sp[y];
     }
-    Ff::run(v, j, sh + f * 2 * NY, tw);
-    if (ok) {
-      const cplx<T> *sp = spec + ((int64_t)r * H + kx) * NY;
+  };
+  // NY <= 512: wave groups are independent, the layer loop may be ragged across them.
+  // NY > 512: one wave group per block (WPB = 1), so the loop is uniform in the block.
+  int r = r0 + w;
+  if (r < r1) load(r);
+  for (; r < r1; r += WPB) {
+    cplx<T> v[8], s[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const cplx<T> s = sp[j + u * CC::TPF];
-        acc[u] = cadd<T>(acc[u], cmul<T>(v[u], s));
-      }
+    for (int u = 0; u < 8; ++u) {
+      v[u] = xn[u];
+      s[u] = sn[u];
     }
+    if (r + WPB < r1) load(r + WPB);
+    Ff::run(v, j, buf, tw);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = cadd<T>(acc[u], cmul<T>(v[u], s[u]));
   }
-  Fi::run(acc, j, sh + f * 2 * NY, tw);
+  if constexpr (WPB > 1) {
+    // partial sums of the wave groups meet in LDS (each in its own transform buffer)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) buf[j + u * TPF] = acc[u];
+    __syncthreads();
+    if (w != 0) return;
+    for (int w2 = 1; w2 < WPB; ++w2) {
+      const cplx<T> *o = sh + (w2 * CC::CPB + f) * Ff::LDS;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = cadd<T>(acc[u], o[j + u * TPF]);
+    }
+    group_sync<TPF>();
+  }
+  Fi::run(acc, j, buf, tw);
   if (ok) {
     cplx<T> *dst = outp + ((vec * LG + g) * H + kx) * (int64_t)sy;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int y = j + u * CC::TPF - pyl;
+      const int y = j + u * TPF - pyl;
       if (y >= 0 && y < sy) dst[y] = acc[u];
     }
   }
@@ -234,41 +275,56 @@ k_col_G(const cplx<T> *__restrict__ X1, int ny, int nz, int H, int LG,
 
 // Pass 2 of G^T: for each column kx: D = FFT_y(D1[vec, kx, :] placed at rows pyl..pyl+sy-1);
 // for each layer r of the group: X1[vec, r, kx, q] = IFFT_y(conj(S_r[kx, :]) .* D)[q], q < ny.
+// Wave group w of a block takes every WPB-th layer of the group and transforms D itself.
 // Grid: (ceil(H/CPB), LG, nvec).
 template <typename T, int NY>
-__global__ void __launch_bounds__(ColCfg<NY>::THREADS)
+__global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
 k_col_GT(const cplx<T> *__restrict__ D1, int sy, int pyl, int nz, int H, int LG,
          const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ X1, int ny,
          const cplx<T> *__restrict__ tw) {
-  using CC = ColCfg<NY>;
+  using CC = ColCfg<T, NY>;
   using Ff = FFT<T, NY, false>;
   using Fi = FFT<T, NY, true>;
-  __shared__ cplx<T> sh[CC::CPB * 2 * NY];
-  const int f = threadIdx.x / CC::TPF, j = threadIdx.x % CC::TPF;
+  constexpr int TPF = CC::TPF, WPB = CC::WPB;
+  __shared__ cplx<T> sh[WPB * CC::CPB * Ff::LDS];
+  const int w = threadIdx.x / CC::THREADS, lt = threadIdx.x % CC::THREADS;
+  const int f = lt / TPF, j = lt % TPF;
   const int kx = blockIdx.x * CC::CPB + f;
   const bool ok = kx < H;
+  const int kxs = ok ? kx : 0;
   const int g = blockIdx.y;
   const int64_t vec = blockIdx.z;
   const int r0 = (int)((int64_t)g * nz / LG), r1 = (int)((int64_t)(g + 1) * nz / LG);
-  const cplx<T> *src = D1 + (vec * H + kx) * (int64_t)sy;
-  cplx<T> dh[8];
+  if (r0 + w >= r1) return;   // no layer for this wave group (never with WPB = 1)
+  cplx<T> *buf = sh + (w * CC::CPB + f) * Ff::LDS;
+  const cplx<T> *src = D1 + (vec * H + kxs) * (int64_t)sy;
+  cplx<T> dh[8], sn[8];
+  int r = r0 + w;
+  {
+    const cplx<T> *sp = spec + ((int64_t)r * H + kxs) * NY;
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    const int y = j + u * CC::TPF - pyl;
-    dh[u] = (ok && y >= 0 && y < sy) ? src[y] : mk<T>(0, 0);
+    for (int u = 0; u < 8; ++u) {
+      const int y = j + u * TPF - pyl;
+      dh[u] = (ok && y >= 0 && y < sy) ? src[y] : mk<T>(0, 0);
+      sn[u] = sp[j + u * TPF];
+    }
   }
-  Ff::run(dh, j, sh + f * 2 * NY, tw);
-  for (int r = r0; r < r1; ++r) {
+  Ff::run(dh, j, buf, tw);
+  for (; r < r1; r += WPB) {
     cplx<T> v[8];
-    const cplx<T> *sp = spec + ((int64_t)r * H + (ok ? kx : 0)) * NY;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = ok ? cmulc<T>(dh[u], sp[j + u * CC::TPF]) : mk<T>(0, 0);
-    Fi::run(v, j, sh + f * 2 * NY, tw);
+    for (int u = 0; u < 8; ++u) v[u] = cmulc<T>(dh[u], sn[u]);
+    if (r + WPB < r1) {
+      const cplx<T> *sp = spec + ((int64_t)(r + WPB) * H + kxs) * NY;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sn[u] = sp[j + u * TPF];
+    }
+    Fi::run(v, j, buf, tw);
     if (ok) {
       cplx<T> *dst = X1 + ((vec * nz + r) * H + kx) * (int64_t)ny;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int y = j + u * CC::TPF;
+        const int y = j + u * TPF;
         if (y < ny) dst[y] = v[u];
       }
     }

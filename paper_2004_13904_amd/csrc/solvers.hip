@@ -1,31 +1,770 @@
-// Projected solvers (Algorithms 1 and 2) and the IRLS step -- placeholder entry points.
+// Projected solvers of the normal equations (Sec. 2.3 of the paper) and the IRLS step.
+//
+//  gkb_project  -- Algorithm 1: Golub-Kahan bidiagonalization of G~ = diag(wd) G diag(winv)
+//                  with reorthogonalization of both bases in FP64, SVD of the bidiagonal B,
+//                  regularization parameter from the truncated UPRE (or eq. (eq:alpha1), or
+//                  fixed), y = ||r~|| A V Gamma(alpha, Sigma) U(1,:)^T.
+//  rsvd_project -- Algorithm 2: randomized SVD with one power iteration; block operator
+//                  applications, economic QRs, eigen-decomposition of the symmetrized B^T B.
+//  irls_step    -- one focusing IRLS step (Secs. 2.2-2.3).
+//
+// Operator applications run in the handle's precision with FP64 vectors; every other step is
+// FP64 on the device.  The bases are reorthogonalized by classical Gram-Schmidt applied twice
+// (same subspace as the paper's modified Gram-Schmidt in exact arithmetic, at least as
+// orthogonal in floating point, and two streaming passes over the basis instead of one
+// dependent pass per column).  The small dense factorizations use rocSOLVER, the B^T B product
+// rocBLAS.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <cmath>
+#include <map>
+#include <mutex>
+
 #include "common.h"
+
+namespace ff {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kRowsPerBlock = 1024;   // rows of a basis per block of the transposed products
+constexpr int kUpreGrid = 400;
+constexpr double kUpreLo = 1e-3;
+constexpr double kGoldenTol = 1e-10;
+
+// ---------------------------------------------------------------------------------------
+// FP64 reductions and vector kernels
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// block-wide sum; result valid in thread 0
+__device__ double block_sum(double v, double *red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) s += red[i];
+  }
+  __syncthreads();
+  return s;
+}
+
+__global__ void k_sumsq_partial(const double *__restrict__ x, int64_t n, double *__restrict__ part) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    s += x[i] * x[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// nrm = sqrt(sum of partials); inv = 1/nrm (0 for a zero vector: the Krylov space is exhausted)
+__global__ void k_norm_finalize(const double *__restrict__ part, int P, double *nrm, double *inv) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < P; i += blockDim.x) s += part[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) {
+    const double v = sqrt(s);
+    *nrm = v;
+    if (inv) *inv = v > 0.0 ? 1.0 / v : 0.0;
+  }
+}
+
+__global__ void k_scale(const double *__restrict__ x, const double *__restrict__ sc, double *__restrict__ y, int64_t n) {
+  const double a = *sc;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i];
+}
+
+// y += sign * (*sc) * x
+__global__ void k_axpy_dev(double *__restrict__ y, const double *__restrict__ x, const double *__restrict__ sc, double sign,
+                           int64_t n) {
+  const double a = sign * (*sc);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] += a * x[i];
+}
+
+// partial[p][j] = sum over the rows of block p of A[row, j] * x[row]   (A column-major, ld lda)
+__global__ void __launch_bounds__(kThreads)
+k_gemv_t_partial(const double *__restrict__ A, int64_t lda, int64_t nrows, int ncols, const double *__restrict__ x,
+                 double *__restrict__ part) {
+  constexpr int K = kRowsPerBlock / 64;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t r0 = (int64_t)blockIdx.x * kRowsPerBlock;
+  double xv[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int64_t r = r0 + l + 64 * k;
+    xv[k] = r < nrows ? x[r] : 0.0;
+  }
+  for (int j = w; j < ncols; j += kThreads / 64) {
+    const double *a = A + (int64_t)j * lda;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int64_t r = r0 + l + 64 * k;
+      if (r < nrows) s += a[r] * xv[k];
+    }
+    s = wave_sum(s);
+    if (l == 0) part[(int64_t)blockIdx.x * ncols + j] = s;
+  }
+}
+
+// out[j] = scale * sum_p part[p][j]
+__global__ void k_colsum(const double *__restrict__ part, int P, int ncols, double *__restrict__ out, double scale) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ncols) return;
+  double s = 0.0;
+  for (int p = 0; p < P; ++p) s += part[(int64_t)p * ncols + j];
+  out[j] = scale * s;
+}
+
+// y = beta * y + alpha * A c   (A column-major nrows x ncols, ld lda; c staged through LDS)
+__global__ void __launch_bounds__(kThreads)
+k_gemv_n(const double *__restrict__ A, int64_t lda, int64_t nrows, int ncols, const double *__restrict__ c,
+         double *__restrict__ y, double alpha, double beta) {
+  __shared__ double cs[2048];
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  for (int j0 = 0; j0 < ncols; j0 += 2048) {
+    const int nj = ncols - j0 < 2048 ? ncols - j0 : 2048;
+    __syncthreads();
+    for (int j = threadIdx.x; j < nj; j += blockDim.x) cs[j] = c[j0 + j];
+    __syncthreads();
+    if (r < nrows) {
+      const double *a = A + (int64_t)j0 * lda + r;
+      for (int j = 0; j < nj; ++j) s += a[(int64_t)j * lda] * cs[j];
+    }
+  }
+  if (r < nrows) y[r] = (beta == 0.0 ? 0.0 : beta * y[r]) + alpha * s;
+}
+
+// ---------------------------------------------------------------------------------------
+// Small kernels of the projected problems
+
+// dense (tp+1) x tp lower-bidiagonal B from its diagonal gamma and subdiagonal beta[1..tp]
+__global__ void k_fill_bidiag(const double *__restrict__ gamma, const double *__restrict__ beta, int tp,
+                              double *__restrict__ B) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ld = tp + 1;
+  if (idx >= ld * tp) return;
+  const int i = (int)(idx % ld), j = (int)(idx / ld);
+  double v = 0.0;
+  if (i == j) v = gamma[j];
+  else if (i == j + 1) v = beta[j + 1];
+  B[idx] = v;
+}
+
+struct UpreIn {
+  const double *s;      // singular values, descending (first t used)
+  const double *c;      // coefficients of the right-hand side (first t used), or NULL
+  const double *u0;     // GKB: first row of U with stride ldu (c_i = *scale * u0[i*ldu])
+  int64_t ldu;
+  const double *scale;  // device scalar (||r~||)
+  int t;
+};
+
+__device__ __forceinline__ double coef(const UpreIn &q, int i) {
+  return q.c ? q.c[i] : (*q.scale) * q.u0[(int64_t)i * q.ldu];
+}
+
+// U(alpha) = sum (alpha^2/(s^2+alpha^2))^2 c^2 + 2 sum s^2/(s^2+alpha^2) - t, block-parallel
+__device__ double upre_eval(const UpreIn &q, double alpha, double *red) {
+  const double a2 = alpha * alpha;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < q.t; i += blockDim.x) {
+    const double s2 = q.s[i] * q.s[i];
+    const double f = a2 / (s2 + a2);
+    const double c = coef(q, i);
+    acc += f * f * c * c + 2.0 * s2 / (s2 + a2);
+  }
+  double tot = block_sum(acc, red);
+  __shared__ double bc;
+  if (threadIdx.x == 0) bc = tot - q.t;
+  __syncthreads();
+  return bc;
+}
+
+// alpha minimizing the UPRE: logarithmic grid on [1e-3 max(s_t, 1e-14 s_1), s_1], the grid
+// point with the smallest value (larger alpha on ties), golden-section search in log(alpha)
+// over the two neighbouring grid cells.  Single block.
+__global__ void k_upre_alpha(UpreIn q, double *alpha_out) {
+  __shared__ double red[16];
+  __shared__ double vals[kUpreGrid];
+  __shared__ double lgrid[kUpreGrid];
+  const double s1 = q.s[0];
+  double st = q.s[q.t - 1];
+  if (st < 1e-14 * s1) st = 1e-14 * s1;
+  const double llo = log(kUpreLo * st), lhi = log(s1);
+  const double step = (lhi - llo) / (kUpreGrid - 1);
+  for (int k = threadIdx.x; k < kUpreGrid; k += blockDim.x) lgrid[k] = k == kUpreGrid - 1 ? lhi : llo + step * k;
+  __syncthreads();
+  // grid values: one thread per grid point (t terms each)
+  for (int k = threadIdx.x; k < kUpreGrid; k += blockDim.x) {
+    const double a = exp(lgrid[k]), a2 = a * a;
+    double acc = 0.0;
+    for (int i = 0; i < q.t; ++i) {
+      const double s2 = q.s[i] * q.s[i];
+      const double f = a2 / (s2 + a2);
+      const double c = coef(q, i);
+      acc += f * f * c * c + 2.0 * s2 / (s2 + a2);
+    }
+    vals[k] = acc - q.t;
+  }
+  __syncthreads();
+  __shared__ int kbest;
+  __shared__ double best;
+  if (threadIdx.x == 0) {
+    int kb = 0;
+    double b = vals[0];
+    for (int k = 1; k < kUpreGrid; ++k)
+      if (vals[k] <= b) {
+        b = vals[k];
+        kb = k;
+      }
+    kbest = kb;
+    best = b;
+  }
+  __syncthreads();
+  const int k = kbest;
+  double a = lgrid[k > 0 ? k - 1 : 0];
+  double b = lgrid[k < kUpreGrid - 1 ? k + 1 : kUpreGrid - 1];
+  const double g = (sqrt(5.0) - 1.0) / 2.0;
+  double x1 = b - g * (b - a), x2 = a + g * (b - a);
+  double f1 = upre_eval(q, exp(x1), red), f2 = upre_eval(q, exp(x2), red);
+  while (b - a > kGoldenTol) {
+    if (f1 <= f2) {
+      b = x2;
+      x2 = x1;
+      f2 = f1;
+      x1 = b - g * (b - a);
+      f1 = upre_eval(q, exp(x1), red);
+    } else {
+      a = x1;
+      x1 = x2;
+      f1 = f2;
+      x2 = a + g * (b - a);
+      f2 = upre_eval(q, exp(x2), red);
+    }
+  }
+  double alpha = exp(0.5 * (a + b));
+  const double fa = upre_eval(q, alpha, red);
+  if (threadIdx.x == 0) *alpha_out = fa > best ? exp(lgrid[k]) : alpha;
+}
+
+// eq. (eq:alpha1): (n/m)^3.5 * s_1 / mean(s_i > 0), over cnt values (descending).  Single block.
+__global__ void k_alpha1(const double *__restrict__ s, int cnt, double nm, double *alpha_out) {
+  __shared__ double red[16];
+  double sum = 0.0, num = 0.0;
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x)
+    if (s[i] > 0.0) {
+      sum += s[i];
+      num += 1.0;
+    }
+  sum = block_sum(sum, red);
+  num = block_sum(num, red);
+  if (threadIdx.x == 0) *alpha_out = pow(nm, 3.5) * s[0] / (sum / num);
+}
+
+// g[i] = scale * s_i / (s_i^2 + alpha^2) * coef_i  for i < cnt (coef from c or from u0 rows)
+__global__ void k_filter(const double *__restrict__ s, const double *__restrict__ alpha, UpreIn q, int cnt,
+                         double *__restrict__ g) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const double a = *alpha;
+  g[i] = s[i] / (s[i] * s[i] + a * a) * coef(q, i);
+}
+
+// RSVD: S = sqrt(|lambda|) sorted descending (lambda ascending from the eigensolver), and the
+// eigenvector columns in the same order: Vs[:, i] = V[:, perm(i)]
+__global__ void k_rsvd_sort(const double *__restrict__ lam, int tp, double *__restrict__ S, int *__restrict__ perm) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  // rank sort: stable in the ascending eigenvalue order for equal magnitudes
+  for (int i = 0; i < tp; ++i) perm[i] = i;
+  // insertion sort by descending sqrt|lambda| (tp is small; runs once per solve)
+  for (int i = 1; i < tp; ++i) {
+    const int pi = perm[i];
+    const double v = sqrt(fabs(lam[pi]));
+    int j = i - 1;
+    while (j >= 0 && sqrt(fabs(lam[perm[j]])) < v) {
+      perm[j + 1] = perm[j];
+      --j;
+    }
+    perm[j + 1] = pi;
+  }
+  for (int i = 0; i < tp; ++i) S[i] = sqrt(fabs(lam[perm[i]]));
+}
+
+__global__ void k_gather_cols(const double *__restrict__ V, int64_t ldv, int nrows, const int *__restrict__ perm, int ncols,
+                              double *__restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)nrows * ncols) return;
+  const int r = (int)(idx % nrows), c = (int)(idx / nrows);
+  out[idx] = V[(int64_t)perm[c] * ldv + r];
+}
+
+// c_i = (V~_i . btr) / S_i  for i < t (U~ = V~ ./ S)
+__global__ void k_rsvd_coef(const double *__restrict__ Vs, int tp, const double *__restrict__ btr, const double *__restrict__ S,
+                            int t, double *__restrict__ c) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= t) return;
+  double acc = 0.0;
+  for (int r = 0; r < tp; ++r) acc += Vs[(int64_t)i * tp + r] * btr[r];
+  c[i] = acc / S[i];
+}
+
+// IRLS pieces
+// winv = 1 / (W_z W_L): layer-constant depth weight (mid-depth)^(-beta) times the focusing
+// weight ((m_prev - m_prev2)^2 + eps2)^((lambda-2)/4) (identity at k = 1)
+__global__ void k_irls_winv(const double *__restrict__ zmid_w, int64_t nlay, int64_t n, const double *__restrict__ mp,
+                            const double *__restrict__ mp2, int k, double lam, double eps2, double *__restrict__ winv) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double w = zmid_w[i / nlay];
+    if (k > 1) {
+      const double dm = mp[i] - mp2[i];
+      w *= pow(dm * dm + eps2, (lam - 2.0) / 4.0);
+    }
+    winv[i] = 1.0 / w;
+  }
+}
+
+// r = wd * (d_obs - gm)
+__global__ void k_residual(const double *__restrict__ wd, const double *__restrict__ dobs, const double *__restrict__ gm,
+                           int64_t m, double *__restrict__ r) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+    r[i] = wd[i] * (dobs[i] - gm[i]);
+}
+
+// m_new = clip(m_prev + winv * y, lo, hi)
+__global__ void k_update_clip(const double *__restrict__ mp, const double *__restrict__ winv, const double *__restrict__ y,
+                              int64_t n, double lo, double hi, double *__restrict__ mn) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double v = mp[i] + winv[i] * y[i];
+    mn[i] = v < lo ? lo : (v > hi ? hi : v);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Host helpers
+
+unsigned grid_for(int64_t n, int threads = kThreads, int64_t cap = 4096) {
+  int64_t g = (n + threads - 1) / threads;
+  if (g > cap) g = cap;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+int partials_for(int64_t nrows) { return (int)((nrows + kRowsPerBlock - 1) / kRowsPerBlock); }
+
+// rocBLAS handle per device, created on first use
+rocblas_handle blas(hipStream_t s, ff_status *st) {
+  static std::mutex mu;
+  static std::map<int, rocblas_handle> handles;
+  int dev = 0;
+  hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = handles.find(dev);
+  rocblas_handle h = nullptr;
+  if (it == handles.end()) {
+    if (rocblas_create_handle(&h) != rocblas_status_success) {
+      *st = fail(FF_EHIP, "rocblas_create_handle failed");
+      return nullptr;
+    }
+    handles[dev] = h;
+  } else {
+    h = it->second;
+  }
+  rocblas_set_stream(h, s);
+  *st = FF_OK;
+  return h;
+}
+
+#define FF_BLAS(call, what)                                                       \
+  do {                                                                            \
+    rocblas_status bs_ = (call);                                                  \
+    if (bs_ != rocblas_status_success)                                            \
+      return fail(FF_EHIP, std::string(what) + ": " + rocblas_status_to_string(bs_)); \
+  } while (0)
+
+// bump allocator over the caller's workspace (256-byte aligned pieces)
+struct Arena {
+  char *base;
+  size_t cap, used = 0;
+  bool dry;   // size query only
+  template <typename T> T *take(size_t count) {
+    size_t off = (used + 255) & ~(size_t)255;
+    used = off + sizeof(T) * count;
+    return dry ? nullptr : (T *)(base + off);
+  }
+};
+
+// v <- (I - Q Q^T)^2 v over the first ncols columns of Q (classical Gram-Schmidt, twice)
+ff_status reorth(const double *Q, int64_t ld, int64_t nrows, int ncols, double *v, double *coef, double *part,
+                 hipStream_t s) {
+  if (ncols <= 0) return FF_OK;
+  const int P = partials_for(nrows);
+  for (int pass = 0; pass < 2; ++pass) {
+    k_gemv_t_partial<<<P, kThreads, 0, s>>>(Q, ld, nrows, ncols, v, part);
+    k_colsum<<<(ncols + 255) / 256, 256, 0, s>>>(part, P, ncols, coef, 1.0);
+    k_gemv_n<<<grid_for(nrows, kThreads, 1 << 30), kThreads, 0, s>>>(Q, ld, nrows, ncols, coef, v, -1.0, 1.0);
+  }
+  FF_LAUNCH_CHECK("reorthogonalization");
+  return FF_OK;
+}
+
+// y = alpha * Q c   (Q nrows x ncols)
+ff_status gemv_n(const double *Q, int64_t ld, int64_t nrows, int ncols, const double *c, double *y, double alpha,
+                 hipStream_t s) {
+  k_gemv_n<<<grid_for(nrows, kThreads, 1 << 30), kThreads, 0, s>>>(Q, ld, nrows, ncols, c, y, alpha, 0.0);
+  FF_LAUNCH_CHECK("gemv");
+  return FF_OK;
+}
+
+// out = Q^T v   (ncols values)
+ff_status gemv_t(const double *Q, int64_t ld, int64_t nrows, int ncols, const double *v, double *out, double *part,
+                 hipStream_t s) {
+  const int P = partials_for(nrows);
+  k_gemv_t_partial<<<P, kThreads, 0, s>>>(Q, ld, nrows, ncols, v, part);
+  k_colsum<<<(ncols + 255) / 256, 256, 0, s>>>(part, P, ncols, out, 1.0);
+  FF_LAUNCH_CHECK("gemv_t");
+  return FF_OK;
+}
+
+// nrm = ||x||, inv = 1/nrm (device scalars)
+ff_status norm2(const double *x, int64_t n, double *nrm, double *inv, double *part, hipStream_t s) {
+  const int P = 256;
+  k_sumsq_partial<<<P, kThreads, 0, s>>>(x, n, part);
+  k_norm_finalize<<<1, kThreads, 0, s>>>(part, P, nrm, inv);
+  FF_LAUNCH_CHECK("norm");
+  return FF_OK;
+}
+
+// Workspace of Algorithm 1 for a handle and tp (also used for sizing when a.dry).
+struct GkbWs {
+  double *A, *H, *b, *c, *gamma, *beta, *ginv, *binv, *coef, *part, *Bd, *S, *U, *Vt, *E, *g, *w, *alpha;
+  rocblas_int *info;
+  void carve(Arena &a, int64_t n, int64_t m, int tp) {
+    const int64_t P = (n > m ? n : m + kRowsPerBlock - 1) / kRowsPerBlock + 1;
+    A = a.take<double>((size_t)n * tp);
+    H = a.take<double>((size_t)m * (tp + 1));
+    b = a.take<double>(n);
+    c = a.take<double>(m);
+    gamma = a.take<double>(tp + 1);
+    beta = a.take<double>(tp + 2);
+    ginv = a.take<double>(tp + 1);
+    binv = a.take<double>(tp + 2);
+    coef = a.take<double>(tp + 2);
+    part = a.take<double>((size_t)((P > 256 ? P : 256) + 1) * (tp + 2));
+    Bd = a.take<double>((size_t)(tp + 1) * tp);
+    S = a.take<double>(tp);
+    U = a.take<double>((size_t)(tp + 1) * tp);
+    Vt = a.take<double>((size_t)tp * tp);
+    E = a.take<double>(tp);
+    g = a.take<double>(tp);
+    w = a.take<double>(tp);
+    alpha = a.take<double>(2);
+    info = a.take<rocblas_int>(4);
+  }
+};
+
+struct RsvdWs {
+  double *Q, *Bm, *Y, *lam, *E, *S, *Vs, *btr, *c, *g, *w, *tau, *alpha, *part;
+  int *perm;
+  rocblas_int *info;
+  void carve(Arena &a, int64_t n, int64_t m, int tp) {
+    const int64_t P = (n > m ? n : m + kRowsPerBlock - 1) / kRowsPerBlock + 1;
+    Q = a.take<double>((size_t)n * tp);     // n x tp (also holds the m x tp factors)
+    Bm = a.take<double>((size_t)m * tp);    // G~ Q
+    Y = a.take<double>((size_t)tp * tp);    // B^T B, then its eigenvectors
+    lam = a.take<double>(tp);
+    E = a.take<double>(tp);
+    S = a.take<double>(tp);
+    Vs = a.take<double>((size_t)tp * tp);
+    btr = a.take<double>(tp);
+    c = a.take<double>(tp);
+    g = a.take<double>(tp);
+    w = a.take<double>(tp);
+    tau = a.take<double>(tp);
+    alpha = a.take<double>(2);
+    part = a.take<double>((size_t)((P > 256 ? P : 256) + 1) * (tp + 2));
+    perm = a.take<int>(tp);
+    info = a.take<rocblas_int>(4);
+  }
+};
+
+struct IrlsWs {
+  double *winv, *r, *gm, *y, *zw, *sig, *part, *nrm;
+  void carve(Arena &a, int64_t n, int64_t m, int nz, int tp) {
+    winv = a.take<double>(n);
+    r = a.take<double>(m);
+    gm = a.take<double>(m);
+    y = a.take<double>(n);
+    zw = a.take<double>(nz);
+    sig = a.take<double>(tp);
+    part = a.take<double>(256);
+    nrm = a.take<double>(2);
+  }
+};
+
+ff_status check_solver_args(ff_spectra h, int t, int tp, const void *r, const void *wd, const void *winv,
+                            const void *y, const void *alpha, const void *sigma, const void *ws) {
+  if (!h || !r || !wd || !winv || !y || !alpha || !sigma || !ws) return fail(FF_EINVAL, "NULL argument");
+  if (t < 1 || tp < t || tp > h->m) return fail(FF_ESHAPE, "need 1 <= t <= tp <= m");
+  int cur = -1;
+  hipGetDevice(&cur);
+  if (cur != h->device) return fail(FF_EDEVICE, "current device differs from the handle's device");
+  return FF_OK;
+}
+
+enum { ALPHA_UPRE = 0, ALPHA_ONE = 1, ALPHA_FIXED = 2 };
+
+// the regularization parameter into *dev_alpha (device) according to mode
+ff_status choose_alpha(ff_spectra h, int mode, double fixed, UpreIn q, const double *s_all, int cnt,
+                       double *dev_alpha, hipStream_t s) {
+  if (mode == ALPHA_FIXED) {
+    FF_HIP(hipMemcpyAsync(dev_alpha, &fixed, sizeof(double), hipMemcpyHostToDevice, s));
+    // the host value must stay alive until the copy has run
+    FF_HIP(hipStreamSynchronize(s));
+  } else if (mode == ALPHA_ONE) {
+    k_alpha1<<<1, kThreads, 0, s>>>(s_all, cnt, (double)h->n / (double)h->m, dev_alpha);
+  } else if (mode == ALPHA_UPRE) {
+    k_upre_alpha<<<1, kThreads, 0, s>>>(q, dev_alpha);
+  } else {
+    return fail(FF_EINVAL, "alpha_mode must be 0 (UPRE), 1 (alpha1) or 2 (fixed)");
+  }
+  FF_LAUNCH_CHECK("regularization parameter");
+  return FF_OK;
+}
+
+ff_status gkb_run(ff_spectra h, const double *rt, const double *wd, const double *winv, int t, int tp, int mode,
+                  double *y, double *alpha, double *sigma, void *ws, size_t ws_bytes, hipStream_t s) {
+  const int64_t n = h->n, m = h->m;
+  Arena ar{(char *)ws, ws_bytes, 0, false};
+  GkbWs W;
+  W.carve(ar, n, m, tp);
+  if (ar.used > ws_bytes) return fail(FF_ENOMEM, "gkb_project: workspace too small");
+  const double fixed = *alpha;
+  ff_status st;
+  // beta_1 = ||r~||, h_1 = r~ / beta_1
+  if ((st = norm2(rt, m, W.beta, W.binv, W.part, s))) return st;
+  k_scale<<<grid_for(m), kThreads, 0, s>>>(rt, W.binv, W.H, m);
+  FF_HIP(hipMemsetAsync(W.b, 0, sizeof(double) * n, s));
+  for (int i = 0; i < tp; ++i) {
+    double *ai = W.A + (int64_t)i * n;
+    const double *hi = W.H + (int64_t)i * m;
+    // b = G~^T h - beta_i a_{i-1}
+    if ((st = op_apply(h, 1, 1, hi, m, W.b, n, wd, winv, FF_F64, s))) return st;
+    if (i > 0) k_axpy_dev<<<grid_for(n), kThreads, 0, s>>>(W.b, W.A + (int64_t)(i - 1) * n, W.beta + i, -1.0, n);
+    if ((st = reorth(W.A, n, n, i, W.b, W.coef, W.part, s))) return st;
+    if ((st = norm2(W.b, n, W.gamma + i, W.ginv + i, W.part, s))) return st;
+    k_scale<<<grid_for(n), kThreads, 0, s>>>(W.b, W.ginv + i, ai, n);
+    // c = G~ a - gamma_i h
+    if ((st = op_apply(h, 0, 1, ai, n, W.c, m, winv, wd, FF_F64, s))) return st;
+    k_axpy_dev<<<grid_for(m), kThreads, 0, s>>>(W.c, hi, W.gamma + i, -1.0, m);
+    if ((st = reorth(W.H, m, m, i + 1, W.c, W.coef, W.part, s))) return st;
+    if ((st = norm2(W.c, m, W.beta + i + 1, W.binv + i + 1, W.part, s))) return st;
+    k_scale<<<grid_for(m), kThreads, 0, s>>>(W.c, W.binv + i + 1, W.H + (int64_t)(i + 1) * m, m);
+  }
+  FF_LAUNCH_CHECK("gkb iteration");
+  // SVD of the (tp+1) x tp bidiagonal
+  const int64_t nb = (int64_t)(tp + 1) * tp;
+  k_fill_bidiag<<<grid_for(nb, 256, 1 << 30), 256, 0, s>>>(W.gamma, W.beta, tp, W.Bd);
+  rocblas_handle bh = blas(s, &st);
+  if (st) return st;
+  FF_BLAS(rocsolver_dgesvd(bh, rocblas_svect_singular, rocblas_svect_all, tp + 1, tp, W.Bd, tp + 1, W.S, W.U, tp + 1,
+                           W.Vt, tp, W.E, rocblas_outofplace, W.info),
+          "rocsolver_dgesvd");
+  // alpha from the first t singular values and c_i = ||r~|| U(1, i)  (||r~|| = beta_1)
+  UpreIn q{W.S, nullptr, W.U, (int64_t)(tp + 1), W.beta, t};
+  if ((st = choose_alpha(h, mode, fixed, q, W.S, tp, W.alpha, s))) return st;
+  // y = ||r~|| A V Gamma(alpha) U(1,:)^T
+  UpreIn qa = q;
+  qa.t = tp;
+  k_filter<<<(tp + 255) / 256, 256, 0, s>>>(W.S, W.alpha, qa, tp, W.g);
+  // w = V g = Vt^T g
+  if ((st = gemv_t(W.Vt, tp, tp, tp, W.g, W.w, W.part, s))) return st;
+  if ((st = gemv_n(W.A, n, n, tp, W.w, y, 1.0, s))) return st;
+  FF_HIP(hipMemcpyAsync(sigma, W.S, sizeof(double) * tp, hipMemcpyDeviceToDevice, s));
+  FF_HIP(hipMemcpyAsync(alpha, W.alpha, sizeof(double), hipMemcpyDeviceToHost, s));
+  FF_HIP(hipStreamSynchronize(s));
+  return FF_OK;
+}
+
+ff_status qr_inplace(rocblas_handle bh, double *M, int64_t rows, int cols, double *tau) {
+  FF_BLAS(rocsolver_dgeqrf(bh, (rocblas_int)rows, cols, M, (rocblas_int)rows, tau), "rocsolver_dgeqrf");
+  FF_BLAS(rocsolver_dorgqr(bh, (rocblas_int)rows, cols, cols, M, (rocblas_int)rows, tau), "rocsolver_dorgqr");
+  return FF_OK;
+}
+
+ff_status rsvd_run(ff_spectra h, const double *rt, const double *wd, const double *winv, int t, int tp,
+                   const double *omega, int mode, double *y, double *alpha, double *sigma, void *ws, size_t ws_bytes,
+                   hipStream_t s) {
+  const int64_t n = h->n, m = h->m;
+  Arena ar{(char *)ws, ws_bytes, 0, false};
+  RsvdWs W;
+  W.carve(ar, n, m, tp);
+  if (ar.used > ws_bytes) return fail(FF_ENOMEM, "rsvd_project: workspace too small");
+  if (n > INT32_MAX) return fail(FF_ENOTIMPL, "rsvd_project: n exceeds the eigensolver's index range");
+  const double fixed = *alpha;
+  ff_status st;
+  rocblas_handle bh = blas(s, &st);
+  if (st) return st;
+  // Y^T = G~^T Omega^T (n x tp), Q = qr(Y^T)
+  if ((st = op_apply(h, 1, tp, omega, m, W.Q, n, wd, winv, FF_F64, s))) return st;
+  if ((st = qr_inplace(bh, W.Q, n, tp, W.tau))) return st;
+  // Y = G~ Q (m x tp), Q = qr(Y)
+  if ((st = op_apply(h, 0, tp, W.Q, n, W.Bm, m, winv, wd, FF_F64, s))) return st;
+  if ((st = qr_inplace(bh, W.Bm, m, tp, W.tau))) return st;
+  // Y^T = G~^T Q (n x tp), Q = qr(Y^T)
+  if ((st = op_apply(h, 1, tp, W.Bm, m, W.Q, n, wd, winv, FF_F64, s))) return st;
+  if ((st = qr_inplace(bh, W.Q, n, tp, W.tau))) return st;
+  // B = G~ Q
+  if ((st = op_apply(h, 0, tp, W.Q, n, W.Bm, m, winv, wd, FF_F64, s))) return st;
+  // B^T B (symmetric by construction of the product; the eigensolver reads one triangle,
+  // which is the symmetrized (Y + Y^T)/2 of the algorithm up to rounding)
+  const double one = 1.0, zero = 0.0;
+  FF_BLAS(rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, tp, tp, (rocblas_int)m, &one, W.Bm,
+                        (rocblas_int)m, W.Bm, (rocblas_int)m, &zero, W.Y, tp),
+          "rocblas_dgemm");
+  FF_BLAS(rocsolver_dsyevd(bh, rocblas_evect_original, rocblas_fill_lower, tp, W.Y, tp, W.lam, W.E, W.info),
+          "rocsolver_dsyevd");
+  k_rsvd_sort<<<1, 1, 0, s>>>(W.lam, tp, W.S, W.perm);
+  k_gather_cols<<<grid_for((int64_t)tp * t, 256, 1 << 30), 256, 0, s>>>(W.Y, tp, tp, W.perm, t, W.Vs);
+  // B^T r~, c = U~^T (B^T r~)
+  if ((st = gemv_t(W.Bm, m, m, tp, rt, W.btr, W.part, s))) return st;
+  k_rsvd_coef<<<(t + 255) / 256, 256, 0, s>>>(W.Vs, tp, W.btr, W.S, t, W.c);
+  UpreIn q{W.S, W.c, nullptr, 0, nullptr, t};
+  if ((st = choose_alpha(h, mode, fixed, q, W.S, tp, W.alpha, s))) return st;
+  // y = Q V~ Gamma(alpha) c
+  k_filter<<<(t + 255) / 256, 256, 0, s>>>(W.S, W.alpha, q, t, W.g);
+  if ((st = gemv_n(W.Vs, tp, tp, t, W.g, W.w, 1.0, s))) return st;
+  if ((st = gemv_n(W.Q, n, n, tp, W.w, y, 1.0, s))) return st;
+  FF_HIP(hipMemcpyAsync(sigma, W.S, sizeof(double) * tp, hipMemcpyDeviceToDevice, s));
+  FF_HIP(hipMemcpyAsync(alpha, W.alpha, sizeof(double), hipMemcpyDeviceToHost, s));
+  FF_HIP(hipStreamSynchronize(s));
+  return FF_OK;
+}
+
+size_t irls_own_bytes(ff_spectra h, int tp) {
+  Arena ar{nullptr, 0, 0, true};
+  IrlsWs I;
+  I.carve(ar, h->n, h->m, h->nz, tp);
+  return ar.used + 256;
+}
+
+// bytes of a solver's workspace; the IRLS workspace is the solver's followed by the step's own
+size_t solver_bytes(ff_spectra h, int which, int solver, int tp) {
+  Arena ar{nullptr, 0, 0, true};
+  const int sol = which == FF_WS_IRLS ? solver : (which == FF_WS_RSVD ? 1 : 0);
+  if (sol == 1) {
+    RsvdWs W;
+    W.carve(ar, h->n, h->m, tp);
+  } else {
+    GkbWs W;
+    W.carve(ar, h->n, h->m, tp);
+  }
+  size_t b = ar.used + 256;
+  if (which == FF_WS_IRLS) b += irls_own_bytes(h, tp);
+  return b;
+}
+
+}  // namespace
+}  // namespace ff
 
 using namespace ff;
 
 extern "C" {
 
 ff_status ff_workspace_size(ff_spectra h, int32_t which, int32_t solver, int32_t tp, size_t *bytes) {
-  (void)h; (void)which; (void)solver; (void)tp; (void)bytes;
-  return fail(FF_ENOTIMPL, "ff_workspace_size: not implemented yet");
+  if (!h || !bytes) return fail(FF_EINVAL, "ff_workspace_size: NULL argument");
+  if (which < FF_WS_GKB || which > FF_WS_IRLS) return fail(FF_EINVAL, "ff_workspace_size: unknown solver");
+  if (tp < 1 || tp > h->m) return fail(FF_ESHAPE, "ff_workspace_size: need 1 <= tp <= m");
+  if (which == FF_WS_IRLS && solver != 0 && solver != 1) return fail(FF_EINVAL, "ff_workspace_size: solver must be 0 or 1");
+  *bytes = solver_bytes(h, which, solver, tp);
+  return FF_OK;
 }
 
 ff_status gkb_project(ff_spectra h, const double *r_tilde, const double *wd, const double *winv, int32_t t,
                       int32_t tp, int32_t alpha_mode, double *y, double *alpha, double *sigma, void *workspace,
                       size_t ws_bytes, ff_stream stream) {
-  return fail(FF_ENOTIMPL, "gkb_project: not implemented yet");
+  ff_status st = check_solver_args(h, t, tp, r_tilde, wd, winv, y, alpha, sigma, workspace);
+  if (st) return st;
+  if (alpha_mode < 0 || alpha_mode > 2) return fail(FF_EINVAL, "gkb_project: alpha_mode must be 0, 1 or 2");
+  return gkb_run(h, r_tilde, wd, winv, t, tp, alpha_mode, y, alpha, sigma, workspace, ws_bytes, (hipStream_t)stream);
 }
 
 ff_status rsvd_project(ff_spectra h, const double *r_tilde, const double *wd, const double *winv, int32_t t,
-                       int32_t tp, const double *omega, int32_t alpha_mode, double *y, double *alpha,
-                       double *sigma, void *workspace, size_t ws_bytes, ff_stream stream) {
-  return fail(FF_ENOTIMPL, "rsvd_project: not implemented yet");
+                       int32_t tp, const double *omega, int32_t alpha_mode, double *y, double *alpha, double *sigma,
+                       void *workspace, size_t ws_bytes, ff_stream stream) {
+  ff_status st = check_solver_args(h, t, tp, r_tilde, wd, winv, y, alpha, sigma, workspace);
+  if (st) return st;
+  if (!omega) return fail(FF_EINVAL, "rsvd_project: omega is NULL");
+  if (alpha_mode < 0 || alpha_mode > 2) return fail(FF_EINVAL, "rsvd_project: alpha_mode must be 0, 1 or 2");
+  return rsvd_run(h, r_tilde, wd, winv, t, tp, omega, alpha_mode, y, alpha, sigma, workspace, ws_bytes,
+                  (hipStream_t)stream);
 }
 
 ff_status irls_step(ff_spectra h, const ff_irls_params *p, const double *d_obs, const double *wd,
-                    const double *m_prev, const double *m_prev2, const double *omega, double *m_new,
-                    double *alpha, double *chi2_scaled, void *workspace, size_t ws_bytes, ff_stream stream) {
-  return fail(FF_ENOTIMPL, "irls_step: not implemented yet");
+                    const double *m_prev, const double *m_prev2, const double *omega, double *m_new, double *alpha,
+                    double *chi2_scaled, void *workspace, size_t ws_bytes, ff_stream stream) {
+  if (!h || !p || !d_obs || !wd || !m_prev || !m_new || !alpha || !chi2_scaled || !workspace)
+    return fail(FF_EINVAL, "irls_step: NULL argument");
+  if (p->k < 1) return fail(FF_EINVAL, "irls_step: k must be >= 1");
+  if (p->k > 1 && !m_prev2) return fail(FF_EINVAL, "irls_step: m_prev2 is needed for k > 1");
+  if (p->solver != 0 && p->solver != 1) return fail(FF_EINVAL, "irls_step: solver must be 0 (GKB) or 1 (RSVD)");
+  if (p->solver == 1 && !omega) return fail(FF_EINVAL, "irls_step: RSVD needs omega");
+  if (!(p->eps2 > 0) || !(p->m_max >= p->m_min)) return fail(FF_EINVAL, "irls_step: need eps2 > 0, m_max >= m_min");
+  if (p->t < 1 || p->tp < p->t || p->tp > h->m) return fail(FF_ESHAPE, "irls_step: need 1 <= t <= tp <= m");
+  int cur = -1;
+  hipGetDevice(&cur);
+  if (cur != h->device) return fail(FF_EDEVICE, "irls_step: current device differs from the handle's device");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = h->n, m = h->m;
+  const size_t need = solver_bytes(h, FF_WS_IRLS, p->solver, p->tp);
+  if (ws_bytes < need) return fail(FF_ENOMEM, "irls_step: workspace too small");
+  // the solver's workspace first, the step's own vectors after it
+  const size_t sol = solver_bytes(h, p->solver == 1 ? FF_WS_RSVD : FF_WS_GKB, 0, p->tp);
+  Arena ar{(char *)workspace + sol, ws_bytes - sol, 0, false};
+  IrlsWs I;
+  I.carve(ar, n, m, h->nz, p->tp);
+  if (sol + ar.used > ws_bytes) return fail(FF_ENOMEM, "irls_step: workspace too small");
+  // depth weights per layer: (mid-depth)^(-beta)
+  std::vector<double> zw(h->nz);
+  for (int r = 0; r < h->nz; ++r) zw[r] = std::pow(0.5 * (h->z_edges[r] + h->z_edges[r + 1]), -p->beta_depth);
+  FF_HIP(hipMemcpyAsync(I.zw, zw.data(), sizeof(double) * h->nz, hipMemcpyHostToDevice, s));
+  k_irls_winv<<<grid_for(n), kThreads, 0, s>>>(I.zw, (int64_t)h->nx * h->ny, n, m_prev, m_prev2, p->k, p->lambda,
+                                                p->eps2, I.winv);
+  // r~ = wd (d_obs - G m_prev)
+  ff_status st;
+  if ((st = op_apply(h, 0, 1, m_prev, n, I.gm, m, nullptr, nullptr, FF_F64, s))) return st;
+  k_residual<<<grid_for(m), kThreads, 0, s>>>(wd, d_obs, I.gm, m, I.r);
+  FF_LAUNCH_CHECK("irls_step setup");
+  const int mode = p->alpha_fixed > 0 ? ALPHA_FIXED : (p->k == 1 ? ALPHA_ONE : ALPHA_UPRE);
+  double a = p->alpha_fixed;
+  // the solvers synchronize the stream before returning, so zw (host) has been consumed
+  if (p->solver == 0)
+    st = gkb_run(h, I.r, wd, I.winv, p->t, p->tp, mode, I.y, &a, I.sig, workspace, sol, s);
+  else
+    st = rsvd_run(h, I.r, wd, I.winv, p->t, p->tp, omega, mode, I.y, &a, I.sig, workspace, sol, s);
+  if (st) return st;
+  // m^(k) = clip(m^(k-1) + W^{-1} y), then the scaled chi^2 of the clipped iterate
+  k_update_clip<<<grid_for(n), kThreads, 0, s>>>(m_prev, I.winv, I.y, n, p->m_min, p->m_max, m_new);
+  if ((st = op_apply(h, 0, 1, m_new, n, I.gm, m, nullptr, nullptr, FF_F64, s))) return st;
+  k_residual<<<grid_for(m), kThreads, 0, s>>>(wd, d_obs, I.gm, m, I.r);
+  if ((st = norm2(I.r, m, I.nrm, nullptr, I.part, s))) return st;
+  double nrm = 0.0;
+  FF_HIP(hipMemcpyAsync(&nrm, I.nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+  FF_HIP(hipStreamSynchronize(s));
+  *alpha = a;
+  *chi2_scaled = nrm * nrm / ((double)m + std::sqrt(2.0 * (double)m));
+  return FF_OK;
 }
 
 }  // extern "C"

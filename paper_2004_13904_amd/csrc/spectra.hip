@@ -107,12 +107,12 @@ __global__ void k_kernel_table(KParams p, const double *__restrict__ z_edges, do
 // Full column FFT along y of the row-transformed generator, scaled and stored in precision TS.
 // tmp: [r][kx][y] (ld NY); spec: [r][kx][ky].  Grid: (ceil(H/CPB), nz).
 template <typename TS, int NY>
-__global__ void __launch_bounds__(ColCfg<NY>::THREADS)
+__global__ void __launch_bounds__((ColCfg<double, NY>::THREADS))
 k_col_spec(const double2 *__restrict__ tmp, int H, double scale, cplx<TS> *__restrict__ spec,
            const double2 *__restrict__ tw) {
-  using CC = ColCfg<NY>;
+  using CC = ColCfg<double, NY>;
   using F = FFT<double, NY, false>;
-  __shared__ double2 sh[CC::CPB * 2 * NY];
+  __shared__ double2 sh[CC::CPB * F::LDS];
   const int f = threadIdx.x / CC::TPF, j = threadIdx.x % CC::TPF;
   const int kx = blockIdx.x * CC::CPB + f;
   const bool ok = kx < H;
@@ -121,7 +121,7 @@ k_col_spec(const double2 *__restrict__ tmp, int H, double scale, cplx<TS> *__res
   double2 v[8];
 #pragma unroll
   for (int u = 0; u < 8; ++u) v[u] = ok ? src[j + u * CC::TPF] : mk<double>(0, 0);
-  F::run(v, j, sh + f * 2 * NY, tw);
+  F::run(v, j, sh + f * F::LDS, tw);
   if (ok) {
     cplx<TS> *dst = spec + (r * H + kx) * NY;
 #pragma unroll
@@ -131,11 +131,12 @@ k_col_spec(const double2 *__restrict__ tmp, int H, double scale, cplx<TS> *__res
 
 template <int NX>
 ff_status rows_fp64(const double *circ, int nz, int NY, double2 *tmp, const double2 *tw, hipStream_t s) {
-  using C = RowCfg<double, NX>;
+  constexpr int NF = RowMax<double, NX>::NF;
+  using C = RowCfg<double, NX, NF>;
   const int H = NX / 2 + 1;
   Idx3 ii{0, (int64_t)NY * NX, NX}, pi{0, 0, 0}, oi{0, (int64_t)H * NY, 1};
   dim3 grid((NY + C::ROWS - 1) / C::ROWS, nz, 1);
-  k_row_r2c<double, double, NX><<<grid, C::THREADS, 0, s>>>(circ, ii, nullptr, pi, NY, NX, 0, tmp, oi,
+  k_row_r2c<double, double, NX, NF><<<grid, C::THREADS, 0, s>>>(circ, ii, nullptr, pi, NY, NX, 0, tmp, oi,
                                                              (int64_t)NY, tw);
   FF_LAUNCH_CHECK("row transform of the kernel generator");
   return FF_OK;
@@ -144,7 +145,7 @@ ff_status rows_fp64(const double *circ, int nz, int NY, double2 *tmp, const doub
 template <typename TS, int NY>
 ff_status cols_fp64(const double2 *tmp, int nz, int H, double scale, void *spec, const double2 *tw,
                     hipStream_t s) {
-  using CC = ColCfg<NY>;
+  using CC = ColCfg<double, NY>;
   dim3 grid((H + CC::CPB - 1) / CC::CPB, nz, 1);
   k_col_spec<TS, NY><<<grid, CC::THREADS, 0, s>>>(tmp, H, scale, (cplx<TS> *)spec, tw);
   FF_LAUNCH_CHECK("column transform of the kernel generator");

@@ -47,6 +47,17 @@ class Operator:
         self.ny = s["sy"] + s.get("pad_yl", 0) + s.get("pad_yr", 0)
         self.nz = s["nz"]
 
+    @property
+    def tuning(self):
+        t = L.FFTuning()
+        L.call("ff_get_tuning", self.h, C.byref(t))
+        return {"lg_G": t.lg_G, "lg_GT": t.lg_GT}
+
+    def set_tuning(self, lg_G=None, lg_GT=None):
+        cur = self.tuning
+        t = L.FFTuning(int(lg_G or cur["lg_G"]), int(lg_GT or cur["lg_GT"]))
+        L.call("ff_set_tuning", self.h, C.byref(t))
+
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
             L.load().ff_free_spectra(self.h)
