@@ -61,6 +61,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--cold-reps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched / RSVD-block / IRLS legs")
+    ap.add_argument("--irls-steps", type=int, default=25)
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the operator and solvers run on a single MI355X "
@@ -93,18 +95,43 @@ def main(argv=None):
         step()
     torch.cuda.synchronize()
 
-    # ---- timed region: K back-to-back pairs ----------------------------------------------
+    # ---- timed region: K pairs replayed from a hipGraph (R pairs per graph) -----------
+    # The operator launches on torch's current stream, so a torch CUDA graph captures the
+    # library's kernels; replaying it removes the host launch cost from the loop.
+    R = 20
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    with torch.cuda.graph(graph):
+        for _ in range(R):
+            step()
+    reps = max(1, a.steps // R)
+    for _ in range(2):
+        graph.replay()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record()
-    for _ in range(a.steps):
-        step()
+    for _ in range(reps):
+        graph.replay()
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_step = ev0.elapsed_time(ev1) / a.steps
-    log(f"timed {a.steps} steps: {ms_step * 1e3:.2f} us/pair (wall {wall:.3f} s)")
+    steps_done = reps * R
+    ms_step = ev0.elapsed_time(ev1) / steps_done
+    log(f"timed {steps_done} graph-replayed pairs: {ms_step * 1e3:.2f} us/pair (wall {wall:.3f} s)")
+
+    # eager launches (no graph), same K
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps_done):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_eager = e0.elapsed_time(e1) / steps_done
 
     # ---- per-pass durations: HIP events recorded between the passes ---------------------
     lib = L.load()
@@ -148,7 +175,7 @@ def main(argv=None):
         "value": round(1e3 / ms_step, 1),
         "unit": "pairs/s",
         "n_gpus": 1,
-        "steps": a.steps,
+        "steps": steps_done,
         "warmup": a.warmup,
         "ms_per_step": round(ms_step, 6),
         "higher_is_better": True,
@@ -168,13 +195,129 @@ def main(argv=None):
                           "cold_ms_per_pair": round(cold_ms, 5),
                           "cold_frac": round(b_alg_pair / (cold_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "passes": passes,
+        "eager_ms_per_step": round(ms_eager, 6),
+        "launch": "hipGraph replay of 20 pairs per graph (torch CUDA graph capture of the library's launches)",
     }
+    if not a.no_extra:
+        result["batched"] = batched_leg(A, s, x_h, d_h, ms_step)
+        result["rsvd_block"] = rsvd_block_leg()
+        result["irls"] = irls_leg(a.irls_steps, lam=0.0)
+        result["irls_l1"] = irls_leg(a.irls_steps, lam=1.0, stop=True)
 
     # ---- CPU oracle on the host cores (bounded sample) ----------------------------------
     if not a.no_cpu:
         result["cpu_baseline"], result["rel_err"] = cpu_baseline(s, x_h, d_h, A, x, d)
     print(json.dumps(result), flush=True)
     return 0
+
+
+def timed(fn, reps, warm=2):
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def batched_leg(A, s, x_h, d_h, ms_pair_single, k=16):
+    """G and G^T on a block of k vectors in one call each (batched column passes reading each
+    spectrum column once per 4 vectors), against the per-vector pair time."""
+    import torch
+    g = torch.Generator(device="cuda").manual_seed(7)
+    X = torch.rand(k, A.n, device="cuda", generator=g)
+    D = torch.randn(k, A.m, device="cuda", generator=g)
+    Y = torch.empty(k, A.m, device="cuda")
+    Z = torch.empty(k, A.n, device="cuda")
+
+    def pair():
+        A.G_block(X, out=Y)
+        A.G_block(D, transpose=True, out=Z)
+    ms = timed(pair, 20)
+    log(f"batched k={k}: {ms / k * 1e3:.2f} us per pair")
+    return {"k": k, "ms_per_block_pair": round(ms, 5), "pairs_per_s": round(k * 1e3 / ms, 1),
+            "speedup_vs_per_vector": round(ms_pair_single * k / ms, 3)}
+
+
+def rsvd_block_leg(k=3750):
+    """The RSVD block product: gravity 200 x 150 x 12 (n = 360000), G applied to k = 3750
+    Gaussian vectors and G^T to k data vectors, FP32; algorithmic bytes 4nk + 4mk + S each."""
+    import torch
+
+    from paper_2004_13904_amd import workloads as W
+    from paper_2004_13904_amd.operator import Operator
+    s = W.SURVEYS["gravity_rsvd"]
+    B = Operator(s, torch.float32)
+    g = torch.Generator(device="cuda").manual_seed(3)
+    X = torch.randn(k, B.n, device="cuda", generator=g)
+    Om = torch.randn(k, B.m, device="cuda", generator=g)
+    Y = torch.empty(k, B.m, device="cuda")
+    Z = torch.empty(k, B.n, device="cuda")
+    msG = timed(lambda: B.G_block(X, out=Y), 3, warm=1)
+    msT = timed(lambda: B.G_block(Om, transpose=True, out=Z), 3, warm=1)
+    NX, NY = B.nfft
+    S = s["nz"] * (NX // 2 + 1) * NY * 8
+    balg = 4 * B.n * k + 4 * B.m * k + S
+    ms_one = timed(lambda: B.G(X[0], out=Y[0]), 10)
+    log(f"rsvd block k={k}: G {msG:.2f} ms, G^T {msT:.2f} ms")
+    out = {"workload": "gravity_rsvd: 200x150 stations, nz=12, 20 m cubes, n=360000, k=3750 FP32 vectors",
+           "k": k, "ms_G": round(msG, 4), "ms_GT": round(msT, 4),
+           "GBs_G": round(balg / (msG * 1e-3) / 1e9, 1), "GBs_GT": round(balg / (msT * 1e-3) / 1e9, 1),
+           "frac_G": round(balg / (msG * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "frac_GT": round(balg / (msT * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "per_vector_loop_ms_G": round(ms_one * k, 3)}
+    del X, Om, Y, Z
+    B.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def irls_leg(steps, lam=0.0, stop=False):
+    """IRLS time on the gravity 100 x 60 x 10 survey (m = 6000, n = 60000): two 1 g/cc blocks,
+    1 % noise (tau1 = 0.01, tau2 = 0.001), stabilizer lambda (0 = minimum support, timed over a
+    fixed number of steps; 1 = the paper's L1 choice, run to the chi^2 test), depth weighting
+    beta = 0.8, bounds [0, 1], GKB with t = m/8 = 750, t_p = 787, FP32 operator."""
+    import torch
+
+    from paper_2004_13904_amd import solvers as SV
+    from paper_2004_13904_amd import workloads as W
+    from paper_2004_13904_amd.operator import Operator
+    s = W.SURVEYS["gravity_l4"]
+    A = Operator(s, torch.float32)
+    m_true = torch.tensor(W.block_model(s, W.GRAVITY_L4_BLOCKS), dtype=torch.float32, device="cuda")
+    d_exact = A.G(m_true).double().cpu().numpy()
+    eta, sd = W.noise(d_exact, 0.01, 0.001, 2)
+    d_obs = torch.tensor(d_exact + eta, dtype=torch.float64, device="cuda")
+    wd = torch.tensor(1.0 / sd, dtype=torch.float64, device="cuda")
+    p = SV.IrlsParams(solver="gkb", t=750, tp=787, lam=lam, eps2=1e-9, beta_depth=0.8, m_min=0.0,
+                      m_max=1.0)
+    times = []
+    t_last = [time.perf_counter()]
+
+    def cb(k, m, alpha, chi2):
+        torch.cuda.synchronize()
+        now = time.perf_counter()
+        times.append(now - t_last[0])
+        t_last[0] = now
+        log(f"irls step {k}: alpha {alpha:.4g} chi2 {chi2:.4f} ({times[-1]:.3f} s)")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_last[0] = t0
+    m, hist = SV.irls(A, p, d_obs, wd, k_max=steps, callback=cb, stop_at_chi2=stop)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    mt = m_true.double()
+    re = float(torch.linalg.norm(mt - m) / torch.linalg.norm(mt))
+    return {"workload": "gravity_l4: 100x60 stations, nz=10, GKB t=750 t_p=787, FP32 operator, FP64 solve",
+            "lambda": lam,
+            "steps": len(hist), "converged": hist[-1][2] <= 1.0, "seconds_total": round(total, 3),
+            "seconds_per_step": round(total / len(hist), 4), "final_chi2_scaled": round(hist[-1][2], 4),
+            "alpha_1": hist[0][1], "alpha_K": hist[-1][1], "RE": round(re, 4)}
 
 
 def cpu_baseline(s, x_h, d_h, A, x, d):

@@ -1,10 +1,15 @@
 // Host launchers of the three-pass BCCB operator (Appendix A of the paper): G X and G^T Y for
 // a batch of vectors, with the diagonal weights of eq. (forwardmult) fused into the first and
 // last passes.  Launches are asynchronous on the caller's stream and allocate nothing.
+#include <type_traits>
+
 #include "passes.h"
 
 namespace ff {
 namespace {
+
+// vectors per block of the batched column passes (each spectrum column read once per group)
+constexpr int kVecPerBlock = 4;
 
 // Row-pass launch: full-size blocks (RowMax transforms, 2*NF rows, written back as 2*NF-row
 // contiguous segments) when the pass has at least 2048 rows, else one transform (two rows)
@@ -40,9 +45,10 @@ void launch_c2r(int nrows, int nb, int kb, const cplx<T> *in, Idx3 ii, int64_t i
 }
 
 template <typename T, typename TI, typename TO>
-ff_status run_G(ff_spectra h, int kb, const TI *X, int64_t ldx, TO *Y, int64_t ldy, const TI *pre,
+ff_status run_G(ff_spectra h, int kb, const TI *X, int64_t ldx, TO *Y, int64_t ldy_out, const TI *pre,
                 const TO *post, hipStream_t s) {
   const int H = h->H, nz = h->nz, nx = h->nx, ny = h->ny, sx = h->sx, sy = h->sy, LG = h->lg_G;
+  const int ldy = h->ldy, lds = h->lds;
   cplx<T> *X1 = (cplx<T> *)h->ws_rows;
   cplx<T> *Ap = (cplx<T> *)h->ws_cols;
   const cplx<T> *spec = (const cplx<T> *)h->spec;
@@ -50,27 +56,36 @@ ff_status run_G(ff_spectra h, int kb, const TI *X, int64_t ldx, TO *Y, int64_t l
   const int64_t lay = (int64_t)ny * nx;
   prof_mark(h, 0, 0, s);
   FF_SWITCH_N(h->NX, launch_r2c<T, TI, NN>(ny, nz, kb, X, Idx3{ldx, lay, nx}, pre, Idx3{0, lay, nx}, nx, 0, X1,
-                                           Idx3{(int64_t)nz * H * ny, (int64_t)H * ny, 1}, ny, twx, s));
+                                           Idx3{(int64_t)nz * H * ldy, (int64_t)H * ldy, 1}, ldy, twx, s));
   FF_LAUNCH_CHECK("G pass 1 (row transforms)");
   prof_mark(h, 1, 0, s);
   FF_SWITCH_N(h->NY, {
     using CC = ColCfg<T, NN>;
+    if constexpr (std::is_same<T, float>::value && CC::WPB >= kVecPerBlock) {
+      if (kb > 1) {
+        dim3 g((H + CC::CPB - 1) / CC::CPB, LG, (kb + kVecPerBlock - 1) / kVecPerBlock);
+        k_col_G_batch<T, NN, kVecPerBlock><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, ldy, nz, H, LG, kb, spec, Ap,
+                                                                                sy, lds, h->pyl, twy);
+        break;
+      }
+    }
     dim3 g((H + CC::CPB - 1) / CC::CPB, LG, kb);
-    k_col_G<T, NN><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, nz, H, LG, spec, Ap, sy, h->pyl, twy);
+    k_col_G<T, NN><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, ldy, nz, H, LG, spec, Ap, sy, lds, h->pyl, twy);
   });
   FF_LAUNCH_CHECK("G pass 2 (column transforms and spectral products)");
   prof_mark(h, 2, 0, s);
-  FF_SWITCH_N(h->NX, launch_c2r<T, TO, NN>(sy, 1, kb, Ap, Idx3{(int64_t)LG * H * sy, 0, 1}, sy, (int64_t)H * sy, LG,
-                                           Y, Idx3{ldy, 0, sx}, post, Idx3{0, 0, sx}, sx, h->pxl, twx, s));
+  FF_SWITCH_N(h->NX, launch_c2r<T, TO, NN>(sy, 1, kb, Ap, Idx3{(int64_t)LG * H * lds, 0, 1}, lds, (int64_t)H * lds,
+                                           LG, Y, Idx3{ldy_out, 0, sx}, post, Idx3{0, 0, sx}, sx, h->pxl, twx, s));
   FF_LAUNCH_CHECK("G pass 3 (inverse row transforms)");
   prof_mark(h, 3, 0, s);
   return FF_OK;
 }
 
 template <typename T, typename TI, typename TO>
-ff_status run_GT(ff_spectra h, int kb, const TI *X, int64_t ldx, TO *Y, int64_t ldy, const TI *pre,
+ff_status run_GT(ff_spectra h, int kb, const TI *X, int64_t ldx, TO *Y, int64_t ldy_out, const TI *pre,
                  const TO *post, hipStream_t s) {
   const int H = h->H, nz = h->nz, nx = h->nx, ny = h->ny, sx = h->sx, sy = h->sy, LG = h->lg_GT;
+  const int ldy = h->ldy, lds = h->lds;
   cplx<T> *X1 = (cplx<T> *)h->ws_rows;
   cplx<T> *D1 = (cplx<T> *)h->ws_cols;
   const cplx<T> *spec = (const cplx<T> *)h->spec;
@@ -78,18 +93,26 @@ ff_status run_GT(ff_spectra h, int kb, const TI *X, int64_t ldx, TO *Y, int64_t 
   const int64_t lay = (int64_t)ny * nx;
   prof_mark(h, 0, 1, s);
   FF_SWITCH_N(h->NX, launch_r2c<T, TI, NN>(sy, 1, kb, X, Idx3{ldx, 0, sx}, pre, Idx3{0, 0, sx}, sx, h->pxl, D1,
-                                           Idx3{(int64_t)H * sy, 0, 1}, sy, twx, s));
+                                           Idx3{(int64_t)H * lds, 0, 1}, lds, twx, s));
   FF_LAUNCH_CHECK("G^T pass 1 (row transforms)");
   prof_mark(h, 1, 1, s);
   FF_SWITCH_N(h->NY, {
     using CC = ColCfg<T, NN>;
+    if constexpr (std::is_same<T, float>::value && CC::WPB >= kVecPerBlock) {
+      if (kb > 1) {
+        dim3 g((H + CC::CPB - 1) / CC::CPB, LG, (kb + kVecPerBlock - 1) / kVecPerBlock);
+        k_col_GT_batch<T, NN, kVecPerBlock><<<g, CC::THREADS * CC::WPB, 0, s>>>(D1, sy, lds, h->pyl, nz, H, LG, kb,
+                                                                                 spec, X1, ny, ldy, twy);
+        break;
+      }
+    }
     dim3 g((H + CC::CPB - 1) / CC::CPB, LG, kb);
-    k_col_GT<T, NN><<<g, CC::THREADS * CC::WPB, 0, s>>>(D1, sy, h->pyl, nz, H, LG, spec, X1, ny, twy);
+    k_col_GT<T, NN><<<g, CC::THREADS * CC::WPB, 0, s>>>(D1, sy, lds, h->pyl, nz, H, LG, spec, X1, ny, ldy, twy);
   });
   FF_LAUNCH_CHECK("G^T pass 2 (column transforms and spectral products)");
   prof_mark(h, 2, 1, s);
-  FF_SWITCH_N(h->NX, launch_c2r<T, TO, NN>(ny, nz, kb, X1, Idx3{(int64_t)nz * H * ny, (int64_t)H * ny, 1}, ny, 0, 1,
-                                           Y, Idx3{ldy, lay, nx}, post, Idx3{0, lay, nx}, nx, 0, twx, s));
+  FF_SWITCH_N(h->NX, launch_c2r<T, TO, NN>(ny, nz, kb, X1, Idx3{(int64_t)nz * H * ldy, (int64_t)H * ldy, 1}, ldy, 0, 1,
+                                           Y, Idx3{ldy_out, lay, nx}, post, Idx3{0, lay, nx}, nx, 0, twx, s));
   FF_LAUNCH_CHECK("G^T pass 3 (inverse row transforms)");
   prof_mark(h, 3, 1, s);
   return FF_OK;

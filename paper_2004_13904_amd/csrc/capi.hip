@@ -138,6 +138,9 @@ ff_status build_spectra(const ff_geometry *g, int32_t dtype, ff_stream stream, f
   h->kernel = g->kernel;
   h->z_edges.assign(g->z_edges, g->z_edges + g->nz + 1);
   h->NX = NX; h->NY = NY; h->H = NX / 2 + 1;
+  // intermediate columns start on 128-byte (complex64) boundaries
+  h->ldy = (h->ny + 15) / 16 * 16;
+  h->lds = (h->sy + 15) / 16 * 16;
   h->m = (int64_t)g->sx * g->sy;
   h->n = nx * ny * g->nz;
   // Layer groups across blocks of the column passes: enough wavefronts to fill the chip
@@ -152,10 +155,10 @@ ff_status build_spectra(const ff_geometry *g, int32_t dtype, ff_stream stream, f
   h->lg_GT = lg;
 
   const size_t cs = csize(dtype);
-  const int64_t rows = ny > g->sy ? ny : g->sy;
+  const int64_t rows = h->ldy > h->lds ? h->ldy : h->lds;
   h->ws_rows_bytes = cs * (size_t)kMaxBatch * h->nz * h->H * rows;
   // room for the G partial sums of up to nz layer groups (ff_set_tuning may raise lg_G)
-  h->ws_cols_bytes = cs * (size_t)kMaxBatch * h->nz * h->H * g->sy;
+  h->ws_cols_bytes = cs * (size_t)kMaxBatch * h->nz * h->H * h->lds;
   ff_status st = FF_OK;
   if (hipMalloc(&h->spec, cs * (size_t)h->nz * h->H * NY) != hipSuccess ||
       hipMalloc(&h->ws_rows, h->ws_rows_bytes) != hipSuccess ||

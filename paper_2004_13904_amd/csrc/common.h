@@ -90,6 +90,7 @@ struct ff_spectra_s {
   std::vector<double> z_edges;
   // embedding
   int NX = 0, NY = 0, H = 0;         // H = NX/2 + 1 half-spectrum columns
+  int ldy = 0, lds = 0;              // column strides of the intermediates (ny, sy rounded up to 16)
   int64_t m = 0, n = 0;
   // device memory
   void *spec = nullptr;              // [nz][H][NY] complex (float2 or double2), scaled by 1/(NX NY)

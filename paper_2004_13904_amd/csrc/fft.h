@@ -113,6 +113,80 @@ template <typename T, int N, bool INV> struct FFT {
   static constexpr bool SINGLE = WAVE || 2 * HALF * (int)sizeof(cplx<T>) > 32768;
   static constexpr int LDS = SINGLE ? HALF : 2 * HALF;
 
+  // Per-thread twiddles of the radix-8 stages after the first (7 per stage) and of the final
+  // radix-4/2 stage, read once and reused by every transform the thread performs.
+  static constexpr int NTW = (L8 > 1 ? (L8 - 1) * 7 : 0) + (REM == 4 ? 6 : (REM == 2 ? 4 : 0));
+  struct Tw {
+    cplx<T> w[NTW > 0 ? NTW : 1];
+  };
+  __device__ static void load_tw(Tw &t, int j, const cplx<T> *__restrict__ tw) {
+    int Ns = 8, q = 0;
+#pragma unroll
+    for (int st = 1; st < L8; ++st) {
+      const int step = (j % Ns) * (N / (Ns * 8));
+#pragma unroll
+      for (int u = 1; u < 8; ++u) t.w[q++] = tw[step * u];
+      Ns *= 8;
+    }
+    if (REM == 4) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int step = ((j + c * TPF) % Ns) * (N / (Ns * 4));
+#pragma unroll
+        for (int u = 1; u < 4; ++u) t.w[q++] = tw[step * u];
+      }
+    } else if (REM == 2) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) t.w[q++] = tw[((j + c * TPF) % Ns) * (N / (Ns * 2))];
+    }
+  }
+  __device__ static cplx<T> tmul(cplx<T> v, cplx<T> w) { return INV ? cmulc<T>(v, w) : cmul<T>(v, w); }
+
+  // Same transform as run(), with the twiddles taken from registers.
+  __device__ static void run_tw(cplx<T> (&v)[8], int j, cplx<T> *buf, const Tw &t) {
+    int Ns = 1, q = 0;
+    bool used_lds = false;
+#pragma unroll
+    for (int st = 0; st < L8; ++st) {
+      const bool last = (st == L8 - 1) && REM == 1;
+      const int k = j % Ns;
+      if (st > 0) {
+#pragma unroll
+        for (int u = 1; u < 8; ++u) v[u] = tmul(v[u], t.w[q++]);
+      }
+      dft8<INV, T>(v);
+      if (!last) {
+        cplx<T> *dst = SINGLE ? buf : buf + (st & 1) * HALF;
+        const int base = (j / Ns) * Ns * 8 + k;
+        if (SINGLE) group_sync<TPF>();
+#pragma unroll
+        for (int s = 0; s < 8; ++s) dst[pad8(base + s * Ns)] = v[s];
+        group_sync<TPF>();
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = dst[pad8(j + u * TPF)];
+        used_lds = true;
+      }
+      Ns *= 8;
+    }
+    if (REM == 4) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        if (Ns > 1) {
+#pragma unroll
+          for (int u = 1; u < 4; ++u) v[c + 2 * u] = tmul(v[c + 2 * u], t.w[q++]);
+        }
+        dft4<INV, T>(v[c], v[c + 2], v[c + 4], v[c + 6]);
+      }
+    } else if (REM == 2) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (Ns > 1) v[c + 4] = tmul(v[c + 4], t.w[q++]);
+        dft2<INV, T>(v[c], v[c + 4]);
+      }
+    }
+    if (used_lds) group_sync<TPF>();
+  }
+
   // v[u] = x[j + u*TPF] on entry, X[j + u*TPF] on exit.  buf: this group's LDS elements.
   __device__ static void run(cplx<T> (&v)[8], int j, cplx<T> *buf, const cplx<T> *__restrict__ tw) {
     int Ns = 1;

@@ -119,10 +119,20 @@ k_row_r2c(const TI *__restrict__ in, Idx3 ii, const TI *__restrict__ pre, Idx3 p
     }
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < C::H * C::ROWS; idx += C::THREADS) {
+  constexpr int PER = (C::H * C::ROWS + C::THREADS - 1) / C::THREADS;
+  cplx<T> tv[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int idx = threadIdx.x + q * C::THREADS;
+    const int k = idx / C::ROWS, rr = idx - k * C::ROWS;
+    if (idx < C::H * C::ROWS) tv[q] = tile[k * C::TS + rr];
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int idx = threadIdx.x + q * C::THREADS;
     const int k = idx / C::ROWS, rr = idx - k * C::ROWS;
     const int row = row0 + rr;
-    if (row < nrows) out[oi.at(vec, b, row) + k * out_kx] = tile[k * C::TS + rr];
+    if (idx < C::H * C::ROWS && row < nrows) out[oi.at(vec, b, row) + k * out_kx] = tv[q];
   }
 }
 
@@ -142,15 +152,32 @@ k_row_c2r(const cplx<T> *__restrict__ in, Idx3 ii, int64_t in_kx, int64_t pstrid
   const int64_t vec = blockIdx.z, b = blockIdx.y;
   const int row0 = blockIdx.x * C::ROWS;
   cplx<T> *tile = sh;
-  for (int idx = threadIdx.x; idx < C::H * C::ROWS; idx += C::THREADS) {
+  // every thread issues all of its tile loads before the first LDS write, so the global
+  // load latencies overlap instead of adding up
+  constexpr int PER = (C::H * C::ROWS + C::THREADS - 1) / C::THREADS;
+  cplx<T> tv[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int idx = threadIdx.x + q * C::THREADS;
     const int k = idx / C::ROWS, rr = idx - k * C::ROWS;
     const int row = row0 + rr;
-    cplx<T> val = mk<T>(0, 0);
-    if (row < nrows) {
-      const cplx<T> *src = in + ii.at(vec, b, row) + k * in_kx;
-      for (int p = 0; p < P; ++p) val = cadd<T>(val, src[p * pstride]);
+    tv[q] = mk<T>(0, 0);
+    if (idx < C::H * C::ROWS && row < nrows) tv[q] = in[ii.at(vec, b, row) + k * in_kx];
+  }
+  for (int p = 1; p < P; ++p) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = threadIdx.x + q * C::THREADS;
+      const int k = idx / C::ROWS, rr = idx - k * C::ROWS;
+      const int row = row0 + rr;
+      if (idx < C::H * C::ROWS && row < nrows) tv[q] = cadd<T>(tv[q], in[ii.at(vec, b, row) + k * in_kx + p * pstride]);
     }
-    tile[k * C::TS + rr] = val;
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int idx = threadIdx.x + q * C::THREADS;
+    const int k = idx / C::ROWS, rr = idx - k * C::ROWS;
+    if (idx < C::H * C::ROWS) tile[k * C::TS + rr] = tv[q];
   }
   __syncthreads();
   cplx<T> v[8];
@@ -203,8 +230,8 @@ k_row_c2r(const cplx<T> *__restrict__ in, Idx3 ii, int64_t in_kx, int64_t pstrid
 // Grid: (ceil(H/CPB), LG, nvec).
 template <typename T, int NY>
 __global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
-k_col_G(const cplx<T> *__restrict__ X1, int ny, int nz, int H, int LG,
-        const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ outp, int sy, int pyl,
+k_col_G(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int H, int LG,
+        const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ outp, int sy, int lds, int pyl,
         const cplx<T> *__restrict__ tw) {
   using CC = ColCfg<T, NY>;
   using Ff = FFT<T, NY, false>;
@@ -220,11 +247,13 @@ k_col_G(const cplx<T> *__restrict__ X1, int ny, int nz, int H, int LG,
   const int64_t vec = blockIdx.z;
   const int r0 = (int)((int64_t)g * nz / LG), r1 = (int)((int64_t)(g + 1) * nz / LG);
   cplx<T> *buf = sh + (w * CC::CPB + f) * Ff::LDS;
+  typename Ff::Tw twr;
+  Ff::load_tw(twr, j, tw);
   cplx<T> acc[8], xn[8], sn[8];
 #pragma unroll
   for (int u = 0; u < 8; ++u) acc[u] = mk<T>(0, 0);
   auto load = [&](int r) {
-    const cplx<T> *src = X1 + ((vec * nz + r) * H + kxs) * (int64_t)ny;
+    const cplx<T> *src = X1 + ((vec * nz + r) * H + kxs) * (int64_t)ldy;
     const cplx<T> *sp = spec + ((int64_t)r * H + kxs) * NY;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -245,7 +274,7 @@ k_col_G(const cplx<T> *__restrict__ X1, int ny, int nz, int H, int LG,
       s[u] = sn[u];
     }
     if (r + WPB < r1) load(r + WPB);
-    Ff::run(v, j, buf, tw);
+    Ff::run_tw(v, j, buf, twr);
 #pragma unroll
     for (int u = 0; u < 8; ++u) acc[u] = cadd<T>(acc[u], cmul<T>(v[u], s[u]));
   }
@@ -262,9 +291,10 @@ k_col_G(const cplx<T> *__restrict__ X1, int ny, int nz, int H, int LG,
     }
     group_sync<TPF>();
   }
-  Fi::run(acc, j, buf, tw);
+  // the inverse transform uses the conjugate twiddles of the same table
+  Fi::run_tw(acc, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
   if (ok) {
-    cplx<T> *dst = outp + ((vec * LG + g) * H + kx) * (int64_t)sy;
+    cplx<T> *dst = outp + ((vec * LG + g) * H + kx) * (int64_t)lds;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int y = j + u * TPF - pyl;
@@ -279,8 +309,8 @@ k_col_G(const cplx<T> *__restrict__ X1, int ny, int nz, int H, int LG,
 // Grid: (ceil(H/CPB), LG, nvec).
 template <typename T, int NY>
 __global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
-k_col_GT(const cplx<T> *__restrict__ D1, int sy, int pyl, int nz, int H, int LG,
-         const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ X1, int ny,
+k_col_GT(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz, int H, int LG,
+         const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ X1, int ny, int ldy,
          const cplx<T> *__restrict__ tw) {
   using CC = ColCfg<T, NY>;
   using Ff = FFT<T, NY, false>;
@@ -297,7 +327,9 @@ k_col_GT(const cplx<T> *__restrict__ D1, int sy, int pyl, int nz, int H, int LG,
   const int r0 = (int)((int64_t)g * nz / LG), r1 = (int)((int64_t)(g + 1) * nz / LG);
   if (r0 + w >= r1) return;   // no layer for this wave group (never with WPB = 1)
   cplx<T> *buf = sh + (w * CC::CPB + f) * Ff::LDS;
-  const cplx<T> *src = D1 + (vec * H + kxs) * (int64_t)sy;
+  typename Ff::Tw twr;
+  Ff::load_tw(twr, j, tw);
+  const cplx<T> *src = D1 + (vec * H + kxs) * (int64_t)ldd;
   cplx<T> dh[8], sn[8];
   int r = r0 + w;
   {
@@ -309,7 +341,7 @@ k_col_GT(const cplx<T> *__restrict__ D1, int sy, int pyl, int nz, int H, int LG,
       sn[u] = sp[j + u * TPF];
     }
   }
-  Ff::run(dh, j, buf, tw);
+  Ff::run_tw(dh, j, buf, twr);
   for (; r < r1; r += WPB) {
     cplx<T> v[8];
 #pragma unroll
@@ -319,13 +351,168 @@ k_col_GT(const cplx<T> *__restrict__ D1, int sy, int pyl, int nz, int H, int LG,
 #pragma unroll
       for (int u = 0; u < 8; ++u) sn[u] = sp[j + u * TPF];
     }
-    Fi::run(v, j, buf, tw);
+    Fi::run_tw(v, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
     if (ok) {
-      cplx<T> *dst = X1 + ((vec * nz + r) * H + kx) * (int64_t)ny;
+      cplx<T> *dst = X1 + ((vec * nz + r) * H + kx) * (int64_t)ldy;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int y = j + u * TPF;
         if (y < ny) dst[y] = v[u];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Batched column passes: V vectors per block, so every spectrum column is read once per V
+// vectors (single precision, NY <= 512, several wave groups per block).  Results equal the
+// single-vector kernels' bit for bit: every vector sees the same operations in the same order.
+
+// Pass 2 of G for vectors vec0 .. vec0+V-1 (vec0 = blockIdx.z * V; vectors >= kb are skipped).
+// Wave group w takes layers r = r0 + w, r0 + w + WPB, ...; for each of its layers it loads the
+// spectrum column once and transforms the V vectors' columns.  Partial sums meet in LDS one
+// vector at a time; wave group (v mod WPB) adds them up and does vector v's inverse transform.
+template <typename T, int NY, int V>
+__global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
+k_col_G_batch(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int H, int LG, int kb,
+              const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ outp, int sy, int lds, int pyl,
+              const cplx<T> *__restrict__ tw) {
+  using CC = ColCfg<T, NY>;
+  using Ff = FFT<T, NY, false>;
+  using Fi = FFT<T, NY, true>;
+  constexpr int TPF = CC::TPF, WPB = CC::WPB;
+  static_assert(WPB >= V, "one inverse transform per wave group");
+  __shared__ cplx<T> sh[WPB * CC::CPB * Ff::LDS];
+  const int w = threadIdx.x / CC::THREADS, lt = threadIdx.x % CC::THREADS;
+  const int f = lt / TPF, j = lt % TPF;
+  const int kx = blockIdx.x * CC::CPB + f;
+  const bool ok = kx < H;
+  const int kxs = ok ? kx : 0;
+  const int g = blockIdx.y;
+  const int64_t vec0 = (int64_t)blockIdx.z * V;
+  const int r0 = (int)((int64_t)g * nz / LG), r1 = (int)((int64_t)(g + 1) * nz / LG);
+  cplx<T> *buf = sh + (w * CC::CPB + f) * Ff::LDS;
+  typename Ff::Tw twr;
+  Ff::load_tw(twr, j, tw);
+  cplx<T> acc[V][8];
+#pragma unroll
+  for (int v = 0; v < V; ++v)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[v][u] = mk<T>(0, 0);
+  for (int r = r0 + w; r < r1; r += WPB) {
+    cplx<T> sv[8];
+    const cplx<T> *sp = spec + ((int64_t)r * H + kxs) * NY;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sv[u] = sp[j + u * TPF];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const bool okv = ok && vec0 + v < kb;
+      const cplx<T> *src = X1 + (((vec0 + v) * nz + r) * H + kxs) * (int64_t)ldy;
+      cplx<T> xv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int y = j + u * TPF;
+        xv[u] = (okv && y < ny) ? src[y] : mk<T>(0, 0);
+      }
+      Ff::run_tw(xv, j, buf, twr);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[v][u] = cadd<T>(acc[v][u], cmul<T>(xv[u], sv[u]));
+    }
+  }
+  // reduction over the wave groups, one vector per round
+  cplx<T> mine[8];
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) buf[j + u * TPF] = acc[v][u];
+    __syncthreads();
+    if (w == v) {
+      // wave-group order 0, 1, ..., as in the single-vector kernel
+#pragma unroll
+      for (int u = 0; u < 8; ++u) mine[u] = v == 0 ? acc[v][u] : sh[f * Ff::LDS + j + u * TPF];
+      for (int w2 = 1; w2 < WPB; ++w2) {
+        const cplx<T> *o = sh + (w2 * CC::CPB + f) * Ff::LDS;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) mine[u] = cadd<T>(mine[u], w2 == v ? acc[v][u] : o[j + u * TPF]);
+      }
+    }
+    __syncthreads();
+  }
+  if (w >= V || vec0 + w >= kb) return;
+  Fi::run_tw(mine, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
+  if (ok) {
+    cplx<T> *dst = outp + (((vec0 + w) * LG + g) * H + kx) * (int64_t)lds;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int y = j + u * TPF - pyl;
+      if (y >= 0 && y < sy) dst[y] = mine[u];
+    }
+  }
+}
+
+// Pass 2 of G^T for vectors vec0 .. vec0+V-1: wave group v < V transforms vector v's data
+// column and shares it through LDS; then every wave group takes its layers, loads each
+// spectrum column once and forms the V products and inverse transforms.
+template <typename T, int NY, int V>
+__global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
+k_col_GT_batch(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz, int H, int LG, int kb,
+               const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ X1, int ny, int ldy,
+               const cplx<T> *__restrict__ tw) {
+  using CC = ColCfg<T, NY>;
+  using Ff = FFT<T, NY, false>;
+  using Fi = FFT<T, NY, true>;
+  constexpr int TPF = CC::TPF, WPB = CC::WPB;
+  static_assert(WPB >= V, "one forward transform per wave group");
+  __shared__ cplx<T> sh[WPB * CC::CPB * Ff::LDS];
+  __shared__ cplx<T> dsh[V * CC::CPB * NY];
+  const int w = threadIdx.x / CC::THREADS, lt = threadIdx.x % CC::THREADS;
+  const int f = lt / TPF, j = lt % TPF;
+  const int kx = blockIdx.x * CC::CPB + f;
+  const bool ok = kx < H;
+  const int kxs = ok ? kx : 0;
+  const int g = blockIdx.y;
+  const int64_t vec0 = (int64_t)blockIdx.z * V;
+  const int r0 = (int)((int64_t)g * nz / LG), r1 = (int)((int64_t)(g + 1) * nz / LG);
+  cplx<T> *buf = sh + (w * CC::CPB + f) * Ff::LDS;
+  typename Ff::Tw twr;
+  Ff::load_tw(twr, j, tw);
+  if (w < V) {
+    const bool okv = ok && vec0 + w < kb;
+    const cplx<T> *src = D1 + ((vec0 + w) * H + kxs) * (int64_t)ldd;
+    cplx<T> dv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int y = j + u * TPF - pyl;
+      dv[u] = (okv && y >= 0 && y < sy) ? src[y] : mk<T>(0, 0);
+    }
+    Ff::run_tw(dv, j, buf, twr);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) dsh[(w * CC::CPB + f) * NY + j + u * TPF] = dv[u];
+  }
+  __syncthreads();
+  cplx<T> dh[V][8];
+#pragma unroll
+  for (int v = 0; v < V; ++v)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) dh[v][u] = dsh[(v * CC::CPB + f) * NY + j + u * TPF];
+  for (int r = r0 + w; r < r1; r += WPB) {
+    cplx<T> sv[8];
+    const cplx<T> *sp = spec + ((int64_t)r * H + kxs) * NY;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sv[u] = sp[j + u * TPF];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      cplx<T> xv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) xv[u] = cmulc<T>(dh[v][u], sv[u]);
+      Fi::run_tw(xv, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
+      if (ok && vec0 + v < kb) {
+        cplx<T> *dst = X1 + (((vec0 + v) * nz + r) * H + kx) * (int64_t)ldy;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int y = j + u * TPF;
+          if (y < ny) dst[y] = xv[u];
+        }
       }
     }
   }

@@ -27,7 +27,8 @@ namespace ff {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kRowsPerBlock = 1024;   // rows of a basis per block of the transposed products
+constexpr int kRowsPerBlock = 512;    // rows of a basis per block of the transposed products
+constexpr int kColsPerBlock = 32;     // columns of a basis per block of the transposed products
 constexpr int kUpreGrid = 400;
 constexpr double kUpreLo = 1e-3;
 constexpr double kGoldenTol = 1e-10;
@@ -91,11 +92,15 @@ __global__ void k_axpy_dev(double *__restrict__ y, const double *__restrict__ x,
     y[i] += a * x[i];
 }
 
-// partial[p][j] = sum over the rows of block p of A[row, j] * x[row]   (A column-major, ld lda)
+// partial[p][j] = sum over the rows of row block p of A[row, j] * x[row]  (A column-major, ld
+// lda).  A block covers kRowsPerBlock rows and kColsPerBlock columns; each of its four waves
+// takes kColsPerBlock/4 columns, each lane kRowsPerBlock/64 rows (x held in registers).
+// Grid: (ceil(nrows / kRowsPerBlock), ceil(ncols / kColsPerBlock)).
 __global__ void __launch_bounds__(kThreads)
 k_gemv_t_partial(const double *__restrict__ A, int64_t lda, int64_t nrows, int ncols, const double *__restrict__ x,
                  double *__restrict__ part) {
   constexpr int K = kRowsPerBlock / 64;
+  constexpr int CW = kColsPerBlock / (kThreads / 64);
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t r0 = (int64_t)blockIdx.x * kRowsPerBlock;
   double xv[K];
@@ -104,26 +109,47 @@ k_gemv_t_partial(const double *__restrict__ A, int64_t lda, int64_t nrows, int n
     const int64_t r = r0 + l + 64 * k;
     xv[k] = r < nrows ? x[r] : 0.0;
   }
-  for (int j = w; j < ncols; j += kThreads / 64) {
-    const double *a = A + (int64_t)j * lda;
-    double s = 0.0;
+  const int c0 = blockIdx.y * kColsPerBlock + w * CW;
+  double s[CW];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int64_t r = r0 + l + 64 * k;
-      if (r < nrows) s += a[r] * xv[k];
+  for (int c = 0; c < CW; ++c) {
+    s[c] = 0.0;
+    const int j = c0 + c;
+    if (j < ncols) {
+      const double *a = A + (int64_t)j * lda;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int64_t r = r0 + l + 64 * k;
+        if (r < nrows) s[c] += a[r] * xv[k];
+      }
     }
-    s = wave_sum(s);
-    if (l == 0) part[(int64_t)blockIdx.x * ncols + j] = s;
+  }
+#pragma unroll
+  for (int c = 0; c < CW; ++c) {
+    const double t = wave_sum(s[c]);
+    if (l == 0 && c0 + c < ncols) part[(int64_t)blockIdx.x * ncols + c0 + c] = t;
   }
 }
 
-// out[j] = scale * sum_p part[p][j]
-__global__ void k_colsum(const double *__restrict__ part, int P, int ncols, double *__restrict__ out, double scale) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= ncols) return;
+// out[j] = scale * sum_p part[p][j]: 64 columns per block, the row-block range split over
+// the block's four waves, then summed in LDS in wave order.
+__global__ void __launch_bounds__(kThreads)
+k_colsum(const double *__restrict__ part, int P, int ncols, double *__restrict__ out, double scale) {
+  __shared__ double red[kThreads];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int j = blockIdx.x * 64 + l;
+  const int nw = kThreads / 64;
+  const int p0 = (int)((int64_t)P * w / nw), p1 = (int)((int64_t)P * (w + 1) / nw);
   double s = 0.0;
-  for (int p = 0; p < P; ++p) s += part[(int64_t)p * ncols + j];
-  out[j] = scale * s;
+  if (j < ncols)
+    for (int p = p0; p < p1; ++p) s += part[(int64_t)p * ncols + j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (w == 0 && j < ncols) {
+    double t = red[l];
+    for (int q = 1; q < nw; ++q) t += red[q * 64 + l];
+    out[j] = scale * t;
+  }
 }
 
 // y = beta * y + alpha * A c   (A column-major nrows x ncols, ld lda; c staged through LDS)
@@ -149,17 +175,37 @@ k_gemv_n(const double *__restrict__ A, int64_t lda, int64_t nrows, int ncols, co
 // ---------------------------------------------------------------------------------------
 // Small kernels of the projected problems
 
-// dense (tp+1) x tp lower-bidiagonal B from its diagonal gamma and subdiagonal beta[1..tp]
-__global__ void k_fill_bidiag(const double *__restrict__ gamma, const double *__restrict__ beta, int tp,
-                              double *__restrict__ B) {
+// The SVD of the (tp+1) x tp lower-bidiagonal B (diagonal gamma_i, subdiagonal beta_{i+1}) from
+// the symmetric eigenproblem of its Golub-Kahan tridiagonal: zero diagonal of order 2 tp + 1 and
+// off-diagonal (gamma_0, beta_1, gamma_1, beta_2, ..., gamma_{tp-1}, beta_tp).  For a singular
+// triplet (s, u, v) of B the vector interleaving u and v (u_0, v_0, u_1, v_1, ..., u_tp), scaled
+// by 1/sqrt(2), is an eigenvector with eigenvalue s; B is never squared.
+__global__ void k_tgk_build(const double *__restrict__ gamma, const double *__restrict__ beta, int tp,
+                            double *__restrict__ d, double *__restrict__ e) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 2 * tp + 1) d[i] = 0.0;
+  if (i < tp) {
+    e[2 * i] = gamma[i];
+    e[2 * i + 1] = beta[i + 1];
+  }
+}
+
+// S[j] = j-th largest eigenvalue, V[:, j] = sqrt2 * odd entries of its eigenvector (V column-major
+// tp x tp), u0[j] = sqrt2 * first entry (the first row of U).
+__global__ void k_tgk_extract(const double *__restrict__ lam, const double *__restrict__ C, int tp,
+                              double *__restrict__ S, double *__restrict__ V, double *__restrict__ u0) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t ld = tp + 1;
-  if (idx >= ld * tp) return;
-  const int i = (int)(idx % ld), j = (int)(idx / ld);
-  double v = 0.0;
-  if (i == j) v = gamma[j];
-  else if (i == j + 1) v = beta[j + 1];
-  B[idx] = v;
+  if (idx >= (int64_t)tp * tp) return;
+  const int n2 = 2 * tp + 1;
+  const int i = (int)(idx % tp), j = (int)(idx / tp);
+  const int jj = n2 - 1 - j;
+  const double r2 = 1.4142135623730950488;
+  const double *z = C + (int64_t)jj * n2;
+  V[idx] = r2 * z[2 * i + 1];
+  if (i == 0) {
+    u0[j] = r2 * z[0];
+    S[j] = lam[jj] > 0.0 ? lam[jj] : 0.0;
+  }
 }
 
 struct UpreIn {
@@ -410,9 +456,10 @@ ff_status reorth(const double *Q, int64_t ld, int64_t nrows, int ncols, double *
                  hipStream_t s) {
   if (ncols <= 0) return FF_OK;
   const int P = partials_for(nrows);
+  const dim3 gt(P, (ncols + kColsPerBlock - 1) / kColsPerBlock);
   for (int pass = 0; pass < 2; ++pass) {
-    k_gemv_t_partial<<<P, kThreads, 0, s>>>(Q, ld, nrows, ncols, v, part);
-    k_colsum<<<(ncols + 255) / 256, 256, 0, s>>>(part, P, ncols, coef, 1.0);
+    k_gemv_t_partial<<<gt, kThreads, 0, s>>>(Q, ld, nrows, ncols, v, part);
+    k_colsum<<<(ncols + 63) / 64, kThreads, 0, s>>>(part, P, ncols, coef, 1.0);
     k_gemv_n<<<grid_for(nrows, kThreads, 1 << 30), kThreads, 0, s>>>(Q, ld, nrows, ncols, coef, v, -1.0, 1.0);
   }
   FF_LAUNCH_CHECK("reorthogonalization");
@@ -431,8 +478,9 @@ ff_status gemv_n(const double *Q, int64_t ld, int64_t nrows, int ncols, const do
 ff_status gemv_t(const double *Q, int64_t ld, int64_t nrows, int ncols, const double *v, double *out, double *part,
                  hipStream_t s) {
   const int P = partials_for(nrows);
-  k_gemv_t_partial<<<P, kThreads, 0, s>>>(Q, ld, nrows, ncols, v, part);
-  k_colsum<<<(ncols + 255) / 256, 256, 0, s>>>(part, P, ncols, out, 1.0);
+  const dim3 gt(P, (ncols + kColsPerBlock - 1) / kColsPerBlock);
+  k_gemv_t_partial<<<gt, kThreads, 0, s>>>(Q, ld, nrows, ncols, v, part);
+  k_colsum<<<(ncols + 63) / 64, kThreads, 0, s>>>(part, P, ncols, out, 1.0);
   FF_LAUNCH_CHECK("gemv_t");
   return FF_OK;
 }
@@ -448,7 +496,7 @@ ff_status norm2(const double *x, int64_t n, double *nrm, double *inv, double *pa
 
 // Workspace of Algorithm 1 for a handle and tp (also used for sizing when a.dry).
 struct GkbWs {
-  double *A, *H, *b, *c, *gamma, *beta, *ginv, *binv, *coef, *part, *Bd, *S, *U, *Vt, *E, *g, *w, *alpha;
+  double *A, *H, *b, *c, *gamma, *beta, *ginv, *binv, *coef, *part, *dT, *eT, *C, *S, *V, *u0, *g, *w, *alpha;
   rocblas_int *info;
   void carve(Arena &a, int64_t n, int64_t m, int tp) {
     const int64_t P = (n > m ? n : m + kRowsPerBlock - 1) / kRowsPerBlock + 1;
@@ -462,11 +510,12 @@ struct GkbWs {
     binv = a.take<double>(tp + 2);
     coef = a.take<double>(tp + 2);
     part = a.take<double>((size_t)((P > 256 ? P : 256) + 1) * (tp + 2));
-    Bd = a.take<double>((size_t)(tp + 1) * tp);
+    dT = a.take<double>(2 * (size_t)tp + 1);
+    eT = a.take<double>(2 * (size_t)tp + 1);
+    C = a.take<double>((2 * (size_t)tp + 1) * (2 * (size_t)tp + 1));
     S = a.take<double>(tp);
-    U = a.take<double>((size_t)(tp + 1) * tp);
-    Vt = a.take<double>((size_t)tp * tp);
-    E = a.take<double>(tp);
+    V = a.take<double>((size_t)tp * tp);
+    u0 = a.take<double>(tp);
     g = a.take<double>(tp);
     w = a.take<double>(tp);
     alpha = a.take<double>(2);
@@ -573,23 +622,22 @@ ff_status gkb_run(ff_spectra h, const double *rt, const double *wd, const double
     k_scale<<<grid_for(m), kThreads, 0, s>>>(W.c, W.binv + i + 1, W.H + (int64_t)(i + 1) * m, m);
   }
   FF_LAUNCH_CHECK("gkb iteration");
-  // SVD of the (tp+1) x tp bidiagonal
-  const int64_t nb = (int64_t)(tp + 1) * tp;
-  k_fill_bidiag<<<grid_for(nb, 256, 1 << 30), 256, 0, s>>>(W.gamma, W.beta, tp, W.Bd);
+  // SVD of the (tp+1) x tp bidiagonal through its Golub-Kahan tridiagonal
+  const int n2 = 2 * tp + 1;
+  k_tgk_build<<<(n2 + 255) / 256, 256, 0, s>>>(W.gamma, W.beta, tp, W.dT, W.eT);
   rocblas_handle bh = blas(s, &st);
   if (st) return st;
-  FF_BLAS(rocsolver_dgesvd(bh, rocblas_svect_singular, rocblas_svect_all, tp + 1, tp, W.Bd, tp + 1, W.S, W.U, tp + 1,
-                           W.Vt, tp, W.E, rocblas_outofplace, W.info),
-          "rocsolver_dgesvd");
+  FF_BLAS(rocsolver_dstedc(bh, rocblas_evect_tridiagonal, n2, W.dT, W.eT, W.C, n2, W.info), "rocsolver_dstedc");
+  k_tgk_extract<<<grid_for((int64_t)tp * tp, 256, 1 << 30), 256, 0, s>>>(W.dT, W.C, tp, W.S, W.V, W.u0);
+  FF_LAUNCH_CHECK("bidiagonal SVD");
   // alpha from the first t singular values and c_i = ||r~|| U(1, i)  (||r~|| = beta_1)
-  UpreIn q{W.S, nullptr, W.U, (int64_t)(tp + 1), W.beta, t};
+  UpreIn q{W.S, nullptr, W.u0, 1, W.beta, t};
   if ((st = choose_alpha(h, mode, fixed, q, W.S, tp, W.alpha, s))) return st;
   // y = ||r~|| A V Gamma(alpha) U(1,:)^T
   UpreIn qa = q;
   qa.t = tp;
   k_filter<<<(tp + 255) / 256, 256, 0, s>>>(W.S, W.alpha, qa, tp, W.g);
-  // w = V g = Vt^T g
-  if ((st = gemv_t(W.Vt, tp, tp, tp, W.g, W.w, W.part, s))) return st;
+  if ((st = gemv_n(W.V, tp, tp, tp, W.g, W.w, 1.0, s))) return st;
   if ((st = gemv_n(W.A, n, n, tp, W.w, y, 1.0, s))) return st;
   FF_HIP(hipMemcpyAsync(sigma, W.S, sizeof(double) * tp, hipMemcpyDeviceToDevice, s));
   FF_HIP(hipMemcpyAsync(alpha, W.alpha, sizeof(double), hipMemcpyDeviceToHost, s));

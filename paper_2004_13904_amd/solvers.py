@@ -105,10 +105,10 @@ def irls_step(op, p: IrlsParams, k, d_obs, wd, m_prev, m_prev2=None, omega=None,
     return m_new, a.value, chi2.value
 
 
-def irls(op, p: IrlsParams, d_obs, wd, k_max=25, omega_fn=None, callback=None):
+def irls(op, p: IrlsParams, d_obs, wd, k_max=25, omega_fn=None, callback=None, stop_at_chi2=True):
     """The IRLS iteration of Secs. 2.3 and 3.1: m^(0) = 0, steps k = 1.. until the scaled
-    chi^2 of eq. (scaledchi2) is <= 1 or k = k_max.  omega_fn(k) supplies the RSVD matrix.
-    Returns (m, history) with history a list of (k, alpha, chi2)."""
+    chi^2 of eq. (scaledchi2) is <= 1 (when stop_at_chi2) or k = k_max.  omega_fn(k) supplies
+    the RSVD matrix.  Returns (m, history) with history a list of (k, alpha, chi2)."""
     m_prev = torch.zeros(op.n, dtype=torch.float64, device=op.device)
     m_prev2 = torch.zeros_like(m_prev)
     ws = _workspace(op, "irls", p.tp, 0 if p.solver == "gkb" else 1)
@@ -120,6 +120,6 @@ def irls(op, p: IrlsParams, d_obs, wd, k_max=25, omega_fn=None, callback=None):
         if callback is not None:
             callback(k, m_new, a, chi2)
         m_prev2, m_prev = m_prev, m_new
-        if chi2 <= 1.0:
+        if stop_at_chi2 and chi2 <= 1.0:
             break
     return m_prev, hist

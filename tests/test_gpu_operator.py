@@ -149,6 +149,21 @@ def test_block_apply_equals_vector_loop(dtype, k):
     assert rel(to_host(GTY), Y @ G) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("k", [2, 6])
+def test_batched_full_size_equals_vector_loop(k):
+    # the batched column passes (4 vectors per block) at the n = 1e6 magnetic survey
+    s = W.SURVEYS["magnetic_1m"]
+    A = Operator(s, F32)
+    g = torch.Generator(device="cuda").manual_seed(k)
+    X = torch.rand(k, A.n, device="cuda", generator=g)
+    D = torch.randn(k, A.m, device="cuda", generator=g)
+    GX = A.G_block(X)
+    GTD = A.G_block(D, transpose=True)
+    for c in range(k):
+        assert torch.equal(GX[c], A.G(X[c].contiguous()))
+        assert torch.equal(GTD[c], A.GT(D[c].contiguous()))
+
+
 def test_zero_and_impulse_inputs():
     s = SMALL["mag45"]
     g = ogeom(s)
