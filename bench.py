@@ -201,6 +201,7 @@ def main(argv=None):
     if not a.no_extra:
         result["batched"] = batched_leg(A, s, x_h, d_h, ms_step)
         result["rsvd_block"] = rsvd_block_leg()
+        result["multi_survey"] = multi_survey_leg()
         result["irls"] = irls_leg(a.irls_steps, lam=0.0)
         result["irls_l1"] = irls_leg(a.irls_steps, lam=1.0, stop=True)
 
@@ -275,6 +276,25 @@ def rsvd_block_leg(k=3750):
     B.close()
     torch.cuda.empty_cache()
     return out
+
+
+def multi_survey_leg():
+    """Eight gravity surveys of uneven size (32x32x6 .. 180x120x16) applied together: one graph
+    replay of all their G and G^T launches against the same launches issued one by one."""
+    import torch
+
+    from paper_2004_13904_amd import workloads as W
+    from paper_2004_13904_amd.operator import SurveyBatch
+    B = SurveyBatch(W.uneven_surveys(), torch.float32)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    xs = [torch.rand(o.n, device="cuda", generator=g) for o in B.ops]
+    ds = [torch.randn(o.m, device="cuda", generator=g) for o in B.ops]
+    B.bind(xs, ds)
+    ms_graph = timed(B.replay, 50)
+    ms_eager = timed(B.eager, 50)
+    log(f"multi-survey: graph {ms_graph * 1e3:.1f} us, eager {ms_eager * 1e3:.1f} us")
+    return {"surveys": [list(x) for x in W.UNEVEN], "ms_graph": round(ms_graph, 5),
+            "ms_sequential_launches": round(ms_eager, 5), "speedup": round(ms_eager / ms_graph, 3)}
 
 
 def irls_leg(steps, lam=0.0, stop=False):

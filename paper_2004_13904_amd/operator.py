@@ -163,3 +163,38 @@ class GTOp(torch.autograd.Function):
         g = g.contiguous()
         gd = ctx.op.G_block(g) if g.dim() == 2 else ctx.op.G(g)
         return None, gd
+
+
+class SurveyBatch:
+    """Several surveys of uneven size applied together: every survey's G and G^T launches are
+    captured once into a single HIP graph (torch CUDA graph) and replayed as one launch.
+
+    ``xs`` / ``ds`` are the per-survey input tensors (model and data vectors); replay() refreshes
+    ``gx`` (G x_i) and ``gtd`` (G^T d_i) in place from the current contents of the inputs.
+    """
+
+    def __init__(self, surveys, dtype=torch.float32):
+        self.ops = [Operator(s, dtype) for s in surveys]
+        self.graph = None
+
+    def bind(self, xs, ds):
+        self.xs, self.ds = list(xs), list(ds)
+        self.gx = [op._new(op.m) for op in self.ops]
+        self.gtd = [op._new(op.n) for op in self.ops]
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self.eager()
+        torch.cuda.current_stream().wait_stream(side)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.eager()
+        return self
+
+    def eager(self):
+        for op, x, d, a, b in zip(self.ops, self.xs, self.ds, self.gx, self.gtd):
+            op.G(x, out=a)
+            op.GT(d, out=b)
+
+    def replay(self):
+        self.graph.replay()
