@@ -63,6 +63,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched / RSVD-block / IRLS legs")
     ap.add_argument("--irls-steps", type=int, default=25)
+    ap.add_argument("--calib", action="store_true",
+                    help="end with a plain 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the operator and solvers run on a single MI355X "
@@ -133,16 +135,34 @@ def main(argv=None):
     torch.cuda.synchronize()
     ms_eager = e0.elapsed_time(e1) / steps_done
 
-    # ---- per-pass durations: HIP events recorded between the passes ---------------------
+    # ---- per-kernel durations: each pass launched alone, back to back, between HIP events ----
+    # (ff_time_pass runs one full application, then repeats only the chosen pass on the same
+    # stream; the events bracket the repeats, so the average is the kernel's own duration)
     lib = L.load()
-    L.check("ff_profile_begin", lib.ff_profile_begin(A.h, 2 * a.steps))
-    for _ in range(a.steps):
-        step()
-    ms = (C.c_double * 6)()
-    ops = (C.c_int64 * 2)()
-    L.check("ff_profile_end", lib.ff_profile_end(A.h, ms, ops))
     names = ["G.rows", "G.cols", "G.irows", "GT.rows", "GT.cols", "GT.irows"]
-    per_pass_us = {nm: ms[i] / max(ops[i // 3], 1) * 1e3 for i, nm in enumerate(names)}
+    per_pass_us = {}
+    reps = 200
+    for i, nm in enumerate(names):
+        t, p = divmod(i, 3)
+        xin, yout = (d, gtd) if t else (x, gx)
+        L.check("ff_time_pass", lib.ff_time_pass(A.h, t, p, 1, xin.data_ptr(), yout.data_ptr(), C.c_void_p(
+            torch.cuda.current_stream().cuda_stream)))
+        torch.cuda.synchronize()
+        q0, q1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        # the full application inside ff_time_pass precedes the repeats; time it separately
+        # and subtract it
+        q0.record()
+        L.check("ff_time_pass", lib.ff_time_pass(A.h, t, p, reps, xin.data_ptr(), yout.data_ptr(), C.c_void_p(
+            torch.cuda.current_stream().cuda_stream)))
+        q1.record()
+        torch.cuda.synchronize()
+        w0, w1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        w0.record()
+        L.check("ff_time_pass", lib.ff_time_pass(A.h, t, p, 0, xin.data_ptr(), yout.data_ptr(), C.c_void_p(
+            torch.cuda.current_stream().cuda_stream)))
+        w1.record()
+        torch.cuda.synchronize()
+        per_pass_us[nm] = (q0.elapsed_time(q1) - w0.elapsed_time(w1)) / reps * 1e3
     NX, NY = A.nfft
     lg = A.tuning
     pbytes, S = pass_bytes(A, lg["lg_G"], lg["lg_GT"])
@@ -187,9 +207,9 @@ def main(argv=None):
                                f"20 m cubes, n=1000000, m=50000, embedding {NX}x{NY}, "
                                "m~U[0,1) seed 0, d~N(0,1) seed 1",
                    "n": A.n, "m": A.m, "nfft": [NX, NY], "layer_groups": lg},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+        "roofline": {"bound": "hbm", "kernel": dom, "kernel_us": round(per_pass_us[dom], 3),
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(dom)},
         "path_roofline": {"bytes_per_pair": b_alg_pair, "achieved_GBs": round(path_gbs, 1),
                           "frac": round(path_gbs / HBM_PEAK_GBS, 4),
                           "cold_ms_per_pair": round(cold_ms, 5),
@@ -205,11 +225,37 @@ def main(argv=None):
         result["irls"] = irls_leg(a.irls_steps, lam=0.0)
         result["irls_l1"] = irls_leg(a.irls_steps, lam=1.0, stop=True)
 
+    if a.calib:
+        src = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        result["calib_copy_bytes"] = src.numel() * 4
+
     # ---- CPU oracle on the host cores (bounded sample) ----------------------------------
     if not a.no_cpu:
         result["cpu_baseline"], result["rel_err"] = cpu_baseline(s, x_h, d_h, A, x, d)
     print(json.dumps(result), flush=True)
     return 0
+
+
+def traffic_for(kernel):
+    """HBM bytes per launch of a pass kernel from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources (hash of csrc/); else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_magnetic_1m.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2004_13904_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    if rec.get("csrc_sha256") != h.hexdigest():
+        return None
+    return rec.get("kernels", {}).get(kernel, {}).get("bytes")
 
 
 def timed(fn, reps, warm=2):

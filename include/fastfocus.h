@@ -187,6 +187,13 @@ ff_status ff_set_tuning(ff_spectra h, const ff_tuning *t);
 ff_status ff_profile_begin(ff_spectra h, int32_t max_ops);
 ff_status ff_profile_end(ff_spectra h, double *ms, int64_t *ops);
 
+/* Pass timing (instrumentation for benchmarks): applies G (transpose = 0) or G^T (1) to x once,
+   writing y (handle dtype, unweighted), then launches only pass `pass` (0, 1 or 2 as above)
+   `reps` more times back to back on `stream`, re-reading the intermediates of that application.
+   Events recorded around the call divided by reps give the pass kernel's own duration. */
+ff_status ff_time_pass(ff_spectra h, int32_t transpose, int32_t pass, int32_t reps, const void *x, void *y,
+                       ff_stream stream);
+
 /* Thread-local message of the last failure ("" if none).  Valid until the next call. */
 const char *ff_last_error(void);
 

@@ -44,77 +44,83 @@ void launch_c2r(int nrows, int nb, int kb, const cplx<T> *in, Idx3 ii, int64_t i
   }
 }
 
+// One pass of G (transpose = 0) or G^T (transpose = 1) for kb vectors: pass 0 = row
+// transforms, 1 = column transforms with the spectral products, 2 = inverse row transforms.
 template <typename T, typename TI, typename TO>
-ff_status run_G(ff_spectra h, int kb, const TI *X, int64_t ldx, TO *Y, int64_t ldy_out, const TI *pre,
-                const TO *post, hipStream_t s) {
-  const int H = h->H, nz = h->nz, nx = h->nx, ny = h->ny, sx = h->sx, sy = h->sy, LG = h->lg_G;
+ff_status run_pass(ff_spectra h, int transpose, int pass, int kb, const TI *X, int64_t ldx, TO *Y, int64_t ldy_out,
+                   const TI *pre, const TO *post, hipStream_t s) {
+  const int H = h->H, nz = h->nz, nx = h->nx, ny = h->ny, sx = h->sx, sy = h->sy;
   const int ldy = h->ldy, lds = h->lds;
-  cplx<T> *X1 = (cplx<T> *)h->ws_rows;
-  cplx<T> *Ap = (cplx<T> *)h->ws_cols;
+  cplx<T> *X1 = (cplx<T> *)h->ws_rows;   // [vec][r][kx][row] (ld ldy)
+  cplx<T> *C2 = (cplx<T> *)h->ws_cols;   // G: partial sums [vec][g][kx][j]; G^T: D1 [vec][kx][j] (ld lds)
   const cplx<T> *spec = (const cplx<T> *)h->spec;
   const cplx<T> *twx = (const cplx<T> *)h->tw_x, *twy = (const cplx<T> *)h->tw_y;
   const int64_t lay = (int64_t)ny * nx;
-  prof_mark(h, 0, 0, s);
-  FF_SWITCH_N(h->NX, launch_r2c<T, TI, NN>(ny, nz, kb, X, Idx3{ldx, lay, nx}, pre, Idx3{0, lay, nx}, nx, 0, X1,
-                                           Idx3{(int64_t)nz * H * ldy, (int64_t)H * ldy, 1}, ldy, twx, s));
-  FF_LAUNCH_CHECK("G pass 1 (row transforms)");
-  prof_mark(h, 1, 0, s);
-  FF_SWITCH_N(h->NY, {
-    using CC = ColCfg<T, NN>;
-    if constexpr (std::is_same<T, float>::value && CC::WPB >= kVecPerBlock) {
-      if (kb > 1) {
-        dim3 g((H + CC::CPB - 1) / CC::CPB, LG, (kb + kVecPerBlock - 1) / kVecPerBlock);
-        k_col_G_batch<T, NN, kVecPerBlock><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, ldy, nz, H, LG, kb, spec, Ap,
-                                                                                sy, lds, h->pyl, twy);
-        break;
-      }
+  if (!transpose) {
+    const int LG = h->lg_G;
+    if (pass == 0) {
+      FF_SWITCH_N(h->NX, launch_r2c<T, TI, NN>(ny, nz, kb, X, Idx3{ldx, lay, nx}, pre, Idx3{0, lay, nx}, nx, 0, X1,
+                                               Idx3{(int64_t)nz * H * ldy, (int64_t)H * ldy, 1}, ldy, twx, s));
+      FF_LAUNCH_CHECK("G pass 1 (row transforms)");
+    } else if (pass == 1) {
+      FF_SWITCH_N(h->NY, {
+        using CC = ColCfg<T, NN>;
+        if constexpr (std::is_same<T, float>::value && CC::WPB >= kVecPerBlock) {
+          if (kb > 1) {
+            dim3 g((H + CC::CPB - 1) / CC::CPB, LG, (kb + kVecPerBlock - 1) / kVecPerBlock);
+            k_col_G_batch<T, NN, kVecPerBlock><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, ldy, nz, H, LG, kb, spec,
+                                                                                    C2, sy, lds, h->pyl, twy);
+            break;
+          }
+        }
+        dim3 g((H + CC::CPB - 1) / CC::CPB, LG, kb);
+        k_col_G<T, NN><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, ldy, nz, H, LG, spec, C2, sy, lds, h->pyl, twy);
+      });
+      FF_LAUNCH_CHECK("G pass 2 (column transforms and spectral products)");
+    } else {
+      FF_SWITCH_N(h->NX, launch_c2r<T, TO, NN>(sy, 1, kb, C2, Idx3{(int64_t)LG * H * lds, 0, 1}, lds, (int64_t)H * lds,
+                                               LG, Y, Idx3{ldy_out, 0, sx}, post, Idx3{0, 0, sx}, sx, h->pxl, twx, s));
+      FF_LAUNCH_CHECK("G pass 3 (inverse row transforms)");
     }
-    dim3 g((H + CC::CPB - 1) / CC::CPB, LG, kb);
-    k_col_G<T, NN><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, ldy, nz, H, LG, spec, Ap, sy, lds, h->pyl, twy);
-  });
-  FF_LAUNCH_CHECK("G pass 2 (column transforms and spectral products)");
-  prof_mark(h, 2, 0, s);
-  FF_SWITCH_N(h->NX, launch_c2r<T, TO, NN>(sy, 1, kb, Ap, Idx3{(int64_t)LG * H * lds, 0, 1}, lds, (int64_t)H * lds,
-                                           LG, Y, Idx3{ldy_out, 0, sx}, post, Idx3{0, 0, sx}, sx, h->pxl, twx, s));
-  FF_LAUNCH_CHECK("G pass 3 (inverse row transforms)");
-  prof_mark(h, 3, 0, s);
+  } else {
+    const int LG = h->lg_GT;
+    if (pass == 0) {
+      FF_SWITCH_N(h->NX, launch_r2c<T, TI, NN>(sy, 1, kb, X, Idx3{ldx, 0, sx}, pre, Idx3{0, 0, sx}, sx, h->pxl, C2,
+                                               Idx3{(int64_t)H * lds, 0, 1}, lds, twx, s));
+      FF_LAUNCH_CHECK("G^T pass 1 (row transforms)");
+    } else if (pass == 1) {
+      FF_SWITCH_N(h->NY, {
+        using CC = ColCfg<T, NN>;
+        if constexpr (std::is_same<T, float>::value && CC::WPB >= kVecPerBlock) {
+          if (kb > 1) {
+            dim3 g((H + CC::CPB - 1) / CC::CPB, LG, (kb + kVecPerBlock - 1) / kVecPerBlock);
+            k_col_GT_batch<T, NN, kVecPerBlock><<<g, CC::THREADS * CC::WPB, 0, s>>>(C2, sy, lds, h->pyl, nz, H, LG, kb,
+                                                                                     spec, X1, ny, ldy, twy);
+            break;
+          }
+        }
+        dim3 g((H + CC::CPB - 1) / CC::CPB, LG, kb);
+        k_col_GT<T, NN><<<g, CC::THREADS * CC::WPB, 0, s>>>(C2, sy, lds, h->pyl, nz, H, LG, spec, X1, ny, ldy, twy);
+      });
+      FF_LAUNCH_CHECK("G^T pass 2 (column transforms and spectral products)");
+    } else {
+      FF_SWITCH_N(h->NX, launch_c2r<T, TO, NN>(ny, nz, kb, X1, Idx3{(int64_t)nz * H * ldy, (int64_t)H * ldy, 1}, ldy, 0,
+                                               1, Y, Idx3{ldy_out, lay, nx}, post, Idx3{0, lay, nx}, nx, 0, twx, s));
+      FF_LAUNCH_CHECK("G^T pass 3 (inverse row transforms)");
+    }
+  }
   return FF_OK;
 }
 
 template <typename T, typename TI, typename TO>
-ff_status run_GT(ff_spectra h, int kb, const TI *X, int64_t ldx, TO *Y, int64_t ldy_out, const TI *pre,
+ff_status run_op(ff_spectra h, int transpose, int kb, const TI *X, int64_t ldx, TO *Y, int64_t ldy, const TI *pre,
                  const TO *post, hipStream_t s) {
-  const int H = h->H, nz = h->nz, nx = h->nx, ny = h->ny, sx = h->sx, sy = h->sy, LG = h->lg_GT;
-  const int ldy = h->ldy, lds = h->lds;
-  cplx<T> *X1 = (cplx<T> *)h->ws_rows;
-  cplx<T> *D1 = (cplx<T> *)h->ws_cols;
-  const cplx<T> *spec = (const cplx<T> *)h->spec;
-  const cplx<T> *twx = (const cplx<T> *)h->tw_x, *twy = (const cplx<T> *)h->tw_y;
-  const int64_t lay = (int64_t)ny * nx;
-  prof_mark(h, 0, 1, s);
-  FF_SWITCH_N(h->NX, launch_r2c<T, TI, NN>(sy, 1, kb, X, Idx3{ldx, 0, sx}, pre, Idx3{0, 0, sx}, sx, h->pxl, D1,
-                                           Idx3{(int64_t)H * lds, 0, 1}, lds, twx, s));
-  FF_LAUNCH_CHECK("G^T pass 1 (row transforms)");
-  prof_mark(h, 1, 1, s);
-  FF_SWITCH_N(h->NY, {
-    using CC = ColCfg<T, NN>;
-    if constexpr (std::is_same<T, float>::value && CC::WPB >= kVecPerBlock) {
-      if (kb > 1) {
-        dim3 g((H + CC::CPB - 1) / CC::CPB, LG, (kb + kVecPerBlock - 1) / kVecPerBlock);
-        k_col_GT_batch<T, NN, kVecPerBlock><<<g, CC::THREADS * CC::WPB, 0, s>>>(D1, sy, lds, h->pyl, nz, H, LG, kb,
-                                                                                 spec, X1, ny, ldy, twy);
-        break;
-      }
-    }
-    dim3 g((H + CC::CPB - 1) / CC::CPB, LG, kb);
-    k_col_GT<T, NN><<<g, CC::THREADS * CC::WPB, 0, s>>>(D1, sy, lds, h->pyl, nz, H, LG, spec, X1, ny, ldy, twy);
-  });
-  FF_LAUNCH_CHECK("G^T pass 2 (column transforms and spectral products)");
-  prof_mark(h, 2, 1, s);
-  FF_SWITCH_N(h->NX, launch_c2r<T, TO, NN>(ny, nz, kb, X1, Idx3{(int64_t)nz * H * ldy, (int64_t)H * ldy, 1}, ldy, 0, 1,
-                                           Y, Idx3{ldy_out, lay, nx}, post, Idx3{0, lay, nx}, nx, 0, twx, s));
-  FF_LAUNCH_CHECK("G^T pass 3 (inverse row transforms)");
-  prof_mark(h, 3, 1, s);
+  for (int pass = 0; pass < 3; ++pass) {
+    prof_mark(h, pass, transpose, s);
+    ff_status st = run_pass<T, TI, TO>(h, transpose, pass, kb, X, ldx, Y, ldy, pre, post, s);
+    if (st != FF_OK) return st;
+  }
+  prof_mark(h, 3, transpose, s);
   return FF_OK;
 }
 
@@ -125,9 +131,8 @@ ff_status run(ff_spectra h, int transpose, int64_t k, const void *X, int64_t ldx
   TIO *y = (TIO *)Y;
   for (int64_t c0 = 0; c0 < k; c0 += kMaxBatch) {
     const int kb = (int)((k - c0) < kMaxBatch ? (k - c0) : kMaxBatch);
-    ff_status st = transpose
-        ? run_GT<T, TIO, TIO>(h, kb, x + c0 * ldx, ldx, y + c0 * ldy, ldy, (const TIO *)w_pre, (const TIO *)w_post, s)
-        : run_G<T, TIO, TIO>(h, kb, x + c0 * ldx, ldx, y + c0 * ldy, ldy, (const TIO *)w_pre, (const TIO *)w_post, s);
+    ff_status st = run_op<T, TIO, TIO>(h, transpose, kb, x + c0 * ldx, ldx, y + c0 * ldy, ldy, (const TIO *)w_pre,
+                                       (const TIO *)w_post, s);
     if (st != FF_OK) return st;
   }
   return FF_OK;
@@ -166,6 +171,22 @@ void prof_mark(ff_spectra h, int slot, int transpose, hipStream_t s) {
   }
   if (h->prof_cur < 0) return;
   hipEventRecord(h->prof_ev[4 * h->prof_cur + slot], s);
+}
+
+ff_status op_time_pass(ff_spectra h, int transpose, int pass, int reps, const void *X, void *Y, hipStream_t s) {
+  // populate the intermediates with one full application, then repeat the chosen pass
+  ff_status st = op_apply(h, transpose, 1, X, transpose ? h->m : h->n, Y, transpose ? h->n : h->m, nullptr, nullptr,
+                          h->dtype, s);
+  if (st != FF_OK) return st;
+  const int64_t ldx = transpose ? h->m : h->n, ldy = transpose ? h->n : h->m;
+  for (int r = 0; r < reps && st == FF_OK; ++r) {
+    if (h->dtype == FF_F32)
+      st = run_pass<float, float, float>(h, transpose, pass, 1, (const float *)X, ldx, (float *)Y, ldy, nullptr, nullptr, s);
+    else
+      st = run_pass<double, double, double>(h, transpose, pass, 1, (const double *)X, ldx, (double *)Y, ldy, nullptr,
+                                            nullptr, s);
+  }
+  return st;
 }
 
 ff_status op_apply(ff_spectra h, int transpose, int64_t k, const void *X, int64_t ldx, void *Y, int64_t ldy,

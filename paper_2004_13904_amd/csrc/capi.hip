@@ -250,6 +250,16 @@ ff_status ff_set_tuning(ff_spectra h, const ff_tuning *t) {
   return FF_OK;
 }
 
+ff_status ff_time_pass(ff_spectra h, int32_t transpose, int32_t pass, int32_t reps, const void *x, void *y,
+                       ff_stream stream) {
+  if (!h || !x || !y) return fail(FF_EINVAL, "ff_time_pass: NULL argument");
+  if ((transpose != 0 && transpose != 1) || pass < 0 || pass > 2 || reps < 0)
+    return fail(FF_EINVAL, "ff_time_pass: transpose in {0,1}, pass in {0,1,2}, reps >= 0");
+  ff_status st = check_device(h);
+  if (st != FF_OK) return st;
+  return op_time_pass(h, transpose, pass, reps, x, y, (hipStream_t)stream);
+}
+
 ff_status ff_profile_begin(ff_spectra h, int32_t max_ops) {
   if (!h || max_ops < 1) return fail(FF_EINVAL, "ff_profile_begin: NULL handle or max_ops < 1");
   ff_status st = check_device(h);

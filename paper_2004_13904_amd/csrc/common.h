@@ -113,6 +113,7 @@ size_t csize(int dtype);
 ff_status op_apply(ff_spectra h, int transpose, int64_t k, const void *X, int64_t ldx, void *Y,
                    int64_t ldy, const void *w_pre, const void *w_post, int io_dtype,
                    hipStream_t s);
+ff_status op_time_pass(ff_spectra h, int transpose, int pass, int reps, const void *X, void *Y, hipStream_t s);
 // spectra construction (spectra.hip)
 ff_status make_spectra(ff_spectra h, hipStream_t s);
 ff_status kernel_table(ff_spectra h, double *table, hipStream_t s);
