@@ -20,12 +20,12 @@ void launch_r2c(int nrows, int nb, int kb, const TI *in, Idx3 ii, const TI *pre,
   constexpr int NFM = RowMax<T, N>::NF;
   if (NFM == 1 || (int64_t)nrows * nb * kb >= 2048) {
     using C = RowCfg<T, N, NFM>;
-    dim3 g((nrows + C::ROWS - 1) / C::ROWS, nb, kb);
-    k_row_r2c<T, TI, N, NFM><<<g, C::THREADS, 0, s>>>(in, ii, pre, pi, nrows, len, off, out, oi, out_kx, tw);
+    dim3 g((nrows * nb + C::ROWS - 1) / C::ROWS, 1, kb);
+    k_row_r2c<T, TI, N, NFM><<<g, C::THREADS, 0, s>>>(in, ii, pre, pi, nrows, nb, len, off, out, oi, out_kx, tw);
   } else {
     using C = RowCfg<T, N, 1>;
-    dim3 g((nrows + C::ROWS - 1) / C::ROWS, nb, kb);
-    k_row_r2c<T, TI, N, 1><<<g, C::THREADS, 0, s>>>(in, ii, pre, pi, nrows, len, off, out, oi, out_kx, tw);
+    dim3 g((nrows * nb + C::ROWS - 1) / C::ROWS, 1, kb);
+    k_row_r2c<T, TI, N, 1><<<g, C::THREADS, 0, s>>>(in, ii, pre, pi, nrows, nb, len, off, out, oi, out_kx, tw);
   }
 }
 
@@ -35,12 +35,12 @@ void launch_c2r(int nrows, int nb, int kb, const cplx<T> *in, Idx3 ii, int64_t i
   constexpr int NFM = RowMax<T, N>::NF;
   if (NFM == 1 || (int64_t)nrows * nb * kb >= 2048) {
     using C = RowCfg<T, N, NFM>;
-    dim3 g((nrows + C::ROWS - 1) / C::ROWS, nb, kb);
-    k_row_c2r<T, TO, N, NFM><<<g, C::THREADS, 0, s>>>(in, ii, in_kx, pstride, P, nrows, out, oi, post, qi, len, off, tw);
+    dim3 g((nrows * nb + C::ROWS - 1) / C::ROWS, 1, kb);
+    k_row_c2r<T, TO, N, NFM><<<g, C::THREADS, 0, s>>>(in, ii, in_kx, pstride, P, nrows, nb, out, oi, post, qi, len, off, tw);
   } else {
     using C = RowCfg<T, N, 1>;
-    dim3 g((nrows + C::ROWS - 1) / C::ROWS, nb, kb);
-    k_row_c2r<T, TO, N, 1><<<g, C::THREADS, 0, s>>>(in, ii, in_kx, pstride, P, nrows, out, oi, post, qi, len, off, tw);
+    dim3 g((nrows * nb + C::ROWS - 1) / C::ROWS, 1, kb);
+    k_row_c2r<T, TO, N, 1><<<g, C::THREADS, 0, s>>>(in, ii, in_kx, pstride, P, nrows, nb, out, oi, post, qi, len, off, tw);
   }
 }
 
@@ -49,10 +49,10 @@ void launch_c2r(int nrows, int nb, int kb, const cplx<T> *in, Idx3 ii, int64_t i
 template <typename T, typename TI, typename TO>
 ff_status run_pass(ff_spectra h, int transpose, int pass, int kb, const TI *X, int64_t ldx, TO *Y, int64_t ldy_out,
                    const TI *pre, const TO *post, hipStream_t s) {
-  const int H = h->H, nz = h->nz, nx = h->nx, ny = h->ny, sx = h->sx, sy = h->sy;
+  const int HC = h->NX / 2, nz = h->nz, nx = h->nx, ny = h->ny, sx = h->sx, sy = h->sy;
   const int ldy = h->ldy, lds = h->lds;
-  cplx<T> *X1 = (cplx<T> *)h->ws_rows;   // [vec][r][kx][row] (ld ldy)
-  cplx<T> *C2 = (cplx<T> *)h->ws_cols;   // G: partial sums [vec][g][kx][j]; G^T: D1 [vec][kx][j] (ld lds)
+  cplx<T> *X1 = (cplx<T> *)h->ws_rows;   // [vec][r][c][row] (ld ldy), HC column slots
+  cplx<T> *C2 = (cplx<T> *)h->ws_cols;   // G: partial sums [vec][g][c][j]; G^T: D1 [vec][c][j] (ld lds)
   const cplx<T> *spec = (const cplx<T> *)h->spec;
   const cplx<T> *twx = (const cplx<T> *)h->tw_x, *twy = (const cplx<T> *)h->tw_y;
   const int64_t lay = (int64_t)ny * nx;
@@ -60,25 +60,25 @@ ff_status run_pass(ff_spectra h, int transpose, int pass, int kb, const TI *X, i
     const int LG = h->lg_G;
     if (pass == 0) {
       FF_SWITCH_N(h->NX, launch_r2c<T, TI, NN>(ny, nz, kb, X, Idx3{ldx, lay, nx}, pre, Idx3{0, lay, nx}, nx, 0, X1,
-                                               Idx3{(int64_t)nz * H * ldy, (int64_t)H * ldy, 1}, ldy, twx, s));
+                                               Idx3{(int64_t)nz * HC * ldy, (int64_t)HC * ldy, 1}, ldy, twx, s));
       FF_LAUNCH_CHECK("G pass 1 (row transforms)");
     } else if (pass == 1) {
       FF_SWITCH_N(h->NY, {
         using CC = ColCfg<T, NN>;
         if constexpr (std::is_same<T, float>::value && CC::WPB >= kVecPerBlock) {
           if (kb > 1) {
-            dim3 g((H + CC::CPB - 1) / CC::CPB, LG, (kb + kVecPerBlock - 1) / kVecPerBlock);
-            k_col_G_batch<T, NN, kVecPerBlock><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, ldy, nz, H, LG, kb, spec,
+            dim3 g((HC + CC::CPB - 1) / CC::CPB, LG, (kb + kVecPerBlock - 1) / kVecPerBlock);
+            k_col_G_batch<T, NN, kVecPerBlock><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, ldy, nz, HC, LG, kb, spec,
                                                                                     C2, sy, lds, h->pyl, twy);
             break;
           }
         }
-        dim3 g((H + CC::CPB - 1) / CC::CPB, LG, kb);
-        k_col_G<T, NN><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, ldy, nz, H, LG, spec, C2, sy, lds, h->pyl, twy);
+        dim3 g((HC + CC::CPB - 1) / CC::CPB, LG, kb);
+        k_col_G<T, NN><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, ldy, nz, HC, LG, spec, C2, sy, lds, h->pyl, twy);
       });
       FF_LAUNCH_CHECK("G pass 2 (column transforms and spectral products)");
     } else {
-      FF_SWITCH_N(h->NX, launch_c2r<T, TO, NN>(sy, 1, kb, C2, Idx3{(int64_t)LG * H * lds, 0, 1}, lds, (int64_t)H * lds,
+      FF_SWITCH_N(h->NX, launch_c2r<T, TO, NN>(sy, 1, kb, C2, Idx3{(int64_t)LG * HC * lds, 0, 1}, lds, (int64_t)HC * lds,
                                                LG, Y, Idx3{ldy_out, 0, sx}, post, Idx3{0, 0, sx}, sx, h->pxl, twx, s));
       FF_LAUNCH_CHECK("G pass 3 (inverse row transforms)");
     }
@@ -86,25 +86,25 @@ ff_status run_pass(ff_spectra h, int transpose, int pass, int kb, const TI *X, i
     const int LG = h->lg_GT;
     if (pass == 0) {
       FF_SWITCH_N(h->NX, launch_r2c<T, TI, NN>(sy, 1, kb, X, Idx3{ldx, 0, sx}, pre, Idx3{0, 0, sx}, sx, h->pxl, C2,
-                                               Idx3{(int64_t)H * lds, 0, 1}, lds, twx, s));
+                                               Idx3{(int64_t)HC * lds, 0, 1}, lds, twx, s));
       FF_LAUNCH_CHECK("G^T pass 1 (row transforms)");
     } else if (pass == 1) {
       FF_SWITCH_N(h->NY, {
         using CC = ColCfg<T, NN>;
         if constexpr (std::is_same<T, float>::value && CC::WPB >= kVecPerBlock) {
           if (kb > 1) {
-            dim3 g((H + CC::CPB - 1) / CC::CPB, LG, (kb + kVecPerBlock - 1) / kVecPerBlock);
-            k_col_GT_batch<T, NN, kVecPerBlock><<<g, CC::THREADS * CC::WPB, 0, s>>>(C2, sy, lds, h->pyl, nz, H, LG, kb,
+            dim3 g((HC + CC::CPB - 1) / CC::CPB, LG, (kb + kVecPerBlock - 1) / kVecPerBlock);
+            k_col_GT_batch<T, NN, kVecPerBlock><<<g, CC::THREADS * CC::WPB, 0, s>>>(C2, sy, lds, h->pyl, nz, HC, LG, kb,
                                                                                      spec, X1, ny, ldy, twy);
             break;
           }
         }
-        dim3 g((H + CC::CPB - 1) / CC::CPB, LG, kb);
-        k_col_GT<T, NN><<<g, CC::THREADS * CC::WPB, 0, s>>>(C2, sy, lds, h->pyl, nz, H, LG, spec, X1, ny, ldy, twy);
+        dim3 g((HC + CC::CPB - 1) / CC::CPB, LG, kb);
+        k_col_GT<T, NN><<<g, CC::THREADS * CC::WPB, 0, s>>>(C2, sy, lds, h->pyl, nz, HC, LG, spec, X1, ny, ldy, twy);
       });
       FF_LAUNCH_CHECK("G^T pass 2 (column transforms and spectral products)");
     } else {
-      FF_SWITCH_N(h->NX, launch_c2r<T, TO, NN>(ny, nz, kb, X1, Idx3{(int64_t)nz * H * ldy, (int64_t)H * ldy, 1}, ldy, 0,
+      FF_SWITCH_N(h->NX, launch_c2r<T, TO, NN>(ny, nz, kb, X1, Idx3{(int64_t)nz * HC * ldy, (int64_t)HC * ldy, 1}, ldy, 0,
                                                1, Y, Idx3{ldy_out, lay, nx}, post, Idx3{0, lay, nx}, nx, 0, twx, s));
       FF_LAUNCH_CHECK("G^T pass 3 (inverse row transforms)");
     }

@@ -145,7 +145,7 @@ ff_status build_spectra(const ff_geometry *g, int32_t dtype, ff_stream stream, f
   h->n = nx * ny * g->nz;
   // Layer groups across blocks of the column passes: enough wavefronts to fill the chip
   // (about 2048), while every group keeps at least one layer per wave group of its block.
-  const int cb = column_blocks(h->H, NY);
+  const int cb = column_blocks(NX / 2, NY);   // NX/2 packed column slots
   const int wpb = col_wave_groups(dtype, NY);
   int lg = (2048 + cb * wpb - 1) / (cb * wpb);
   const int lgmax_layers = h->nz / wpb > 0 ? h->nz / wpb : 1;

@@ -57,37 +57,63 @@ struct Idx3 {
   }
 };
 
+// Row of a transposed tile element: tile element idx belongs to tile row idx % ROWS, i.e. to
+// flat row R = R0 + idx % ROWS = b*nrows + row.  When THREADS is a multiple of ROWS each
+// thread always meets the same tile row, and the division by nrows is done once.
+template <class C> struct TileRow {
+  static constexpr bool FIXED = C::THREADS % C::ROWS == 0;
+  int R0, total, nrows, R, b;
+  __device__ __forceinline__ TileRow(int R0_, int total_, int nrows_) : R0(R0_), total(total_), nrows(nrows_) {
+    R = R0 + (int)threadIdx.x % C::ROWS;
+    b = R / nrows;
+  }
+  // false when the row lies past the last one; else o = ix.at(vec, b, row)
+  __device__ __forceinline__ bool get(int idx, const Idx3 &ix, int64_t vec, int64_t &o) const {
+    int r = R, bb = b;
+    if (!FIXED) {
+      r = R0 + idx % C::ROWS;
+      bb = r / nrows;
+    }
+    o = ix.at(vec, bb, r - bb * nrows);
+    return r < total;
+  }
+};
+
 // ---------------------------------------------------------------------------------------
 // Pass 1: real rows -> half spectra along x, written transposed.
 // Input row (vec, b, row) holds `len` values that sit at x = off .. off+len-1 of the length-N
 // embedding (zero elsewhere); `pre` (optional) multiplies them (indexed without the vector
-// stride).  Output element (vec, b, kx, row) at out[o.at(vec, b, row) + kx*out_kx].
-// Grid: (ceil(nrows/ROWS), nb, nvec).
-template <typename T, typename TI, int N, int NF>
+// stride).  Output element (vec, b, kx, row) at out[o.at(vec, b, row) + kx*out_kx], for
+// kx < N/2 + 1, or with PACK for the N/2 column slots of the column passes (slot 0 holds the
+// real DC and Nyquist bins as one complex value, DC + i Nyquist).  Rows are numbered across the nb batches (R = b*nrows + row), so a pass of nb*nrows rows
+// fills exactly ceil(nb*nrows/ROWS) blocks.  Grid: (ceil(nb*nrows/ROWS), 1, nvec).
+template <typename T, typename TI, int N, int NF, bool PACK = true>
 __global__ void __launch_bounds__((RowCfg<T, N, NF>::THREADS))
-k_row_r2c(const TI *__restrict__ in, Idx3 ii, const TI *__restrict__ pre, Idx3 pi, int nrows, int len,
+k_row_r2c(const TI *__restrict__ in, Idx3 ii, const TI *__restrict__ pre, Idx3 pi, int nrows, int nb, int len,
           int off, cplx<T> *__restrict__ out, Idx3 oi, int64_t out_kx,
           const cplx<T> *__restrict__ tw) {
   using C = RowCfg<T, N, NF>;
   using F = FFT<T, N, false>;
   __shared__ cplx<T> sh[C::SH];
   const int f = threadIdx.x / F::TPF, j = threadIdx.x % F::TPF;
-  const int64_t vec = blockIdx.z, b = blockIdx.y;
-  const int row0 = blockIdx.x * C::ROWS;
-  const int ra = row0 + 2 * f, rb = ra + 1;
+  const int64_t vec = blockIdx.z;
+  const int total = nrows * nb;
+  const int R0 = blockIdx.x * C::ROWS;
+  const int ra = R0 + 2 * f, rb = ra + 1;
+  const int ba = ra / nrows, qa = ra - ba * nrows, bb = rb / nrows, qb = rb - bb * nrows;
   cplx<T> v[8];
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
     const int c = j + u * F::TPF - off;
     T a = 0, bv = 0;
     if (c >= 0 && c < len) {
-      if (ra < nrows) {
-        a = (T)in[ii.at(vec, b, ra) + c];
-        if (pre) a *= (T)pre[pi.at(0, b, ra) + c];
+      if (ra < total) {
+        a = (T)in[ii.at(vec, ba, qa) + c];
+        if (pre) a *= (T)pre[pi.at(0, ba, qa) + c];
       }
-      if (rb < nrows) {
-        bv = (T)in[ii.at(vec, b, rb) + c];
-        if (pre) bv *= (T)pre[pi.at(0, b, rb) + c];
+      if (rb < total) {
+        bv = (T)in[ii.at(vec, bb, qb) + c];
+        if (pre) bv *= (T)pre[pi.at(0, bb, qb) + c];
       }
     }
     v[u] = mk<T>(a, bv);
@@ -113,71 +139,83 @@ k_row_r2c(const TI *__restrict__ in, Idx3 ii, const TI *__restrict__ pre, Idx3 p
 #pragma unroll
   for (int u = 0; u < 5; ++u) {
     const int k = j + u * F::TPF;
-    if (u < 4 || j == 0) {
-      tile[k * C::TS + 2 * f] = xa[u];
-      tile[k * C::TS + 2 * f + 1] = xb[u];
+    if (u < 4 || (!PACK && j == 0)) {
+      cplx<T> a = xa[u], b = xb[u];
+      if (PACK && u == 0 && j == 0) {   // both bins are real: slot 0 = DC + i Nyquist
+        a.y = xa[4].x;
+        b.y = xb[4].x;
+      }
+      tile[k * C::TS + 2 * f] = a;
+      tile[k * C::TS + 2 * f + 1] = b;
     }
   }
   __syncthreads();
-  constexpr int PER = (C::H * C::ROWS + C::THREADS - 1) / C::THREADS;
-  cplx<T> tv[PER];
+  constexpr int HO = PACK ? N / 2 : N / 2 + 1;   // output columns
+  constexpr int PER = (HO * C::ROWS + C::THREADS - 1) / C::THREADS;
+  cplx<T> tv[PER];   // every element read (clamped index), so that tv stays in registers
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int idx = threadIdx.x + q * C::THREADS;
+    const int idx = min((int)threadIdx.x + q * C::THREADS, HO * C::ROWS - 1);
     const int k = idx / C::ROWS, rr = idx - k * C::ROWS;
-    if (idx < C::H * C::ROWS) tv[q] = tile[k * C::TS + rr];
+    tv[q] = tile[k * C::TS + rr];
   }
+  TileRow<C> tr(R0, total, nrows);
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int idx = threadIdx.x + q * C::THREADS;
-    const int k = idx / C::ROWS, rr = idx - k * C::ROWS;
-    const int row = row0 + rr;
-    if (idx < C::H * C::ROWS && row < nrows) out[oi.at(vec, b, row) + k * out_kx] = tv[q];
+    const int k = idx / C::ROWS;
+    int64_t o;
+    if (idx < HO * C::ROWS && tr.get(idx, oi, vec, o)) out[o + k * out_kx] = tv[q];
   }
 }
 
 // ---------------------------------------------------------------------------------------
-// Pass 3: half spectra (vec, b, kx, row), summed over P partial buffers `pstride` apart, ->
+// Pass 3: half spectra (vec, b, c, row) in the N/2 packed column slots of pass 1, summed over
+// P partial buffers `pstride` apart, ->
 // real rows; keeps x = off .. off+len-1, multiplies by `post` (optional, indexed without the
-// vector stride).  Grid: (ceil(nrows/ROWS), nb, nvec).
+// vector stride).  Rows numbered across batches as in pass 1.
+// Grid: (ceil(nb*nrows/ROWS), 1, nvec).
 template <typename T, typename TO, int N, int NF>
 __global__ void __launch_bounds__((RowCfg<T, N, NF>::THREADS))
-k_row_c2r(const cplx<T> *__restrict__ in, Idx3 ii, int64_t in_kx, int64_t pstride, int P, int nrows,
+k_row_c2r(const cplx<T> *__restrict__ in, Idx3 ii, int64_t in_kx, int64_t pstride, int P, int nrows, int nb,
           TO *__restrict__ out, Idx3 oi, const TO *__restrict__ post, Idx3 qi, int len, int off,
           const cplx<T> *__restrict__ tw) {
   using C = RowCfg<T, N, NF>;
   using F = FFT<T, N, true>;
   __shared__ cplx<T> sh[C::SH];
   const int f = threadIdx.x / F::TPF, j = threadIdx.x % F::TPF;
-  const int64_t vec = blockIdx.z, b = blockIdx.y;
-  const int row0 = blockIdx.x * C::ROWS;
+  const int64_t vec = blockIdx.z;
+  const int total = nrows * nb;
+  const int R0 = blockIdx.x * C::ROWS;
   cplx<T> *tile = sh;
   // every thread issues all of its tile loads before the first LDS write, so the global
   // load latencies overlap instead of adding up
-  constexpr int PER = (C::H * C::ROWS + C::THREADS - 1) / C::THREADS;
+  constexpr int HI = N / 2;   // input column slots (slot 0 = DC + i Nyquist)
+  constexpr int PER = (HI * C::ROWS + C::THREADS - 1) / C::THREADS;
   cplx<T> tv[PER];
+  TileRow<C> tr(R0, total, nrows);
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int idx = threadIdx.x + q * C::THREADS;
-    const int k = idx / C::ROWS, rr = idx - k * C::ROWS;
-    const int row = row0 + rr;
+    const int k = idx / C::ROWS;
+    int64_t o;
     tv[q] = mk<T>(0, 0);
-    if (idx < C::H * C::ROWS && row < nrows) tv[q] = in[ii.at(vec, b, row) + k * in_kx];
+    if (idx < HI * C::ROWS && tr.get(idx, ii, vec, o)) tv[q] = in[o + k * in_kx];
   }
   for (int p = 1; p < P; ++p) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int idx = threadIdx.x + q * C::THREADS;
-      const int k = idx / C::ROWS, rr = idx - k * C::ROWS;
-      const int row = row0 + rr;
-      if (idx < C::H * C::ROWS && row < nrows) tv[q] = cadd<T>(tv[q], in[ii.at(vec, b, row) + k * in_kx + p * pstride]);
+      const int k = idx / C::ROWS;
+      int64_t o;
+      if (idx < HI * C::ROWS && tr.get(idx, ii, vec, o)) tv[q] = cadd<T>(tv[q], in[o + k * in_kx + p * pstride]);
     }
   }
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int idx = threadIdx.x + q * C::THREADS;
     const int k = idx / C::ROWS, rr = idx - k * C::ROWS;
-    if (idx < C::H * C::ROWS) tile[k * C::TS + rr] = tv[q];
+    if (idx < HI * C::ROWS) tile[k * C::TS + rr] = tv[q];
   }
   __syncthreads();
   cplx<T> v[8];
@@ -185,13 +223,16 @@ k_row_c2r(const cplx<T> *__restrict__ in, Idx3 ii, int64_t in_kx, int64_t pstrid
   for (int u = 0; u < 8; ++u) {
     const int k = j + u * F::TPF;
     cplx<T> A, B;
-    if (k <= N / 2) {
+    if (k < N / 2) {
       A = tile[k * C::TS + 2 * f];
       B = tile[k * C::TS + 2 * f + 1];
-      if (k == 0 || k == N / 2) {  // real signal: DC and Nyquist bins are real
+      if (k == 0) {   // real signal: the DC bin is the real part of slot 0
         A.y = 0;
         B.y = 0;
       }
+    } else if (k == N / 2) {   // the Nyquist bin is the imaginary part of slot 0
+      A = mk<T>(tile[2 * f].y, 0);
+      B = mk<T>(tile[2 * f + 1].y, 0);
     } else {
       A = cconj<T>(tile[(N - k) * C::TS + 2 * f]);
       B = cconj<T>(tile[(N - k) * C::TS + 2 * f + 1]);
@@ -200,37 +241,50 @@ k_row_c2r(const cplx<T> *__restrict__ in, Idx3 ii, int64_t in_kx, int64_t pstrid
   }
   __syncthreads();
   F::run(v, j, sh + f * F::LDS, tw);
-  const int ra = row0 + 2 * f, rb = ra + 1;
+  const int ra = R0 + 2 * f, rb = ra + 1;
+  const int ba = ra / nrows, qa = ra - ba * nrows, bb = rb / nrows, qb = rb - bb * nrows;
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
     const int c = j + u * F::TPF - off;
     if (c >= 0 && c < len) {
-      if (ra < nrows) {
+      if (ra < total) {
         T a = v[u].x;
-        if (post) a *= (T)post[qi.at(0, b, ra) + c];
-        out[oi.at(vec, b, ra) + c] = (TO)a;
+        if (post) a *= (T)post[qi.at(0, ba, qa) + c];
+        out[oi.at(vec, ba, qa) + c] = (TO)a;
       }
-      if (rb < nrows) {
+      if (rb < total) {
         T bv = v[u].y;
-        if (post) bv *= (T)post[qi.at(0, b, rb) + c];
-        out[oi.at(vec, b, rb) + c] = (TO)bv;
+        if (post) bv *= (T)post[qi.at(0, bb, qb) + c];
+        out[oi.at(vec, bb, qb) + c] = (TO)bv;
       }
     }
   }
 }
 
 // ---------------------------------------------------------------------------------------
-// Pass 2 of G: for each half-spectrum column kx and layer group g:
-//   acc = sum_{r in group} S_r[kx, :] .* FFT_y(X1[vec, r, kx, 0:ny]),
-//   out[vec, g, kx, j] = IFFT_y(acc)[pyl + j], j in [0, sy).
-// X1 rows are stored [vec][r][kx][y] (ld = ny); spectra [r][kx][ky].
+// Column passes.  The half spectrum along x has NX/2 + 1 columns, of which kx = 0 (DC) and
+// kx = NX/2 (Nyquist) hold real sequences along y (the rows are real).  The row passes store
+// them packed in one complex column, slot 0 = DC + i Nyquist, so the intermediates have
+// HC = NX/2 column slots (slot c >= 1 is kx = c) and the column passes run over exactly HC
+// columns.  For slot 0 the spectra hold, in place of S_r[0] and S_r[NX/2] (both Hermitian),
+//   P_r = (S_r[0] + S_r[NX/2]) / 2   (spectrum column 0),
+//   M_r = (S_r[0] - S_r[NX/2]) / 2   (spectrum column NX/2).
+// With Z = FFT_y(DC + i Nyquist), the packed result of applying S_r[0] to the DC column and
+// S_r[NX/2] to the Nyquist column is P_r[k] Z[k] + M_r[k] conj(Z[-k]) (the adjoint: the
+// conjugate spectra), i.e. one extra product per layer and one index reversal per column.
+
+// Pass 2 of G: for each column slot c and layer group g:
+//   acc = sum_{r in group} S_r[c, :] .* FFT_y(X1[vec, r, c, 0:ny]),
+//   out[vec, g, c, j] = IFFT_y(acc)[pyl + j], j in [0, sy).
+// Slot 0 also sums accm = sum_r M_r .* FFT_y(...) and takes acc[k] + conj(accm[-k]).
+// X1 rows are stored [vec][r][c][y] (ld ldy); spectra [r][kx][ky] (HC + 1 columns).
 // A block holds WPB wave groups on the same CPB columns; wave group w takes every WPB-th
 // layer of the group (loading the next layer while transforming the current one); the
 // partial sums meet in LDS and wave group 0 does the inverse transform.
-// Grid: (ceil(H/CPB), LG, nvec).
+// Grid: (ceil(HC/CPB), LG, nvec).
 template <typename T, int NY>
 __global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
-k_col_G(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int H, int LG,
+k_col_G(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, int LG,
         const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ outp, int sy, int lds, int pyl,
         const cplx<T> *__restrict__ tw) {
   using CC = ColCfg<T, NY>;
@@ -241,20 +295,25 @@ k_col_G(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int H, int LG,
   const int w = threadIdx.x / CC::THREADS, lt = threadIdx.x % CC::THREADS;
   const int f = lt / TPF, j = lt % TPF;
   const int kx = blockIdx.x * CC::CPB + f;
-  const bool ok = kx < H;
+  const bool ok = kx < HC;
   const int kxs = ok ? kx : 0;
+  const bool pk = blockIdx.x == 0;   // block-uniform: this block holds the packed slot 0 (f == 0)
+  const int64_t SH = HC + 1;         // spectrum columns
   const int g = blockIdx.y;
   const int64_t vec = blockIdx.z;
   const int r0 = (int)((int64_t)g * nz / LG), r1 = (int)((int64_t)(g + 1) * nz / LG);
   cplx<T> *buf = sh + (w * CC::CPB + f) * Ff::LDS;
   typename Ff::Tw twr;
   Ff::load_tw(twr, j, tw);
-  cplx<T> acc[8], xn[8], sn[8];
+  cplx<T> acc[8], accm[8], xn[8], sn[8];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) acc[u] = mk<T>(0, 0);
+  for (int u = 0; u < 8; ++u) {
+    acc[u] = mk<T>(0, 0);
+    accm[u] = mk<T>(0, 0);
+  }
   auto load = [&](int r) {
-    const cplx<T> *src = X1 + ((vec * nz + r) * H + kxs) * (int64_t)ldy;
-    const cplx<T> *sp = spec + ((int64_t)r * H + kxs) * NY;
+    const cplx<T> *src = X1 + ((vec * nz + r) * HC + kxs) * (int64_t)ldy;
+    const cplx<T> *sp = spec + ((int64_t)r * SH + kxs) * NY;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int y = j + u * TPF;
@@ -266,35 +325,86 @@ k_col_G(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int H, int LG,
   // NY > 512: one wave group per block (WPB = 1), so the loop is uniform in the block.
   int r = r0 + w;
   if (r < r1) load(r);
-  for (; r < r1; r += WPB) {
-    cplx<T> v[8], s[8];
+  if (!pk) {
+    for (; r < r1; r += WPB) {
+      cplx<T> v[8], s[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      v[u] = xn[u];
-      s[u] = sn[u];
+      for (int u = 0; u < 8; ++u) {
+        v[u] = xn[u];
+        s[u] = sn[u];
+      }
+      if (r + WPB < r1) load(r + WPB);
+      Ff::run_tw(v, j, buf, twr);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = cadd<T>(acc[u], cmul<T>(v[u], s[u]));
     }
-    if (r + WPB < r1) load(r + WPB);
-    Ff::run_tw(v, j, buf, twr);
+  } else {
+    // the same loop plus the M_r products (M_r is loaded at the start of its own iteration;
+    // in double precision the next layer is loaded after the products, within the registers)
+    constexpr bool PREFETCH = sizeof(T) == 4;
+    for (; r < r1; r += WPB) {
+      cplx<T> v[8], s[8], mm[8];
+      const cplx<T> *mp = spec + ((int64_t)r * SH + HC) * NY;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc[u] = cadd<T>(acc[u], cmul<T>(v[u], s[u]));
+      for (int u = 0; u < 8; ++u) {
+        v[u] = xn[u];
+        s[u] = sn[u];
+        mm[u] = mp[j + u * TPF];
+      }
+      if (PREFETCH && r + WPB < r1) load(r + WPB);
+      Ff::run_tw(v, j, buf, twr);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        acc[u] = cadd<T>(acc[u], cmul<T>(v[u], s[u]));
+        accm[u] = cadd<T>(accm[u], cmul<T>(v[u], mm[u]));
+      }
+      if (!PREFETCH && r + WPB < r1) load(r + WPB);
+    }
   }
   if constexpr (WPB > 1) {
-    // partial sums of the wave groups meet in LDS (each in its own transform buffer)
+    // partial sums of the wave groups meet in LDS (each in its own transform buffer), in
+    // wave-group order 0, 1, ...
 #pragma unroll
     for (int u = 0; u < 8; ++u) buf[j + u * TPF] = acc[u];
     __syncthreads();
-    if (w != 0) return;
-    for (int w2 = 1; w2 < WPB; ++w2) {
-      const cplx<T> *o = sh + (w2 * CC::CPB + f) * Ff::LDS;
+    if (w == 0) {
+      for (int w2 = 1; w2 < WPB; ++w2) {
+        const cplx<T> *o = sh + (w2 * CC::CPB + f) * Ff::LDS;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc[u] = cadd<T>(acc[u], o[j + u * TPF]);
+        for (int u = 0; u < 8; ++u) acc[u] = cadd<T>(acc[u], o[j + u * TPF]);
+      }
+    }
+    if (pk) {
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 8; ++u) buf[j + u * TPF] = accm[u];
+      __syncthreads();
+      if (w == 0) {
+        for (int w2 = 1; w2 < WPB; ++w2) {
+          const cplx<T> *o = sh + (w2 * CC::CPB + f) * Ff::LDS;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) accm[u] = cadd<T>(accm[u], o[j + u * TPF]);
+        }
+      }
+    }
+    if (w != 0) return;
+    group_sync<TPF>();
+  }
+  if (pk) {
+    // slot 0: acc[k] + conj(accm[-k])
+#pragma unroll
+    for (int u = 0; u < 8; ++u) buf[pad8(j + u * TPF)] = accm[u];
+    group_sync<TPF>();
+    if (f == 0) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = cadd<T>(acc[u], cconj<T>(buf[pad8((NY - j - u * TPF) & (NY - 1))]));
     }
     group_sync<TPF>();
   }
   // the inverse transform uses the conjugate twiddles of the same table
   Fi::run_tw(acc, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
   if (ok) {
-    cplx<T> *dst = outp + ((vec * LG + g) * H + kx) * (int64_t)lds;
+    cplx<T> *dst = outp + ((vec * LG + g) * HC + kx) * (int64_t)lds;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int y = j + u * TPF - pyl;
@@ -303,13 +413,14 @@ k_col_G(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int H, int LG,
   }
 }
 
-// Pass 2 of G^T: for each column kx: D = FFT_y(D1[vec, kx, :] placed at rows pyl..pyl+sy-1);
-// for each layer r of the group: X1[vec, r, kx, q] = IFFT_y(conj(S_r[kx, :]) .* D)[q], q < ny.
+// Pass 2 of G^T: for each column slot c: D = FFT_y(D1[vec, c, :] placed at rows pyl..pyl+sy-1);
+// for each layer r of the group: X1[vec, r, c, q] = IFFT_y(conj(S_r[c, :]) .* D)[q], q < ny
+// (slot 0: conj(P_r) .* D + conj(M_r) .* conj(D[-k])).
 // Wave group w of a block takes every WPB-th layer of the group and transforms D itself.
-// Grid: (ceil(H/CPB), LG, nvec).
+// Grid: (ceil(HC/CPB), LG, nvec).
 template <typename T, int NY>
 __global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
-k_col_GT(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz, int H, int LG,
+k_col_GT(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz, int HC, int LG,
          const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ X1, int ny, int ldy,
          const cplx<T> *__restrict__ tw) {
   using CC = ColCfg<T, NY>;
@@ -320,8 +431,11 @@ k_col_GT(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz, int H
   const int w = threadIdx.x / CC::THREADS, lt = threadIdx.x % CC::THREADS;
   const int f = lt / TPF, j = lt % TPF;
   const int kx = blockIdx.x * CC::CPB + f;
-  const bool ok = kx < H;
+  const bool ok = kx < HC;
   const int kxs = ok ? kx : 0;
+  const bool pk = blockIdx.x == 0;        // block-uniform
+  const bool pk0 = pk && f == 0;          // this lane's column is the packed slot 0
+  const int64_t SH = HC + 1;
   const int g = blockIdx.y;
   const int64_t vec = blockIdx.z;
   const int r0 = (int)((int64_t)g * nz / LG), r1 = (int)((int64_t)(g + 1) * nz / LG);
@@ -329,11 +443,11 @@ k_col_GT(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz, int H
   cplx<T> *buf = sh + (w * CC::CPB + f) * Ff::LDS;
   typename Ff::Tw twr;
   Ff::load_tw(twr, j, tw);
-  const cplx<T> *src = D1 + (vec * H + kxs) * (int64_t)ldd;
+  const cplx<T> *src = D1 + (vec * HC + kxs) * (int64_t)ldd;
   cplx<T> dh[8], sn[8];
   int r = r0 + w;
   {
-    const cplx<T> *sp = spec + ((int64_t)r * H + kxs) * NY;
+    const cplx<T> *sp = spec + ((int64_t)r * SH + kxs) * NY;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int y = j + u * TPF - pyl;
@@ -342,23 +456,55 @@ k_col_GT(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz, int H
     }
   }
   Ff::run_tw(dh, j, buf, twr);
-  for (; r < r1; r += WPB) {
-    cplx<T> v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = cmulc<T>(dh[u], sn[u]);
-    if (r + WPB < r1) {
-      const cplx<T> *sp = spec + ((int64_t)(r + WPB) * H + kxs) * NY;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) sn[u] = sp[j + u * TPF];
-    }
-    Fi::run_tw(v, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
+  auto store = [&](int r, const cplx<T> *v) {
     if (ok) {
-      cplx<T> *dst = X1 + ((vec * nz + r) * H + kx) * (int64_t)ldy;
+      cplx<T> *dst = X1 + ((vec * nz + r) * HC + kx) * (int64_t)ldy;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int y = j + u * TPF;
         if (y < ny) dst[y] = v[u];
       }
+    }
+  };
+  if (!pk) {
+    for (; r < r1; r += WPB) {
+      cplx<T> v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = cmulc<T>(dh[u], sn[u]);
+      if (r + WPB < r1) {
+        const cplx<T> *sp = spec + ((int64_t)(r + WPB) * SH + kxs) * NY;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sn[u] = sp[j + u * TPF];
+      }
+      Fi::run_tw(v, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
+      store(r, v);
+    }
+  } else {
+    // dr[k] = conj(D[-k]) for the packed slot 0
+    cplx<T> dr[8];
+    group_sync<TPF>();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) buf[pad8(j + u * TPF)] = dh[u];
+    group_sync<TPF>();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) dr[u] = cconj<T>(buf[pad8((NY - j - u * TPF) & (NY - 1))]);
+    group_sync<TPF>();
+    for (; r < r1; r += WPB) {
+      cplx<T> v[8];
+      const cplx<T> *mp = spec + ((int64_t)r * SH + HC) * NY;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = cmulc<T>(dh[u], sn[u]);
+      if (pk0) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = cadd<T>(v[u], cmulc<T>(dr[u], mp[j + u * TPF]));
+      }
+      if (r + WPB < r1) {
+        const cplx<T> *sp = spec + ((int64_t)(r + WPB) * SH + kxs) * NY;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sn[u] = sp[j + u * TPF];
+      }
+      Fi::run_tw(v, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
+      store(r, v);
     }
   }
 }
@@ -372,9 +518,10 @@ k_col_GT(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz, int H
 // Wave group w takes layers r = r0 + w, r0 + w + WPB, ...; for each of its layers it loads the
 // spectrum column once and transforms the V vectors' columns.  Partial sums meet in LDS one
 // vector at a time; wave group (v mod WPB) adds them up and does vector v's inverse transform.
+// Block 0 (slot 0 at f == 0) also sums the M_r products, one vector at a time.
 template <typename T, int NY, int V>
 __global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
-k_col_G_batch(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int H, int LG, int kb,
+k_col_G_batch(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, int LG, int kb,
               const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ outp, int sy, int lds, int pyl,
               const cplx<T> *__restrict__ tw) {
   using CC = ColCfg<T, NY>;
@@ -382,12 +529,15 @@ k_col_G_batch(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int H, in
   using Fi = FFT<T, NY, true>;
   constexpr int TPF = CC::TPF, WPB = CC::WPB;
   static_assert(WPB >= V, "one inverse transform per wave group");
+  static_assert(TPF <= 64, "wave-level synchronisation of a column");
   __shared__ cplx<T> sh[WPB * CC::CPB * Ff::LDS];
   const int w = threadIdx.x / CC::THREADS, lt = threadIdx.x % CC::THREADS;
   const int f = lt / TPF, j = lt % TPF;
   const int kx = blockIdx.x * CC::CPB + f;
-  const bool ok = kx < H;
+  const bool ok = kx < HC;
   const int kxs = ok ? kx : 0;
+  const bool pk = blockIdx.x == 0;   // block-uniform
+  const int64_t SH = HC + 1;
   const int g = blockIdx.y;
   const int64_t vec0 = (int64_t)blockIdx.z * V;
   const int r0 = (int)((int64_t)g * nz / LG), r1 = (int)((int64_t)(g + 1) * nz / LG);
@@ -399,25 +549,106 @@ k_col_G_batch(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int H, in
   for (int v = 0; v < V; ++v)
 #pragma unroll
     for (int u = 0; u < 8; ++u) acc[v][u] = mk<T>(0, 0);
-  for (int r = r0 + w; r < r1; r += WPB) {
-    cplx<T> sv[8];
-    const cplx<T> *sp = spec + ((int64_t)r * H + kxs) * NY;
+  if (!pk) {
+    for (int r = r0 + w; r < r1; r += WPB) {
+      cplx<T> sv[8];
+      const cplx<T> *sp = spec + ((int64_t)r * SH + kxs) * NY;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) sv[u] = sp[j + u * TPF];
+      for (int u = 0; u < 8; ++u) sv[u] = sp[j + u * TPF];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const bool okv = ok && vec0 + v < kb;
+        const cplx<T> *src = X1 + (((vec0 + v) * nz + r) * HC + kxs) * (int64_t)ldy;
+        cplx<T> xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int y = j + u * TPF;
+          xv[u] = (okv && y < ny) ? src[y] : mk<T>(0, 0);
+        }
+        Ff::run_tw(xv, j, buf, twr);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[v][u] = cadd<T>(acc[v][u], cmul<T>(xv[u], sv[u]));
+      }
+    }
+  } else {
+    // block 0: every vector in turn (the same per-vector operation order), with the M_r sums
+    // beside the main ones; each vector's two sums are reduced before the next vector starts
+    cplx<T> mine[8], mred[8];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       const bool okv = ok && vec0 + v < kb;
-      const cplx<T> *src = X1 + (((vec0 + v) * nz + r) * H + kxs) * (int64_t)ldy;
-      cplx<T> xv[8];
+      cplx<T> a[8], am[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int y = j + u * TPF;
-        xv[u] = (okv && y < ny) ? src[y] : mk<T>(0, 0);
+        a[u] = mk<T>(0, 0);
+        am[u] = mk<T>(0, 0);
       }
-      Ff::run_tw(xv, j, buf, twr);
+      for (int r = r0 + w; r < r1; r += WPB) {
+        const cplx<T> *sp = spec + ((int64_t)r * SH + kxs) * NY;
+        const cplx<T> *mp = spec + ((int64_t)r * SH + HC) * NY;
+        const cplx<T> *src = X1 + (((vec0 + v) * nz + r) * HC + kxs) * (int64_t)ldy;
+        cplx<T> xv[8], sv[8], mv[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc[v][u] = cadd<T>(acc[v][u], cmul<T>(xv[u], sv[u]));
+        for (int u = 0; u < 8; ++u) {
+          const int y = j + u * TPF;
+          xv[u] = (okv && y < ny) ? src[y] : mk<T>(0, 0);
+          sv[u] = sp[y];
+          mv[u] = mp[y];
+        }
+        Ff::run_tw(xv, j, buf, twr);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          a[u] = cadd<T>(a[u], cmul<T>(xv[u], sv[u]));
+          am[u] = cadd<T>(am[u], cmul<T>(xv[u], mv[u]));
+        }
+      }
+      // wave-group order 0, 1, ..., as in the single-vector kernel
+#pragma unroll
+      for (int u = 0; u < 8; ++u) buf[j + u * TPF] = a[u];
+      __syncthreads();
+      if (w == v) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) mine[u] = v == 0 ? a[u] : sh[f * Ff::LDS + j + u * TPF];
+        for (int w2 = 1; w2 < WPB; ++w2) {
+          const cplx<T> *o = sh + (w2 * CC::CPB + f) * Ff::LDS;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) mine[u] = cadd<T>(mine[u], w2 == v ? a[u] : o[j + u * TPF]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 8; ++u) buf[j + u * TPF] = am[u];
+      __syncthreads();
+      if (w == v) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) mred[u] = v == 0 ? am[u] : sh[f * Ff::LDS + j + u * TPF];
+        for (int w2 = 1; w2 < WPB; ++w2) {
+          const cplx<T> *o = sh + (w2 * CC::CPB + f) * Ff::LDS;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) mred[u] = cadd<T>(mred[u], w2 == v ? am[u] : o[j + u * TPF]);
+        }
+      }
+      __syncthreads();
     }
+    if (w >= V || vec0 + w >= kb) return;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) buf[pad8(j + u * TPF)] = mred[u];
+    group_sync<TPF>();
+    if (f == 0) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) mine[u] = cadd<T>(mine[u], cconj<T>(buf[pad8((NY - j - u * TPF) & (NY - 1))]));
+    }
+    group_sync<TPF>();
+    Fi::run_tw(mine, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
+    if (ok) {
+      cplx<T> *dst = outp + (((vec0 + w) * LG + g) * HC + kx) * (int64_t)lds;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int y = j + u * TPF - pyl;
+        if (y >= 0 && y < sy) dst[y] = mine[u];
+      }
+    }
+    return;
   }
   // reduction over the wave groups, one vector per round
   cplx<T> mine[8];
@@ -441,7 +672,7 @@ k_col_G_batch(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int H, in
   if (w >= V || vec0 + w >= kb) return;
   Fi::run_tw(mine, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
   if (ok) {
-    cplx<T> *dst = outp + (((vec0 + w) * LG + g) * H + kx) * (int64_t)lds;
+    cplx<T> *dst = outp + (((vec0 + w) * LG + g) * HC + kx) * (int64_t)lds;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int y = j + u * TPF - pyl;
@@ -452,10 +683,11 @@ k_col_G_batch(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int H, in
 
 // Pass 2 of G^T for vectors vec0 .. vec0+V-1: wave group v < V transforms vector v's data
 // column and shares it through LDS; then every wave group takes its layers, loads each
-// spectrum column once and forms the V products and inverse transforms.
+// spectrum column once and forms the V products and inverse transforms.  Slot 0 reads the
+// reversed transform conj(D[-k]) from the same LDS copy.
 template <typename T, int NY, int V>
 __global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
-k_col_GT_batch(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz, int H, int LG, int kb,
+k_col_GT_batch(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz, int HC, int LG, int kb,
                const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ X1, int ny, int ldy,
                const cplx<T> *__restrict__ tw) {
   using CC = ColCfg<T, NY>;
@@ -468,8 +700,11 @@ k_col_GT_batch(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz,
   const int w = threadIdx.x / CC::THREADS, lt = threadIdx.x % CC::THREADS;
   const int f = lt / TPF, j = lt % TPF;
   const int kx = blockIdx.x * CC::CPB + f;
-  const bool ok = kx < H;
+  const bool ok = kx < HC;
   const int kxs = ok ? kx : 0;
+  const bool pk = blockIdx.x == 0;   // block-uniform
+  const bool pk0 = pk && f == 0;
+  const int64_t SH = HC + 1;
   const int g = blockIdx.y;
   const int64_t vec0 = (int64_t)blockIdx.z * V;
   const int r0 = (int)((int64_t)g * nz / LG), r1 = (int)((int64_t)(g + 1) * nz / LG);
@@ -478,7 +713,7 @@ k_col_GT_batch(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz,
   Ff::load_tw(twr, j, tw);
   if (w < V) {
     const bool okv = ok && vec0 + w < kb;
-    const cplx<T> *src = D1 + ((vec0 + w) * H + kxs) * (int64_t)ldd;
+    const cplx<T> *src = D1 + ((vec0 + w) * HC + kxs) * (int64_t)ldd;
     cplx<T> dv[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -496,18 +731,30 @@ k_col_GT_batch(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz,
 #pragma unroll
     for (int u = 0; u < 8; ++u) dh[v][u] = dsh[(v * CC::CPB + f) * NY + j + u * TPF];
   for (int r = r0 + w; r < r1; r += WPB) {
-    cplx<T> sv[8];
-    const cplx<T> *sp = spec + ((int64_t)r * H + kxs) * NY;
+    cplx<T> sv[8], mv[8];
+    const cplx<T> *sp = spec + ((int64_t)r * SH + kxs) * NY;
 #pragma unroll
     for (int u = 0; u < 8; ++u) sv[u] = sp[j + u * TPF];
+    if (pk) {
+      const cplx<T> *mp = spec + ((int64_t)r * SH + HC) * NY;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) mv[u] = mp[j + u * TPF];
+    }
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       cplx<T> xv[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) xv[u] = cmulc<T>(dh[v][u], sv[u]);
+      if (pk0) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const cplx<T> dr = cconj<T>(dsh[(v * CC::CPB + f) * NY + ((NY - j - u * TPF) & (NY - 1))]);
+          xv[u] = cadd<T>(xv[u], cmulc<T>(dr, mv[u]));
+        }
+      }
       Fi::run_tw(xv, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
       if (ok && vec0 + v < kb) {
-        cplx<T> *dst = X1 + (((vec0 + v) * nz + r) * H + kx) * (int64_t)ldy;
+        cplx<T> *dst = X1 + (((vec0 + v) * nz + r) * HC + kx) * (int64_t)ldy;
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int y = j + u * TPF;

@@ -129,14 +129,28 @@ k_col_spec(const double2 *__restrict__ tmp, int H, double scale, cplx<TS> *__res
   }
 }
 
+// The column passes carry the real DC (kx = 0) and Nyquist (kx = NX/2) columns packed in one
+// complex column and need, for it, P = (S[0] + S[NX/2]) / 2 and M = (S[0] - S[NX/2]) / 2 in
+// place of the two spectra.  Both are linear in the row-transformed generator, so the
+// combination is taken on tmp before the column FFT.  Grid: (ceil(NY/256), nz).
+__global__ void k_pack_dc_nyquist(double2 *__restrict__ tmp, int H, int NY) {
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= NY) return;
+  double2 *c0 = tmp + (int64_t)blockIdx.y * H * NY;
+  double2 *cn = c0 + (int64_t)(H - 1) * NY;
+  const double2 a = c0[y], b = cn[y];
+  c0[y] = mk<double>(0.5 * (a.x + b.x), 0.5 * (a.y + b.y));
+  cn[y] = mk<double>(0.5 * (a.x - b.x), 0.5 * (a.y - b.y));
+}
+
 template <int NX>
 ff_status rows_fp64(const double *circ, int nz, int NY, double2 *tmp, const double2 *tw, hipStream_t s) {
   constexpr int NF = RowMax<double, NX>::NF;
   using C = RowCfg<double, NX, NF>;
   const int H = NX / 2 + 1;
   Idx3 ii{0, (int64_t)NY * NX, NX}, pi{0, 0, 0}, oi{0, (int64_t)H * NY, 1};
-  dim3 grid((NY + C::ROWS - 1) / C::ROWS, nz, 1);
-  k_row_r2c<double, double, NX, NF><<<grid, C::THREADS, 0, s>>>(circ, ii, nullptr, pi, NY, NX, 0, tmp, oi,
+  dim3 grid((NY * nz + C::ROWS - 1) / C::ROWS, 1, 1);
+  k_row_r2c<double, double, NX, NF, false><<<grid, C::THREADS, 0, s>>>(circ, ii, nullptr, pi, NY, nz, NX, 0, tmp, oi,
                                                              (int64_t)NY, tw);
   FF_LAUNCH_CHECK("row transform of the kernel generator");
   return FF_OK;
@@ -216,6 +230,11 @@ ff_status make_spectra(ff_spectra h, hipStream_t s) {
   st = launch_table(h, nullptr, circ, s);
   if (st == FF_OK) {
     FF_SWITCH_N(NX, st = rows_fp64<NN>(circ, nz, NY, tmp, twx, s));
+  }
+  if (st == FF_OK) {
+    k_pack_dc_nyquist<<<dim3((NY + 255) / 256, nz), 256, 0, s>>>(tmp, H, NY);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) st = hip_fail(e, "DC/Nyquist combination of the kernel spectra");
   }
   if (st == FF_OK) {
     const double scale = 1.0 / ((double)NX * (double)NY);
