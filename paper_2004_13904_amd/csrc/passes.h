@@ -276,11 +276,13 @@ k_row_c2r(const cplx<T> *__restrict__ in, Idx3 ii, int64_t in_kx, int64_t pstrid
 // Pass 2 of G: for each column slot c and layer group g:
 //   acc = sum_{r in group} S_r[c, :] .* FFT_y(X1[vec, r, c, 0:ny]),
 //   out[vec, g, c, j] = IFFT_y(acc)[pyl + j], j in [0, sy).
-// Slot 0 also sums accm = sum_r M_r .* FFT_y(...) and takes acc[k] + conj(accm[-k]).
+// Slot 0 also sums accm = sum_r M_r .* FFT_y(...) and adds conj(accm[-k]) to acc[k] (each wave
+// group on its own partial sums, before they are added up).
 // X1 rows are stored [vec][r][c][y] (ld ldy); spectra [r][kx][ky] (HC + 1 columns).
 // A block holds WPB wave groups on the same CPB columns; wave group w takes every WPB-th
 // layer of the group (loading the next layer while transforming the current one); the
-// partial sums meet in LDS and wave group 0 does the inverse transform.
+// partial sums are added up in LDS, each wave group taking a share of the elements, and wave
+// group 0 does the inverse transform.
 // Grid: (ceil(HC/CPB), LG, nvec).
 template <typename T, int NY>
 __global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
@@ -305,12 +307,9 @@ k_col_G(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, int LG,
   cplx<T> *buf = sh + (w * CC::CPB + f) * Ff::LDS;
   typename Ff::Tw twr;
   Ff::load_tw(twr, j, tw);
-  cplx<T> acc[8], accm[8], xn[8], sn[8];
+  cplx<T> acc[8], xn[8], sn[8];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    acc[u] = mk<T>(0, 0);
-    accm[u] = mk<T>(0, 0);
-  }
+  for (int u = 0; u < 8; ++u) acc[u] = mk<T>(0, 0);
   auto load = [&](int r) {
     const cplx<T> *src = X1 + ((vec * nz + r) * HC + kxs) * (int64_t)ldy;
     const cplx<T> *sp = spec + ((int64_t)r * SH + kxs) * NY;
@@ -339,19 +338,31 @@ k_col_G(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, int LG,
       for (int u = 0; u < 8; ++u) acc[u] = cadd<T>(acc[u], cmul<T>(v[u], s[u]));
     }
   } else {
-    // the same loop plus the M_r products (M_r is loaded at the start of its own iteration;
-    // in double precision the next layer is loaded after the products, within the registers)
+    // the same loop plus the M_r products.  Single precision prefetches M_r with the rest;
+    // double precision loads it at the start of its own iteration (register budget).
     constexpr bool PREFETCH = sizeof(T) == 4;
+    cplx<T> accm[8], mn[8];
+    auto loadm = [&](int rr) {
+      const cplx<T> *mp = spec + ((int64_t)rr * SH + HC) * NY;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) mn[u] = mp[j + u * TPF];
+    };
+#pragma unroll
+    for (int u = 0; u < 8; ++u) accm[u] = mk<T>(0, 0);
+    if (PREFETCH && r < r1) loadm(r);
     for (; r < r1; r += WPB) {
       cplx<T> v[8], s[8], mm[8];
-      const cplx<T> *mp = spec + ((int64_t)r * SH + HC) * NY;
+      if (!PREFETCH) loadm(r);
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         v[u] = xn[u];
         s[u] = sn[u];
-        mm[u] = mp[j + u * TPF];
+        mm[u] = mn[u];
       }
-      if (PREFETCH && r + WPB < r1) load(r + WPB);
+      if (PREFETCH && r + WPB < r1) {
+        load(r + WPB);
+        loadm(r + WPB);
+      }
       Ff::run_tw(v, j, buf, twr);
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -360,38 +371,8 @@ k_col_G(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, int LG,
       }
       if (!PREFETCH && r + WPB < r1) load(r + WPB);
     }
-  }
-  if constexpr (WPB > 1) {
-    // partial sums of the wave groups meet in LDS (each in its own transform buffer), in
-    // wave-group order 0, 1, ...
-#pragma unroll
-    for (int u = 0; u < 8; ++u) buf[j + u * TPF] = acc[u];
-    __syncthreads();
-    if (w == 0) {
-      for (int w2 = 1; w2 < WPB; ++w2) {
-        const cplx<T> *o = sh + (w2 * CC::CPB + f) * Ff::LDS;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc[u] = cadd<T>(acc[u], o[j + u * TPF]);
-      }
-    }
-    if (pk) {
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < 8; ++u) buf[j + u * TPF] = accm[u];
-      __syncthreads();
-      if (w == 0) {
-        for (int w2 = 1; w2 < WPB; ++w2) {
-          const cplx<T> *o = sh + (w2 * CC::CPB + f) * Ff::LDS;
-#pragma unroll
-          for (int u = 0; u < 8; ++u) accm[u] = cadd<T>(accm[u], o[j + u * TPF]);
-        }
-      }
-    }
-    if (w != 0) return;
+    // each wave group folds its own M sum in: acc[k] += conj(accm[-k]) (slot 0 lanes)
     group_sync<TPF>();
-  }
-  if (pk) {
-    // slot 0: acc[k] + conj(accm[-k])
 #pragma unroll
     for (int u = 0; u < 8; ++u) buf[pad8(j + u * TPF)] = accm[u];
     group_sync<TPF>();
@@ -399,6 +380,25 @@ k_col_G(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, int LG,
 #pragma unroll
       for (int u = 0; u < 8; ++u) acc[u] = cadd<T>(acc[u], cconj<T>(buf[pad8((NY - j - u * TPF) & (NY - 1))]));
     }
+  }
+  if constexpr (WPB > 1) {
+    // partial sums of the wave groups meet in LDS (each in its own transform buffer).  Wave
+    // group w adds up the elements u = w, w + WPB, ... of every lane over the wave groups in
+    // order 0, 1, ..., and leaves the sums in wave group 0's buffer.
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) buf[j + u * TPF] = acc[u];
+    __syncthreads();
+    for (int u = w; u < 8; u += WPB) {
+      const int e = f * Ff::LDS + j + u * TPF;
+      cplx<T> t = sh[e];
+      for (int w2 = 1; w2 < WPB; ++w2) t = cadd<T>(t, sh[w2 * CC::CPB * Ff::LDS + e]);
+      sh[e] = t;
+    }
+    __syncthreads();
+    if (w != 0) return;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = buf[j + u * TPF];
     group_sync<TPF>();
   }
   // the inverse transform uses the conjugate twiddles of the same table
@@ -489,19 +489,29 @@ k_col_GT(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz, int H
 #pragma unroll
     for (int u = 0; u < 8; ++u) dr[u] = cconj<T>(buf[pad8((NY - j - u * TPF) & (NY - 1))]);
     group_sync<TPF>();
+    // M_r is prefetched with S_r in single precision, loaded at use in double (registers)
+    constexpr bool PREFETCH = sizeof(T) == 4;
+    cplx<T> mn[8];
+    auto loadm = [&](int rr) {
+      const cplx<T> *mp = spec + ((int64_t)rr * SH + HC) * NY;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) mn[u] = mp[j + u * TPF];
+    };
+    if (PREFETCH) loadm(r);
     for (; r < r1; r += WPB) {
       cplx<T> v[8];
-      const cplx<T> *mp = spec + ((int64_t)r * SH + HC) * NY;
+      if (!PREFETCH) loadm(r);
 #pragma unroll
       for (int u = 0; u < 8; ++u) v[u] = cmulc<T>(dh[u], sn[u]);
       if (pk0) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = cadd<T>(v[u], cmulc<T>(dr[u], mp[j + u * TPF]));
+        for (int u = 0; u < 8; ++u) v[u] = cadd<T>(v[u], cmulc<T>(dr[u], mn[u]));
       }
       if (r + WPB < r1) {
         const cplx<T> *sp = spec + ((int64_t)(r + WPB) * SH + kxs) * NY;
 #pragma unroll
         for (int u = 0; u < 8; ++u) sn[u] = sp[j + u * TPF];
+        if (PREFETCH) loadm(r + WPB);
       }
       Fi::run_tw(v, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
       store(r, v);
@@ -518,7 +528,8 @@ k_col_GT(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz, int H
 // Wave group w takes layers r = r0 + w, r0 + w + WPB, ...; for each of its layers it loads the
 // spectrum column once and transforms the V vectors' columns.  Partial sums meet in LDS one
 // vector at a time; wave group (v mod WPB) adds them up and does vector v's inverse transform.
-// Block 0 (slot 0 at f == 0) also sums the M_r products, one vector at a time.
+// Block 0 (slot 0 at f == 0) also sums the M_r products, one vector at a time, and folds them
+// in per wave group before the reduction, as the single-vector kernel does.
 template <typename T, int NY, int V>
 __global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
 k_col_G_batch(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, int LG, int kb,
@@ -572,8 +583,8 @@ k_col_G_batch(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, i
     }
   } else {
     // block 0: every vector in turn (the same per-vector operation order), with the M_r sums
-    // beside the main ones; each vector's two sums are reduced before the next vector starts
-    cplx<T> mine[8], mred[8];
+    // beside the main ones, folded in per wave group before each vector's reduction
+    cplx<T> mine[8];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       const bool okv = ok && vec0 + v < kb;
@@ -602,7 +613,16 @@ k_col_G_batch(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, i
           am[u] = cadd<T>(am[u], cmul<T>(xv[u], mv[u]));
         }
       }
+      group_sync<TPF>();
+#pragma unroll
+      for (int u = 0; u < 8; ++u) buf[pad8(j + u * TPF)] = am[u];
+      group_sync<TPF>();
+      if (f == 0) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = cadd<T>(a[u], cconj<T>(buf[pad8((NY - j - u * TPF) & (NY - 1))]));
+      }
       // wave-group order 0, 1, ..., as in the single-vector kernel
+      __syncthreads();
 #pragma unroll
       for (int u = 0; u < 8; ++u) buf[j + u * TPF] = a[u];
       __syncthreads();
@@ -616,29 +636,8 @@ k_col_G_batch(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, i
         }
       }
       __syncthreads();
-#pragma unroll
-      for (int u = 0; u < 8; ++u) buf[j + u * TPF] = am[u];
-      __syncthreads();
-      if (w == v) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) mred[u] = v == 0 ? am[u] : sh[f * Ff::LDS + j + u * TPF];
-        for (int w2 = 1; w2 < WPB; ++w2) {
-          const cplx<T> *o = sh + (w2 * CC::CPB + f) * Ff::LDS;
-#pragma unroll
-          for (int u = 0; u < 8; ++u) mred[u] = cadd<T>(mred[u], w2 == v ? am[u] : o[j + u * TPF]);
-        }
-      }
-      __syncthreads();
     }
     if (w >= V || vec0 + w >= kb) return;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) buf[pad8(j + u * TPF)] = mred[u];
-    group_sync<TPF>();
-    if (f == 0) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) mine[u] = cadd<T>(mine[u], cconj<T>(buf[pad8((NY - j - u * TPF) & (NY - 1))]));
-    }
-    group_sync<TPF>();
     Fi::run_tw(mine, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
     if (ok) {
       cplx<T> *dst = outp + (((vec0 + w) * LG + g) * HC + kx) * (int64_t)lds;
