@@ -27,8 +27,10 @@ namespace ff {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kRowsPerBlock = 512;    // rows of a basis per block of the transposed products
-constexpr int kColsPerBlock = 32;     // columns of a basis per block of the transposed products
+constexpr int kTLoads = 4;                 // row loads per lane in the transposed products
+constexpr int kTCols = 16;                 // basis columns per block of the transposed products
+constexpr int kRowsMin = 64 * kTLoads;     // rows per transposed-product block at one row per load
+constexpr int kNWaves = 8;                 // waves per block of the basis products A c
 constexpr int kUpreGrid = 400;
 constexpr double kUpreLo = 1e-3;
 constexpr double kGoldenTol = 1e-10;
@@ -93,23 +95,25 @@ __global__ void k_axpy_dev(double *__restrict__ y, const double *__restrict__ x,
 }
 
 // partial[p][j] = sum over the rows of row block p of A[row, j] * x[row]  (A column-major, ld
-// lda).  A block covers kRowsPerBlock rows and kColsPerBlock columns; each of its four waves
-// takes kColsPerBlock/4 columns, each lane kRowsPerBlock/64 rows (x held in registers).
-// Grid: (ceil(nrows / kRowsPerBlock), ceil(ncols / kColsPerBlock)).
+// lda).  Each lane loads RPL consecutive rows at once (RPL = 2: 16-byte loads), kTLoads times,
+// so a block covers kRowsMin * RPL rows and kTCols columns; each of its four waves takes
+// kTCols/4 columns (x held in registers).  Grid: (ceil(nrows / (kRowsMin * RPL)), ceil(ncols / kTCols)).
+template <int RPL>
 __global__ void __launch_bounds__(kThreads)
 k_gemv_t_partial(const double *__restrict__ A, int64_t lda, int64_t nrows, int ncols, const double *__restrict__ x,
                  double *__restrict__ part) {
-  constexpr int K = kRowsPerBlock / 64;
-  constexpr int CW = kColsPerBlock / (kThreads / 64);
+  constexpr int K = kTLoads, CW = kTCols / (kThreads / 64);
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int64_t r0 = (int64_t)blockIdx.x * kRowsPerBlock;
-  double xv[K];
+  const int64_t r0 = (int64_t)blockIdx.x * kRowsMin * RPL;
+  double xv[K][RPL];
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int64_t r = r0 + l + 64 * k;
-    xv[k] = r < nrows ? x[r] : 0.0;
-  }
-  const int c0 = blockIdx.y * kColsPerBlock + w * CW;
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int64_t r = r0 + (int64_t)(l + 64 * k) * RPL + q;
+      xv[k][q] = r < nrows ? x[r] : 0.0;
+    }
+  const int c0 = blockIdx.y * kTCols + w * CW;
   double s[CW];
 #pragma unroll
   for (int c = 0; c < CW; ++c) {
@@ -119,8 +123,20 @@ k_gemv_t_partial(const double *__restrict__ A, int64_t lda, int64_t nrows, int n
       const double *a = A + (int64_t)j * lda;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const int64_t r = r0 + l + 64 * k;
-        if (r < nrows) s[c] += a[r] * xv[k];
+        const int64_t r = r0 + (int64_t)(l + 64 * k) * RPL;
+        if (r + RPL <= nrows) {
+          if constexpr (RPL == 2) {
+            const double2 p = *(const double2 *)(a + r);
+            s[c] += p.x * xv[k][0];
+            s[c] += p.y * xv[k][1];
+          } else {
+            s[c] += a[r] * xv[k][0];
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < RPL; ++q)
+            if (r + q < nrows) s[c] += a[r + q] * xv[k][q];
+        }
       }
     }
   }
@@ -152,24 +168,68 @@ k_colsum(const double *__restrict__ part, int P, int ncols, double *__restrict__
   }
 }
 
-// y = beta * y + alpha * A c   (A column-major nrows x ncols, ld lda; c staged through LDS)
-__global__ void __launch_bounds__(kThreads)
+// y = beta * y + alpha * A c   (A column-major nrows x ncols, ld lda).  A block of kNWaves waves
+// covers 64 * RPL rows (RPL consecutive rows per lane, 16-byte loads when RPL = 2); wave w takes
+// the columns [w ncols / kNWaves, (w + 1) ncols / kNWaves), so that many column loads of a lane
+// are in flight; the waves' sums meet in LDS and are added in wave order.
+// Grid: ceil(nrows / (64 * RPL)) blocks of 64 * kNWaves threads.
+template <int RPL>
+__global__ void __launch_bounds__(64 * kNWaves)
 k_gemv_n(const double *__restrict__ A, int64_t lda, int64_t nrows, int ncols, const double *__restrict__ c,
          double *__restrict__ y, double alpha, double beta) {
-  __shared__ double cs[2048];
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double s = 0.0;
-  for (int j0 = 0; j0 < ncols; j0 += 2048) {
-    const int nj = ncols - j0 < 2048 ? ncols - j0 : 2048;
-    __syncthreads();
-    for (int j = threadIdx.x; j < nj; j += blockDim.x) cs[j] = c[j0 + j];
-    __syncthreads();
-    if (r < nrows) {
-      const double *a = A + (int64_t)j0 * lda + r;
-      for (int j = 0; j < nj; ++j) s += a[(int64_t)j * lda] * cs[j];
+  __shared__ double red[kNWaves][64 * RPL];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t r = ((int64_t)blockIdx.x * 64 + l) * RPL;
+  const int j0 = (int)((int64_t)ncols * w / kNWaves), j1 = (int)((int64_t)ncols * (w + 1) / kNWaves);
+  double s[RPL];
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) s[q] = 0.0;
+  if (r + RPL <= nrows) {
+    const double *a = A + r;
+    int j = j0;
+    for (; j + 4 <= j1; j += 4) {
+      double v[4][RPL];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if constexpr (RPL == 2) {
+          const double2 p = *(const double2 *)(a + (int64_t)(j + t) * lda);
+          v[t][0] = p.x;
+          v[t][1] = p.y;
+        } else {
+          v[t][0] = a[(int64_t)(j + t) * lda];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const double cj = c[j + t];
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) s[q] += v[t][q] * cj;
+      }
+    }
+    for (; j < j1; ++j) {
+      const double cj = c[j];
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) s[q] += a[(int64_t)j * lda + q] * cj;
+    }
+  } else {
+    for (int j = j0; j < j1; ++j) {
+      const double cj = c[j];
+#pragma unroll
+      for (int q = 0; q < RPL; ++q)
+        if (r + q < nrows) s[q] += A[(int64_t)j * lda + r + q] * cj;
     }
   }
-  if (r < nrows) y[r] = (beta == 0.0 ? 0.0 : beta * y[r]) + alpha * s;
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) red[w][l * RPL + q] = s[q];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * RPL; e += 64 * kNWaves) {
+    const int64_t rr = (int64_t)blockIdx.x * 64 * RPL + e;
+    if (rr < nrows) {
+      double t = red[0][e];
+      for (int q = 1; q < kNWaves; ++q) t += red[q][e];
+      y[rr] = (beta == 0.0 ? 0.0 : beta * y[rr]) + alpha * t;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -407,7 +467,13 @@ unsigned grid_for(int64_t n, int threads = kThreads, int64_t cap = 4096) {
   return (unsigned)g;
 }
 
-int partials_for(int64_t nrows) { return (int)((nrows + kRowsPerBlock - 1) / kRowsPerBlock); }
+// Rows per lane load of the basis products: two (16-byte loads) when every column start of the
+// basis is 16-byte aligned.
+int rows_per_load(const double *Q, int64_t ld) { return (ld % 2 == 0 && ((uintptr_t)Q & 15) == 0) ? 2 : 1; }
+int partials_for(int64_t nrows, int rpl) {
+  const int64_t rows = (int64_t)kRowsMin * rpl;
+  return (int)((nrows + rows - 1) / rows);
+}
 
 // rocBLAS handle per device, created on first use
 rocblas_handle blas(hipStream_t s, ff_status *st) {
@@ -451,16 +517,36 @@ struct Arena {
   }
 };
 
+// out = Q^T v (partials in part, then summed) and y = beta y + alpha Q c, with the launch shapes
+// of the kernels above.
+void launch_gemv_t(const double *Q, int64_t ld, int64_t nrows, int ncols, const double *v, double *out, double *part,
+                   hipStream_t s) {
+  const int rpl = rows_per_load(Q, ld);
+  const int P = partials_for(nrows, rpl);
+  const dim3 gt(P, (ncols + kTCols - 1) / kTCols);
+  if (rpl == 2)
+    k_gemv_t_partial<2><<<gt, kThreads, 0, s>>>(Q, ld, nrows, ncols, v, part);
+  else
+    k_gemv_t_partial<1><<<gt, kThreads, 0, s>>>(Q, ld, nrows, ncols, v, part);
+  k_colsum<<<(ncols + 63) / 64, kThreads, 0, s>>>(part, P, ncols, out, 1.0);
+}
+
+void launch_gemv_n(const double *Q, int64_t ld, int64_t nrows, int ncols, const double *c, double *y, double alpha,
+                   double beta, hipStream_t s) {
+  // paired rows pay off on long bases; short ones want more blocks
+  if (rows_per_load(Q, ld) == 2 && nrows >= 32768)
+    k_gemv_n<2><<<(unsigned)((nrows + 127) / 128), 64 * kNWaves, 0, s>>>(Q, ld, nrows, ncols, c, y, alpha, beta);
+  else
+    k_gemv_n<1><<<(unsigned)((nrows + 63) / 64), 64 * kNWaves, 0, s>>>(Q, ld, nrows, ncols, c, y, alpha, beta);
+}
+
 // v <- (I - Q Q^T)^2 v over the first ncols columns of Q (classical Gram-Schmidt, twice)
 ff_status reorth(const double *Q, int64_t ld, int64_t nrows, int ncols, double *v, double *coef, double *part,
                  hipStream_t s) {
   if (ncols <= 0) return FF_OK;
-  const int P = partials_for(nrows);
-  const dim3 gt(P, (ncols + kColsPerBlock - 1) / kColsPerBlock);
   for (int pass = 0; pass < 2; ++pass) {
-    k_gemv_t_partial<<<gt, kThreads, 0, s>>>(Q, ld, nrows, ncols, v, part);
-    k_colsum<<<(ncols + 63) / 64, kThreads, 0, s>>>(part, P, ncols, coef, 1.0);
-    k_gemv_n<<<grid_for(nrows, kThreads, 1 << 30), kThreads, 0, s>>>(Q, ld, nrows, ncols, coef, v, -1.0, 1.0);
+    launch_gemv_t(Q, ld, nrows, ncols, v, coef, part, s);
+    launch_gemv_n(Q, ld, nrows, ncols, coef, v, -1.0, 1.0, s);
   }
   FF_LAUNCH_CHECK("reorthogonalization");
   return FF_OK;
@@ -469,7 +555,7 @@ ff_status reorth(const double *Q, int64_t ld, int64_t nrows, int ncols, double *
 // y = alpha * Q c   (Q nrows x ncols)
 ff_status gemv_n(const double *Q, int64_t ld, int64_t nrows, int ncols, const double *c, double *y, double alpha,
                  hipStream_t s) {
-  k_gemv_n<<<grid_for(nrows, kThreads, 1 << 30), kThreads, 0, s>>>(Q, ld, nrows, ncols, c, y, alpha, 0.0);
+  launch_gemv_n(Q, ld, nrows, ncols, c, y, alpha, 0.0, s);
   FF_LAUNCH_CHECK("gemv");
   return FF_OK;
 }
@@ -477,10 +563,7 @@ ff_status gemv_n(const double *Q, int64_t ld, int64_t nrows, int ncols, const do
 // out = Q^T v   (ncols values)
 ff_status gemv_t(const double *Q, int64_t ld, int64_t nrows, int ncols, const double *v, double *out, double *part,
                  hipStream_t s) {
-  const int P = partials_for(nrows);
-  const dim3 gt(P, (ncols + kColsPerBlock - 1) / kColsPerBlock);
-  k_gemv_t_partial<<<gt, kThreads, 0, s>>>(Q, ld, nrows, ncols, v, part);
-  k_colsum<<<(ncols + 63) / 64, kThreads, 0, s>>>(part, P, ncols, out, 1.0);
+  launch_gemv_t(Q, ld, nrows, ncols, v, out, part, s);
   FF_LAUNCH_CHECK("gemv_t");
   return FF_OK;
 }
@@ -499,7 +582,7 @@ struct GkbWs {
   double *A, *H, *b, *c, *gamma, *beta, *ginv, *binv, *coef, *part, *dT, *eT, *C, *S, *V, *u0, *g, *w, *alpha;
   rocblas_int *info;
   void carve(Arena &a, int64_t n, int64_t m, int tp) {
-    const int64_t P = (n > m ? n : m + kRowsPerBlock - 1) / kRowsPerBlock + 1;
+    const int64_t P = ((n > m ? n : m) + kRowsMin - 1) / kRowsMin + 1;   // partial rows at one row per load
     A = a.take<double>((size_t)n * tp);
     H = a.take<double>((size_t)m * (tp + 1));
     b = a.take<double>(n);
@@ -528,7 +611,7 @@ struct RsvdWs {
   int *perm;
   rocblas_int *info;
   void carve(Arena &a, int64_t n, int64_t m, int tp) {
-    const int64_t P = (n > m ? n : m + kRowsPerBlock - 1) / kRowsPerBlock + 1;
+    const int64_t P = ((n > m ? n : m) + kRowsMin - 1) / kRowsMin + 1;   // partial rows at one row per load
     Q = a.take<double>((size_t)n * tp);     // n x tp (also holds the m x tp factors)
     Bm = a.take<double>((size_t)m * tp);    // G~ Q
     Y = a.take<double>((size_t)tp * tp);    // B^T B, then its eigenvectors
