@@ -8,8 +8,6 @@
 namespace ff {
 namespace {
 
-// vectors per block of the batched column passes (each spectrum column read once per group)
-constexpr int kVecPerBlock = 4;
 
 // Row-pass launch: full-size blocks (RowMax transforms, 2*NF rows, written back as 2*NF-row
 // contiguous segments) when the pass has at least 2048 rows, else one transform (two rows)
@@ -65,10 +63,10 @@ ff_status run_pass(ff_spectra h, int transpose, int pass, int kb, const TI *X, i
     } else if (pass == 1) {
       FF_SWITCH_N(h->NY, {
         using CC = ColCfg<T, NN>;
-        if constexpr (std::is_same<T, float>::value && CC::WPB >= kVecPerBlock) {
+        if constexpr (BatchCfg<T, NN>::OK) {
           if (kb > 1) {
-            dim3 g((HC + CC::CPB - 1) / CC::CPB, LG, (kb + kVecPerBlock - 1) / kVecPerBlock);
-            k_col_G_batch<T, NN, kVecPerBlock><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, ldy, nz, HC, LG, kb, spec,
+            dim3 g((HC + CC::CPB - 1) / CC::CPB, LG, (kb + BatchCfg<T, NN>::V - 1) / BatchCfg<T, NN>::V);
+            k_col_G_batch<T, NN><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, ldy, nz, HC, LG, kb, spec,
                                                                                     C2, sy, lds, h->pyl, twy);
             break;
           }
@@ -91,10 +89,10 @@ ff_status run_pass(ff_spectra h, int transpose, int pass, int kb, const TI *X, i
     } else if (pass == 1) {
       FF_SWITCH_N(h->NY, {
         using CC = ColCfg<T, NN>;
-        if constexpr (std::is_same<T, float>::value && CC::WPB >= kVecPerBlock) {
+        if constexpr (BatchCfg<T, NN>::OK) {
           if (kb > 1) {
-            dim3 g((HC + CC::CPB - 1) / CC::CPB, LG, (kb + kVecPerBlock - 1) / kVecPerBlock);
-            k_col_GT_batch<T, NN, kVecPerBlock><<<g, CC::THREADS * CC::WPB, 0, s>>>(C2, sy, lds, h->pyl, nz, HC, LG, kb,
+            dim3 g((HC + CC::CPB - 1) / CC::CPB, LG, (kb + BatchCfg<T, NN>::V - 1) / BatchCfg<T, NN>::V);
+            k_col_GT_batch<T, NN><<<g, CC::THREADS * CC::WPB, 0, s>>>(C2, sy, lds, h->pyl, nz, HC, LG, kb,
                                                                                      spec, X1, ny, ldy, twy);
             break;
           }
@@ -170,7 +168,7 @@ void prof_mark(ff_spectra h, int slot, int transpose, hipStream_t s) {
     h->prof_kind[h->prof_cur] = transpose;
   }
   if (h->prof_cur < 0) return;
-  hipEventRecord(h->prof_ev[4 * h->prof_cur + slot], s);
+  (void)hipEventRecord(h->prof_ev[4 * h->prof_cur + slot], s);   // best effort: a failed mark only loses a timing
 }
 
 ff_status op_time_pass(ff_spectra h, int transpose, int pass, int reps, const void *X, void *Y, hipStream_t s) {

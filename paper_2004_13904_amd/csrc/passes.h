@@ -12,6 +12,8 @@
 // contiguous columns and the row passes transpose through LDS.
 #pragma once
 
+#include <type_traits>
+
 #include "fft.h"
 
 namespace ff {
@@ -520,158 +522,128 @@ k_col_GT(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz, int H
 }
 
 // ---------------------------------------------------------------------------------------
-// Batched column passes: V vectors per block, so every spectrum column is read once per V
-// vectors (single precision, NY <= 512, several wave groups per block).  Results equal the
-// single-vector kernels' bit for bit: every vector sees the same operations in the same order.
+// Batched column passes (single precision, NY <= 512): V = 4 vectors per block.  The block's
+// WPB wave groups form GL = WPB/2 layer groups times 2 vector pairs: wave group w takes the
+// vectors 2p, 2p+1 (p = w mod 2) and the layers r0 + l, r0 + l + GL, ... (l = w / 2), so every
+// wave group does the same number of transforms (the layer split alone leaves some wave groups
+// with one layer more than others).  A spectrum column is loaded once per wave group for two
+// vectors.  Results agree with the single-vector kernels to rounding (the layer sums are taken
+// in another order).
+template <typename T, int NY> struct BatchCfg {
+  static constexpr int V = 4;                    // vectors per block
+  static constexpr int GV = 2;                   // vectors per wave group
+  static constexpr int GL = ColCfg<T, NY>::WPB / 2;   // layer groups
+  static constexpr bool OK = std::is_same<T, float>::value && ColCfg<T, NY>::TPF <= 64 &&
+                             ColCfg<T, NY>::WPB >= 4 && ColCfg<T, NY>::WPB % 2 == 0;
+};
 
-// Pass 2 of G for vectors vec0 .. vec0+V-1 (vec0 = blockIdx.z * V; vectors >= kb are skipped).
-// Wave group w takes layers r = r0 + w, r0 + w + WPB, ...; for each of its layers it loads the
-// spectrum column once and transforms the V vectors' columns.  Partial sums meet in LDS one
-// vector at a time; wave group (v mod WPB) adds them up and does vector v's inverse transform.
-// Block 0 (slot 0 at f == 0) also sums the M_r products, one vector at a time, and folds them
-// in per wave group before the reduction, as the single-vector kernel does.
-template <typename T, int NY, int V>
+// Pass 2 of G for vectors vec0 .. vec0+3 (vec0 = 4 blockIdx.z; vectors >= kb are skipped).
+// The partial sums of vector 2p + i sit in the wave groups 2l + p (l < GL); wave group 2i + p
+// adds them up in layer-group order and does the vector's inverse transform.  Block 0 (slot 0
+// at f == 0) also sums the M_r products and folds them in per wave group before the reduction.
+template <typename T, int NY>
 __global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
 k_col_G_batch(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, int LG, int kb,
               const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ outp, int sy, int lds, int pyl,
               const cplx<T> *__restrict__ tw) {
   using CC = ColCfg<T, NY>;
+  using BC = BatchCfg<T, NY>;
   using Ff = FFT<T, NY, false>;
   using Fi = FFT<T, NY, true>;
-  constexpr int TPF = CC::TPF, WPB = CC::WPB;
-  static_assert(WPB >= V, "one inverse transform per wave group");
-  static_assert(TPF <= 64, "wave-level synchronisation of a column");
-  __shared__ cplx<T> sh[WPB * CC::CPB * Ff::LDS];
+  constexpr int TPF = CC::TPF, GL = BC::GL;
+  static_assert(BC::OK, "batched column pass configuration");
+  __shared__ cplx<T> sh[CC::WPB * CC::CPB * Ff::LDS];
   const int w = threadIdx.x / CC::THREADS, lt = threadIdx.x % CC::THREADS;
   const int f = lt / TPF, j = lt % TPF;
+  const int p = w % 2, lgw = w / 2;
   const int kx = blockIdx.x * CC::CPB + f;
   const bool ok = kx < HC;
   const int kxs = ok ? kx : 0;
   const bool pk = blockIdx.x == 0;   // block-uniform
   const int64_t SH = HC + 1;
   const int g = blockIdx.y;
-  const int64_t vec0 = (int64_t)blockIdx.z * V;
+  const int64_t vec0 = (int64_t)blockIdx.z * BC::V;
   const int r0 = (int)((int64_t)g * nz / LG), r1 = (int)((int64_t)(g + 1) * nz / LG);
   cplx<T> *buf = sh + (w * CC::CPB + f) * Ff::LDS;
   typename Ff::Tw twr;
   Ff::load_tw(twr, j, tw);
-  cplx<T> acc[V][8];
+  cplx<T> acc[2][8], accm[2][8];
 #pragma unroll
-  for (int v = 0; v < V; ++v)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc[v][u] = mk<T>(0, 0);
-  if (!pk) {
-    for (int r = r0 + w; r < r1; r += WPB) {
-      cplx<T> sv[8];
-      const cplx<T> *sp = spec + ((int64_t)r * SH + kxs) * NY;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) sv[u] = sp[j + u * TPF];
-#pragma unroll
-      for (int v = 0; v < V; ++v) {
-        const bool okv = ok && vec0 + v < kb;
-        const cplx<T> *src = X1 + (((vec0 + v) * nz + r) * HC + kxs) * (int64_t)ldy;
-        cplx<T> xv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int y = j + u * TPF;
-          xv[u] = (okv && y < ny) ? src[y] : mk<T>(0, 0);
-        }
-        Ff::run_tw(xv, j, buf, twr);
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc[v][u] = cadd<T>(acc[v][u], cmul<T>(xv[u], sv[u]));
-      }
+    for (int u = 0; u < 8; ++u) {
+      acc[i][u] = mk<T>(0, 0);
+      accm[i][u] = mk<T>(0, 0);
     }
-  } else {
-    // block 0: every vector in turn (the same per-vector operation order), with the M_r sums
-    // beside the main ones, folded in per wave group before each vector's reduction
-    cplx<T> mine[8];
+  for (int r = r0 + lgw; r < r1; r += GL) {
+    cplx<T> sv[8], mv[8];
+    const cplx<T> *sp = spec + ((int64_t)r * SH + kxs) * NY;
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-      const bool okv = ok && vec0 + v < kb;
-      cplx<T> a[8], am[8];
+    for (int u = 0; u < 8; ++u) sv[u] = sp[j + u * TPF];
+    if (pk) {
+      const cplx<T> *mp = spec + ((int64_t)r * SH + HC) * NY;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) mv[u] = mp[j + u * TPF];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int64_t vec = vec0 + 2 * p + i;
+      const bool okv = ok && vec < kb;
+      const cplx<T> *src = X1 + ((vec * nz + r) * HC + kxs) * (int64_t)ldy;
+      cplx<T> xv[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        a[u] = mk<T>(0, 0);
-        am[u] = mk<T>(0, 0);
+        const int y = j + u * TPF;
+        xv[u] = (okv && y < ny) ? src[y] : mk<T>(0, 0);
       }
-      for (int r = r0 + w; r < r1; r += WPB) {
-        const cplx<T> *sp = spec + ((int64_t)r * SH + kxs) * NY;
-        const cplx<T> *mp = spec + ((int64_t)r * SH + HC) * NY;
-        const cplx<T> *src = X1 + (((vec0 + v) * nz + r) * HC + kxs) * (int64_t)ldy;
-        cplx<T> xv[8], sv[8], mv[8];
+      Ff::run_tw(xv, j, buf, twr);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int y = j + u * TPF;
-          xv[u] = (okv && y < ny) ? src[y] : mk<T>(0, 0);
-          sv[u] = sp[y];
-          mv[u] = mp[y];
-        }
-        Ff::run_tw(xv, j, buf, twr);
+      for (int u = 0; u < 8; ++u) acc[i][u] = cadd<T>(acc[i][u], cmul<T>(xv[u], sv[u]));
+      if (pk) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          a[u] = cadd<T>(a[u], cmul<T>(xv[u], sv[u]));
-          am[u] = cadd<T>(am[u], cmul<T>(xv[u], mv[u]));
-        }
+        for (int u = 0; u < 8; ++u) accm[i][u] = cadd<T>(accm[i][u], cmul<T>(xv[u], mv[u]));
       }
+    }
+  }
+  if (pk) {
+    // slot 0: acc[k] += conj(accm[-k]), per wave group and vector
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
       group_sync<TPF>();
 #pragma unroll
-      for (int u = 0; u < 8; ++u) buf[pad8(j + u * TPF)] = am[u];
+      for (int u = 0; u < 8; ++u) buf[pad8(j + u * TPF)] = accm[i][u];
       group_sync<TPF>();
       if (f == 0) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) a[u] = cadd<T>(a[u], cconj<T>(buf[pad8((NY - j - u * TPF) & (NY - 1))]));
-      }
-      // wave-group order 0, 1, ..., as in the single-vector kernel
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < 8; ++u) buf[j + u * TPF] = a[u];
-      __syncthreads();
-      if (w == v) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) mine[u] = v == 0 ? a[u] : sh[f * Ff::LDS + j + u * TPF];
-        for (int w2 = 1; w2 < WPB; ++w2) {
-          const cplx<T> *o = sh + (w2 * CC::CPB + f) * Ff::LDS;
-#pragma unroll
-          for (int u = 0; u < 8; ++u) mine[u] = cadd<T>(mine[u], w2 == v ? a[u] : o[j + u * TPF]);
-        }
-      }
-      __syncthreads();
-    }
-    if (w >= V || vec0 + w >= kb) return;
-    Fi::run_tw(mine, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
-    if (ok) {
-      cplx<T> *dst = outp + (((vec0 + w) * LG + g) * HC + kx) * (int64_t)lds;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int y = j + u * TPF - pyl;
-        if (y >= 0 && y < sy) dst[y] = mine[u];
+        for (int u = 0; u < 8; ++u)
+          acc[i][u] = cadd<T>(acc[i][u], cconj<T>(buf[pad8((NY - j - u * TPF) & (NY - 1))]));
       }
     }
-    return;
   }
-  // reduction over the wave groups, one vector per round
+  // two rounds: in round i the wave groups 2i and 2i + 1 collect the vectors 2p + i
   cplx<T> mine[8];
 #pragma unroll
-  for (int v = 0; v < V; ++v) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) buf[j + u * TPF] = acc[v][u];
+  for (int i = 0; i < 2; ++i) {
     __syncthreads();
-    if (w == v) {
-      // wave-group order 0, 1, ..., as in the single-vector kernel
 #pragma unroll
-      for (int u = 0; u < 8; ++u) mine[u] = v == 0 ? acc[v][u] : sh[f * Ff::LDS + j + u * TPF];
-      for (int w2 = 1; w2 < WPB; ++w2) {
-        const cplx<T> *o = sh + (w2 * CC::CPB + f) * Ff::LDS;
+    for (int u = 0; u < 8; ++u) buf[j + u * TPF] = acc[i][u];
+    __syncthreads();
+    if (lgw == i) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) mine[u] = cadd<T>(mine[u], w2 == v ? acc[v][u] : o[j + u * TPF]);
+      for (int u = 0; u < 8; ++u) mine[u] = sh[(p * CC::CPB + f) * Ff::LDS + j + u * TPF];
+      for (int l = 1; l < GL; ++l) {
+        const cplx<T> *o = sh + ((2 * l + p) * CC::CPB + f) * Ff::LDS;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) mine[u] = cadd<T>(mine[u], o[j + u * TPF]);
       }
     }
-    __syncthreads();
   }
-  if (w >= V || vec0 + w >= kb) return;
+  __syncthreads();
+  const int64_t vo = vec0 + 2 * p + lgw;   // the vector this wave group finishes (lgw < 2)
+  if (lgw >= 2 || vo >= kb) return;
   Fi::run_tw(mine, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
   if (ok) {
-    cplx<T> *dst = outp + (((vec0 + w) * LG + g) * HC + kx) * (int64_t)lds;
+    cplx<T> *dst = outp + ((vo * LG + g) * HC + kx) * (int64_t)lds;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int y = j + u * TPF - pyl;
@@ -680,24 +652,26 @@ k_col_G_batch(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, i
   }
 }
 
-// Pass 2 of G^T for vectors vec0 .. vec0+V-1: wave group v < V transforms vector v's data
-// column and shares it through LDS; then every wave group takes its layers, loads each
-// spectrum column once and forms the V products and inverse transforms.  Slot 0 reads the
-// reversed transform conj(D[-k]) from the same LDS copy.
-template <typename T, int NY, int V>
+// Pass 2 of G^T for vectors vec0 .. vec0+3: wave group v < 4 transforms vector v's data column
+// into LDS; then wave group w takes the vectors 2p, 2p+1 and the layers r0 + l + k GL as above,
+// loading each spectrum column once for its two products and inverse transforms.  Slot 0
+// reads the reversed transform conj(D[-k]) from the same LDS copy.
+template <typename T, int NY>
 __global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
 k_col_GT_batch(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz, int HC, int LG, int kb,
                const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ X1, int ny, int ldy,
                const cplx<T> *__restrict__ tw) {
   using CC = ColCfg<T, NY>;
+  using BC = BatchCfg<T, NY>;
   using Ff = FFT<T, NY, false>;
   using Fi = FFT<T, NY, true>;
-  constexpr int TPF = CC::TPF, WPB = CC::WPB;
-  static_assert(WPB >= V, "one forward transform per wave group");
-  __shared__ cplx<T> sh[WPB * CC::CPB * Ff::LDS];
-  __shared__ cplx<T> dsh[V * CC::CPB * NY];
+  constexpr int TPF = CC::TPF, GL = BC::GL;
+  static_assert(BC::OK, "batched column pass configuration");
+  __shared__ cplx<T> sh[CC::WPB * CC::CPB * Ff::LDS];
+  __shared__ cplx<T> dsh[BC::V * CC::CPB * NY];
   const int w = threadIdx.x / CC::THREADS, lt = threadIdx.x % CC::THREADS;
   const int f = lt / TPF, j = lt % TPF;
+  const int p = w % 2, lgw = w / 2;
   const int kx = blockIdx.x * CC::CPB + f;
   const bool ok = kx < HC;
   const int kxs = ok ? kx : 0;
@@ -705,12 +679,12 @@ k_col_GT_batch(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz,
   const bool pk0 = pk && f == 0;
   const int64_t SH = HC + 1;
   const int g = blockIdx.y;
-  const int64_t vec0 = (int64_t)blockIdx.z * V;
+  const int64_t vec0 = (int64_t)blockIdx.z * BC::V;
   const int r0 = (int)((int64_t)g * nz / LG), r1 = (int)((int64_t)(g + 1) * nz / LG);
   cplx<T> *buf = sh + (w * CC::CPB + f) * Ff::LDS;
   typename Ff::Tw twr;
   Ff::load_tw(twr, j, tw);
-  if (w < V) {
+  if (w < BC::V) {
     const bool okv = ok && vec0 + w < kb;
     const cplx<T> *src = D1 + ((vec0 + w) * HC + kxs) * (int64_t)ldd;
     cplx<T> dv[8];
@@ -724,12 +698,12 @@ k_col_GT_batch(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz,
     for (int u = 0; u < 8; ++u) dsh[(w * CC::CPB + f) * NY + j + u * TPF] = dv[u];
   }
   __syncthreads();
-  cplx<T> dh[V][8];
+  cplx<T> dh[2][8];
 #pragma unroll
-  for (int v = 0; v < V; ++v)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int u = 0; u < 8; ++u) dh[v][u] = dsh[(v * CC::CPB + f) * NY + j + u * TPF];
-  for (int r = r0 + w; r < r1; r += WPB) {
+    for (int u = 0; u < 8; ++u) dh[i][u] = dsh[((2 * p + i) * CC::CPB + f) * NY + j + u * TPF];
+  for (int r = r0 + lgw; r < r1; r += GL) {
     cplx<T> sv[8], mv[8];
     const cplx<T> *sp = spec + ((int64_t)r * SH + kxs) * NY;
 #pragma unroll
@@ -740,20 +714,21 @@ k_col_GT_batch(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz,
       for (int u = 0; u < 8; ++u) mv[u] = mp[j + u * TPF];
     }
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
+    for (int i = 0; i < 2; ++i) {
+      const int64_t vec = vec0 + 2 * p + i;
       cplx<T> xv[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) xv[u] = cmulc<T>(dh[v][u], sv[u]);
+      for (int u = 0; u < 8; ++u) xv[u] = cmulc<T>(dh[i][u], sv[u]);
       if (pk0) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          const cplx<T> dr = cconj<T>(dsh[(v * CC::CPB + f) * NY + ((NY - j - u * TPF) & (NY - 1))]);
+          const cplx<T> dr = cconj<T>(dsh[((2 * p + i) * CC::CPB + f) * NY + ((NY - j - u * TPF) & (NY - 1))]);
           xv[u] = cadd<T>(xv[u], cmulc<T>(dr, mv[u]));
         }
       }
       Fi::run_tw(xv, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
-      if (ok && vec0 + v < kb) {
-        cplx<T> *dst = X1 + (((vec0 + v) * nz + r) * HC + kx) * (int64_t)ldy;
+      if (ok && vec < kb) {
+        cplx<T> *dst = X1 + ((vec * nz + r) * HC + kx) * (int64_t)ldy;
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int y = j + u * TPF;

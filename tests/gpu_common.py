@@ -15,6 +15,18 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def same(a, b):
+    """Batched against single-vector results: bit-identical in FP64 (same kernels); in FP32 the
+    batched column passes add the layer terms in another order, so agreement is to rounding
+    (a few units of 2^-24 on the norm)."""
+    assert a.dtype == b.dtype and a.shape == b.shape
+    if a.dtype == torch.float64:
+        assert torch.equal(a, b)
+    else:
+        e = rel(to_host(a), to_host(b))
+        assert e <= 2e-6, e
+
+
 def announce(*parts):
     print("[case]", *parts, flush=True)
     sys.stdout.flush()

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_common import ogeom, rel, to_dev, to_host
+from gpu_common import ogeom, rel, same, to_dev, to_host
 from oracle import operator as op
 from paper_2004_13904_amd import workloads as W
 from paper_2004_13904_amd.operator import GOp, GTOp, Operator
@@ -114,5 +114,5 @@ def test_batched_forward_backward_equals_per_vector():
     w = torch.randn_like(Y)
     (Y * w).sum().backward()
     for c in range(4):
-        assert torch.equal(Y[c], A.G(models[c].contiguous()))
-        assert torch.equal(X.grad[c], A.GT(w[c].contiguous()))
+        same(Y[c], A.G(models[c].contiguous()))
+        same(X.grad[c], A.GT(w[c].contiguous()))
