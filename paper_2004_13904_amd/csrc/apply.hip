@@ -127,8 +127,9 @@ ff_status run(ff_spectra h, int transpose, int64_t k, const void *X, int64_t ldx
               const void *w_pre, const void *w_post, hipStream_t s) {
   const TIO *x = (const TIO *)X;
   TIO *y = (TIO *)Y;
-  for (int64_t c0 = 0; c0 < k; c0 += kMaxBatch) {
-    const int kb = (int)((k - c0) < kMaxBatch ? (k - c0) : kMaxBatch);
+  const int B = h->batch;
+  for (int64_t c0 = 0; c0 < k; c0 += B) {
+    const int kb = (int)((k - c0) < B ? (k - c0) : B);
     ff_status st = run_op<T, TIO, TIO>(h, transpose, kb, x + c0 * ldx, ldx, y + c0 * ldy, ldy, (const TIO *)w_pre,
                                        (const TIO *)w_post, s);
     if (st != FF_OK) return st;

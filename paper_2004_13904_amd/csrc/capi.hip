@@ -156,9 +156,13 @@ ff_status build_spectra(const ff_geometry *g, int32_t dtype, ff_stream stream, f
 
   const size_t cs = csize(dtype);
   const int64_t rows = h->ldy > h->lds ? h->ldy : h->lds;
-  h->ws_rows_bytes = cs * (size_t)kMaxBatch * h->nz * h->H * rows;
+  const size_t per_vec = cs * (size_t)h->nz * (NX / 2) * rows;   // row-pass intermediates of a vector
+  size_t b = kBatchBytes / per_vec;
+  b = b < (size_t)kMinBatch ? kMinBatch : b > (size_t)kMaxBatch ? kMaxBatch : b;
+  h->batch = (int)(b / 4 * 4);
+  h->ws_rows_bytes = cs * (size_t)h->batch * h->nz * h->H * rows;
   // room for the G partial sums of up to nz layer groups (ff_set_tuning may raise lg_G)
-  h->ws_cols_bytes = cs * (size_t)kMaxBatch * h->nz * h->H * h->lds;
+  h->ws_cols_bytes = cs * (size_t)h->batch * h->nz * h->H * h->lds;
   ff_status st = FF_OK;
   if (hipMalloc(&h->spec, cs * (size_t)h->nz * h->H * NY) != hipSuccess ||
       hipMalloc(&h->ws_rows, h->ws_rows_bytes) != hipSuccess ||

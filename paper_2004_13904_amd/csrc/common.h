@@ -72,9 +72,11 @@ ff_status hip_fail(hipError_t e, const char *what);
 
 inline bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
-// Largest number of vectors one batched operator launch processes (the handle's pass
-// workspace is sized for it).
-constexpr int kMaxBatch = 16;
+// Vectors per batched operator launch: each handle picks a batch (a multiple of 4 within
+// [kMinBatch, kMaxBatch]) whose row-pass intermediates fit in about kBatchBytes, so that the
+// column pass re-reads them from the last-level cache; its pass workspace is sized for it.
+constexpr int kMinBatch = 16, kMaxBatch = 64;
+constexpr size_t kBatchBytes = (size_t)96 << 20;
 
 }  // namespace ff
 
@@ -96,6 +98,7 @@ struct ff_spectra_s {
   void *spec = nullptr;              // [nz][H][NY] complex (float2 or double2), scaled by 1/(NX NY)
   void *tw_x = nullptr, *tw_y = nullptr;   // twiddle tables exp(-2 pi i e / N), e in [0, N)
   double *z_dev = nullptr;           // z_edges on the device
+  int batch = ff::kMinBatch;          // vectors per batched launch
   void *ws_rows = nullptr;           // batch x nz x H x max(ny, sy) complex: row-pass <-> column-pass
   void *ws_cols = nullptr;           // batch x LG x H x max(sy, ...) complex: column-pass partials / D1
   size_t ws_rows_bytes = 0, ws_cols_bytes = 0;
