@@ -25,6 +25,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X FP32 vector peak (256 CUs at 2.4 GHz)
 WORKLOAD = "magnetic_1m"
 
 
@@ -39,17 +40,18 @@ def pass_bytes(A, lg_G, lg_GT):
     sx, sy, nz = s["sx"], s["sy"], s["nz"]
     nx, ny = A.nx, A.ny
     NX, NY = A.nfft
-    H = NX // 2 + 1
+    H = NX // 2 + 1      # spectrum columns
+    HC = NX // 2         # intermediate column slots (DC and Nyquist share slot 0)
     c = 8  # complex64
     S = nz * H * NY * c
     n, m = A.n, A.m
-    X1 = nz * ny * H * c
+    X1 = nz * ny * HC * c
     return {
         "G.rows": 4 * n + X1,
-        "G.cols": X1 + S + lg_G * sy * H * c,
-        "G.irows": lg_G * sy * H * c + 4 * m,
-        "GT.rows": 4 * m + sy * H * c,
-        "GT.cols": sy * H * c + S + X1,
+        "G.cols": X1 + S + lg_G * sy * HC * c,
+        "G.irows": lg_G * sy * HC * c + 4 * m,
+        "GT.rows": 4 * m + sy * HC * c,
+        "GT.cols": sy * HC * c + S + X1,
         "GT.irows": X1 + 4 * n,
     }, S
 
@@ -239,21 +241,29 @@ def main(argv=None):
     return 0
 
 
+# the sources that define the operator's pass kernels and their launches
+PASS_SOURCES = ("apply.hip", "common.h", "fft.h", "passes.h")
+
+
+def pass_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2004_13904_amd", "csrc")
+    for name in PASS_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()
+
+
 def traffic_for(kernel):
     """HBM bytes per launch of a pass kernel from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources (hash of csrc/); else None."""
-    import hashlib
+    was taken on the current pass-kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic_magnetic_1m.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2004_13904_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode() + f.read())
-    if rec.get("csrc_sha256") != h.hexdigest():
+    if rec.get("pass_sources_sha256") != pass_sources_sha256():
         return None
     return rec.get("kernels", {}).get(kernel, {}).get("bytes")
 
@@ -291,6 +301,22 @@ def batched_leg(A, s, x_h, d_h, ms_pair_single, k=16):
             "speedup_vs_per_vector": round(ms_pair_single * k / ms, 3)}
 
 
+def fft_flops(A):
+    """Arithmetic of one G (or G^T) application by the three-pass method, counting 5 N log2 N
+    real flops per complex FFT of length N and 8 per complex product-accumulate: the row
+    transforms (two real rows per complex FFT) of the nz*ny model rows and the sy data rows,
+    nz forward and one inverse column FFT per column slot, and nz spectral products per column."""
+    s = A.survey
+    NX, NY = A.nfft
+    nz, sy = s["nz"], s["sy"]
+    HC = NX // 2
+    fx = 5 * NX * math.log2(NX)
+    fy = 5 * NY * math.log2(NY)
+    rows = (nz * A.ny + sy) / 2 * fx
+    cols = HC * ((nz + 1) * fy + nz * 8 * NY)
+    return int(rows + cols)
+
+
 def rsvd_block_leg(k=3750):
     """The RSVD block product: gravity 200 x 150 x 12 (n = 360000), G applied to k = 3750
     Gaussian vectors and G^T to k data vectors, FP32; algorithmic bytes 4nk + 4mk + S each."""
@@ -310,6 +336,7 @@ def rsvd_block_leg(k=3750):
     NX, NY = B.nfft
     S = s["nz"] * (NX // 2 + 1) * NY * 8
     balg = 4 * B.n * k + 4 * B.m * k + S
+    fl = fft_flops(B)
     ms_one = timed(lambda: B.G(X[0], out=Y[0]), 10)
     log(f"rsvd block k={k}: G {msG:.2f} ms, G^T {msT:.2f} ms")
     out = {"workload": "gravity_rsvd: 200x150 stations, nz=12, 20 m cubes, n=360000, k=3750 FP32 vectors",
@@ -317,6 +344,12 @@ def rsvd_block_leg(k=3750):
            "GBs_G": round(balg / (msG * 1e-3) / 1e9, 1), "GBs_GT": round(balg / (msT * 1e-3) / 1e9, 1),
            "frac_G": round(balg / (msG * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
            "frac_GT": round(balg / (msT * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           # the block products are bound by the FFT arithmetic, not by HBM
+           "alu": {"bound": "alu", "flops_per_vector": fl, "unit": "TFLOP/s", "peak": FP32_VECTOR_PEAK_TFLOPS,
+                   "achieved_G": round(fl * k / (msG * 1e-3) / 1e12, 2),
+                   "achieved_GT": round(fl * k / (msT * 1e-3) / 1e12, 2),
+                   "frac_G": round(fl * k / (msG * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4),
+                   "frac_GT": round(fl * k / (msT * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4)},
            "per_vector_loop_ms_G": round(ms_one * k, 3)}
     del X, Om, Y, Z
     B.close()
