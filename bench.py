@@ -64,6 +64,8 @@ def main(argv=None):
     ap.add_argument("--cold-reps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched / RSVD-block / IRLS legs")
+    ap.add_argument("--legs", default="batched,rsvd,multi,autograd,irls",
+                    help="comma list of extra legs (batched, rsvd, multi, autograd, irls)")
     ap.add_argument("--irls-steps", type=int, default=25)
     ap.add_argument("--calib", action="store_true",
                     help="end with a plain 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
@@ -220,10 +222,19 @@ def main(argv=None):
         "eager_ms_per_step": round(ms_eager, 6),
         "launch": "hipGraph replay of 20 pairs per graph (torch CUDA graph capture of the library's launches)",
     }
-    if not a.no_extra:
-        result["batched"] = batched_leg(A, s, x_h, d_h, ms_step)
-        result["rsvd_block"] = rsvd_block_leg()
+    result["hbm_copy"] = copy_bandwidth()
+    result["path_roofline"]["frac_of_copy"] = round(path_gbs / result["hbm_copy"]["GBs"], 4)
+    legs = set() if a.no_extra else set(a.legs.split(","))
+    check = not a.no_cpu
+    if "batched" in legs:
+        result["batched"] = batched_leg(A, s, x_h, d_h, ms_step, check=check)
+    if "rsvd" in legs:
+        result["rsvd_block"] = rsvd_block_leg(check=check)
+    if "multi" in legs:
         result["multi_survey"] = multi_survey_leg()
+    if "autograd" in legs:
+        result["autograd"] = autograd_leg(check=check)
+    if "irls" in legs:
         result["irls"] = irls_leg(a.irls_steps, lam=0.0)
         result["irls_l1"] = irls_leg(a.irls_steps, lam=1.0, stop=True)
 
@@ -282,9 +293,10 @@ def timed(fn, reps, warm=2):
     return e0.elapsed_time(e1) / reps
 
 
-def batched_leg(A, s, x_h, d_h, ms_pair_single, k=16):
+def batched_leg(A, s, x_h, d_h, ms_pair_single, k=16, check=True):
     """G and G^T on a block of k vectors in one call each (batched column passes reading each
-    spectrum column once per 4 vectors), against the per-vector pair time."""
+    spectrum column once per 4 vectors), against the per-vector pair time; the first column
+    checked against the oracle."""
     import torch
     g = torch.Generator(device="cuda").manual_seed(7)
     X = torch.rand(k, A.n, device="cuda", generator=g)
@@ -297,8 +309,126 @@ def batched_leg(A, s, x_h, d_h, ms_pair_single, k=16):
         A.G_block(D, transpose=True, out=Z)
     ms = timed(pair, 20)
     log(f"batched k={k}: {ms / k * 1e3:.2f} us per pair")
-    return {"k": k, "ms_per_block_pair": round(ms, 5), "pairs_per_s": round(k * 1e3 / ms, 1),
-            "speedup_vs_per_vector": round(ms_pair_single * k / ms, 3)}
+    out = {"k": k, "ms_per_block_pair": round(ms, 5), "pairs_per_s": round(k * 1e3 / ms, 1),
+           "speedup_vs_per_vector": round(ms_pair_single * k / ms, 3)}
+    if check:
+        out["rel_err_vs_oracle"] = oracle_errors(s, X[0], D[0], Y[0], Z[0])
+    return out
+
+
+def oracle_errors(s, x, d, gx, gtd):
+    """Relative l2 errors of one GPU G x and G^T d against the FP64 oracle's direct sums."""
+    from oracle import geometry, operator as op
+    g = geometry.Geometry(**s)
+    T = op.kernel_table(g)
+    xh = x.double().cpu().numpy()
+    dh = d.double().cpu().numpy()
+    ref_d = op.apply_G(g, xh, T)
+    ref_x = op.apply_GT(g, dh, T)
+    e = {"G": float(np.linalg.norm(gx.double().cpu().numpy() - ref_d) / np.linalg.norm(ref_d)),
+         "GT": float(np.linalg.norm(gtd.double().cpu().numpy() - ref_x) / np.linalg.norm(ref_x))}
+    log(f"oracle check: rel err G {e['G']:.2e} GT {e['GT']:.2e}")
+    return e
+
+
+def copy_bandwidth():
+    """Attainable HBM bandwidth on this machine: a 1 GiB device-to-device copy (read + write)."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    ms = timed(lambda: dst.copy_(src), 10)
+    gbs = 2 * src.numel() * 4 / (ms * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    log(f"copy: {gbs:.0f} GB/s")
+    return {"bytes": 2 * (1 << 30), "GBs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def autograd_leg(check=True, alpha=1.0, eps2=1e-9):
+    """The differentiable form: gravity 128 x 128 x 16 (n = 262144), batch of 4 random block
+    models, loss ||W_d (G m - d_obs)||^2 + alpha * sum m^2 / (m^2 + eps^2) through GOp (backward =
+    the G^T kernel), forward + backward timed against the plain block pair G X, G^T R; the
+    gradient of the first model checked against the oracle's direct sums."""
+    import torch
+
+    from paper_2004_13904_amd import workloads as W
+    from paper_2004_13904_amd.operator import GOp, Operator
+    s = W.SURVEYS["gravity_diff"]
+    A = Operator(s, torch.float32)
+    M = torch.tensor(W.gravity_diff_models(s, 4, seed=5), dtype=torch.float32, device="cuda")
+    d_ex = A.G_block(M).double().cpu().numpy()
+    noisy = [W.noise(d_ex[i], 0.01, 0.001, 6 + i) for i in range(4)]    # 1 % noise per model
+    d_obs = torch.tensor(np.stack([d_ex[i] + noisy[i][0] for i in range(4)]), dtype=torch.float32, device="cuda")
+    wd = torch.tensor(np.stack([1.0 / noisy[i][1] for i in range(4)]), dtype=torch.float32, device="cuda")
+    m0 = (0.5 * M).contiguous()
+
+    def fwd_bwd():
+        m = m0.clone().requires_grad_(True)
+        r = wd * (GOp.apply(A, m) - d_obs)
+        L = (r * r).sum() + alpha * (m * m / (m * m + eps2)).sum()
+        L.backward()
+        return m.grad
+    R = torch.randn(4, A.m, device="cuda")
+    Y = torch.empty(4, A.m, device="cuda")
+    Z = torch.empty(4, A.n, device="cuda")
+
+    def plain():
+        A.G_block(m0, out=Y)
+        A.G_block(R, transpose=True, out=Z)
+    ms_ad = timed(fwd_bwd, 20)
+    ms_plain = timed(plain, 20)
+    log(f"autograd: forward+backward {ms_ad * 1e3:.1f} us, plain block pair {ms_plain * 1e3:.1f} us")
+    out = {"workload": "gravity_diff: 128x128 stations, nz=16, 20 m cubes, n=262144, batch 4, FP32",
+           "ms_forward_backward": round(ms_ad, 5), "ms_plain_block_pair": round(ms_plain, 5),
+           "overhead_vs_plain": round(ms_ad / ms_plain, 3)}
+    # the same forward + backward captured once into a graph (the eager form is bound by the
+    # host launches of autograd's elementwise kernels); every replay is checked against eager
+    ref = fwd_bwd().clone()
+    sm = m0.clone().requires_grad_(True)
+
+    def loss_backward():
+        r = wd * (GOp.apply(A, sm) - d_obs)
+        L = (r * r).sum() + alpha * (sm * sm / (sm * sm + eps2)).sum()
+        L.backward()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(3):
+            sm.grad = None
+            loss_backward()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    sm.grad = None
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        loss_backward()
+    same = True
+    for _ in range(3):
+        plain()                       # unrelated eager work between replays
+        graph.replay()
+        torch.cuda.synchronize()
+        same = same and bool(torch.equal(sm.grad, ref))
+    if same:
+        ms_g = timed(graph.replay, 20)
+        out["ms_forward_backward_graph"] = round(ms_g, 5)
+        out["graph_overhead_vs_plain"] = round(ms_g / ms_plain, 3)
+        log(f"autograd in a graph: {ms_g * 1e3:.1f} us")
+    else:
+        out["ms_forward_backward_graph"] = None
+        log("autograd graph replay differs from eager: not timed")
+    if check:
+        from oracle import geometry, operator as op
+        grad = fwd_bwd()[0].double().cpu().numpy()
+        g = geometry.Geometry(**s)
+        T = op.kernel_table(g)
+        mh = m0[0].double().cpu().numpy()
+        wdh = wd[0].double().cpu().numpy()
+        res = wdh * (op.apply_G(g, mh, T) - d_obs[0].double().cpu().numpy())
+        ref = 2.0 * op.apply_GT(g, wdh * res, T) + alpha * 2.0 * mh * eps2 / (mh * mh + eps2) ** 2
+        out["grad_rel_err_vs_oracle"] = float(np.linalg.norm(grad - ref) / np.linalg.norm(ref))
+        log(f"autograd gradient rel err {out['grad_rel_err_vs_oracle']:.2e}")
+    A.close()
+    return out
 
 
 def fft_flops(A):
@@ -317,7 +447,7 @@ def fft_flops(A):
     return int(rows + cols)
 
 
-def rsvd_block_leg(k=3750):
+def rsvd_block_leg(k=3750, check=True):
     """The RSVD block product: gravity 200 x 150 x 12 (n = 360000), G applied to k = 3750
     Gaussian vectors and G^T to k data vectors, FP32; algorithmic bytes 4nk + 4mk + S each."""
     import torch
@@ -351,6 +481,8 @@ def rsvd_block_leg(k=3750):
                    "frac_G": round(fl * k / (msG * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4),
                    "frac_GT": round(fl * k / (msT * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4)},
            "per_vector_loop_ms_G": round(ms_one * k, 3)}
+    if check:
+        out["rel_err_vs_oracle"] = oracle_errors(s, X[0], Om[0], Y[0], Z[0])
     del X, Om, Y, Z
     B.close()
     torch.cuda.empty_cache()

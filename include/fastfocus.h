@@ -110,7 +110,9 @@ ff_status apply_GT(ff_spectra h, const void *d, void *x, const void *w_pre, cons
    Y = w_post .* G (w_pre .* X) for transpose = 0, Y = w_post .* G^T (w_pre .* X) for
    transpose = 1, for k column vectors.  X is column-major with leading dimension ldx
    (>= n, or >= m when transposed), Y likewise with ldy.  The weights apply to every column.
-   Vectors are processed in batched launches that read each spectrum tile once per batch. */
+   Vectors are processed in launches of up to the handle's batch (16 to 64 vectors, chosen at
+   build_spectra from the intermediates' size); in single precision the column passes take 4
+   vectors per block, which agree with the one-vector launches to rounding. */
 ff_status apply_G_block(ff_spectra h, int32_t transpose, int64_t k, const void *X, int64_t ldx,
                         void *Y, int64_t ldy, const void *w_pre, const void *w_post,
                         ff_stream stream);
