@@ -196,6 +196,25 @@ ff_status ff_profile_end(ff_spectra h, double *ms, int64_t *ops);
 ff_status ff_time_pass(ff_spectra h, int32_t transpose, int32_t pass, int32_t reps, const void *x, void *y,
                        ff_stream stream);
 
+/* ---------------------------------------------------------------------------------------
+   Several surveys at once (Sec. 2.4: the products are independent per column; here the columns
+   belong to different surveys).  A plan binds, for count single-precision handles of distinct
+   surveys, device vectors x[i] (n_i floats) -> gx[i] = G_i x[i] (m_i floats) and d[i] (m_i) ->
+   gtd[i] = G_i^T d[i] (n_i); either pair of a survey may be NULL to skip that product.
+   ff_multi_apply then computes all of them with three grouped launches on `stream`: every row
+   transform of every survey, every column pass, every inverse row transform.  Results equal
+   the handles' own apply_G / apply_GT.  Requirements: FP32 handles on the current device,
+   embeddings of at most 512 x 512 (FF_ENOTIMPL otherwise; use the per-handle calls), each
+   handle at most once (FF_EINVAL).  The plan copies its launch tables to the device
+   (ff_multi_create blocks for that copy) and holds no reference to host memory; it uses the
+   handles' pass workspaces, so no other call may use those handles while a multi apply runs.
+   The bound vectors and the handles must outlive the plan. */
+typedef struct ff_multi_s *ff_multi;
+ff_status ff_multi_create(int32_t count, const ff_spectra *handles, const void *const *x, void *const *gx,
+                          const void *const *d, void *const *gtd, ff_multi *out);
+ff_status ff_multi_apply(ff_multi plan, ff_stream stream);
+ff_status ff_multi_free(ff_multi plan);
+
 /* Thread-local message of the last failure ("" if none).  Valid until the next call. */
 const char *ff_last_error(void);
 

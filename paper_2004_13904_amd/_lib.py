@@ -21,7 +21,7 @@ STATUS = {0: "FF_OK", -1: "FF_EINVAL", -2: "FF_ESHAPE", -3: "FF_EDTYPE", -4: "FF
 EXPORTS = ["build_spectra", "ff_free_spectra", "ff_spectra_info", "ff_kernel_table", "apply_G",
            "apply_GT", "apply_G_block", "ff_workspace_size", "gkb_project", "rsvd_project",
            "irls_step", "ff_get_tuning", "ff_set_tuning", "ff_profile_begin", "ff_profile_end", "ff_time_pass",
-           "ff_last_error"]
+           "ff_multi_create", "ff_multi_apply", "ff_multi_free", "ff_last_error"]
 
 
 class FFGeometry(C.Structure):
@@ -81,6 +81,10 @@ def load(path=None):
         "ff_profile_begin": [vp, i32],
         "ff_time_pass": [vp, i32, i32, i32, vp, vp, vp],
         "ff_profile_end": [vp, dp, C.POINTER(i64)],
+        "ff_multi_create": [i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
+                            C.POINTER(vp)],
+        "ff_multi_apply": [vp, vp],
+        "ff_multi_free": [vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

@@ -90,17 +90,16 @@ template <class C> struct TileRow {
 // real DC and Nyquist bins as one complex value, DC + i Nyquist).  Rows are numbered across the nb batches (R = b*nrows + row), so a pass of nb*nrows rows
 // fills exactly ceil(nb*nrows/ROWS) blocks.  Grid: (ceil(nb*nrows/ROWS), 1, nvec).
 template <typename T, typename TI, int N, int NF, bool PACK = true>
-__global__ void __launch_bounds__((RowCfg<T, N, NF>::THREADS))
-k_row_r2c(const TI *__restrict__ in, Idx3 ii, const TI *__restrict__ pre, Idx3 pi, int nrows, int nb, int len,
+__device__ __forceinline__ void
+row_r2c_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const TI *__restrict__ in, Idx3 ii, const TI *__restrict__ pre, Idx3 pi, int nrows, int nb, int len,
           int off, cplx<T> *__restrict__ out, Idx3 oi, int64_t out_kx,
           const cplx<T> *__restrict__ tw) {
   using C = RowCfg<T, N, NF>;
   using F = FFT<T, N, false>;
-  __shared__ cplx<T> sh[C::SH];
   const int f = threadIdx.x / F::TPF, j = threadIdx.x % F::TPF;
-  const int64_t vec = blockIdx.z;
+  const int64_t vec = bz;
   const int total = nrows * nb;
-  const int R0 = blockIdx.x * C::ROWS;
+  const int R0 = bx * C::ROWS;
   const int ra = R0 + 2 * f, rb = ra + 1;
   const int ba = ra / nrows, qa = ra - ba * nrows, bb = rb / nrows, qb = rb - bb * nrows;
   cplx<T> v[8];
@@ -171,6 +170,15 @@ k_row_r2c(const TI *__restrict__ in, Idx3 ii, const TI *__restrict__ pre, Idx3 p
   }
 }
 
+template <typename T, typename TI, int N, int NF, bool PACK = true>
+__global__ void __launch_bounds__((RowCfg<T, N, NF>::THREADS))
+k_row_r2c(const TI *__restrict__ in, Idx3 ii, const TI *__restrict__ pre, Idx3 pi, int nrows, int nb, int len,
+          int off, cplx<T> *__restrict__ out, Idx3 oi, int64_t out_kx,
+          const cplx<T> *__restrict__ tw) {
+  __shared__ cplx<T> sh[RowCfg<T, N, NF>::SH];
+  row_r2c_body<T, TI, N, NF, PACK>(sh, blockIdx.x, blockIdx.y, blockIdx.z, in, ii, pre, pi, nrows, nb, len, off, out, oi, out_kx, tw);
+}
+
 // ---------------------------------------------------------------------------------------
 // Pass 3: half spectra (vec, b, c, row) in the N/2 packed column slots of pass 1, summed over
 // P partial buffers `pstride` apart, ->
@@ -178,17 +186,16 @@ k_row_r2c(const TI *__restrict__ in, Idx3 ii, const TI *__restrict__ pre, Idx3 p
 // vector stride).  Rows numbered across batches as in pass 1.
 // Grid: (ceil(nb*nrows/ROWS), 1, nvec).
 template <typename T, typename TO, int N, int NF>
-__global__ void __launch_bounds__((RowCfg<T, N, NF>::THREADS))
-k_row_c2r(const cplx<T> *__restrict__ in, Idx3 ii, int64_t in_kx, int64_t pstride, int P, int nrows, int nb,
+__device__ __forceinline__ void
+row_c2r_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<T> *__restrict__ in, Idx3 ii, int64_t in_kx, int64_t pstride, int P, int nrows, int nb,
           TO *__restrict__ out, Idx3 oi, const TO *__restrict__ post, Idx3 qi, int len, int off,
           const cplx<T> *__restrict__ tw) {
   using C = RowCfg<T, N, NF>;
   using F = FFT<T, N, true>;
-  __shared__ cplx<T> sh[C::SH];
   const int f = threadIdx.x / F::TPF, j = threadIdx.x % F::TPF;
-  const int64_t vec = blockIdx.z;
+  const int64_t vec = bz;
   const int total = nrows * nb;
-  const int R0 = blockIdx.x * C::ROWS;
+  const int R0 = bx * C::ROWS;
   cplx<T> *tile = sh;
   // every thread issues all of its tile loads before the first LDS write, so the global
   // load latencies overlap instead of adding up
@@ -263,6 +270,15 @@ k_row_c2r(const cplx<T> *__restrict__ in, Idx3 ii, int64_t in_kx, int64_t pstrid
   }
 }
 
+template <typename T, typename TO, int N, int NF>
+__global__ void __launch_bounds__((RowCfg<T, N, NF>::THREADS))
+k_row_c2r(const cplx<T> *__restrict__ in, Idx3 ii, int64_t in_kx, int64_t pstride, int P, int nrows, int nb,
+          TO *__restrict__ out, Idx3 oi, const TO *__restrict__ post, Idx3 qi, int len, int off,
+          const cplx<T> *__restrict__ tw) {
+  __shared__ cplx<T> sh[RowCfg<T, N, NF>::SH];
+  row_c2r_body<T, TO, N, NF>(sh, blockIdx.x, blockIdx.y, blockIdx.z, in, ii, in_kx, pstride, P, nrows, nb, out, oi, post, qi, len, off, tw);
+}
+
 // ---------------------------------------------------------------------------------------
 // Column passes.  The half spectrum along x has NX/2 + 1 columns, of which kx = 0 (DC) and
 // kx = NX/2 (Nyquist) hold real sequences along y (the rows are real).  The row passes store
@@ -287,24 +303,23 @@ k_row_c2r(const cplx<T> *__restrict__ in, Idx3 ii, int64_t in_kx, int64_t pstrid
 // group 0 does the inverse transform.
 // Grid: (ceil(HC/CPB), LG, nvec).
 template <typename T, int NY>
-__global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
-k_col_G(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, int LG,
+__device__ __forceinline__ void
+col_G_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, int LG,
         const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ outp, int sy, int lds, int pyl,
         const cplx<T> *__restrict__ tw) {
   using CC = ColCfg<T, NY>;
   using Ff = FFT<T, NY, false>;
   using Fi = FFT<T, NY, true>;
   constexpr int TPF = CC::TPF, WPB = CC::WPB;
-  __shared__ cplx<T> sh[WPB * CC::CPB * Ff::LDS];
   const int w = threadIdx.x / CC::THREADS, lt = threadIdx.x % CC::THREADS;
   const int f = lt / TPF, j = lt % TPF;
-  const int kx = blockIdx.x * CC::CPB + f;
+  const int kx = bx * CC::CPB + f;
   const bool ok = kx < HC;
   const int kxs = ok ? kx : 0;
-  const bool pk = blockIdx.x == 0;   // block-uniform: this block holds the packed slot 0 (f == 0)
+  const bool pk = bx == 0;   // block-uniform: this block holds the packed slot 0 (f == 0)
   const int64_t SH = HC + 1;         // spectrum columns
-  const int g = blockIdx.y;
-  const int64_t vec = blockIdx.z;
+  const int g = by;
+  const int64_t vec = bz;
   const int r0 = (int)((int64_t)g * nz / LG), r1 = (int)((int64_t)(g + 1) * nz / LG);
   cplx<T> *buf = sh + (w * CC::CPB + f) * Ff::LDS;
   typename Ff::Tw twr;
@@ -415,31 +430,39 @@ k_col_G(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, int LG,
   }
 }
 
+template <typename T, int NY>
+__global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
+k_col_G(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, int LG,
+        const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ outp, int sy, int lds, int pyl,
+        const cplx<T> *__restrict__ tw) {
+  __shared__ cplx<T> sh[ColCfg<T, NY>::WPB * ColCfg<T, NY>::CPB * FFT<T, NY, false>::LDS];
+  col_G_body<T, NY>(sh, blockIdx.x, blockIdx.y, blockIdx.z, X1, ny, ldy, nz, HC, LG, spec, outp, sy, lds, pyl, tw);
+}
+
 // Pass 2 of G^T: for each column slot c: D = FFT_y(D1[vec, c, :] placed at rows pyl..pyl+sy-1);
 // for each layer r of the group: X1[vec, r, c, q] = IFFT_y(conj(S_r[c, :]) .* D)[q], q < ny
 // (slot 0: conj(P_r) .* D + conj(M_r) .* conj(D[-k])).
 // Wave group w of a block takes every WPB-th layer of the group and transforms D itself.
 // Grid: (ceil(HC/CPB), LG, nvec).
 template <typename T, int NY>
-__global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
-k_col_GT(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz, int HC, int LG,
+__device__ __forceinline__ void
+col_GT_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz, int HC, int LG,
          const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ X1, int ny, int ldy,
          const cplx<T> *__restrict__ tw) {
   using CC = ColCfg<T, NY>;
   using Ff = FFT<T, NY, false>;
   using Fi = FFT<T, NY, true>;
   constexpr int TPF = CC::TPF, WPB = CC::WPB;
-  __shared__ cplx<T> sh[WPB * CC::CPB * Ff::LDS];
   const int w = threadIdx.x / CC::THREADS, lt = threadIdx.x % CC::THREADS;
   const int f = lt / TPF, j = lt % TPF;
-  const int kx = blockIdx.x * CC::CPB + f;
+  const int kx = bx * CC::CPB + f;
   const bool ok = kx < HC;
   const int kxs = ok ? kx : 0;
-  const bool pk = blockIdx.x == 0;        // block-uniform
+  const bool pk = bx == 0;        // block-uniform
   const bool pk0 = pk && f == 0;          // this lane's column is the packed slot 0
   const int64_t SH = HC + 1;
-  const int g = blockIdx.y;
-  const int64_t vec = blockIdx.z;
+  const int g = by;
+  const int64_t vec = bz;
   const int r0 = (int)((int64_t)g * nz / LG), r1 = (int)((int64_t)(g + 1) * nz / LG);
   if (r0 + w >= r1) return;   // no layer for this wave group (never with WPB = 1)
   cplx<T> *buf = sh + (w * CC::CPB + f) * Ff::LDS;
@@ -519,6 +542,15 @@ k_col_GT(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz, int H
       store(r, v);
     }
   }
+}
+
+template <typename T, int NY>
+__global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
+k_col_GT(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz, int HC, int LG,
+         const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ X1, int ny, int ldy,
+         const cplx<T> *__restrict__ tw) {
+  __shared__ cplx<T> sh[ColCfg<T, NY>::WPB * ColCfg<T, NY>::CPB * FFT<T, NY, false>::LDS];
+  col_GT_body<T, NY>(sh, blockIdx.x, blockIdx.y, blockIdx.z, D1, sy, ldd, pyl, nz, HC, LG, spec, X1, ny, ldy, tw);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -166,35 +166,85 @@ class GTOp(torch.autograd.Function):
 
 
 class SurveyBatch:
-    """Several surveys of uneven size applied together: every survey's G and G^T launches are
-    captured once into a single HIP graph (torch CUDA graph) and replayed as one launch.
+    """Several surveys of uneven size applied together.
 
-    ``xs`` / ``ds`` are the per-survey input tensors (model and data vectors); replay() refreshes
-    ``gx`` (G x_i) and ``gtd`` (G^T d_i) in place from the current contents of the inputs.
+    bind() builds a grouped plan (``ff_multi_create``): every survey's G x_i and G^T d_i then run
+    in three grouped launches (all row transforms, all column passes, all inverse row
+    transforms), captured once into a HIP graph (torch CUDA graph) and replayed.  Surveys the
+    grouped kernels do not cover (double precision, embeddings above 512 x 512) make the batch
+    fall back to one graph holding every survey's own launches.  ``xs`` / ``ds`` are the
+    per-survey inputs; replay() refreshes ``gx`` (G x_i) and ``gtd`` (G^T d_i) in place from their
+    current contents.
     """
 
     def __init__(self, surveys, dtype=torch.float32):
         self.ops = [Operator(s, dtype) for s in surveys]
         self.graph = None
+        self.plan = None
 
     def bind(self, xs, ds):
         self.xs, self.ds = list(xs), list(ds)
+        for op, x, d in zip(self.ops, self.xs, self.ds):
+            op._vec(x, op.n, "SurveyBatch")
+            op._vec(d, op.m, "SurveyBatch")
         self.gx = [op._new(op.m) for op in self.ops]
         self.gtd = [op._new(op.n) for op in self.ops]
+        self._free_plan()
+        n = len(self.ops)
+        arr = C.c_void_p * n
+        try:
+            plan = C.c_void_p()
+            L.call("ff_multi_create", n, arr(*[op.h.value for op in self.ops]),
+                   arr(*[t.data_ptr() for t in self.xs]), arr(*[t.data_ptr() for t in self.gx]),
+                   arr(*[t.data_ptr() for t in self.ds]), arr(*[t.data_ptr() for t in self.gtd]),
+                   C.byref(plan))
+            self.plan = plan
+        except L.FastFocusError as e:
+            if e.code not in (-3, -7):      # FF_EDTYPE, FF_ENOTIMPL: not covered, use per-survey launches
+                raise
+            self.plan = None
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
-            self.eager()
+            self.apply()
         torch.cuda.current_stream().wait_stream(side)
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
-            self.eager()
+            self.apply()
         return self
 
+    @property
+    def grouped_launches(self):
+        return self.plan is not None
+
+    def apply(self):
+        """All surveys' products on the current stream: grouped launches if planned, else eager."""
+        if self.plan is not None:
+            L.call("ff_multi_apply", self.plan, _stream())
+        else:
+            self.eager()
+
     def eager(self):
+        """Every survey's own G and G^T launches, one survey after another."""
         for op, x, d, a, b in zip(self.ops, self.xs, self.ds, self.gx, self.gtd):
             op.G(x, out=a)
             op.GT(d, out=b)
 
     def replay(self):
         self.graph.replay()
+
+    def _free_plan(self):
+        if self.plan is not None and self.plan.value:
+            L.load().ff_multi_free(self.plan)
+        self.plan = None
+
+    def close(self):
+        self._free_plan()
+        for op in self.ops:
+            op.close()
+
+    def __del__(self):
+        try:
+            self._free_plan()
+        except Exception:
+            pass

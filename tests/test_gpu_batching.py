@@ -22,6 +22,13 @@ def test_uneven_surveys_in_one_graph():
     xs = [torch.rand(o.n, device="cuda", generator=g) for o in B.ops]
     ds = [torch.randn(o.m, device="cuda", generator=g) for o in B.ops]
     B.bind(xs, ds)
+    assert B.grouped_launches          # all eight fit the grouped kernels (FP32, <= 512 x 512)
+    # the grouped launches without the graph
+    B.apply()
+    torch.cuda.synchronize()
+    for o, x, d, a, b in zip(B.ops, xs, ds, B.gx, B.gtd):
+        assert torch.equal(a, o.G(x))
+        assert torch.equal(b, o.GT(d))
     for rep in range(3):
         # new inputs between replays, eager work in between, every replay checked
         for x, d in zip(xs, ds):
@@ -38,6 +45,55 @@ def test_uneven_surveys_in_one_graph():
         T = op.kernel_table(gi)
         assert rel(to_host(B.gx[i]), op.apply_G(gi, to_host(xs[i]), T)) <= 1e-5
         assert rel(to_host(B.gtd[i]), op.apply_GT(gi, to_host(ds[i]), T)) <= 1e-5
+
+
+def test_grouped_plan_partial_products_and_fallback():
+    # G only for some surveys, G^T only for others; a layer-group tuning of 2; and an FP64 batch,
+    # which the grouped kernels do not take (per-survey launches instead)
+    surveys = W.uneven_surveys()[:4]
+    ops = [Operator(s, F32) for s in surveys]
+    ops[1].set_tuning(lg_G=2, lg_GT=2)
+    g = torch.Generator(device="cuda").manual_seed(1)
+    xs = [torch.rand(o.n, device="cuda", generator=g) for o in ops]
+    ds = [torch.randn(o.m, device="cuda", generator=g) for o in ops]
+    gx = [torch.full((o.m,), -1.0, device="cuda") for o in ops]
+    gtd = [torch.full((o.n,), -1.0, device="cuda") for o in ops]
+    import ctypes as C
+    from paper_2004_13904_amd import _lib as L
+    arr = C.c_void_p * 4
+    use_g, use_t = [True, True, False, True], [True, False, True, True]
+    plan = C.c_void_p()
+    L.call("ff_multi_create", 4, arr(*[o.h.value for o in ops]),
+           arr(*[x.data_ptr() if u else None for x, u in zip(xs, use_g)]),
+           arr(*[y.data_ptr() if u else None for y, u in zip(gx, use_g)]),
+           arr(*[d.data_ptr() if u else None for d, u in zip(ds, use_t)]),
+           arr(*[y.data_ptr() if u else None for y, u in zip(gtd, use_t)]), C.byref(plan))
+    L.call("ff_multi_apply", plan, C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    for o, x, d, a, b, ug, ut in zip(ops, xs, ds, gx, gtd, use_g, use_t):
+        if ug:
+            assert torch.equal(a, o.G(x))
+        else:
+            assert bool((a == -1.0).all())
+        if ut:
+            assert torch.equal(b, o.GT(d))
+        else:
+            assert bool((b == -1.0).all())
+    L.call("ff_multi_free", plan)
+    # the same handle twice is refused
+    with pytest.raises(L.FastFocusError):
+        L.call("ff_multi_create", 2, arr(ops[0].h.value, ops[0].h.value), arr(xs[0].data_ptr(), xs[0].data_ptr()),
+               arr(gx[0].data_ptr(), gx[0].data_ptr()), None, None, C.byref(plan))
+    B = SurveyBatch(surveys, torch.float64)
+    xs64 = [x.double() for x in xs]
+    ds64 = [d.double() for d in ds]
+    B.bind(xs64, ds64)
+    assert not B.grouped_launches
+    B.replay()
+    torch.cuda.synchronize()
+    for o, x, d, a, b in zip(B.ops, xs64, ds64, B.gx, B.gtd):
+        assert torch.equal(a, o.G(x))
+        assert torch.equal(b, o.GT(d))
 
 
 def test_autotune_picks_valid_tuning_and_keeps_results(tmp_path):
