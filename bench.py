@@ -236,7 +236,7 @@ def main(argv=None):
         "config": {"workload": f"{WORKLOAD}: magnetic TFA (I=D=45 deg), 250x200 stations, nz=20, "
                                f"20 m cubes, n=1000000, m=50000, embedding {NX}x{NY}, "
                                "m~U[0,1) seed 0, d~N(0,1) seed 1",
-                   "n": A.n, "m": A.m, "nfft": [NX, NY], "layer_groups": lg},
+                   "n": A.n, "m": A.m, "nfft": [NX, NY], "tuning": lg},
         "roofline": {"bound": "hbm", "kernel": dom, "kernel_us": round(per_pass_us[dom], 3),
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(dom)},

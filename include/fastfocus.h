@@ -169,12 +169,25 @@ ff_status irls_step(ff_spectra h, const ff_irls_params *p, const double *d_obs, 
                     double *m_new, double *alpha, double *chi2_scaled, void *workspace,
                     size_t ws_bytes, ff_stream stream);
 
-/* Launch tuning of a handle's column passes: the layers of every column are split over
-   lg_G (G) and lg_GT (G^T) groups of blocks (1 <= lg <= nz); the G partial sums of the groups
-   are added in the inverse row pass.  build_spectra picks values that fill the chip; an
-   autotuner may change them.  Results do not depend on them beyond rounding order. */
+/* Launch tuning of a handle (tile shapes and batch schedule; the FFT radices follow from the
+   embedding sizes: radix-8 passes with one radix-4 or radix-2 pass when log2 N is not a
+   multiple of 3).  build_spectra picks values that fill the chip; an autotuner may change them.
+   Results do not depend on them beyond rounding order.
+     lg_G, lg_GT   the layers of every column are split over this many groups of column-pass
+                   blocks (1 <= lg <= nz); the G partial sums of the groups are added in the
+                   inverse row pass.
+     row_tile      transforms per row-pass block: 0 = automatic (the largest tile that fits
+                   64 KB of LDS when a pass has at least 2048 rows, one transform otherwise),
+                   1 = always one transform (two rows), 2 = always the largest tile.
+     batch         vectors per launch of apply_G_block, 1 <= batch <= the batch the handle's
+                   workspace was sized for (the value build_spectra sets).
+     col_batched   1 = block applies use the 4-vectors-per-block column passes (single
+                   precision), 0 = one vector per column block. */
 typedef struct {
     int32_t lg_G, lg_GT;
+    int32_t row_tile;
+    int32_t batch;
+    int32_t col_batched;
 } ff_tuning;
 ff_status ff_get_tuning(ff_spectra h, ff_tuning *t);
 ff_status ff_set_tuning(ff_spectra h, const ff_tuning *t);

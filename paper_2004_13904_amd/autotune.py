@@ -1,10 +1,18 @@
-"""Launch autotuner for the operator's column passes.
+"""Launch autotuner of a handle: tile shapes and batch schedule.
 
-The only free launch parameters of a handle are the layer-group counts of the two column
-passes (``ff_set_tuning``): more groups give more waves but more partial sums (G) or more
-forward transforms (G^T).  ``autotune`` times every candidate on the caller's own vectors with
-HIP events, keeps the fastest, and caches the choice in a JSON file keyed by the embedding,
-layer count, survey size, dtype and batch width.
+The free launch parameters of a handle (``ff_set_tuning``; the FFT radices are fixed by the
+embedding sizes) are:
+
+* ``lg_G``, ``lg_GT``: layer groups of the two column passes (more groups give more waves but more
+  partial sums for G, more forward transforms for G^T);
+* ``row_tile``: transforms per row-pass block (automatic, one, or the largest that fits LDS);
+* ``batch`` and ``col_batched`` (block applies only): vectors per launch, and whether the column
+  passes take 4 vectors per block.
+
+``autotune`` times candidates on the caller's own vectors with HIP events (one G plus one G^T
+per trial), by coordinate descent over the parameters in that order, keeps the fastest, and
+caches the choice in a JSON file keyed by the embedding, layer count, survey size, dtype and
+batch width.
 """
 from __future__ import annotations
 
@@ -22,9 +30,8 @@ def _key(op, k):
     return f"{op.nfft[0]}x{op.nfft[1]}:nz{op.nz}:s{s['sx']}x{s['sy']}:n{op.nx}x{op.ny}:{op.dtype}:k{k}"
 
 
-def _candidates(nz):
-    c = sorted({1, 2, 3, 4, 5, 8, 10, nz} & set(range(1, nz + 1)))
-    return c
+def _lg_candidates(nz):
+    return sorted({1, 2, 3, 4, 5, 8, 10, nz} & set(range(1, nz + 1)))
 
 
 def _time(fn, reps=20):
@@ -40,8 +47,18 @@ def _time(fn, reps=20):
     return e0.elapsed_time(e1) / reps
 
 
-def autotune(op, x, d, cache=CACHE, use_cache=True):
-    """Pick lg_G and lg_GT for op on vectors x (n values or k x n) and d (m values or k x m).
+def candidates(op, batched):
+    """The values tried for each tuning key (dict key -> list), in search order."""
+    c = {"lg_G": _lg_candidates(op.nz), "lg_GT": _lg_candidates(op.nz), "row_tile": [0, 1, 2]}
+    if batched:
+        bmax = op.batch_max
+        c["batch"] = sorted({b for b in (4, 8, 16, 32, 64, bmax) if b <= bmax})
+        c["col_batched"] = [1, 0]
+    return c
+
+
+def autotune(op, x, d, cache=CACHE, use_cache=True, reps=20):
+    """Pick the launch tuning of op for vectors x (n values or k x n) and d (m values or k x m).
     Returns the chosen tuning dict (also applied to op)."""
     k = x.shape[0] if x.dim() == 2 else 1
     key = _key(op, k)
@@ -54,15 +71,25 @@ def autotune(op, x, d, cache=CACHE, use_cache=True):
             table = {}
     if key in table:
         op.set_tuning(**table[key])
-        return table[key]
+        return op.tuning
     batched = x.dim() == 2
-    G = (lambda: op.G_block(x)) if batched else (lambda: op.G(x))
-    GT = (lambda: op.G_block(d, transpose=True)) if batched else (lambda: op.GT(d))
-    cur = op.tuning
-    best_g = min(_candidates(op.nz), key=lambda lg: (op.set_tuning(lg_G=lg, lg_GT=cur["lg_GT"]), _time(G))[1])
-    best_t = min(_candidates(op.nz), key=lambda lg: (op.set_tuning(lg_G=best_g, lg_GT=lg), _time(GT))[1])
-    choice = {"lg_G": int(best_g), "lg_GT": int(best_t)}
-    op.set_tuning(**choice)
+    if batched:
+        def pair():
+            op.G_block(x)
+            op.G_block(d, transpose=True)
+    else:
+        def pair():
+            op.G(x)
+            op.GT(d)
+    for name, values in candidates(op, batched).items():
+        best, best_t = None, None
+        for v in values:
+            op.set_tuning(**{name: v})
+            t = _time(pair, reps)
+            if best_t is None or t < best_t:
+                best, best_t = v, t
+        op.set_tuning(**{name: best})
+    choice = op.tuning
     if cache:
         table[key] = choice
         try:

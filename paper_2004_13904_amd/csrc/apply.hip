@@ -9,14 +9,17 @@ namespace ff {
 namespace {
 
 
-// Row-pass launch: full-size blocks (RowMax transforms, 2*NF rows, written back as 2*NF-row
+// Row-pass tile: full-size blocks (RowMax transforms, 2*NF rows, written back as 2*NF-row
 // contiguous segments) when the pass has at least 2048 rows, else one transform (two rows)
-// per block so that small passes still spread over the chip.
+// per block so that small passes still spread over the chip; `tile` (the handle's row_tile)
+// can force either.
+inline bool big_row_tile(int tile, int64_t rows) { return tile == 2 || (tile == 0 && rows >= 2048); }
+
 template <typename T, typename TI, int N>
-void launch_r2c(int nrows, int nb, int kb, const TI *in, Idx3 ii, const TI *pre, Idx3 pi, int len, int off,
+void launch_r2c(int tile, int nrows, int nb, int kb, const TI *in, Idx3 ii, const TI *pre, Idx3 pi, int len, int off,
                 cplx<T> *out, Idx3 oi, int64_t out_kx, const cplx<T> *tw, hipStream_t s) {
   constexpr int NFM = RowMax<T, N>::NF;
-  if (NFM == 1 || (int64_t)nrows * nb * kb >= 2048) {
+  if (NFM == 1 || big_row_tile(tile, (int64_t)nrows * nb * kb)) {
     using C = RowCfg<T, N, NFM>;
     dim3 g((nrows * nb + C::ROWS - 1) / C::ROWS, 1, kb);
     k_row_r2c<T, TI, N, NFM><<<g, C::THREADS, 0, s>>>(in, ii, pre, pi, nrows, nb, len, off, out, oi, out_kx, tw);
@@ -28,10 +31,10 @@ void launch_r2c(int nrows, int nb, int kb, const TI *in, Idx3 ii, const TI *pre,
 }
 
 template <typename T, typename TO, int N>
-void launch_c2r(int nrows, int nb, int kb, const cplx<T> *in, Idx3 ii, int64_t in_kx, int64_t pstride, int P,
-                TO *out, Idx3 oi, const TO *post, Idx3 qi, int len, int off, const cplx<T> *tw, hipStream_t s) {
+void launch_c2r(int tile, int nrows, int nb, int kb, const cplx<T> *in, Idx3 ii, int64_t in_kx, int64_t pstride,
+                int P, TO *out, Idx3 oi, const TO *post, Idx3 qi, int len, int off, const cplx<T> *tw, hipStream_t s) {
   constexpr int NFM = RowMax<T, N>::NF;
-  if (NFM == 1 || (int64_t)nrows * nb * kb >= 2048) {
+  if (NFM == 1 || big_row_tile(tile, (int64_t)nrows * nb * kb)) {
     using C = RowCfg<T, N, NFM>;
     dim3 g((nrows * nb + C::ROWS - 1) / C::ROWS, 1, kb);
     k_row_c2r<T, TO, N, NFM><<<g, C::THREADS, 0, s>>>(in, ii, in_kx, pstride, P, nrows, nb, out, oi, post, qi, len, off, tw);
@@ -57,14 +60,14 @@ ff_status run_pass(ff_spectra h, int transpose, int pass, int kb, const TI *X, i
   if (!transpose) {
     const int LG = h->lg_G;
     if (pass == 0) {
-      FF_SWITCH_N(h->NX, launch_r2c<T, TI, NN>(ny, nz, kb, X, Idx3{ldx, lay, nx}, pre, Idx3{0, lay, nx}, nx, 0, X1,
+      FF_SWITCH_N(h->NX, launch_r2c<T, TI, NN>(h->row_tile, ny, nz, kb, X, Idx3{ldx, lay, nx}, pre, Idx3{0, lay, nx}, nx, 0, X1,
                                                Idx3{(int64_t)nz * HC * ldy, (int64_t)HC * ldy, 1}, ldy, twx, s));
       FF_LAUNCH_CHECK("G pass 1 (row transforms)");
     } else if (pass == 1) {
       FF_SWITCH_N(h->NY, {
         using CC = ColCfg<T, NN>;
         if constexpr (BatchCfg<T, NN>::OK) {
-          if (kb > 1) {
+          if (kb > 1 && h->col_batched) {
             dim3 g((HC + CC::CPB - 1) / CC::CPB, LG, (kb + BatchCfg<T, NN>::V - 1) / BatchCfg<T, NN>::V);
             k_col_G_batch<T, NN><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, ldy, nz, HC, LG, kb, spec,
                                                                                     C2, sy, lds, h->pyl, twy);
@@ -76,21 +79,21 @@ ff_status run_pass(ff_spectra h, int transpose, int pass, int kb, const TI *X, i
       });
       FF_LAUNCH_CHECK("G pass 2 (column transforms and spectral products)");
     } else {
-      FF_SWITCH_N(h->NX, launch_c2r<T, TO, NN>(sy, 1, kb, C2, Idx3{(int64_t)LG * HC * lds, 0, 1}, lds, (int64_t)HC * lds,
+      FF_SWITCH_N(h->NX, launch_c2r<T, TO, NN>(h->row_tile, sy, 1, kb, C2, Idx3{(int64_t)LG * HC * lds, 0, 1}, lds, (int64_t)HC * lds,
                                                LG, Y, Idx3{ldy_out, 0, sx}, post, Idx3{0, 0, sx}, sx, h->pxl, twx, s));
       FF_LAUNCH_CHECK("G pass 3 (inverse row transforms)");
     }
   } else {
     const int LG = h->lg_GT;
     if (pass == 0) {
-      FF_SWITCH_N(h->NX, launch_r2c<T, TI, NN>(sy, 1, kb, X, Idx3{ldx, 0, sx}, pre, Idx3{0, 0, sx}, sx, h->pxl, C2,
+      FF_SWITCH_N(h->NX, launch_r2c<T, TI, NN>(h->row_tile, sy, 1, kb, X, Idx3{ldx, 0, sx}, pre, Idx3{0, 0, sx}, sx, h->pxl, C2,
                                                Idx3{(int64_t)HC * lds, 0, 1}, lds, twx, s));
       FF_LAUNCH_CHECK("G^T pass 1 (row transforms)");
     } else if (pass == 1) {
       FF_SWITCH_N(h->NY, {
         using CC = ColCfg<T, NN>;
         if constexpr (BatchCfg<T, NN>::OK) {
-          if (kb > 1) {
+          if (kb > 1 && h->col_batched) {
             dim3 g((HC + CC::CPB - 1) / CC::CPB, LG, (kb + BatchCfg<T, NN>::V - 1) / BatchCfg<T, NN>::V);
             k_col_GT_batch<T, NN><<<g, CC::THREADS * CC::WPB, 0, s>>>(C2, sy, lds, h->pyl, nz, HC, LG, kb,
                                                                                      spec, X1, ny, ldy, twy);
@@ -102,7 +105,7 @@ ff_status run_pass(ff_spectra h, int transpose, int pass, int kb, const TI *X, i
       });
       FF_LAUNCH_CHECK("G^T pass 2 (column transforms and spectral products)");
     } else {
-      FF_SWITCH_N(h->NX, launch_c2r<T, TO, NN>(ny, nz, kb, X1, Idx3{(int64_t)nz * HC * ldy, (int64_t)HC * ldy, 1}, ldy, 0,
+      FF_SWITCH_N(h->NX, launch_c2r<T, TO, NN>(h->row_tile, ny, nz, kb, X1, Idx3{(int64_t)nz * HC * ldy, (int64_t)HC * ldy, 1}, ldy, 0,
                                                1, Y, Idx3{ldy_out, lay, nx}, post, Idx3{0, lay, nx}, nx, 0, twx, s));
       FF_LAUNCH_CHECK("G^T pass 3 (inverse row transforms)");
     }

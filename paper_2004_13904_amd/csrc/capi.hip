@@ -160,6 +160,7 @@ ff_status build_spectra(const ff_geometry *g, int32_t dtype, ff_stream stream, f
   size_t b = kBatchBytes / per_vec;
   b = b < (size_t)kMinBatch ? kMinBatch : b > (size_t)kMaxBatch ? kMaxBatch : b;
   h->batch = (int)(b / 4 * 4);
+  h->batch_max = h->batch;
   h->ws_rows_bytes = cs * (size_t)h->batch * h->nz * h->H * rows;
   // room for the G partial sums of up to nz layer groups (ff_set_tuning may raise lg_G)
   h->ws_cols_bytes = cs * (size_t)h->batch * h->nz * h->H * h->lds;
@@ -242,6 +243,9 @@ ff_status ff_get_tuning(ff_spectra h, ff_tuning *t) {
   if (!h || !t) return fail(FF_EINVAL, "ff_get_tuning: NULL argument");
   t->lg_G = h->lg_G;
   t->lg_GT = h->lg_GT;
+  t->row_tile = h->row_tile;
+  t->batch = h->batch;
+  t->col_batched = h->col_batched;
   return FF_OK;
 }
 
@@ -249,8 +253,15 @@ ff_status ff_set_tuning(ff_spectra h, const ff_tuning *t) {
   if (!h || !t) return fail(FF_EINVAL, "ff_set_tuning: NULL argument");
   if (t->lg_G < 1 || t->lg_G > h->nz || t->lg_GT < 1 || t->lg_GT > h->nz)
     return fail(FF_EINVAL, "ff_set_tuning: layer groups must lie in [1, nz]");
+  if (t->row_tile < 0 || t->row_tile > 2) return fail(FF_EINVAL, "ff_set_tuning: row_tile must be 0, 1 or 2");
+  if (t->batch < 1 || t->batch > h->batch_max)
+    return fail(FF_EINVAL, "ff_set_tuning: batch must lie in [1, the handle's workspace batch]");
+  if (t->col_batched != 0 && t->col_batched != 1) return fail(FF_EINVAL, "ff_set_tuning: col_batched must be 0 or 1");
   h->lg_G = t->lg_G;
   h->lg_GT = t->lg_GT;
+  h->row_tile = t->row_tile;
+  h->batch = t->batch;
+  h->col_batched = t->col_batched;
   return FF_OK;
 }
 

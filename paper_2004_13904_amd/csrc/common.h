@@ -98,7 +98,10 @@ struct ff_spectra_s {
   void *spec = nullptr;              // [nz][H][NY] complex (float2 or double2), scaled by 1/(NX NY)
   void *tw_x = nullptr, *tw_y = nullptr;   // twiddle tables exp(-2 pi i e / N), e in [0, N)
   double *z_dev = nullptr;           // z_edges on the device
-  int batch = ff::kMinBatch;          // vectors per batched launch
+  int batch = ff::kMinBatch;          // vectors per batched launch (tunable, <= batch_max)
+  int batch_max = ff::kMinBatch;      // vectors the pass workspace holds
+  int row_tile = 0;                   // 0 auto, 1 one transform per row block, 2 largest tile
+  int col_batched = 1;                // 4-vectors-per-block column passes for block applies
   void *ws_rows = nullptr;           // batch x nz x H x max(ny, sy) complex: row-pass <-> column-pass
   void *ws_cols = nullptr;           // batch x LG x H x max(sy, ...) complex: column-pass partials / D1
   size_t ws_rows_bytes = 0, ws_cols_bytes = 0;

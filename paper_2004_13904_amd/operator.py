@@ -46,16 +46,31 @@ class Operator:
         self.nx = s["sx"] + s.get("pad_xl", 0) + s.get("pad_xr", 0)
         self.ny = s["sy"] + s.get("pad_yl", 0) + s.get("pad_yr", 0)
         self.nz = s["nz"]
+        self._batch_max = self.tuning["batch"]
+
+    TUNING_KEYS = ("lg_G", "lg_GT", "row_tile", "batch", "col_batched")
+
+    @property
+    def batch_max(self):
+        """Vectors per launch the handle's pass workspace holds (the batch build_spectra set)."""
+        return self._batch_max
 
     @property
     def tuning(self):
+        """The handle's launch tuning (see ff_tuning in include/fastfocus.h)."""
         t = L.FFTuning()
         L.call("ff_get_tuning", self.h, C.byref(t))
-        return {"lg_G": t.lg_G, "lg_GT": t.lg_GT}
+        return {k: getattr(t, k) for k in self.TUNING_KEYS}
 
-    def set_tuning(self, lg_G=None, lg_GT=None):
+    def set_tuning(self, **changes):
+        """Change some tuning values (keys of ``tuning``); the others are kept."""
         cur = self.tuning
-        t = L.FFTuning(int(lg_G or cur["lg_G"]), int(lg_GT or cur["lg_GT"]))
+        for k, v in changes.items():
+            if k not in cur:
+                raise L.FastFocusError("ff_set_tuning", -1, f"unknown tuning key {k}")
+            if v is not None:
+                cur[k] = int(v)
+        t = L.FFTuning(*[cur[k] for k in self.TUNING_KEYS])
         L.call("ff_set_tuning", self.h, C.byref(t))
 
     def close(self):

@@ -103,8 +103,9 @@ def test_autotune_picks_valid_tuning_and_keeps_results(tmp_path):
     d = to_dev(W.gaussian_data(s, 1), F32)
     ref_g, ref_t = A.G(x).clone(), A.GT(d).clone()
     cache = str(tmp_path / "tune.json")
-    choice = autotune(A, x, d, cache=cache)
+    choice = autotune(A, x, d, cache=cache, reps=5)
     assert 1 <= choice["lg_G"] <= A.nz and 1 <= choice["lg_GT"] <= A.nz
+    assert choice["row_tile"] in (0, 1, 2)
     assert os.path.exists(cache)
     # the tuning changes only the summation order of the layer groups
     assert rel(to_host(A.G(x)), to_host(ref_g)) <= 1e-6
@@ -112,3 +113,31 @@ def test_autotune_picks_valid_tuning_and_keeps_results(tmp_path):
     B = Operator(s, F32)
     assert autotune(B, x, d, cache=cache) == choice     # cache hit
     assert B.tuning == choice
+
+
+def test_tuning_variants_keep_results():
+    s = W.SURVEYS["gravity_l4"]
+    A = Operator(s, F32)
+    g = torch.Generator(device="cuda").manual_seed(4)
+    X = torch.rand(6, A.n, device="cuda", generator=g)
+    D = torch.randn(6, A.m, device="cuda", generator=g)
+    ref_g, ref_t = A.G_block(X).clone(), A.G_block(D, transpose=True).clone()
+    base = A.tuning
+    assert base["batch"] == A.batch_max >= 16 and base["col_batched"] == 1
+    # the row tile changes only which block runs a row transform: bit-identical
+    for tile in (1, 2, 0):
+        A.set_tuning(row_tile=tile)
+        assert torch.equal(A.G_block(X), ref_g)
+        assert torch.equal(A.G_block(D, transpose=True), ref_t)
+    # batch schedule and per-vector column blocks: the same sums in another order
+    for kw in ({"batch": 1}, {"batch": 4}, {"batch": 5}, {"batch": A.batch_max, "col_batched": 0}):
+        A.set_tuning(**kw)
+        assert rel(to_host(A.G_block(X)), to_host(ref_g)) <= 2e-6
+        assert rel(to_host(A.G_block(D, transpose=True)), to_host(ref_t)) <= 2e-6
+    from paper_2004_13904_amd import _lib as L
+    for bad in ({"row_tile": 3}, {"batch": 0}, {"batch": A.batch_max + 1}, {"col_batched": 2},
+                {"lg_G": 0}, {"lg_GT": A.nz + 1}):
+        with pytest.raises(L.FastFocusError):
+            A.set_tuning(**bad)
+    A.set_tuning(**base)
+    assert A.tuning == base
