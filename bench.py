@@ -65,7 +65,9 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched / RSVD-block / IRLS legs")
     ap.add_argument("--legs", default="batched,rsvd,multi,autograd,irls",
-                    help="comma list of extra legs (batched, rsvd, multi, autograd, irls)")
+                    help="comma list of extra legs (batched, rsvd, multi, autograd, irls; opt-in: irls_c2)")
+    ap.add_argument("--irls-c2-steps", type=int, default=1,
+                    help="IRLS steps of the opt-in n = 1e6 magnetic leg (each step ~20 s)")
     ap.add_argument("--irls-steps", type=int, default=25)
     ap.add_argument("--calib", action="store_true",
                     help="end with a plain 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
@@ -266,6 +268,8 @@ def main(argv=None):
     if "irls" in legs:
         result["irls"] = irls_leg(a.irls_steps, lam=0.0)
         result["irls_l1"] = irls_leg(a.irls_steps, lam=1.0, stop=True)
+    if "irls_c2" in legs:
+        result["irls_magnetic_1m"] = irls_c2_leg(a.irls_c2_steps)
 
     if a.calib:
         src = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
@@ -583,6 +587,54 @@ def irls_leg(steps, lam=0.0, stop=False):
             "steps": len(hist), "converged": hist[-1][2] <= 1.0, "seconds_total": round(total, 3),
             "seconds_per_step": round(total / len(hist), 4), "final_chi2_scaled": round(hist[-1][2], 4),
             "alpha_1": hist[0][1], "alpha_K": hist[-1][1], "RE": round(re, 4)}
+
+
+def irls_c2_leg(steps):
+    """IRLS on the n = 1e6 magnetic survey (250 x 200 x 20, TFA with I = D = 45 deg): a 0.1 SI cube
+    and a 45-degree dipping dike, 2 % noise (tau1 = 0.02, tau2 = 0.002), minimum support
+    (lambda = 0, eps^2 = 1e-9), depth weighting beta = 1.4, bounds [0, 0.1], GKB with
+    t = m/20 = 2500, t_p = 2625 (the n x t_p FP64 basis is 21 GB), FP32 operator.  Each step is
+    timed; the time is dominated by the FP64 reorthogonalization (at least t_p^2 (n + m) doubles
+    read per step)."""
+    import torch
+
+    from paper_2004_13904_amd import solvers as SV
+    from paper_2004_13904_amd import workloads as W
+    from paper_2004_13904_amd.operator import Operator
+    s = W.SURVEYS["magnetic_1m"]
+    A = Operator(s, torch.float32)
+    m_true = torch.tensor(W.block_model(s, W.MAGNETIC_1M_BLOCKS), dtype=torch.float32, device="cuda")
+    d_exact = A.G(m_true).double().cpu().numpy()
+    eta, sd = W.noise(d_exact, 0.02, 0.002, 2)
+    d_obs = torch.tensor(d_exact + eta, dtype=torch.float64, device="cuda")
+    wd = torch.tensor(1.0 / sd, dtype=torch.float64, device="cuda")
+    p = SV.IrlsParams(solver="gkb", t=2500, tp=2625, lam=0.0, eps2=1e-9, beta_depth=1.4, m_min=0.0,
+                      m_max=0.1)
+    times = []
+    t_last = [0.0]
+
+    def cb(k, m, alpha, chi2):
+        torch.cuda.synchronize()
+        now = time.perf_counter()
+        times.append(now - t_last[0])
+        t_last[0] = now
+        log(f"irls (magnetic_1m) step {k}: alpha {alpha:.4g} chi2 {chi2:.4f} ({times[-1]:.2f} s)")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_last[0] = t0
+    m, hist = SV.irls(A, p, d_obs, wd, k_max=steps, callback=cb, stop_at_chi2=False)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    tp, n, mm = p.tp, A.n, A.m
+    # one Gram-Schmidt pass (Q^T v, then v - Q c) over both bases per iteration; the second pass
+    # runs only when the first cancels most of the vector
+    reorth_bytes = 2 * 8 * (n + mm) * tp * (tp + 1) / 2
+    return {"workload": "magnetic_1m: 250x200 stations, nz=20, cube + dipping dike, 2% noise, GKB t=2500 "
+                        "t_p=2625, FP32 operator, FP64 solve",
+            "steps": len(hist), "seconds_per_step": [round(x, 3) for x in times],
+            "seconds_total": round(total, 3), "chi2_scaled": [round(h[2], 4) for h in hist],
+            "reorth_bytes_per_step": reorth_bytes,
+            "reorth_GBs_if_all_time": round(reorth_bytes / (total / len(hist)) / 1e9, 1)}
 
 
 def cpu_baseline(s, x_h, d_h, A, x, d):

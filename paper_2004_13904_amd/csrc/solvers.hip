@@ -86,6 +86,13 @@ __global__ void k_scale(const double *__restrict__ x, const double *__restrict__
     y[i] = a * x[i];
 }
 
+// Second-pass test of the reorthogonalization (Daniel, Gragg, Kaufman and Stewart): the pass
+// is repeated when the first one removed more than half of the vector's squared norm, i.e.
+// when ||v1|| < ||v0|| / sqrt(2).
+__global__ void k_dgks_flag(const double *__restrict__ n0, const double *__restrict__ n1, int *__restrict__ run) {
+  if (threadIdx.x == 0) *run = (*n1 < 0.70710678118654752 * *n0) ? 1 : 0;
+}
+
 // y += sign * (*sc) * x
 __global__ void k_axpy_dev(double *__restrict__ y, const double *__restrict__ x, const double *__restrict__ sc, double sign,
                            int64_t n) {
@@ -101,7 +108,8 @@ __global__ void k_axpy_dev(double *__restrict__ y, const double *__restrict__ x,
 template <int RPL>
 __global__ void __launch_bounds__(kThreads)
 k_gemv_t_partial(const double *__restrict__ A, int64_t lda, int64_t nrows, int ncols, const double *__restrict__ x,
-                 double *__restrict__ part) {
+                 double *__restrict__ part, const int *__restrict__ run) {
+  if (run && *run == 0) return;   // conditional pass switched off on the device
   constexpr int K = kTLoads, CW = kTCols / (kThreads / 64);
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t r0 = (int64_t)blockIdx.x * kRowsMin * RPL;
@@ -150,7 +158,9 @@ k_gemv_t_partial(const double *__restrict__ A, int64_t lda, int64_t nrows, int n
 // out[j] = scale * sum_p part[p][j]: 64 columns per block, the row-block range split over
 // the block's four waves, then summed in LDS in wave order.
 __global__ void __launch_bounds__(kThreads)
-k_colsum(const double *__restrict__ part, int P, int ncols, double *__restrict__ out, double scale) {
+k_colsum(const double *__restrict__ part, int P, int ncols, double *__restrict__ out, double scale,
+         const int *__restrict__ run) {
+  if (run && *run == 0) return;
   __shared__ double red[kThreads];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int j = blockIdx.x * 64 + l;
@@ -176,7 +186,8 @@ k_colsum(const double *__restrict__ part, int P, int ncols, double *__restrict__
 template <int RPL>
 __global__ void __launch_bounds__(64 * kNWaves)
 k_gemv_n(const double *__restrict__ A, int64_t lda, int64_t nrows, int ncols, const double *__restrict__ c,
-         double *__restrict__ y, double alpha, double beta) {
+         double *__restrict__ y, double alpha, double beta, const int *__restrict__ run) {
+  if (run && *run == 0) return;
   __shared__ double red[kNWaves][64 * RPL];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t r = ((int64_t)blockIdx.x * 64 + l) * RPL;
@@ -519,35 +530,46 @@ struct Arena {
 
 // out = Q^T v (partials in part, then summed) and y = beta y + alpha Q c, with the launch shapes
 // of the kernels above.
+// `run` (device flag, may be NULL): the kernels return at once when it is 0.
 void launch_gemv_t(const double *Q, int64_t ld, int64_t nrows, int ncols, const double *v, double *out, double *part,
-                   hipStream_t s) {
+                   hipStream_t s, const int *run = nullptr) {
   const int rpl = rows_per_load(Q, ld);
   const int P = partials_for(nrows, rpl);
   const dim3 gt(P, (ncols + kTCols - 1) / kTCols);
   if (rpl == 2)
-    k_gemv_t_partial<2><<<gt, kThreads, 0, s>>>(Q, ld, nrows, ncols, v, part);
+    k_gemv_t_partial<2><<<gt, kThreads, 0, s>>>(Q, ld, nrows, ncols, v, part, run);
   else
-    k_gemv_t_partial<1><<<gt, kThreads, 0, s>>>(Q, ld, nrows, ncols, v, part);
-  k_colsum<<<(ncols + 63) / 64, kThreads, 0, s>>>(part, P, ncols, out, 1.0);
+    k_gemv_t_partial<1><<<gt, kThreads, 0, s>>>(Q, ld, nrows, ncols, v, part, run);
+  k_colsum<<<(ncols + 63) / 64, kThreads, 0, s>>>(part, P, ncols, out, 1.0, run);
 }
 
 void launch_gemv_n(const double *Q, int64_t ld, int64_t nrows, int ncols, const double *c, double *y, double alpha,
-                   double beta, hipStream_t s) {
+                   double beta, hipStream_t s, const int *run = nullptr) {
   // paired rows pay off on long bases; short ones want more blocks
   if (rows_per_load(Q, ld) == 2 && nrows >= 32768)
-    k_gemv_n<2><<<(unsigned)((nrows + 127) / 128), 64 * kNWaves, 0, s>>>(Q, ld, nrows, ncols, c, y, alpha, beta);
+    k_gemv_n<2><<<(unsigned)((nrows + 127) / 128), 64 * kNWaves, 0, s>>>(Q, ld, nrows, ncols, c, y, alpha, beta,
+                                                                          run);
   else
-    k_gemv_n<1><<<(unsigned)((nrows + 63) / 64), 64 * kNWaves, 0, s>>>(Q, ld, nrows, ncols, c, y, alpha, beta);
+    k_gemv_n<1><<<(unsigned)((nrows + 63) / 64), 64 * kNWaves, 0, s>>>(Q, ld, nrows, ncols, c, y, alpha, beta,
+                                                                        run);
 }
 
-// v <- (I - Q Q^T)^2 v over the first ncols columns of Q (classical Gram-Schmidt, twice)
+// v <- (I - Q Q^T) v over the first ncols columns of Q (classical Gram-Schmidt), repeated once
+// when the first pass cancelled most of v (k_dgks_flag); the test stays on the device.
+// dg: 2 doubles (norms) and flag: 1 int of scratch.
 ff_status reorth(const double *Q, int64_t ld, int64_t nrows, int ncols, double *v, double *coef, double *part,
-                 hipStream_t s) {
+                 double *dg, int *flag, hipStream_t s) {
   if (ncols <= 0) return FF_OK;
-  for (int pass = 0; pass < 2; ++pass) {
-    launch_gemv_t(Q, ld, nrows, ncols, v, coef, part, s);
-    launch_gemv_n(Q, ld, nrows, ncols, coef, v, -1.0, 1.0, s);
-  }
+  const int P = 256;
+  k_sumsq_partial<<<P, kThreads, 0, s>>>(v, nrows, part);
+  k_norm_finalize<<<1, kThreads, 0, s>>>(part, P, dg, nullptr);
+  launch_gemv_t(Q, ld, nrows, ncols, v, coef, part, s);
+  launch_gemv_n(Q, ld, nrows, ncols, coef, v, -1.0, 1.0, s);
+  k_sumsq_partial<<<P, kThreads, 0, s>>>(v, nrows, part);
+  k_norm_finalize<<<1, kThreads, 0, s>>>(part, P, dg + 1, nullptr);
+  k_dgks_flag<<<1, 64, 0, s>>>(dg, dg + 1, flag);
+  launch_gemv_t(Q, ld, nrows, ncols, v, coef, part, s, flag);
+  launch_gemv_n(Q, ld, nrows, ncols, coef, v, -1.0, 1.0, s, flag);
   FF_LAUNCH_CHECK("reorthogonalization");
   return FF_OK;
 }
@@ -579,7 +601,8 @@ ff_status norm2(const double *x, int64_t n, double *nrm, double *inv, double *pa
 
 // Workspace of Algorithm 1 for a handle and tp (also used for sizing when a.dry).
 struct GkbWs {
-  double *A, *H, *b, *c, *gamma, *beta, *ginv, *binv, *coef, *part, *dT, *eT, *C, *S, *V, *u0, *g, *w, *alpha;
+  double *A, *H, *b, *c, *gamma, *beta, *ginv, *binv, *coef, *part, *dT, *eT, *C, *S, *V, *u0, *g, *w, *alpha, *dg;
+  int *flag;
   rocblas_int *info;
   void carve(Arena &a, int64_t n, int64_t m, int tp) {
     const int64_t P = ((n > m ? n : m) + kRowsMin - 1) / kRowsMin + 1;   // partial rows at one row per load
@@ -602,6 +625,8 @@ struct GkbWs {
     g = a.take<double>(tp);
     w = a.take<double>(tp);
     alpha = a.take<double>(2);
+    dg = a.take<double>(2);
+    flag = a.take<int>(1);
     info = a.take<rocblas_int>(4);
   }
 };
@@ -694,13 +719,13 @@ ff_status gkb_run(ff_spectra h, const double *rt, const double *wd, const double
     // b = G~^T h - beta_i a_{i-1}
     if ((st = op_apply(h, 1, 1, hi, m, W.b, n, wd, winv, FF_F64, s))) return st;
     if (i > 0) k_axpy_dev<<<grid_for(n), kThreads, 0, s>>>(W.b, W.A + (int64_t)(i - 1) * n, W.beta + i, -1.0, n);
-    if ((st = reorth(W.A, n, n, i, W.b, W.coef, W.part, s))) return st;
+    if ((st = reorth(W.A, n, n, i, W.b, W.coef, W.part, W.dg, W.flag, s))) return st;
     if ((st = norm2(W.b, n, W.gamma + i, W.ginv + i, W.part, s))) return st;
     k_scale<<<grid_for(n), kThreads, 0, s>>>(W.b, W.ginv + i, ai, n);
     // c = G~ a - gamma_i h
     if ((st = op_apply(h, 0, 1, ai, n, W.c, m, winv, wd, FF_F64, s))) return st;
     k_axpy_dev<<<grid_for(m), kThreads, 0, s>>>(W.c, hi, W.gamma + i, -1.0, m);
-    if ((st = reorth(W.H, m, m, i + 1, W.c, W.coef, W.part, s))) return st;
+    if ((st = reorth(W.H, m, m, i + 1, W.c, W.coef, W.part, W.dg, W.flag, s))) return st;
     if ((st = norm2(W.c, m, W.beta + i + 1, W.binv + i + 1, W.part, s))) return st;
     k_scale<<<grid_for(m), kThreads, 0, s>>>(W.c, W.binv + i + 1, W.H + (int64_t)(i + 1) * m, m);
   }
