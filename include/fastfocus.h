@@ -83,6 +83,19 @@ typedef struct ff_spectra_s *ff_spectra;
 ff_status build_spectra(const ff_geometry *geom, int32_t dtype, ff_stream stream, ff_spectra *out);
 ff_status ff_free_spectra(ff_spectra h);
 
+/* Spectra checkpoints (the precomputed 2-D FFTs of the kernel arrays, Appendix A): save writes
+   the geometry, dtype and spectra of h to the host file `path` (FF_EINVAL if it cannot be
+   written); load rebuilds a handle from such a file without evaluating the prism kernels or the
+   FFTs again and returns it in *out (free with ff_free_spectra).  Load rejects files of another
+   format version, truncated files and spectra whose stored hash does not match (FF_EINVAL),
+   and geometry that build_spectra would reject.  Both block until done; the handle is on the
+   current device.  A loaded handle applies G and G^T bit for bit like the saved one. */
+ff_status ff_spectra_save(ff_spectra h, const char *path);
+/* The geometry a handle was built with (embedding sizes in nfft_x, nfft_y).  z_edges, if not
+   NULL, receives nz + 1 values and is stored in g->z_edges (call first with NULL to read nz). */
+ff_status ff_spectra_geometry(ff_spectra h, ff_geometry *g, double *z_edges);
+ff_status ff_spectra_load(const char *path, ff_stream stream, ff_spectra *out);
+
 /* Sizes of a handle (host outputs, any may be NULL). */
 ff_status ff_spectra_info(ff_spectra h, int64_t *m, int64_t *n, int32_t *nfft_x,
                           int32_t *nfft_y, int32_t *dtype);
@@ -138,13 +151,17 @@ ff_status gkb_project(ff_spectra h, const double *r_tilde, const double *wd, con
                       int32_t t, int32_t tp, int32_t alpha_mode, double *y, double *alpha,
                       double *sigma, void *workspace, size_t ws_bytes, ff_stream stream);
 
-/* Algorithm 2: randomized SVD with one power iteration of G~ (same weights as above),
-   Omega given as a tp x m FP64 device matrix (row-major, i.e. m-vectors stored one after
-   another), eigen-decomposition of the symmetrized B^T B, UPRE over t values, solution
-   y = Q V~ Gamma U~^T (B^T r~).  Outputs as gkb_project; sigma holds all tp values. */
+/* Algorithm 2: randomized SVD of G~ (same weights as above) with power_iters power iterations
+   (the paper uses 1; 0 <= power_iters <= 8), eigen-decomposition of the symmetrized B^T B,
+   UPRE over t values, solution y = Q V~ Gamma U~^T (B^T r~).  Outputs as gkb_project; sigma
+   holds all tp values.  Omega is a tp x m FP64 device matrix (row-major, i.e. m-vectors stored
+   one after another), or NULL: then it is drawn on the device from `seed` with the
+   counter-based Philox4x32-10 generator (Salmon et al., SC 2011): element pair p from the
+   counter (p mod 2^32, p div 2^32, 0, 0) and the key (seed mod 2^32, seed div 2^32), two
+   53-bit uniforms and a Box-Muller transform (see k_gaussian in the sources). */
 ff_status rsvd_project(ff_spectra h, const double *r_tilde, const double *wd, const double *winv,
-                       int32_t t, int32_t tp, const double *omega, int32_t alpha_mode,
-                       double *y, double *alpha, double *sigma, void *workspace,
+                       int32_t t, int32_t tp, const double *omega, uint64_t seed, int32_t power_iters,
+                       int32_t alpha_mode, double *y, double *alpha, double *sigma, void *workspace,
                        size_t ws_bytes, ff_stream stream);
 
 /* Parameters of one IRLS step (Sec. 2.2-2.3, Sec. 3.1). */
@@ -157,11 +174,14 @@ typedef struct {
     double beta_depth;   /* depth weighting exponent (0.8 gravity, 1.4 magnetic)          */
     double m_min, m_max; /* bound constraints                                             */
     double alpha_fixed;  /* > 0: use this alpha; otherwise eq. (eq:alpha1) at k = 1, UPRE after */
+    int32_t power_iters; /* RSVD power iterations (the paper: 1)                            */
+    uint64_t seed;       /* RSVD with omega = NULL: Omega drawn from (seed, counter word 2 = k) */
 } ff_irls_params;
 
 /* One IRLS step: W = W_z W_L^(k) with (W_L^(k))_ii = ((m_prev - m_prev2)_i^2 + eps2)^((lambda-2)/4)
-   (identity at k = 1), r~ = wd .* (d_obs - G m_prev), projected solve (GKB or RSVD with
-   `omega` tp x m when solver = 1), m_new = clip(m_prev + W^{-1} y, m_min, m_max) and the
+   (identity at k = 1), r~ = wd .* (d_obs - G m_prev), projected solve (GKB, or RSVD with
+   `omega` tp x m, or omega = NULL for the generator of rsvd_project with the third counter
+   word set to k), m_new = clip(m_prev + W^{-1} y, m_min, m_max) and the
    scaled chi^2 of eq. (scaledchi2).  d_obs, wd: m; m_prev, m_prev2, m_new: n (FP64 device).
    *alpha and *chi2_scaled are host outputs; the call synchronizes `stream` once at the end. */
 ff_status irls_step(ff_spectra h, const ff_irls_params *p, const double *d_obs, const double *wd,

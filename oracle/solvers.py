@@ -145,8 +145,9 @@ def gkb(apply_Gt, apply_GtT, r_tilde, n, t, tp, alpha_mode="upre", alpha_fixed=N
 
 
 def rsvd(apply_Gt, apply_GtT, r_tilde, n, t, tp, omega, alpha_mode="upre", alpha_fixed=None,
-         return_factors=False):
-    """Algorithm 2 (one power iteration).  omega is the t_p x m Gaussian matrix.
+         return_factors=False, power_iters=1):
+    """Algorithm 2 (power_iters power iterations; the paper's algorithm has one).  omega is the
+    t_p x m Gaussian matrix.
 
     The block products are column loops over the single-vector operators, as the
     paper describes them.  Returns (y, alpha, sigma[, factors]) with sigma all t_p
@@ -164,10 +165,11 @@ def rsvd(apply_Gt, apply_GtT, r_tilde, n, t, tp, omega, alpha_mode="upre", alpha
 
     Y = GtT_block(omega.T).T                  # Y = Omega G~        (tp x n)
     Q, _ = np.linalg.qr(Y.T)                  # Q in R^{n x tp}
-    Y = Gt_block(Q)                           # Y = G~ Q            (m x tp)
-    Q, _ = np.linalg.qr(Y)                    # Q in R^{m x tp}
-    Y = GtT_block(Q).T                        # Y = Q^T G~          (tp x n)
-    Q, _ = np.linalg.qr(Y.T)                  # Q in R^{n x tp}
+    for _ in range(power_iters):
+        Y = Gt_block(Q)                       # Y = G~ Q            (m x tp)
+        Q, _ = np.linalg.qr(Y)                # Q in R^{m x tp}
+        Y = GtT_block(Q).T                    # Y = Q^T G~          (tp x n)
+        Q, _ = np.linalg.qr(Y.T)              # Q in R^{n x tp}
     Bm = Gt_block(Q)                          # B = G~ Q            (m x tp)
     Yt = Bm.T @ Bm
     lam, V = np.linalg.eigh((Yt + Yt.T) / 2.0)

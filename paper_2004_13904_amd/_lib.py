@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libfastfocus.so")
 
 FF_OK = 0
+FF_EINVAL, FF_ESHAPE, FF_EDTYPE, FF_ENOMEM, FF_EHIP, FF_EDEVICE, FF_ENOTIMPL = -1, -2, -3, -4, -5, -6, -7
 FF_F32, FF_F64 = 0, 1
 FF_GRAVITY_GZ, FF_MAGNETIC_TFA = 0, 1
 STATUS = {0: "FF_OK", -1: "FF_EINVAL", -2: "FF_ESHAPE", -3: "FF_EDTYPE", -4: "FF_ENOMEM",
@@ -21,7 +22,8 @@ STATUS = {0: "FF_OK", -1: "FF_EINVAL", -2: "FF_ESHAPE", -3: "FF_EDTYPE", -4: "FF
 EXPORTS = ["build_spectra", "ff_free_spectra", "ff_spectra_info", "ff_kernel_table", "apply_G",
            "apply_GT", "apply_G_block", "ff_workspace_size", "gkb_project", "rsvd_project",
            "irls_step", "ff_get_tuning", "ff_set_tuning", "ff_profile_begin", "ff_profile_end", "ff_time_pass",
-           "ff_multi_create", "ff_multi_apply", "ff_multi_free", "ff_last_error"]
+           "ff_multi_create", "ff_multi_apply", "ff_multi_free", "ff_spectra_save", "ff_spectra_load",
+           "ff_spectra_geometry", "ff_last_error"]
 
 
 class FFGeometry(C.Structure):
@@ -36,7 +38,8 @@ class FFGeometry(C.Structure):
 class FFIrlsParams(C.Structure):
     _fields_ = [("solver", C.c_int32), ("t", C.c_int32), ("tp", C.c_int32), ("k", C.c_int32),
                 ("lam", C.c_double), ("eps2", C.c_double), ("beta_depth", C.c_double),
-                ("m_min", C.c_double), ("m_max", C.c_double), ("alpha_fixed", C.c_double)]
+                ("m_min", C.c_double), ("m_max", C.c_double), ("alpha_fixed", C.c_double),
+                ("power_iters", C.c_int32), ("seed", C.c_uint64)]
 
 
 class FFTuning(C.Structure):
@@ -74,7 +77,7 @@ def load(path=None):
         "apply_G_block": [vp, i32, i64, vp, i64, vp, i64, vp, vp, vp],
         "ff_workspace_size": [vp, i32, i32, i32, C.POINTER(C.c_size_t)],
         "gkb_project": [vp, vp, vp, vp, i32, i32, i32, vp, dp, vp, vp, C.c_size_t, vp],
-        "rsvd_project": [vp, vp, vp, vp, i32, i32, vp, i32, vp, dp, vp, vp, C.c_size_t, vp],
+        "rsvd_project": [vp, vp, vp, vp, i32, i32, vp, C.c_uint64, i32, i32, vp, dp, vp, vp, C.c_size_t, vp],
         "irls_step": [vp, C.POINTER(FFIrlsParams), vp, vp, vp, vp, vp, vp, dp, dp, vp, C.c_size_t,
                       vp],
         "ff_get_tuning": [vp, C.POINTER(FFTuning)],
@@ -86,6 +89,9 @@ def load(path=None):
                             C.POINTER(vp)],
         "ff_multi_apply": [vp, vp],
         "ff_multi_free": [vp],
+        "ff_spectra_save": [vp, C.c_char_p],
+        "ff_spectra_load": [C.c_char_p, vp, C.POINTER(vp)],
+        "ff_spectra_geometry": [vp, C.POINTER(FFGeometry), C.POINTER(C.c_double)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

@@ -2,8 +2,10 @@
 // failure is reported as a negative status plus a thread-local message; nothing throws
 // across the boundary.
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "common.h"
 
@@ -83,51 +85,44 @@ int column_blocks(int H, int NY) {
   return (H + cpb - 1) / cpb;
 }
 
-}  // namespace
-}  // namespace ff
-
-using namespace ff;
-
-extern "C" {
-
-const char *ff_last_error(void) { return g_err.c_str(); }
-
-ff_status build_spectra(const ff_geometry *g, int32_t dtype, ff_stream stream, ff_spectra *out) {
-  if (!g || !out) return fail(FF_EINVAL, "build_spectra: NULL geometry or output");
+// Validates the geometry, fills the handle's fields and allocates its device memory and
+// twiddle tables; the spectra are left to the caller (computed or loaded).
+ff_status create_handle(const ff_geometry *g, int32_t dtype, const std::string &who, ff_spectra *out) {
+  if (!g || !out) return fail(FF_EINVAL, who + ": NULL geometry or output");
   *out = nullptr;
-  if (dtype != FF_F32 && dtype != FF_F64) return fail(FF_EDTYPE, "build_spectra: dtype must be FF_F32 or FF_F64");
-  if (g->sx < 1 || g->sy < 1 || g->nz < 1) return fail(FF_ESHAPE, "build_spectra: sx, sy, nz must be >= 1");
+  if (dtype != FF_F32 && dtype != FF_F64) return fail(FF_EDTYPE, who + ": dtype must be FF_F32 or FF_F64");
+  if (g->sx < 1 || g->sy < 1 || g->nz < 1) return fail(FF_ESHAPE, who + ": sx, sy, nz must be >= 1");
   if (g->pad_xl < 0 || g->pad_xr < 0 || g->pad_yl < 0 || g->pad_yr < 0)
-    return fail(FF_ESHAPE, "build_spectra: negative padding");
+    return fail(FF_ESHAPE, who + ": negative padding");
   if (!(g->dx > 0) || !(g->dy > 0) || !std::isfinite(g->dx) || !std::isfinite(g->dy))
-    return fail(FF_EINVAL, "build_spectra: dx, dy must be positive and finite");
-  if (!g->z_edges) return fail(FF_EINVAL, "build_spectra: z_edges is NULL");
-  if (g->z_edges[0] != 0.0) return fail(FF_EINVAL, "build_spectra: z_edges[0] must be 0 (station plane)");
+    return fail(FF_EINVAL, who + ": dx, dy must be positive and finite");
+  if (!g->z_edges) return fail(FF_EINVAL, who + ": z_edges is NULL");
+  if (g->z_edges[0] != 0.0) return fail(FF_EINVAL, who + ": z_edges[0] must be 0 (station plane)");
   for (int r = 0; r < g->nz; ++r)
     if (!(g->z_edges[r + 1] > g->z_edges[r]) || !std::isfinite(g->z_edges[r + 1]))
-      return fail(FF_EINVAL, "build_spectra: z_edges must increase strictly");
+      return fail(FF_EINVAL, who + ": z_edges must increase strictly");
   if (g->kernel != FF_GRAVITY_GZ && g->kernel != FF_MAGNETIC_TFA)
-    return fail(FF_EINVAL, "build_spectra: unknown kernel");
+    return fail(FF_EINVAL, who + ": unknown kernel");
   if (g->kernel == FF_MAGNETIC_TFA &&
       (!std::isfinite(g->incl_deg) || !std::isfinite(g->decl_deg) || !std::isfinite(g->field_nT)))
-    return fail(FF_EINVAL, "build_spectra: magnetic field parameters must be finite");
+    return fail(FF_EINVAL, who + ": magnetic field parameters must be finite");
   const int64_t nx = (int64_t)g->sx + g->pad_xl + g->pad_xr;
   const int64_t ny = (int64_t)g->sy + g->pad_yl + g->pad_yr;
   const int64_t minx = g->sx + nx - 1, miny = g->sy + ny - 1;
-  if (minx > 2048 || miny > 2048) return fail(FF_ENOTIMPL, "build_spectra: embedding would exceed 2048");
+  if (minx > 2048 || miny > 2048) return fail(FF_ENOTIMPL, who + ": embedding would exceed 2048");
   int NX = g->nfft_x, NY = g->nfft_y;
   if (NX == 0) NX = next_pow2(minx);
   if (NY == 0) NY = next_pow2(miny);
   if (!is_pow2(NX) || !is_pow2(NY) || NX < 8 || NY < 8 || NX > 2048 || NY > 2048)
-    return fail(FF_ENOTIMPL, "build_spectra: embedding sizes must be powers of two in [8, 2048]");
+    return fail(FF_ENOTIMPL, who + ": embedding sizes must be powers of two in [8, 2048]");
   if (NX < minx || NY < miny)
-    return fail(FF_ESHAPE, "build_spectra: embedding smaller than s + n - 1 would wrap around");
+    return fail(FF_ESHAPE, who + ": embedding smaller than s + n - 1 would wrap around");
 
   ff_spectra h = new (std::nothrow) ff_spectra_s();
-  if (!h) return fail(FF_ENOMEM, "build_spectra: host allocation failed");
+  if (!h) return fail(FF_ENOMEM, who + ": host allocation failed");
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;
-    return fail(FF_EHIP, "build_spectra: no HIP device");
+    return fail(FF_EHIP, who + ": no HIP device");
   }
   h->dtype = dtype;
   h->sx = g->sx; h->sy = g->sy; h->nz = g->nz;
@@ -170,21 +165,141 @@ ff_status build_spectra(const ff_geometry *g, int32_t dtype, ff_stream stream, f
       hipMalloc(&h->ws_cols, h->ws_cols_bytes) != hipSuccess ||
       hipMalloc((void **)&h->z_dev, sizeof(double) * (h->nz + 1)) != hipSuccess) {
     free_handle(h);
-    return fail(FF_ENOMEM, "build_spectra: device allocation failed");
+    return fail(FF_ENOMEM, who + ": device allocation failed");
   }
   if (hipMemcpy(h->z_dev, g->z_edges, sizeof(double) * (h->nz + 1), hipMemcpyHostToDevice) != hipSuccess) {
     free_handle(h);
-    return fail(FF_EHIP, "build_spectra: z_edges upload failed");
+    return fail(FF_EHIP, who + ": z_edges upload failed");
   }
   st = dtype == FF_F32 ? upload_twiddles<float>(NX, &h->tw_x) : upload_twiddles<double>(NX, &h->tw_x);
   if (st == FF_OK) st = dtype == FF_F32 ? upload_twiddles<float>(NY, &h->tw_y) : upload_twiddles<double>(NY, &h->tw_y);
-  if (st == FF_OK) st = make_spectra(h, (hipStream_t)stream);
   if (st != FF_OK) {
     std::string msg = g_err;
     free_handle(h);
     return fail(st, msg);
   }
   *out = h;
+  return FF_OK;
+}
+
+}  // namespace
+}  // namespace ff
+
+using namespace ff;
+
+extern "C" {
+
+const char *ff_last_error(void) { return g_err.c_str(); }
+
+ff_status build_spectra(const ff_geometry *g, int32_t dtype, ff_stream stream, ff_spectra *out) {
+  ff_spectra h = nullptr;
+  ff_status st = create_handle(g, dtype, "build_spectra", &h);
+  if (st != FF_OK) return st;
+  st = make_spectra(h, (hipStream_t)stream);
+  if (st != FF_OK) {
+    std::string msg = g_err;
+    free_handle(h);
+    return fail(st, msg);
+  }
+  *out = h;
+  return FF_OK;
+}
+
+// ---- spectra checkpoints -------------------------------------------------------------
+// File layout (host byte order): magic "FFSPEC", u16 version; i32 dtype, sx, sy, nz, pad_xl,
+// pad_xr, pad_yl, pad_yr, kernel, NX, NY; f64 dx, dy, incl, decl, field; f64 z_edges[nz + 1];
+// i64 byte count of the spectra; the spectra ([nz][NX/2 + 1][NY] complex, as on the device);
+// u64 FNV-1a hash of the spectra bytes.
+static const char kMagic[6] = {'F', 'F', 'S', 'P', 'E', 'C'};
+static const uint16_t kVersion = 1;
+
+static uint64_t fnv1a(const unsigned char *p, size_t n) {
+  uint64_t hsh = 1469598103934665603ull;
+  for (size_t i = 0; i < n; ++i) hsh = (hsh ^ p[i]) * 1099511628211ull;
+  return hsh;
+}
+
+ff_status ff_spectra_save(ff_spectra h, const char *path) {
+  if (!h || !path) return fail(FF_EINVAL, "ff_spectra_save: NULL argument");
+  ff_status st = check_device(h);
+  if (st != FF_OK) return st;
+  const size_t bytes = csize(h->dtype) * (size_t)h->nz * h->H * h->NY;
+  std::vector<unsigned char> buf(bytes);
+  if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(buf.data(), h->spec, bytes, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(FF_EHIP, "ff_spectra_save: spectra download failed");
+  FILE *f = std::fopen(path, "wb");
+  if (!f) return fail(FF_EINVAL, std::string("ff_spectra_save: cannot open ") + path);
+  const int32_t iv[11] = {h->dtype, h->sx, h->sy, h->nz, h->pxl, h->pxr, h->pyl, h->pyr, h->kernel, h->NX, h->NY};
+  const double dv[5] = {h->dx, h->dy, h->incl, h->decl, h->field};
+  const int64_t nb = (int64_t)bytes;
+  const uint64_t hsh = fnv1a(buf.data(), bytes);
+  bool ok = std::fwrite(kMagic, 1, 6, f) == 6 && std::fwrite(&kVersion, 2, 1, f) == 1 &&
+            std::fwrite(iv, 4, 11, f) == 11 && std::fwrite(dv, 8, 5, f) == 5 &&
+            std::fwrite(h->z_edges.data(), 8, h->z_edges.size(), f) == h->z_edges.size() &&
+            std::fwrite(&nb, 8, 1, f) == 1 && std::fwrite(buf.data(), 1, bytes, f) == bytes &&
+            std::fwrite(&hsh, 8, 1, f) == 1;
+  ok = (std::fclose(f) == 0) && ok;
+  return ok ? FF_OK : fail(FF_EINVAL, std::string("ff_spectra_save: write failed for ") + path);
+}
+
+ff_status ff_spectra_load(const char *path, ff_stream stream, ff_spectra *out) {
+  (void)stream;
+  if (!path || !out) return fail(FF_EINVAL, "ff_spectra_load: NULL argument");
+  *out = nullptr;
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return fail(FF_EINVAL, std::string("ff_spectra_load: cannot open ") + path);
+  char magic[6];
+  uint16_t ver = 0;
+  int32_t iv[11];
+  double dv[5];
+  bool ok = std::fread(magic, 1, 6, f) == 6 && std::memcmp(magic, kMagic, 6) == 0 && std::fread(&ver, 2, 1, f) == 1 &&
+            ver == kVersion && std::fread(iv, 4, 11, f) == 11 && std::fread(dv, 8, 5, f) == 5;
+  if (!ok || iv[3] < 1 || iv[3] > (1 << 20)) {
+    std::fclose(f);
+    return fail(FF_EINVAL, "ff_spectra_load: not a spectra file of this version");
+  }
+  std::vector<double> z(iv[3] + 1);
+  int64_t nb = 0;
+  ok = std::fread(z.data(), 8, z.size(), f) == z.size() && std::fread(&nb, 8, 1, f) == 1;
+  ff_geometry g{};
+  g.sx = iv[1]; g.sy = iv[2]; g.nz = iv[3];
+  g.pad_xl = iv[4]; g.pad_xr = iv[5]; g.pad_yl = iv[6]; g.pad_yr = iv[7];
+  g.kernel = iv[8]; g.nfft_x = iv[9]; g.nfft_y = iv[10];
+  g.dx = dv[0]; g.dy = dv[1]; g.incl_deg = dv[2]; g.decl_deg = dv[3]; g.field_nT = dv[4];
+  g.z_edges = z.data();
+  ff_spectra h = nullptr;
+  ff_status st = ok ? create_handle(&g, iv[0], "ff_spectra_load", &h) : fail(FF_EINVAL, "ff_spectra_load: truncated file");
+  if (st != FF_OK) {
+    std::fclose(f);
+    return st;
+  }
+  const size_t bytes = csize(h->dtype) * (size_t)h->nz * h->H * h->NY;
+  std::vector<unsigned char> buf(bytes);
+  uint64_t hsh = 0;
+  ok = nb == (int64_t)bytes && std::fread(buf.data(), 1, bytes, f) == bytes && std::fread(&hsh, 8, 1, f) == 1;
+  std::fclose(f);
+  if (!ok || hsh != fnv1a(buf.data(), bytes)) {
+    free_handle(h);
+    return fail(FF_EINVAL, "ff_spectra_load: spectra truncated or corrupted");
+  }
+  if (hipMemcpy(h->spec, buf.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    free_handle(h);
+    return fail(FF_EHIP, "ff_spectra_load: spectra upload failed");
+  }
+  *out = h;
+  return FF_OK;
+}
+
+ff_status ff_spectra_geometry(ff_spectra h, ff_geometry *g, double *z_edges) {
+  if (!h || !g) return fail(FF_EINVAL, "ff_spectra_geometry: NULL argument");
+  g->sx = h->sx; g->sy = h->sy; g->nz = h->nz;
+  g->pad_xl = h->pxl; g->pad_xr = h->pxr; g->pad_yl = h->pyl; g->pad_yr = h->pyr;
+  g->dx = h->dx; g->dy = h->dy;
+  g->kernel = h->kernel;
+  g->incl_deg = h->incl; g->decl_deg = h->decl; g->field_nT = h->field;
+  g->nfft_x = h->NX; g->nfft_y = h->NY;
+  g->z_edges = z_edges;
+  if (z_edges) std::memcpy(z_edges, h->z_edges.data(), sizeof(double) * h->z_edges.size());
   return FF_OK;
 }
 

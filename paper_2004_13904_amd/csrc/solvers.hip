@@ -31,6 +31,7 @@ constexpr int kTLoads = 4;                 // row loads per lane in the transpos
 constexpr int kTCols = 16;                 // basis columns per block of the transposed products
 constexpr int kRowsMin = 64 * kTLoads;     // rows per transposed-product block at one row per load
 constexpr int kNWaves = 8;                 // waves per block of the basis products A c
+constexpr int kMaxPowerIters = 8;          // largest RSVD power-iteration count accepted
 constexpr int kUpreGrid = 400;
 constexpr double kUpreLo = 1e-3;
 constexpr double kGoldenTol = 1e-10;
@@ -84,6 +85,40 @@ __global__ void k_scale(const double *__restrict__ x, const double *__restrict__
   const double a = *sc;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = a * x[i];
+}
+
+// Gaussian test matrix from a counter-based generator: Philox4x32-10 (Salmon, Moraes, Dror and
+// Shaw, SC 2011).  Pair p of the output (elements 2p, 2p+1) is drawn from the counter
+// (p mod 2^32, p / 2^32, stream, 0) under the key (seed mod 2^32, seed / 2^32): two 53-bit
+// uniforms u1 in (0, 1], u2 in [0, 1) from the four output words, then Box-Muller:
+// sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2).
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    c[1] = (uint32_t)p1;
+    c[3] = (uint32_t)p0;
+    c[0] = n0;
+    c[2] = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+__global__ void k_gaussian(double *__restrict__ out, int64_t count, uint64_t seed, uint32_t stream) {
+  const int64_t npair = (count + 1) / 2;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npair; p += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t c[4] = {(uint32_t)p, (uint32_t)((uint64_t)p >> 32), stream, 0u};
+    philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const double a = (double)(((uint64_t)(c[0] >> 5) << 26) | (c[1] >> 6));
+    const double b = (double)(((uint64_t)(c[2] >> 5) << 26) | (c[3] >> 6));
+    const double u1 = (a + 1.0) * 0x1.0p-53, u2 = b * 0x1.0p-53;
+    const double rho = sqrt(-2.0 * log(u1)), th = 6.283185307179586476925 * u2;
+    out[2 * p] = rho * cos(th);
+    if (2 * p + 1 < count) out[2 * p + 1] = rho * sin(th);
+  }
 }
 
 // Second-pass test of the reorthogonalization (Daniel, Gragg, Kaufman and Stewart): the pass
@@ -760,8 +795,8 @@ ff_status qr_inplace(rocblas_handle bh, double *M, int64_t rows, int cols, doubl
 }
 
 ff_status rsvd_run(ff_spectra h, const double *rt, const double *wd, const double *winv, int t, int tp,
-                   const double *omega, int mode, double *y, double *alpha, double *sigma, void *ws, size_t ws_bytes,
-                   hipStream_t s) {
+                   const double *omega, uint64_t seed, uint32_t stream, int power_iters, int mode, double *y,
+                   double *alpha, double *sigma, void *ws, size_t ws_bytes, hipStream_t s) {
   const int64_t n = h->n, m = h->m;
   Arena ar{(char *)ws, ws_bytes, 0, false};
   RsvdWs W;
@@ -772,15 +807,23 @@ ff_status rsvd_run(ff_spectra h, const double *rt, const double *wd, const doubl
   ff_status st;
   rocblas_handle bh = blas(s, &st);
   if (st) return st;
+  // Omega from the counter-based generator when not given (its tp x m values fill Bm, which
+  // is not needed before the first product has read them)
+  if (!omega) {
+    k_gaussian<<<grid_for((int64_t)tp * m), kThreads, 0, s>>>(W.Bm, (int64_t)tp * m, seed, stream);
+    FF_LAUNCH_CHECK("rsvd test matrix");
+    omega = W.Bm;
+  }
   // Y^T = G~^T Omega^T (n x tp), Q = qr(Y^T)
   if ((st = op_apply(h, 1, tp, omega, m, W.Q, n, wd, winv, FF_F64, s))) return st;
   if ((st = qr_inplace(bh, W.Q, n, tp, W.tau))) return st;
-  // Y = G~ Q (m x tp), Q = qr(Y)
-  if ((st = op_apply(h, 0, tp, W.Q, n, W.Bm, m, winv, wd, FF_F64, s))) return st;
-  if ((st = qr_inplace(bh, W.Bm, m, tp, W.tau))) return st;
-  // Y^T = G~^T Q (n x tp), Q = qr(Y^T)
-  if ((st = op_apply(h, 1, tp, W.Bm, m, W.Q, n, wd, winv, FF_F64, s))) return st;
-  if ((st = qr_inplace(bh, W.Q, n, tp, W.tau))) return st;
+  for (int q = 0; q < power_iters; ++q) {
+    // Y = G~ Q (m x tp), Q = qr(Y); Y^T = G~^T Q (n x tp), Q = qr(Y^T)
+    if ((st = op_apply(h, 0, tp, W.Q, n, W.Bm, m, winv, wd, FF_F64, s))) return st;
+    if ((st = qr_inplace(bh, W.Bm, m, tp, W.tau))) return st;
+    if ((st = op_apply(h, 1, tp, W.Bm, m, W.Q, n, wd, winv, FF_F64, s))) return st;
+    if ((st = qr_inplace(bh, W.Q, n, tp, W.tau))) return st;
+  }
   // B = G~ Q
   if ((st = op_apply(h, 0, tp, W.Q, n, W.Bm, m, winv, wd, FF_F64, s))) return st;
   // B^T B (symmetric by construction of the product; the eigensolver reads one triangle,
@@ -857,14 +900,15 @@ ff_status gkb_project(ff_spectra h, const double *r_tilde, const double *wd, con
 }
 
 ff_status rsvd_project(ff_spectra h, const double *r_tilde, const double *wd, const double *winv, int32_t t,
-                       int32_t tp, const double *omega, int32_t alpha_mode, double *y, double *alpha, double *sigma,
-                       void *workspace, size_t ws_bytes, ff_stream stream) {
+                       int32_t tp, const double *omega, uint64_t seed, int32_t power_iters, int32_t alpha_mode,
+                       double *y, double *alpha, double *sigma, void *workspace, size_t ws_bytes, ff_stream stream) {
   ff_status st = check_solver_args(h, t, tp, r_tilde, wd, winv, y, alpha, sigma, workspace);
   if (st) return st;
-  if (!omega) return fail(FF_EINVAL, "rsvd_project: omega is NULL");
+  if (power_iters < 0 || power_iters > kMaxPowerIters)
+    return fail(FF_EINVAL, "rsvd_project: power_iters must lie in [0, 8]");
   if (alpha_mode < 0 || alpha_mode > 2) return fail(FF_EINVAL, "rsvd_project: alpha_mode must be 0, 1 or 2");
-  return rsvd_run(h, r_tilde, wd, winv, t, tp, omega, alpha_mode, y, alpha, sigma, workspace, ws_bytes,
-                  (hipStream_t)stream);
+  return rsvd_run(h, r_tilde, wd, winv, t, tp, omega, seed, 0u, power_iters, alpha_mode, y, alpha, sigma, workspace,
+                  ws_bytes, (hipStream_t)stream);
 }
 
 ff_status irls_step(ff_spectra h, const ff_irls_params *p, const double *d_obs, const double *wd,
@@ -875,7 +919,8 @@ ff_status irls_step(ff_spectra h, const ff_irls_params *p, const double *d_obs, 
   if (p->k < 1) return fail(FF_EINVAL, "irls_step: k must be >= 1");
   if (p->k > 1 && !m_prev2) return fail(FF_EINVAL, "irls_step: m_prev2 is needed for k > 1");
   if (p->solver != 0 && p->solver != 1) return fail(FF_EINVAL, "irls_step: solver must be 0 (GKB) or 1 (RSVD)");
-  if (p->solver == 1 && !omega) return fail(FF_EINVAL, "irls_step: RSVD needs omega");
+  if (p->solver == 1 && (p->power_iters < 0 || p->power_iters > kMaxPowerIters))
+    return fail(FF_EINVAL, "irls_step: power_iters must lie in [0, 8]");
   if (!(p->eps2 > 0) || !(p->m_max >= p->m_min)) return fail(FF_EINVAL, "irls_step: need eps2 > 0, m_max >= m_min");
   if (p->t < 1 || p->tp < p->t || p->tp > h->m) return fail(FF_ESHAPE, "irls_step: need 1 <= t <= tp <= m");
   int cur = -1;
@@ -908,7 +953,8 @@ ff_status irls_step(ff_spectra h, const ff_irls_params *p, const double *d_obs, 
   if (p->solver == 0)
     st = gkb_run(h, I.r, wd, I.winv, p->t, p->tp, mode, I.y, &a, I.sig, workspace, sol, s);
   else
-    st = rsvd_run(h, I.r, wd, I.winv, p->t, p->tp, omega, mode, I.y, &a, I.sig, workspace, sol, s);
+    st = rsvd_run(h, I.r, wd, I.winv, p->t, p->tp, omega, p->seed, (uint32_t)p->k, p->power_iters, mode, I.y, &a,
+                  I.sig, workspace, sol, s);
   if (st) return st;
   // m^(k) = clip(m^(k-1) + W^{-1} y), then the scaled chi^2 of the clipped iterate
   k_update_clip<<<grid_for(n), kThreads, 0, s>>>(m_prev, I.winv, I.y, n, p->m_min, p->m_max, m_new);

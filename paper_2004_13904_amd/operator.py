@@ -8,6 +8,7 @@ operator (G is linear, so no activations are kept: the context holds only the ha
 from __future__ import annotations
 
 import ctypes as C
+import os
 
 import torch
 
@@ -31,22 +32,48 @@ class Operator:
             raise L.FastFocusError("Operator", -6, "no HIP device available")
         if dtype not in (torch.float32, torch.float64):
             raise L.FastFocusError("Operator", -3, "dtype must be float32 or float64")
-        self.survey = dict(survey)
-        self.dtype = dtype
-        self.device = torch.device("cuda", torch.cuda.current_device())
-        geom, self._keep = L.make_geometry(survey, nfft)
+        geom, keep = L.make_geometry(survey, nfft)
         h = C.c_void_p()
         dt = L.FF_F32 if dtype == torch.float32 else L.FF_F64
         L.call("build_spectra", C.byref(geom), dt, _stream(), C.byref(h))
+        self._attach(h, dict(survey))
+
+    def _attach(self, h, survey):
         self.h = h
+        self.survey = survey
+        self.device = torch.device("cuda", torch.cuda.current_device())
         m, n, nfx, nfy, dti = C.c_int64(), C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32()
         L.call("ff_spectra_info", h, C.byref(m), C.byref(n), C.byref(nfx), C.byref(nfy), C.byref(dti))
         self.m, self.n, self.nfft = m.value, n.value, (nfx.value, nfy.value)
+        self.dtype = torch.float32 if dti.value == L.FF_F32 else torch.float64
         s = self.survey
         self.nx = s["sx"] + s.get("pad_xl", 0) + s.get("pad_xr", 0)
         self.ny = s["sy"] + s.get("pad_yl", 0) + s.get("pad_yr", 0)
         self.nz = s["nz"]
         self._batch_max = self.tuning["batch"]
+
+    def save(self, path):
+        """Checkpoint the spectra (and geometry) to a host file; see ff_spectra_save."""
+        L.call("ff_spectra_save", self.h, os.fsencode(path))
+
+    @classmethod
+    def load(cls, path):
+        """An Operator rebuilt from a spectra checkpoint (no prism or FFT evaluation)."""
+        if not torch.cuda.is_available():
+            raise L.FastFocusError("Operator.load", -6, "no HIP device available")
+        h = C.c_void_p()
+        L.call("ff_spectra_load", os.fsencode(path), _stream(), C.byref(h))
+        g = L.FFGeometry()
+        L.call("ff_spectra_geometry", h, C.byref(g), None)
+        z = (C.c_double * (g.nz + 1))()
+        L.call("ff_spectra_geometry", h, C.byref(g), z)
+        survey = dict(sx=g.sx, sy=g.sy, nz=g.nz, dx=g.dx, dy=g.dy, z_edges=tuple(z),
+                      kernel="gravity" if g.kernel == L.FF_GRAVITY_GZ else "magnetic",
+                      incl_deg=g.incl_deg, decl_deg=g.decl_deg, field_nT=g.field_nT,
+                      pad_xl=g.pad_xl, pad_xr=g.pad_xr, pad_yl=g.pad_yl, pad_yr=g.pad_yr)
+        op = cls.__new__(cls)
+        op._attach(h, survey)
+        return op
 
     TUNING_KEYS = ("lg_G", "lg_GT", "row_tile", "batch", "col_batched")
 

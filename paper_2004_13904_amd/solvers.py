@@ -53,20 +53,22 @@ def gkb_project(op, r_tilde, wd, winv, t, tp, alpha_mode="upre", alpha=None, ws=
     return y, a.value, sigma
 
 
-def rsvd_project(op, r_tilde, wd, winv, t, tp, omega, alpha_mode="upre", alpha=None, ws=None,
-                 stream=None):
-    """omega: (tp, m) float64 Gaussian matrix.  Returns (y, alpha, sigma)."""
+def rsvd_project(op, r_tilde, wd, winv, t, tp, omega=None, alpha_mode="upre", alpha=None, ws=None,
+                 stream=None, seed=0, power_iters=1):
+    """omega: (tp, m) float64 Gaussian matrix, or None to draw it on the device from `seed`
+    (Philox4x32-10, see rsvd_project in include/fastfocus.h).  Returns (y, alpha, sigma)."""
     _f64(op, r_tilde, op.m, "rsvd_project")
     _f64(op, wd, op.m, "rsvd_project")
     _f64(op, winv, op.n, "rsvd_project")
-    _f64(op, omega, tp * op.m, "rsvd_project")
+    if omega is not None:
+        _f64(op, omega, tp * op.m, "rsvd_project")
     ws = _workspace(op, "rsvd", tp, 1, ws)
     y = torch.empty(op.n, dtype=torch.float64, device=op.device)
     sigma = torch.empty(tp, dtype=torch.float64, device=op.device)
     a = C.c_double(float(alpha) if alpha is not None else 0.0)
     L.call("rsvd_project", op.h, _ptr(r_tilde), _ptr(wd), _ptr(winv), int(t), int(tp), _ptr(omega),
-           ALPHA_MODES[alpha_mode], _ptr(y), C.byref(a), _ptr(sigma), _ptr(ws), ws.numel(),
-           _stream(stream))
+           int(seed), int(power_iters), ALPHA_MODES[alpha_mode], _ptr(y), C.byref(a), _ptr(sigma), _ptr(ws),
+           ws.numel(), _stream(stream))
     return y, a.value, sigma
 
 
@@ -81,6 +83,8 @@ class IrlsParams:
     m_min: float = 0.0
     m_max: float = 1.0
     alpha_fixed: float = -1.0
+    power_iters: int = 1
+    seed: int = 0
 
 
 def irls_step(op, p: IrlsParams, k, d_obs, wd, m_prev, m_prev2=None, omega=None, ws=None,
@@ -96,7 +100,8 @@ def irls_step(op, p: IrlsParams, k, d_obs, wd, m_prev, m_prev2=None, omega=None,
         _f64(op, omega, p.tp * op.m, "irls_step")
     ws = _workspace(op, "irls", p.tp, solver, ws)
     prm = L.FFIrlsParams(solver, int(p.t), int(p.tp), int(k), float(p.lam), float(p.eps2),
-                         float(p.beta_depth), float(p.m_min), float(p.m_max), float(p.alpha_fixed))
+                         float(p.beta_depth), float(p.m_min), float(p.m_max), float(p.alpha_fixed),
+                         int(p.power_iters), int(p.seed))
     m_new = torch.empty(op.n, dtype=torch.float64, device=op.device)
     a, chi2 = C.c_double(), C.c_double()
     L.call("irls_step", op.h, C.byref(prm), _ptr(d_obs), _ptr(wd), _ptr(m_prev), _ptr(m_prev2),
@@ -108,7 +113,8 @@ def irls_step(op, p: IrlsParams, k, d_obs, wd, m_prev, m_prev2=None, omega=None,
 def irls(op, p: IrlsParams, d_obs, wd, k_max=25, omega_fn=None, callback=None, stop_at_chi2=True):
     """The IRLS iteration of Secs. 2.3 and 3.1: m^(0) = 0, steps k = 1.. until the scaled
     chi^2 of eq. (scaledchi2) is <= 1 (when stop_at_chi2) or k = k_max.  omega_fn(k) supplies
-    the RSVD matrix.  Returns (m, history) with history a list of (k, alpha, chi2)."""
+    the RSVD matrix; without it the device generator draws it from (p.seed, k).
+    Returns (m, history) with history a list of (k, alpha, chi2)."""
     m_prev = torch.zeros(op.n, dtype=torch.float64, device=op.device)
     m_prev2 = torch.zeros_like(m_prev)
     ws = _workspace(op, "irls", p.tp, 0 if p.solver == "gkb" else 1)

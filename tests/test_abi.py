@@ -80,3 +80,16 @@ def test_bad_dtype_and_null_arguments():
     assert lib.build_spectra(None, 0, None, C.byref(h)) == -1
     assert lib.apply_G(None, None, None, None, None, None) == -1
     assert lib.ff_free_spectra(None) == -1
+
+
+def test_spectra_load_rejects_foreign_and_missing_files(tmp_path):
+    # the magic and version are read before any device call
+    L, lib = _lib()
+    h = C.c_void_p(123)
+    missing = str(tmp_path / "none.ffs").encode()
+    assert lib.ff_spectra_load(missing, None, C.byref(h)) == L.FF_EINVAL and h.value is None
+    junk = tmp_path / "junk.ffs"
+    junk.write_bytes(b"NOTSPECTRA" + bytes(200))
+    assert lib.ff_spectra_load(str(junk).encode(), None, C.byref(h)) == L.FF_EINVAL
+    assert b"not a spectra file" in lib.ff_last_error()
+    assert lib.ff_spectra_save(None, b"x") == L.FF_EINVAL

@@ -199,3 +199,31 @@ def test_wrong_tensor_arguments_raise():
         A.G(torch.zeros(10, dtype=F32, device="cuda"))
     with pytest.raises(L.FastFocusError):
         A.G(torch.zeros(A.n, dtype=F64, device="cuda"))
+
+
+@pytest.mark.parametrize("name,dtype", [("mag_padded", F64), ("wide_tail", F32)])
+def test_spectra_checkpoint_round_trip(tmp_path, name, dtype):
+    s = SMALL[name]
+    A = Operator(s, dtype)
+    path = tmp_path / "op.ffs"
+    A.save(str(path))
+    B = Operator.load(str(path))
+    assert B.dtype == dtype and B.nfft == A.nfft and (B.m, B.n) == (A.m, A.n)
+    for k in ("sx", "sy", "nz", "dx", "dy", "kernel", "pad_xl", "pad_xr", "pad_yl", "pad_yr"):
+        assert B.survey[k] == A.survey[k], k
+    assert tuple(B.survey["z_edges"]) == tuple(A.survey["z_edges"])
+    rng = np.random.default_rng(3)
+    x = to_dev(rng.standard_normal(A.n), dtype)
+    d = to_dev(rng.standard_normal(A.m), dtype)
+    assert torch.equal(B.G(x), A.G(x))
+    assert torch.equal(B.GT(d), A.GT(d))
+    # a flipped spectra byte and a truncated file are refused
+    raw = bytearray(path.read_bytes())
+    bad = tmp_path / "bad.ffs"
+    raw[len(raw) // 2] ^= 0x40
+    bad.write_bytes(bytes(raw))
+    with pytest.raises(L.FastFocusError):
+        Operator.load(str(bad))
+    bad.write_bytes(path.read_bytes()[:-100])
+    with pytest.raises(L.FastFocusError):
+        Operator.load(str(bad))

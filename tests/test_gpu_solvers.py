@@ -6,7 +6,7 @@ import pytest
 import torch
 
 from gpu_common import announce, ogeom, rel, to_dev, to_host
-from oracle import irls as oirls, operator as op, solvers as osol
+from oracle import irls as oirls, operator as op, philox, solvers as osol
 from paper_2004_13904_amd import _lib as L
 from paper_2004_13904_amd import solvers as S
 from paper_2004_13904_amd import workloads as W
@@ -112,6 +112,56 @@ def test_rsvd_matches_oracle_algorithm(mode, dtype):
                         to_dev(omega, F64), "fixed", a0)[0]
     assert rel(to_host(ya), y0) <= (1e-8 if dtype == F64 else 1e-4)
     assert rel(to_host(y), y0) <= (1e-8 if dtype == F64 else 1e-4) + 2 * abs(a - a0) / a0
+
+
+@pytest.mark.parametrize("q", [0, 2])
+def test_rsvd_power_iterations_and_device_omega(q):
+    # Omega drawn on the device from a seed (Philox4x32-10) and q power iterations, against the
+    # oracle's Algorithm 2 with the host rendering of the same generator; t_p < m, so the
+    # result depends on Omega
+    s, g, G, wd, winv, Gt, r = problem("mid", kernel="gravity", seed=2)
+    t, tp = 60, 63
+    seed = (1 << 40) + 17
+    announce("rsvd device omega", q)
+    omega = philox.gaussian(tp * g.m, seed).reshape(tp, g.m)
+    y0, a0, s0 = osol.rsvd(*dense_ops(Gt), r, g.n, t, tp, omega, "fixed", 2.0, power_iters=q)
+    A = Operator(s, F64)
+    y, a, sig = S.rsvd_project(A, to_dev(r, F64), to_dev(wd, F64), to_dev(winv, F64), t, tp, None, "fixed", 2.0,
+                               seed=seed, power_iters=q)
+    assert rel(to_host(sig)[:t], s0[:t]) <= 1e-8
+    assert rel(to_host(y), y0) <= 1e-8
+    # another seed is another sketch
+    y2 = S.rsvd_project(A, to_dev(r, F64), to_dev(wd, F64), to_dev(winv, F64), t, tp, None, "fixed", 2.0,
+                        seed=seed + 1, power_iters=q)[0]
+    assert rel(to_host(y2), y0) > 1e-6
+    with pytest.raises(L.FastFocusError):
+        S.rsvd_project(A, to_dev(r, F64), to_dev(wd, F64), to_dev(winv, F64), t, tp, None, "fixed", 2.0,
+                       power_iters=9)
+
+
+def test_irls_rsvd_with_device_omega_matches_oracle():
+    # irls_step draws Omega from (seed, stream = k) when it is not given
+    s = W.survey(16, 12, 5, 25, 25, 25)
+    g = ogeom(s)
+    G = op.dense_G(g)
+    rng = np.random.default_rng(3)
+    m_true = np.zeros(g.n)
+    m_true[rng.choice(g.n, 20, replace=False)] = 1.0
+    d_exact = G @ m_true
+    eta, sd = W.noise(d_exact, 0.02, 0.002, 5)
+    d_obs = d_exact + eta
+    wd = 1.0 / sd
+    t, tp, seed = 40, 42, 99
+    A = Operator(s, F64)
+    po = oirls.IrlsParams(solver="rsvd", t=t, tp=tp, lam=0.0, beta_depth=0.8, m_min=0.0, m_max=1.0)
+    pg = S.IrlsParams(solver="rsvd", t=t, tp=tp, lam=0.0, beta_depth=0.8, m_min=0.0, m_max=1.0, seed=seed)
+    om1 = philox.gaussian(tp * g.m, seed, stream=1).reshape(tp, g.m)
+    m1o, a1o, c1o, _ = oirls.irls_step(g, po, 1, d_obs, wd, np.zeros(g.n), None, om1, G_dense=G)
+    m1, a1, c1 = S.irls_step(A, pg, 1, to_dev(d_obs, F64), to_dev(wd, F64),
+                             torch.zeros(g.n, dtype=F64, device="cuda"), None, None)
+    assert abs(a1 - a1o) <= 1e-8 * a1o
+    assert rel(to_host(m1), m1o) <= 1e-7
+    assert abs(c1 - c1o) <= 1e-8 * c1o
 
 
 @pytest.mark.parametrize("solver", ["gkb", "rsvd"])

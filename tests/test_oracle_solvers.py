@@ -47,12 +47,13 @@ def test_gkb_factorization_relations():
     assert np.allclose(S[:3], s_true[:3], rtol=1e-10)
 
 
-@pytest.mark.parametrize("kernel", ["gravity", "magnetic"])
-def test_rsvd_full_space_equals_tikhonov(kernel):
+@pytest.mark.parametrize("kernel,q", [("gravity", 1), ("magnetic", 1), ("gravity", 0), ("magnetic", 2)])
+def test_rsvd_full_space_equals_tikhonov(kernel, q):
+    # with t_p = m the sketch spans the whole range of G~ for any number q of power iterations
     g, G, wd, winv, Gt, r = small_problem(kernel)
     alpha = 0.3 * np.linalg.svd(Gt, compute_uv=False)[5]
     omega = np.random.default_rng(9).standard_normal((g.m, g.m))
-    y, a, S = solvers.rsvd(*ops(Gt), r, g.n, g.m, g.m, omega, "fixed", alpha)
+    y, a, S = solvers.rsvd(*ops(Gt), r, g.n, g.m, g.m, omega, "fixed", alpha, power_iters=q)
     ref = solvers.tikhonov_z(Gt, r, alpha)
     assert np.linalg.norm(y - ref) <= 1e-8 * np.linalg.norm(ref)
     assert np.allclose(S, np.linalg.svd(Gt, compute_uv=False), rtol=1e-8)
@@ -66,6 +67,18 @@ def test_rsvd_power_iteration_captures_dominant_space():
     assert np.allclose(S[:4], s_true[:4], rtol=1e-4)
     Q = F["Q"]
     assert np.abs(Q.T @ Q - np.eye(24)).max() <= 1e-12
+
+
+def test_rsvd_more_power_iterations_sharpen_the_spectrum():
+    # a rank-deficient sketch: each power iteration raises the accuracy of the leading values
+    g, G, wd, winv, Gt, r = small_problem()
+    s_true = np.linalg.svd(Gt, compute_uv=False)
+    omega = np.random.default_rng(11).standard_normal((12, g.m))
+    err = []
+    for q in (0, 1, 3):
+        _, _, S = solvers.rsvd(*ops(Gt), r, g.n, 8, 12, omega, "fixed", 1.0, power_iters=q)
+        err.append(np.abs(S[:6] - s_true[:6]).max() / s_true[0])
+    assert err[0] > err[1] > err[2]
 
 
 def test_upre_is_unbiased_for_predictive_risk():
