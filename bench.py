@@ -64,8 +64,9 @@ def main(argv=None):
     ap.add_argument("--cold-reps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched / RSVD-block / IRLS legs")
-    ap.add_argument("--legs", default="batched,rsvd,multi,autograd,irls",
-                    help="comma list of extra legs (batched, rsvd, multi, autograd, irls; opt-in: irls_c2)")
+    ap.add_argument("--legs", default="batched,rsvd,multi,autograd,table3,irls",
+                    help="comma list of extra legs (batched, rsvd, multi, autograd, table3, irls; "
+                         "opt-in: irls_c2)")
     ap.add_argument("--irls-c2-steps", type=int, default=1,
                     help="IRLS steps of the opt-in n = 1e6 magnetic leg (each step ~20 s)")
     ap.add_argument("--irls-steps", type=int, default=25)
@@ -265,6 +266,8 @@ def main(argv=None):
         result["multi_survey"] = multi_survey_leg()
     if "autograd" in legs:
         result["autograd"] = autograd_leg(check=check)
+    if "table3" in legs:
+        result["table3"] = [geometry_leg(f"table3_nz{nz}", W.table3_survey(nz), check=check) for nz in (20, 239)]
     if "irls" in legs:
         result["irls"] = irls_leg(a.irls_steps, lam=0.0)
         result["irls_l1"] = irls_leg(a.irls_steps, lam=1.0, stop=True)
@@ -346,6 +349,48 @@ def batched_leg(A, s, x_h, d_h, ms_pair_single, k=16, check=True):
            "speedup_vs_per_vector": round(ms_pair_single * k / ms, 3)}
     if check:
         out["rel_err_vs_oracle"] = oracle_errors(s, X[0], D[0], Y[0], Z[0])
+    return out
+
+
+def geometry_leg(name, s, check=True, R=20, reps=10):
+    """The per-vector pair (graph-replayed, as the headline) on another geometry: the padded,
+    many-layer field geometry of Table 3 (62 x 62 stations, 72 x 72 prisms per layer, up to 239
+    layers, n up to 1238976, embedding 256 x 256)."""
+    import torch
+
+    from paper_2004_13904_amd.operator import Operator
+    A = Operator(s, torch.float32)
+    g = torch.Generator(device="cuda").manual_seed(11)
+    x = torch.rand(A.n, device="cuda", generator=g)
+    d = torch.randn(A.m, device="cuda", generator=g)
+    gx = torch.empty(A.m, device="cuda")
+    gtd = torch.empty(A.n, device="cuda")
+
+    def step():
+        A.G(x, out=gx)
+        A.GT(d, out=gtd)
+    step()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for _ in range(R):
+            step()
+    ms = timed(graph.replay, reps) / R
+    NX, NY = A.nfft
+    S = s["nz"] * (NX // 2 + 1) * NY * 8
+    balg = 2 * (4 * A.n + 4 * A.m + S)
+    out = {"workload": f"{name}: {s['sx']}x{s['sy']} stations, pads {s['pad_xl']},{s['pad_xr']},"
+                       f"{s['pad_yl']},{s['pad_yr']}, nz={s['nz']}, n={A.n}, embedding {NX}x{NY}",
+           "us_per_pair": round(ms * 1e3, 3), "pairs_per_s": round(1e3 / ms, 1),
+           "path_GBs": round(balg / (ms * 1e-3) / 1e9, 1), "path_frac": round(balg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    log(f"{name}: {ms * 1e3:.1f} us per pair")
+    if check:
+        out["rel_err_vs_oracle"] = oracle_errors(s, x, d, gx, gtd)
+    A.close()
     return out
 
 

@@ -21,6 +21,14 @@ plane.  Sizes and models:
 * ``gravity_diff`` 128 x 128 stations, 20 m cubes, 16 layers (m = 16384,
                  n = 262144), gravity; batch of 4 random block models.
 * ``uneven_surveys`` eight gravity surveys from 32 x 32 x 6 to 180 x 120 x 16.
+* ``table3_survey(nz)`` the field-data geometry of Table 3: 62 x 62 stations at 100 m, 5
+                 padding cells on every side (72 x 72 prisms per layer), nz equal layers
+                 down to 2000 m (nz = 20 .. 239, n up to 1238976); TFA kernel with an
+                 assumed field (I = 75 deg, D = 5 deg, F = 50000 nT: the paper prints none
+                 and its data set is not available).
+* ``ladder_survey(l)`` the size ladder of Sec. 3.2 / Table 2: l (25, 15, 2) stations and
+                 layers over 2000 x 1200 x 400 m, padded by round(0.05 s) cells per side
+                 (round half away from zero).
 
 The paper's own synthetic structure exists only in its figures and its field data
 set is not available; the models here stand in for them.
@@ -45,6 +53,28 @@ SURVEYS = {
     "gravity_rsvd": survey(200, 150, 12, 20, 20, 20),
     "gravity_diff": survey(128, 128, 16, 20, 20, 20),
 }
+
+
+def table3_survey(nz, incl=75.0, decl=5.0):
+    return dict(sx=62, sy=62, nz=nz, dx=100.0, dy=100.0,
+                z_edges=tuple(2000.0 * k / nz for k in range(nz + 1)), kernel="magnetic",
+                incl_deg=float(incl), decl_deg=float(decl), field_nT=50000.0,
+                pad_xl=5, pad_xr=5, pad_yl=5, pad_yr=5)
+
+
+TABLE3_NZ = (20, 40, 59, 80, 100, 119, 160, 200, 239)
+
+
+def _round_half_away(v):
+    return int(np.floor(abs(v) + 0.5)) * (1 if v >= 0 else -1)
+
+
+def ladder_survey(ell, kernel="gravity", pad_fraction=0.05, incl=45.0, decl=45.0):
+    sx, sy, nz = 25 * ell, 15 * ell, 2 * ell
+    px, py = _round_half_away(pad_fraction * sx), _round_half_away(pad_fraction * sy)
+    return survey(sx, sy, nz, 2000.0 / sx, 1200.0 / sy, 400.0 / nz, kernel=kernel, incl=incl, decl=decl,
+                  pad=(px, px, py, py))
+
 
 UNEVEN = [(32, 32, 6), (48, 48, 8), (64, 48, 8), (80, 64, 10), (100, 60, 10),
           (128, 96, 12), (160, 100, 14), (180, 120, 16)]

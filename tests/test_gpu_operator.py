@@ -227,3 +227,30 @@ def test_spectra_checkpoint_round_trip(tmp_path, name, dtype):
     bad.write_bytes(path.read_bytes()[:-100])
     with pytest.raises(L.FastFocusError):
         Operator.load(str(bad))
+
+
+def _full_size_check(s, seed):
+    # FP32 G and G^T at full size against the oracle's direct sums over the Toeplitz blocks
+    g = ogeom(s)
+    T = op.kernel_table(g)
+    rng = np.random.default_rng(seed)
+    x = rng.random(g.n)
+    d = rng.standard_normal(g.m)
+    A = Operator(s, F32)
+    assert rel(to_host(A.G(to_dev(x, F32))), op.apply_G(g, x, T)) <= 1e-5
+    assert rel(to_host(A.GT(to_dev(d, F32))), op.apply_GT(g, d, T)) <= 1e-5
+
+
+@pytest.mark.parametrize("nz", [20, 239])
+def test_table3_geometry_padded_many_layers(nz):
+    # Table 3's field geometry: 62 x 62 stations, 5 padding cells per side, up to 239 thin
+    # layers (n = 1238976); non-zero extraction offsets and a long layer loop
+    announce("table3", nz)
+    _full_size_check(W.table3_survey(nz), nz)
+
+
+@pytest.mark.parametrize("ell,kernel", [(4, "gravity"), (7, "gravity"), (5, "magnetic"), (7, "magnetic")])
+def test_padded_size_ladder(ell, kernel):
+    # the padded ladder of Sec. 3.2 / Table 2 (pad = round(0.05 s) cells per side)
+    announce("ladder", ell, kernel)
+    _full_size_check(W.ladder_survey(ell, kernel), ell)

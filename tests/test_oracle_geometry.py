@@ -74,3 +74,19 @@ def test_geometry_coordinates():
     a, b = g.station_xy(0, 0)
     assert (a, b) == (30.0, 15.0)        # centre of surface cell (1, 0)
     assert g.cell_bounds(1, 0, 1)[:6] == (20.0, 40.0, 0.0, 30.0, 10.0, 20.0)
+
+
+def test_workload_ladder_and_table3_geometries_match_the_tables():
+    # the benchmark's padded ladder surveys and Table-3 geometry have the sizes of Tables 2 and 3
+    from paper_2004_13904_amd import workloads as W
+    for ell in (4, 5, 6, 7, 8, 11, 12):
+        s = W.ladder_survey(ell)
+        nx, ny, nz, m, n = W.sizes(s)
+        assert (m, m * nz, n) == geometry.ladder_counts(ell)
+    rows = [r for r in read_golden("table3_fielddata.txt")]
+    assert tuple(int(r[1]) for r in rows) == W.TABLE3_NZ
+    for r in rows:
+        s = W.table3_survey(int(r[1]))
+        assert W.sizes(s)[4] == int(r[0])
+        assert math.floor(s["z_edges"][1]) == int(r[2])            # the table prints floor(2000 / nz)
+        assert s["z_edges"][-1] == 2000.0
