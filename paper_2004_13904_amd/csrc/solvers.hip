@@ -32,6 +32,7 @@ constexpr int kTCols = 16;                 // basis columns per block of the tra
 constexpr int kRowsMin = 64 * kTLoads;     // rows per transposed-product block at one row per load
 constexpr int kNWaves = 8;                 // waves per block of the basis products A c
 constexpr int kMaxPowerIters = 8;          // largest RSVD power-iteration count accepted
+constexpr int kNormBlocks = 256;           // blocks (partial sums) of the norm reductions
 constexpr int kUpreGrid = 400;
 constexpr double kUpreLo = 1e-3;
 constexpr double kGoldenTol = 1e-10;
@@ -87,6 +88,54 @@ __global__ void k_scale(const double *__restrict__ x, const double *__restrict__
     y[i] = a * x[i];
 }
 
+// y += sign * (*sc) * x, and the block's partial sum of the updated y^2 in part[blockIdx.x]
+// (grid-stride; launched with a fixed grid of kNormBlocks blocks)
+__global__ void k_axpy_sumsq(double *__restrict__ y, const double *__restrict__ x, const double *__restrict__ sc,
+                             double sign, int64_t n, double *__restrict__ part) {
+  __shared__ double red[16];
+  const double a = sign * (*sc);
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = y[i] + a * x[i];
+    y[i] = v;
+    s += v * v;
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// After the first Gram-Schmidt pass: n1 = ||v1|| from the partials, the second-pass test
+// against n0 = *dg (flag = n1 < n0 / sqrt 2, Daniel-Gragg-Kaufman-Stewart), and the norm
+// and its inverse as they stand if the second pass is skipped.
+__global__ void k_norm_flag(const double *__restrict__ part, int P, const double *__restrict__ n0,
+                            int *__restrict__ flag, double *__restrict__ nrm, double *__restrict__ inv) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < P; i += blockDim.x) s += part[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) {
+    const double v = sqrt(s);
+    *flag = (v < 0.70710678118654752 * *n0) ? 1 : 0;
+    *nrm = v;
+    *inv = v > 0.0 ? 1.0 / v : 0.0;
+  }
+}
+
+// After a second pass that ran (*flag != 0): the norm from the partials of the pass's update.
+__global__ void k_norm_cond(const double *__restrict__ part, int P, const int *__restrict__ flag,
+                            double *__restrict__ nrm, double *__restrict__ inv) {
+  if (*flag == 0) return;
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < P; i += blockDim.x) s += part[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) {
+    const double v = sqrt(s);
+    *nrm = v;
+    *inv = v > 0.0 ? 1.0 / v : 0.0;
+  }
+}
+
 // Gaussian test matrix from a counter-based generator: Philox4x32-10 (Salmon, Moraes, Dror and
 // Shaw, SC 2011).  Pair p of the output (elements 2p, 2p+1) is drawn from the counter
 // (p mod 2^32, p / 2^32, stream, 0) under the key (seed mod 2^32, seed / 2^32): two 53-bit
@@ -126,14 +175,6 @@ __global__ void k_gaussian(double *__restrict__ out, int64_t count, uint64_t see
 // when ||v1|| < ||v0|| / sqrt(2).
 __global__ void k_dgks_flag(const double *__restrict__ n0, const double *__restrict__ n1, int *__restrict__ run) {
   if (threadIdx.x == 0) *run = (*n1 < 0.70710678118654752 * *n0) ? 1 : 0;
-}
-
-// y += sign * (*sc) * x
-__global__ void k_axpy_dev(double *__restrict__ y, const double *__restrict__ x, const double *__restrict__ sc, double sign,
-                           int64_t n) {
-  const double a = sign * (*sc);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    y[i] += a * x[i];
 }
 
 // partial[p][j] = sum over the rows of row block p of A[row, j] * x[row]  (A column-major, ld
@@ -221,7 +262,7 @@ k_colsum(const double *__restrict__ part, int P, int ncols, double *__restrict__
 template <int RPL>
 __global__ void __launch_bounds__(64 * kNWaves)
 k_gemv_n(const double *__restrict__ A, int64_t lda, int64_t nrows, int ncols, const double *__restrict__ c,
-         double *__restrict__ y, double alpha, double beta, const int *__restrict__ run) {
+         double *__restrict__ y, double alpha, double beta, const int *__restrict__ run, double *__restrict__ sq) {
   if (run && *run == 0) return;
   __shared__ double red[kNWaves][64 * RPL];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -268,13 +309,21 @@ k_gemv_n(const double *__restrict__ A, int64_t lda, int64_t nrows, int ncols, co
 #pragma unroll
   for (int q = 0; q < RPL; ++q) red[w][l * RPL + q] = s[q];
   __syncthreads();
+  double ss = 0.0;
   for (int e = threadIdx.x; e < 64 * RPL; e += 64 * kNWaves) {
     const int64_t rr = (int64_t)blockIdx.x * 64 * RPL + e;
     if (rr < nrows) {
       double t = red[0][e];
       for (int q = 1; q < kNWaves; ++q) t += red[q][e];
-      y[rr] = (beta == 0.0 ? 0.0 : beta * y[rr]) + alpha * t;
+      const double v = (beta == 0.0 ? 0.0 : beta * y[rr]) + alpha * t;
+      y[rr] = v;
+      ss += v * v;
     }
+  }
+  if (sq) {   // this block's partial sum of the updated y^2
+    __shared__ double rs[16];
+    ss = block_sum(ss, rs);
+    if (threadIdx.x == 0) sq[blockIdx.x] = ss;
   }
 }
 
@@ -578,33 +627,41 @@ void launch_gemv_t(const double *Q, int64_t ld, int64_t nrows, int ncols, const 
   k_colsum<<<(ncols + 63) / 64, kThreads, 0, s>>>(part, P, ncols, out, 1.0, run);
 }
 
-void launch_gemv_n(const double *Q, int64_t ld, int64_t nrows, int ncols, const double *c, double *y, double alpha,
-                   double beta, hipStream_t s, const int *run = nullptr) {
+// Returns the number of blocks (= partial sums written to sq, if given).
+int launch_gemv_n(const double *Q, int64_t ld, int64_t nrows, int ncols, const double *c, double *y, double alpha,
+                  double beta, hipStream_t s, const int *run = nullptr, double *sq = nullptr) {
   // paired rows pay off on long bases; short ones want more blocks
-  if (rows_per_load(Q, ld) == 2 && nrows >= 32768)
-    k_gemv_n<2><<<(unsigned)((nrows + 127) / 128), 64 * kNWaves, 0, s>>>(Q, ld, nrows, ncols, c, y, alpha, beta,
-                                                                          run);
-  else
-    k_gemv_n<1><<<(unsigned)((nrows + 63) / 64), 64 * kNWaves, 0, s>>>(Q, ld, nrows, ncols, c, y, alpha, beta,
-                                                                        run);
+  if (rows_per_load(Q, ld) == 2 && nrows >= 32768) {
+    const unsigned nb = (unsigned)((nrows + 127) / 128);
+    k_gemv_n<2><<<nb, 64 * kNWaves, 0, s>>>(Q, ld, nrows, ncols, c, y, alpha, beta, run, sq);
+    return (int)nb;
+  }
+  const unsigned nb = (unsigned)((nrows + 63) / 64);
+  k_gemv_n<1><<<nb, 64 * kNWaves, 0, s>>>(Q, ld, nrows, ncols, c, y, alpha, beta, run, sq);
+  return (int)nb;
 }
 
 // v <- (I - Q Q^T) v over the first ncols columns of Q (classical Gram-Schmidt), repeated once
-// when the first pass cancelled most of v (k_dgks_flag); the test stays on the device.
-// dg: 2 doubles (norms) and flag: 1 int of scratch.
-ff_status reorth(const double *Q, int64_t ld, int64_t nrows, int ncols, double *v, double *coef, double *part,
-                 double *dg, int *flag, hipStream_t s) {
-  if (ncols <= 0) return FF_OK;
-  const int P = 256;
-  k_sumsq_partial<<<P, kThreads, 0, s>>>(v, nrows, part);
-  k_norm_finalize<<<1, kThreads, 0, s>>>(part, P, dg, nullptr);
+// when the first pass cancelled most of v (k_norm_flag); the test stays on the device.  On
+// return *nrm = ||v|| and *inv = 1/||v|| (0 for a zero vector).  `part` holds, on entry when
+// have_sq, the kNormBlocks partial sums of v^2 (else they are formed here); it is also the
+// scratch of the products.  dg: 1 double, flag: 1 int of scratch.
+ff_status reorth_norm(const double *Q, int64_t ld, int64_t nrows, int ncols, double *v, double *coef, double *part,
+                      bool have_sq, double *dg, int *flag, double *nrm, double *inv, hipStream_t s) {
+  if (!have_sq) k_sumsq_partial<<<kNormBlocks, kThreads, 0, s>>>(v, nrows, part);
+  if (ncols <= 0) {
+    k_norm_finalize<<<1, kThreads, 0, s>>>(part, kNormBlocks, nrm, inv);
+    FF_LAUNCH_CHECK("norm");
+    return FF_OK;
+  }
+  k_norm_finalize<<<1, kThreads, 0, s>>>(part, kNormBlocks, dg, nullptr);
   launch_gemv_t(Q, ld, nrows, ncols, v, coef, part, s);
   launch_gemv_n(Q, ld, nrows, ncols, coef, v, -1.0, 1.0, s);
-  k_sumsq_partial<<<P, kThreads, 0, s>>>(v, nrows, part);
-  k_norm_finalize<<<1, kThreads, 0, s>>>(part, P, dg + 1, nullptr);
-  k_dgks_flag<<<1, 64, 0, s>>>(dg, dg + 1, flag);
+  k_sumsq_partial<<<kNormBlocks, kThreads, 0, s>>>(v, nrows, part);
+  k_norm_flag<<<1, kThreads, 0, s>>>(part, kNormBlocks, dg, flag, nrm, inv);
   launch_gemv_t(Q, ld, nrows, ncols, v, coef, part, s, flag);
-  launch_gemv_n(Q, ld, nrows, ncols, coef, v, -1.0, 1.0, s, flag);
+  const int nb = launch_gemv_n(Q, ld, nrows, ncols, coef, v, -1.0, 1.0, s, flag, part);
+  k_norm_cond<<<1, kThreads, 0, s>>>(part, nb, flag, nrm, inv);
   FF_LAUNCH_CHECK("reorthogonalization");
   return FF_OK;
 }
@@ -641,6 +698,8 @@ struct GkbWs {
   rocblas_int *info;
   void carve(Arena &a, int64_t n, int64_t m, int tp) {
     const int64_t P = ((n > m ? n : m) + kRowsMin - 1) / kRowsMin + 1;   // partial rows at one row per load
+    const int64_t Pn = ((n > m ? n : m) + 63) / 64 + 1;                  // blocks of the A c products
+    const int64_t npart = ((P > 256 ? P : 256) + 1) * (tp + 2);
     A = a.take<double>((size_t)n * tp);
     H = a.take<double>((size_t)m * (tp + 1));
     b = a.take<double>(n);
@@ -650,7 +709,7 @@ struct GkbWs {
     ginv = a.take<double>(tp + 1);
     binv = a.take<double>(tp + 2);
     coef = a.take<double>(tp + 2);
-    part = a.take<double>((size_t)((P > 256 ? P : 256) + 1) * (tp + 2));
+    part = a.take<double>((size_t)(npart > Pn ? npart : Pn));
     dT = a.take<double>(2 * (size_t)tp + 1);
     eT = a.take<double>(2 * (size_t)tp + 1);
     C = a.take<double>((2 * (size_t)tp + 1) * (2 * (size_t)tp + 1));
@@ -660,7 +719,7 @@ struct GkbWs {
     g = a.take<double>(tp);
     w = a.take<double>(tp);
     alpha = a.take<double>(2);
-    dg = a.take<double>(2);
+    dg = a.take<double>(1);
     flag = a.take<int>(1);
     info = a.take<rocblas_int>(4);
   }
@@ -751,17 +810,19 @@ ff_status gkb_run(ff_spectra h, const double *rt, const double *wd, const double
   for (int i = 0; i < tp; ++i) {
     double *ai = W.A + (int64_t)i * n;
     const double *hi = W.H + (int64_t)i * m;
-    // b = G~^T h - beta_i a_{i-1}
+    // b = G~^T h - beta_i a_{i-1}, reorthogonalized; gamma_i = ||b||
     if ((st = op_apply(h, 1, 1, hi, m, W.b, n, wd, winv, FF_F64, s))) return st;
-    if (i > 0) k_axpy_dev<<<grid_for(n), kThreads, 0, s>>>(W.b, W.A + (int64_t)(i - 1) * n, W.beta + i, -1.0, n);
-    if ((st = reorth(W.A, n, n, i, W.b, W.coef, W.part, W.dg, W.flag, s))) return st;
-    if ((st = norm2(W.b, n, W.gamma + i, W.ginv + i, W.part, s))) return st;
+    if (i > 0)
+      k_axpy_sumsq<<<kNormBlocks, kThreads, 0, s>>>(W.b, W.A + (int64_t)(i - 1) * n, W.beta + i, -1.0, n, W.part);
+    if ((st = reorth_norm(W.A, n, n, i, W.b, W.coef, W.part, i > 0, W.dg, W.flag, W.gamma + i, W.ginv + i, s)))
+      return st;
     k_scale<<<grid_for(n), kThreads, 0, s>>>(W.b, W.ginv + i, ai, n);
-    // c = G~ a - gamma_i h
+    // c = G~ a - gamma_i h, reorthogonalized; beta_{i+1} = ||c||
     if ((st = op_apply(h, 0, 1, ai, n, W.c, m, winv, wd, FF_F64, s))) return st;
-    k_axpy_dev<<<grid_for(m), kThreads, 0, s>>>(W.c, hi, W.gamma + i, -1.0, m);
-    if ((st = reorth(W.H, m, m, i + 1, W.c, W.coef, W.part, W.dg, W.flag, s))) return st;
-    if ((st = norm2(W.c, m, W.beta + i + 1, W.binv + i + 1, W.part, s))) return st;
+    k_axpy_sumsq<<<kNormBlocks, kThreads, 0, s>>>(W.c, hi, W.gamma + i, -1.0, m, W.part);
+    if ((st = reorth_norm(W.H, m, m, i + 1, W.c, W.coef, W.part, true, W.dg, W.flag, W.beta + i + 1,
+                          W.binv + i + 1, s)))
+      return st;
     k_scale<<<grid_for(m), kThreads, 0, s>>>(W.c, W.binv + i + 1, W.H + (int64_t)(i + 1) * m, m);
   }
   FF_LAUNCH_CHECK("gkb iteration");
