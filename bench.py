@@ -68,7 +68,9 @@ def main(argv=None):
                     help="comma list of extra legs (batched, rsvd, multi, autograd, table3, irls; "
                          "opt-in: irls_c2)")
     ap.add_argument("--irls-c2-steps", type=int, default=1,
-                    help="IRLS steps of the opt-in n = 1e6 magnetic leg (each step ~20 s)")
+                    help="IRLS steps of the opt-in n = 1e6 magnetic leg (each step ~10 s)")
+    ap.add_argument("--irls-c2-basis", default="f64", choices=("f64", "f32"),
+                    help="GKB basis storage of the opt-in n = 1e6 magnetic leg")
     ap.add_argument("--irls-steps", type=int, default=25)
     ap.add_argument("--calib", action="store_true",
                     help="end with a plain 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
@@ -271,8 +273,9 @@ def main(argv=None):
     if "irls" in legs:
         result["irls"] = irls_leg(a.irls_steps, lam=0.0)
         result["irls_l1"] = irls_leg(a.irls_steps, lam=1.0, stop=True)
+        result["irls_l1_f32basis"] = irls_leg(a.irls_steps, lam=1.0, stop=True, basis="f32")
     if "irls_c2" in legs:
-        result["irls_magnetic_1m"] = irls_c2_leg(a.irls_c2_steps)
+        result["irls_magnetic_1m"] = irls_c2_leg(a.irls_c2_steps, a.irls_c2_basis)
 
     if a.calib:
         src = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
@@ -591,7 +594,7 @@ def multi_survey_leg():
             "ms_sequential_launches": round(ms_eager, 5), "speedup": round(ms_eager / ms_graph, 3)}
 
 
-def irls_leg(steps, lam=0.0, stop=False):
+def irls_leg(steps, lam=0.0, stop=False, basis="f64"):
     """IRLS time on the gravity 100 x 60 x 10 survey (m = 6000, n = 60000): two 1 g/cc blocks,
     1 % noise (tau1 = 0.01, tau2 = 0.001), stabilizer lambda (0 = minimum support, timed over a
     fixed number of steps; 1 = the paper's L1 choice, run to the chi^2 test), depth weighting
@@ -609,7 +612,7 @@ def irls_leg(steps, lam=0.0, stop=False):
     d_obs = torch.tensor(d_exact + eta, dtype=torch.float64, device="cuda")
     wd = torch.tensor(1.0 / sd, dtype=torch.float64, device="cuda")
     p = SV.IrlsParams(solver="gkb", t=750, tp=787, lam=lam, eps2=1e-9, beta_depth=0.8, m_min=0.0,
-                      m_max=1.0)
+                      m_max=1.0, basis=basis)
     times = []
     t_last = [time.perf_counter()]
 
@@ -628,13 +631,13 @@ def irls_leg(steps, lam=0.0, stop=False):
     mt = m_true.double()
     re = float(torch.linalg.norm(mt - m) / torch.linalg.norm(mt))
     return {"workload": "gravity_l4: 100x60 stations, nz=10, GKB t=750 t_p=787, FP32 operator, FP64 solve",
-            "lambda": lam,
+            "lambda": lam, "basis": basis,
             "steps": len(hist), "converged": hist[-1][2] <= 1.0, "seconds_total": round(total, 3),
             "seconds_per_step": round(total / len(hist), 4), "final_chi2_scaled": round(hist[-1][2], 4),
             "alpha_1": hist[0][1], "alpha_K": hist[-1][1], "RE": round(re, 4)}
 
 
-def irls_c2_leg(steps):
+def irls_c2_leg(steps, basis="f64"):
     """IRLS on the n = 1e6 magnetic survey (250 x 200 x 20, TFA with I = D = 45 deg): a 0.1 SI cube
     and a 45-degree dipping dike, 2 % noise (tau1 = 0.02, tau2 = 0.002), minimum support
     (lambda = 0, eps^2 = 1e-9), depth weighting beta = 1.4, bounds [0, 0.1], GKB with
@@ -654,7 +657,7 @@ def irls_c2_leg(steps):
     d_obs = torch.tensor(d_exact + eta, dtype=torch.float64, device="cuda")
     wd = torch.tensor(1.0 / sd, dtype=torch.float64, device="cuda")
     p = SV.IrlsParams(solver="gkb", t=2500, tp=2625, lam=0.0, eps2=1e-9, beta_depth=1.4, m_min=0.0,
-                      m_max=0.1)
+                      m_max=0.1, basis=basis)
     times = []
     t_last = [0.0]
 
@@ -673,10 +676,10 @@ def irls_c2_leg(steps):
     tp, n, mm = p.tp, A.n, A.m
     # one Gram-Schmidt pass (Q^T v, then v - Q c) over both bases per iteration; the second pass
     # runs only when the first cancels most of the vector
-    reorth_bytes = 2 * 8 * (n + mm) * tp * (tp + 1) / 2
+    reorth_bytes = 2 * (8 if basis == "f64" else 4) * (n + mm) * tp * (tp + 1) / 2
     return {"workload": "magnetic_1m: 250x200 stations, nz=20, cube + dipping dike, 2% noise, GKB t=2500 "
                         "t_p=2625, FP32 operator, FP64 solve",
-            "steps": len(hist), "seconds_per_step": [round(x, 3) for x in times],
+            "basis": basis, "steps": len(hist), "seconds_per_step": [round(x, 3) for x in times],
             "seconds_total": round(total, 3), "chi2_scaled": [round(h[2], 4) for h in hist],
             "reorth_bytes_per_step": reorth_bytes,
             "reorth_GBs_if_all_time": round(reorth_bytes / (total / len(hist)) / 1e9, 1)}

@@ -138,18 +138,24 @@ ff_status apply_G_block(ff_spectra h, int32_t transpose, int64_t k, const void *
 #define FF_WS_GKB  0
 #define FF_WS_RSVD 1
 #define FF_WS_IRLS 2
-ff_status ff_workspace_size(ff_spectra h, int32_t which, int32_t solver, int32_t tp,
+/* which: FF_WS_GKB, FF_WS_RSVD or FF_WS_IRLS (then solver 0 = GKB, 1 = RSVD); basis_dtype:
+   FF_F64 or FF_F32 storage of the GKB bases (ignored for RSVD); 1 <= tp <= m. */
+ff_status ff_workspace_size(ff_spectra h, int32_t which, int32_t solver, int32_t basis_dtype, int32_t tp,
                             size_t *bytes);
 
 /* Algorithm 1: GKB factorization G~ A = H B of G~ = diag(wd) G diag(winv) with
    reorthogonalization of A and H, SVD of the (tp+1) x tp bidiagonal B, and the solution
    y = ||r~|| A V Gamma(alpha, Sigma) U(1,:)^T.  Inputs r_tilde (m), wd (m), winv (n).
    alpha_mode: 0 = UPRE over the first t singular values, 1 = alpha^(1) of eq. (eq:alpha1),
-   2 = fixed (*alpha on input).  Outputs y (n, standard form: the model update is
-   winv .* y), *alpha (host), sigma (tp, device, descending).  1 <= t <= tp <= m. */
+   2 = fixed (*alpha on input).  basis_dtype: FF_F64 stores A and H in double precision (the
+   default of the method); FF_F32 stores them in single precision (half the memory and the
+   reorthogonalization traffic, orthogonality to about 1e-7; every product and sum is still
+   formed in double).  Outputs y (n, standard form: the model update is winv .* y), *alpha
+   (host), sigma (tp, device, descending).  1 <= t <= tp <= m. */
 ff_status gkb_project(ff_spectra h, const double *r_tilde, const double *wd, const double *winv,
-                      int32_t t, int32_t tp, int32_t alpha_mode, double *y, double *alpha,
-                      double *sigma, void *workspace, size_t ws_bytes, ff_stream stream);
+                      int32_t t, int32_t tp, int32_t alpha_mode, int32_t basis_dtype, double *y,
+                      double *alpha, double *sigma, void *workspace, size_t ws_bytes,
+                      ff_stream stream);
 
 /* Algorithm 2: randomized SVD of G~ (same weights as above) with power_iters power iterations
    (the paper uses 1; 0 <= power_iters <= 8), eigen-decomposition of the symmetrized B^T B,
@@ -176,6 +182,7 @@ typedef struct {
     double alpha_fixed;  /* > 0: use this alpha; otherwise eq. (eq:alpha1) at k = 1, UPRE after */
     int32_t power_iters; /* RSVD power iterations (the paper: 1)                            */
     uint64_t seed;       /* RSVD with omega = NULL: Omega drawn from (seed, counter word 2 = k) */
+    int32_t basis_dtype; /* GKB basis storage: FF_F64 or FF_F32 (see gkb_project)           */
 } ff_irls_params;
 
 /* One IRLS step: W = W_z W_L^(k) with (W_L^(k))_ii = ((m_prev - m_prev2)_i^2 + eps2)^((lambda-2)/4)

@@ -39,7 +39,7 @@ class FFIrlsParams(C.Structure):
     _fields_ = [("solver", C.c_int32), ("t", C.c_int32), ("tp", C.c_int32), ("k", C.c_int32),
                 ("lam", C.c_double), ("eps2", C.c_double), ("beta_depth", C.c_double),
                 ("m_min", C.c_double), ("m_max", C.c_double), ("alpha_fixed", C.c_double),
-                ("power_iters", C.c_int32), ("seed", C.c_uint64)]
+                ("power_iters", C.c_int32), ("seed", C.c_uint64), ("basis_dtype", C.c_int32)]
 
 
 class FFTuning(C.Structure):
@@ -75,8 +75,8 @@ def load(path=None):
         "apply_G": [vp, vp, vp, vp, vp, vp],
         "apply_GT": [vp, vp, vp, vp, vp, vp],
         "apply_G_block": [vp, i32, i64, vp, i64, vp, i64, vp, vp, vp],
-        "ff_workspace_size": [vp, i32, i32, i32, C.POINTER(C.c_size_t)],
-        "gkb_project": [vp, vp, vp, vp, i32, i32, i32, vp, dp, vp, vp, C.c_size_t, vp],
+        "ff_workspace_size": [vp, i32, i32, i32, i32, C.POINTER(C.c_size_t)],
+        "gkb_project": [vp, vp, vp, vp, i32, i32, i32, i32, vp, dp, vp, vp, C.c_size_t, vp],
         "rsvd_project": [vp, vp, vp, vp, i32, i32, vp, C.c_uint64, i32, i32, vp, dp, vp, vp, C.c_size_t, vp],
         "irls_step": [vp, C.POINTER(FFIrlsParams), vp, vp, vp, vp, vp, vp, dp, dp, vp, C.c_size_t,
                       vp],

@@ -88,20 +88,68 @@ __global__ void k_scale(const double *__restrict__ x, const double *__restrict__
     y[i] = a * x[i];
 }
 
+// Basis storage of the GKB factors: FP64 (default) or FP32 (half the memory and traffic; the
+// arithmetic stays FP64).  load_rows reads RPL consecutive rows of a basis column with one
+// vector load (16 bytes: RPL = 2 for double, 4 for float) and widens them to double.
+template <typename TB, int RPL> struct Vec { using type = TB; };
+template <> struct Vec<double, 2> { using type = double2; };
+template <> struct Vec<float, 2> { using type = float2; };
+template <> struct Vec<float, 4> { using type = float4; };
+
+template <typename TB, int RPL> __device__ __forceinline__ void load_rows(const TB *p, double (&o)[RPL]) {
+  const typename Vec<TB, RPL>::type v = *(const typename Vec<TB, RPL>::type *)p;
+  if constexpr (RPL == 1) {
+    o[0] = (double)v;
+  } else if constexpr (RPL == 2) {
+    o[0] = (double)v.x;
+    o[1] = (double)v.y;
+  } else {
+    o[0] = (double)v.x;
+    o[1] = (double)v.y;
+    o[2] = (double)v.z;
+    o[3] = (double)v.w;
+  }
+}
+
 // y += sign * (*sc) * x, and the block's partial sum of the updated y^2 in part[blockIdx.x]
 // (grid-stride; launched with a fixed grid of kNormBlocks blocks)
-__global__ void k_axpy_sumsq(double *__restrict__ y, const double *__restrict__ x, const double *__restrict__ sc,
+template <typename TX>
+__global__ void k_axpy_sumsq(double *__restrict__ y, const TX *__restrict__ x, const double *__restrict__ sc,
                              double sign, int64_t n, double *__restrict__ part) {
   __shared__ double red[16];
   const double a = sign * (*sc);
   double s = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const double v = y[i] + a * x[i];
+    const double v = y[i] + a * (double)x[i];
     y[i] = v;
     s += v * v;
   }
   s = block_sum(s, red);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// b <- (TB)(b * (*sc)) rounded back to double, also stored as a basis column: the operator
+// is then applied to exactly the vector the basis holds.
+template <typename TB>
+__global__ void k_scale_store(double *__restrict__ b, const double *__restrict__ sc, TB *__restrict__ col, int64_t n) {
+  const double a = *sc;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const TB t = (TB)(a * b[i]);
+    col[i] = t;
+    b[i] = (double)t;
+  }
+}
+
+// out = (*sc) * x with x given in double, stored as TB and (rounded) as double
+template <typename TB>
+__global__ void k_scale_from(const double *__restrict__ x, const double *__restrict__ sc, TB *__restrict__ col,
+                             double *__restrict__ dbl, int64_t n) {
+  const double a = *sc;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const TB t = (TB)(a * x[i]);
+    col[i] = t;
+    dbl[i] = (double)t;
+  }
 }
 
 // After the first Gram-Schmidt pass: n1 = ||v1|| from the partials, the second-pass test
@@ -170,20 +218,13 @@ __global__ void k_gaussian(double *__restrict__ out, int64_t count, uint64_t see
   }
 }
 
-// Second-pass test of the reorthogonalization (Daniel, Gragg, Kaufman and Stewart): the pass
-// is repeated when the first one removed more than half of the vector's squared norm, i.e.
-// when ||v1|| < ||v0|| / sqrt(2).
-__global__ void k_dgks_flag(const double *__restrict__ n0, const double *__restrict__ n1, int *__restrict__ run) {
-  if (threadIdx.x == 0) *run = (*n1 < 0.70710678118654752 * *n0) ? 1 : 0;
-}
-
 // partial[p][j] = sum over the rows of row block p of A[row, j] * x[row]  (A column-major, ld
 // lda).  Each lane loads RPL consecutive rows at once (RPL = 2: 16-byte loads), kTLoads times,
 // so a block covers kRowsMin * RPL rows and kTCols columns; each of its four waves takes
 // kTCols/4 columns (x held in registers).  Grid: (ceil(nrows / (kRowsMin * RPL)), ceil(ncols / kTCols)).
-template <int RPL>
+template <int RPL, typename TB>
 __global__ void __launch_bounds__(kThreads)
-k_gemv_t_partial(const double *__restrict__ A, int64_t lda, int64_t nrows, int ncols, const double *__restrict__ x,
+k_gemv_t_partial(const TB *__restrict__ A, int64_t lda, int64_t nrows, int ncols, const double *__restrict__ x,
                  double *__restrict__ part, const int *__restrict__ run) {
   if (run && *run == 0) return;   // conditional pass switched off on the device
   constexpr int K = kTLoads, CW = kTCols / (kThreads / 64);
@@ -204,22 +245,19 @@ k_gemv_t_partial(const double *__restrict__ A, int64_t lda, int64_t nrows, int n
     s[c] = 0.0;
     const int j = c0 + c;
     if (j < ncols) {
-      const double *a = A + (int64_t)j * lda;
+      const TB *a = A + (int64_t)j * lda;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const int64_t r = r0 + (int64_t)(l + 64 * k) * RPL;
         if (r + RPL <= nrows) {
-          if constexpr (RPL == 2) {
-            const double2 p = *(const double2 *)(a + r);
-            s[c] += p.x * xv[k][0];
-            s[c] += p.y * xv[k][1];
-          } else {
-            s[c] += a[r] * xv[k][0];
-          }
+          double e[RPL];
+          load_rows<TB, RPL>(a + r, e);
+#pragma unroll
+          for (int q = 0; q < RPL; ++q) s[c] += e[q] * xv[k][q];
         } else {
 #pragma unroll
           for (int q = 0; q < RPL; ++q)
-            if (r + q < nrows) s[c] += a[r + q] * xv[k][q];
+            if (r + q < nrows) s[c] += (double)a[r + q] * xv[k][q];
         }
       }
     }
@@ -259,9 +297,9 @@ k_colsum(const double *__restrict__ part, int P, int ncols, double *__restrict__
 // the columns [w ncols / kNWaves, (w + 1) ncols / kNWaves), so that many column loads of a lane
 // are in flight; the waves' sums meet in LDS and are added in wave order.
 // Grid: ceil(nrows / (64 * RPL)) blocks of 64 * kNWaves threads.
-template <int RPL>
+template <int RPL, typename TB>
 __global__ void __launch_bounds__(64 * kNWaves)
-k_gemv_n(const double *__restrict__ A, int64_t lda, int64_t nrows, int ncols, const double *__restrict__ c,
+k_gemv_n(const TB *__restrict__ A, int64_t lda, int64_t nrows, int ncols, const double *__restrict__ c,
          double *__restrict__ y, double alpha, double beta, const int *__restrict__ run, double *__restrict__ sq) {
   if (run && *run == 0) return;
   __shared__ double red[kNWaves][64 * RPL];
@@ -272,20 +310,12 @@ k_gemv_n(const double *__restrict__ A, int64_t lda, int64_t nrows, int ncols, co
 #pragma unroll
   for (int q = 0; q < RPL; ++q) s[q] = 0.0;
   if (r + RPL <= nrows) {
-    const double *a = A + r;
+    const TB *a = A + r;
     int j = j0;
     for (; j + 4 <= j1; j += 4) {
       double v[4][RPL];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        if constexpr (RPL == 2) {
-          const double2 p = *(const double2 *)(a + (int64_t)(j + t) * lda);
-          v[t][0] = p.x;
-          v[t][1] = p.y;
-        } else {
-          v[t][0] = a[(int64_t)(j + t) * lda];
-        }
-      }
+      for (int t = 0; t < 4; ++t) load_rows<TB, RPL>(a + (int64_t)(j + t) * lda, v[t]);
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const double cj = c[j + t];
@@ -296,14 +326,14 @@ k_gemv_n(const double *__restrict__ A, int64_t lda, int64_t nrows, int ncols, co
     for (; j < j1; ++j) {
       const double cj = c[j];
 #pragma unroll
-      for (int q = 0; q < RPL; ++q) s[q] += a[(int64_t)j * lda + q] * cj;
+      for (int q = 0; q < RPL; ++q) s[q] += (double)a[(int64_t)j * lda + q] * cj;
     }
   } else {
     for (int j = j0; j < j1; ++j) {
       const double cj = c[j];
 #pragma unroll
       for (int q = 0; q < RPL; ++q)
-        if (r + q < nrows) s[q] += A[(int64_t)j * lda + r + q] * cj;
+        if (r + q < nrows) s[q] += (double)A[(int64_t)j * lda + r + q] * cj;
     }
   }
 #pragma unroll
@@ -564,7 +594,12 @@ unsigned grid_for(int64_t n, int threads = kThreads, int64_t cap = 4096) {
 
 // Rows per lane load of the basis products: two (16-byte loads) when every column start of the
 // basis is 16-byte aligned.
-int rows_per_load(const double *Q, int64_t ld) { return (ld % 2 == 0 && ((uintptr_t)Q & 15) == 0) ? 2 : 1; }
+// Rows per lane load of a basis: 16 bytes (2 doubles or 4 floats) when every column start is
+// 16-byte aligned, else 1.
+template <typename TB> int rows_per_load(const TB *Q, int64_t ld) {
+  constexpr int R = 16 / (int)sizeof(TB);
+  return (ld % R == 0 && ((uintptr_t)Q % 16) == 0) ? R : 1;
+}
 int partials_for(int64_t nrows, int rpl) {
   const int64_t rows = (int64_t)kRowsMin * rpl;
   return (int)((nrows + rows - 1) / rows);
@@ -615,29 +650,33 @@ struct Arena {
 // out = Q^T v (partials in part, then summed) and y = beta y + alpha Q c, with the launch shapes
 // of the kernels above.
 // `run` (device flag, may be NULL): the kernels return at once when it is 0.
-void launch_gemv_t(const double *Q, int64_t ld, int64_t nrows, int ncols, const double *v, double *out, double *part,
+template <typename TB>
+void launch_gemv_t(const TB *Q, int64_t ld, int64_t nrows, int ncols, const double *v, double *out, double *part,
                    hipStream_t s, const int *run = nullptr) {
   const int rpl = rows_per_load(Q, ld);
   const int P = partials_for(nrows, rpl);
   const dim3 gt(P, (ncols + kTCols - 1) / kTCols);
-  if (rpl == 2)
-    k_gemv_t_partial<2><<<gt, kThreads, 0, s>>>(Q, ld, nrows, ncols, v, part, run);
+  constexpr int R = 16 / (int)sizeof(TB);
+  if (rpl == R)
+    k_gemv_t_partial<R, TB><<<gt, kThreads, 0, s>>>(Q, ld, nrows, ncols, v, part, run);
   else
-    k_gemv_t_partial<1><<<gt, kThreads, 0, s>>>(Q, ld, nrows, ncols, v, part, run);
+    k_gemv_t_partial<1, TB><<<gt, kThreads, 0, s>>>(Q, ld, nrows, ncols, v, part, run);
   k_colsum<<<(ncols + 63) / 64, kThreads, 0, s>>>(part, P, ncols, out, 1.0, run);
 }
 
 // Returns the number of blocks (= partial sums written to sq, if given).
-int launch_gemv_n(const double *Q, int64_t ld, int64_t nrows, int ncols, const double *c, double *y, double alpha,
+template <typename TB>
+int launch_gemv_n(const TB *Q, int64_t ld, int64_t nrows, int ncols, const double *c, double *y, double alpha,
                   double beta, hipStream_t s, const int *run = nullptr, double *sq = nullptr) {
-  // paired rows pay off on long bases; short ones want more blocks
-  if (rows_per_load(Q, ld) == 2 && nrows >= 32768) {
-    const unsigned nb = (unsigned)((nrows + 127) / 128);
-    k_gemv_n<2><<<nb, 64 * kNWaves, 0, s>>>(Q, ld, nrows, ncols, c, y, alpha, beta, run, sq);
+  // 16-byte loads pay off on long bases; short ones want more blocks
+  constexpr int R = 16 / (int)sizeof(TB);
+  if (rows_per_load(Q, ld) == R && nrows >= 32768) {
+    const unsigned nb = (unsigned)((nrows + 64 * R - 1) / (64 * R));
+    k_gemv_n<R, TB><<<nb, 64 * kNWaves, 0, s>>>(Q, ld, nrows, ncols, c, y, alpha, beta, run, sq);
     return (int)nb;
   }
   const unsigned nb = (unsigned)((nrows + 63) / 64);
-  k_gemv_n<1><<<nb, 64 * kNWaves, 0, s>>>(Q, ld, nrows, ncols, c, y, alpha, beta, run, sq);
+  k_gemv_n<1, TB><<<nb, 64 * kNWaves, 0, s>>>(Q, ld, nrows, ncols, c, y, alpha, beta, run, sq);
   return (int)nb;
 }
 
@@ -646,7 +685,8 @@ int launch_gemv_n(const double *Q, int64_t ld, int64_t nrows, int ncols, const d
 // return *nrm = ||v|| and *inv = 1/||v|| (0 for a zero vector).  `part` holds, on entry when
 // have_sq, the kNormBlocks partial sums of v^2 (else they are formed here); it is also the
 // scratch of the products.  dg: 1 double, flag: 1 int of scratch.
-ff_status reorth_norm(const double *Q, int64_t ld, int64_t nrows, int ncols, double *v, double *coef, double *part,
+template <typename TB>
+ff_status reorth_norm(const TB *Q, int64_t ld, int64_t nrows, int ncols, double *v, double *coef, double *part,
                       bool have_sq, double *dg, int *flag, double *nrm, double *inv, hipStream_t s) {
   if (!have_sq) k_sumsq_partial<<<kNormBlocks, kThreads, 0, s>>>(v, nrows, part);
   if (ncols <= 0) {
@@ -691,17 +731,19 @@ ff_status norm2(const double *x, int64_t n, double *nrm, double *inv, double *pa
   return FF_OK;
 }
 
-// Workspace of Algorithm 1 for a handle and tp (also used for sizing when a.dry).
-struct GkbWs {
-  double *A, *H, *b, *c, *gamma, *beta, *ginv, *binv, *coef, *part, *dT, *eT, *C, *S, *V, *u0, *g, *w, *alpha, *dg;
+// Workspace of Algorithm 1 for a handle and tp (also used for sizing when a.dry); the bases A
+// (n x tp) and H (m x (tp + 1)) are stored as TB.
+template <typename TB> struct GkbWs {
+  TB *A, *H;
+  double *b, *c, *gamma, *beta, *ginv, *binv, *coef, *part, *dT, *eT, *C, *S, *V, *u0, *g, *w, *alpha, *dg;
   int *flag;
   rocblas_int *info;
   void carve(Arena &a, int64_t n, int64_t m, int tp) {
     const int64_t P = ((n > m ? n : m) + kRowsMin - 1) / kRowsMin + 1;   // partial rows at one row per load
     const int64_t Pn = ((n > m ? n : m) + 63) / 64 + 1;                  // blocks of the A c products
     const int64_t npart = ((P > 256 ? P : 256) + 1) * (tp + 2);
-    A = a.take<double>((size_t)n * tp);
-    H = a.take<double>((size_t)m * (tp + 1));
+    A = a.take<TB>((size_t)n * tp);
+    H = a.take<TB>((size_t)m * (tp + 1));
     b = a.take<double>(n);
     c = a.take<double>(m);
     gamma = a.take<double>(tp + 1);
@@ -794,36 +836,38 @@ ff_status choose_alpha(ff_spectra h, int mode, double fixed, UpreIn q, const dou
   return FF_OK;
 }
 
+template <typename TB>
 ff_status gkb_run(ff_spectra h, const double *rt, const double *wd, const double *winv, int t, int tp, int mode,
                   double *y, double *alpha, double *sigma, void *ws, size_t ws_bytes, hipStream_t s) {
   const int64_t n = h->n, m = h->m;
   Arena ar{(char *)ws, ws_bytes, 0, false};
-  GkbWs W;
+  GkbWs<TB> W;
   W.carve(ar, n, m, tp);
   if (ar.used > ws_bytes) return fail(FF_ENOMEM, "gkb_project: workspace too small");
   const double fixed = *alpha;
   ff_status st;
-  // beta_1 = ||r~||, h_1 = r~ / beta_1
+  // beta_1 = ||r~||, h_1 = r~ / beta_1 (stored in H; c holds the same values in double, the
+  // operand of the next G^T)
   if ((st = norm2(rt, m, W.beta, W.binv, W.part, s))) return st;
-  k_scale<<<grid_for(m), kThreads, 0, s>>>(rt, W.binv, W.H, m);
+  k_scale_from<TB><<<grid_for(m), kThreads, 0, s>>>(rt, W.binv, W.H, W.c, m);
   FF_HIP(hipMemsetAsync(W.b, 0, sizeof(double) * n, s));
   for (int i = 0; i < tp; ++i) {
-    double *ai = W.A + (int64_t)i * n;
-    const double *hi = W.H + (int64_t)i * m;
-    // b = G~^T h - beta_i a_{i-1}, reorthogonalized; gamma_i = ||b||
-    if ((st = op_apply(h, 1, 1, hi, m, W.b, n, wd, winv, FF_F64, s))) return st;
+    TB *ai = W.A + (int64_t)i * n;
+    const TB *hi = W.H + (int64_t)i * m;
+    // b = G~^T h_i - beta_i a_{i-1}, reorthogonalized; gamma_i = ||b||
+    if ((st = op_apply(h, 1, 1, W.c, m, W.b, n, wd, winv, FF_F64, s))) return st;
     if (i > 0)
-      k_axpy_sumsq<<<kNormBlocks, kThreads, 0, s>>>(W.b, W.A + (int64_t)(i - 1) * n, W.beta + i, -1.0, n, W.part);
-    if ((st = reorth_norm(W.A, n, n, i, W.b, W.coef, W.part, i > 0, W.dg, W.flag, W.gamma + i, W.ginv + i, s)))
+      k_axpy_sumsq<TB><<<kNormBlocks, kThreads, 0, s>>>(W.b, W.A + (int64_t)(i - 1) * n, W.beta + i, -1.0, n, W.part);
+    if ((st = reorth_norm<TB>(W.A, n, n, i, W.b, W.coef, W.part, i > 0, W.dg, W.flag, W.gamma + i, W.ginv + i, s)))
       return st;
-    k_scale<<<grid_for(n), kThreads, 0, s>>>(W.b, W.ginv + i, ai, n);
-    // c = G~ a - gamma_i h, reorthogonalized; beta_{i+1} = ||c||
-    if ((st = op_apply(h, 0, 1, ai, n, W.c, m, winv, wd, FF_F64, s))) return st;
-    k_axpy_sumsq<<<kNormBlocks, kThreads, 0, s>>>(W.c, hi, W.gamma + i, -1.0, m, W.part);
-    if ((st = reorth_norm(W.H, m, m, i + 1, W.c, W.coef, W.part, true, W.dg, W.flag, W.beta + i + 1,
-                          W.binv + i + 1, s)))
+    k_scale_store<TB><<<grid_for(n), kThreads, 0, s>>>(W.b, W.ginv + i, ai, n);     // b = a_i as stored
+    // c = G~ a_i - gamma_i h_i, reorthogonalized; beta_{i+1} = ||c||
+    if ((st = op_apply(h, 0, 1, W.b, n, W.c, m, winv, wd, FF_F64, s))) return st;
+    k_axpy_sumsq<TB><<<kNormBlocks, kThreads, 0, s>>>(W.c, hi, W.gamma + i, -1.0, m, W.part);
+    if ((st = reorth_norm<TB>(W.H, m, m, i + 1, W.c, W.coef, W.part, true, W.dg, W.flag, W.beta + i + 1,
+                              W.binv + i + 1, s)))
       return st;
-    k_scale<<<grid_for(m), kThreads, 0, s>>>(W.c, W.binv + i + 1, W.H + (int64_t)(i + 1) * m, m);
+    k_scale_store<TB><<<grid_for(m), kThreads, 0, s>>>(W.c, W.binv + i + 1, W.H + (int64_t)(i + 1) * m, m);
   }
   FF_LAUNCH_CHECK("gkb iteration");
   // SVD of the (tp+1) x tp bidiagonal through its Golub-Kahan tridiagonal
@@ -842,7 +886,8 @@ ff_status gkb_run(ff_spectra h, const double *rt, const double *wd, const double
   qa.t = tp;
   k_filter<<<(tp + 255) / 256, 256, 0, s>>>(W.S, W.alpha, qa, tp, W.g);
   if ((st = gemv_n(W.V, tp, tp, tp, W.g, W.w, 1.0, s))) return st;
-  if ((st = gemv_n(W.A, n, n, tp, W.w, y, 1.0, s))) return st;
+  launch_gemv_n<TB>(W.A, n, n, tp, W.w, y, 1.0, 0.0, s);
+  FF_LAUNCH_CHECK("gkb solution");
   FF_HIP(hipMemcpyAsync(sigma, W.S, sizeof(double) * tp, hipMemcpyDeviceToDevice, s));
   FF_HIP(hipMemcpyAsync(alpha, W.alpha, sizeof(double), hipMemcpyDeviceToHost, s));
   FF_HIP(hipStreamSynchronize(s));
@@ -920,14 +965,18 @@ size_t irls_own_bytes(ff_spectra h, int tp) {
 }
 
 // bytes of a solver's workspace; the IRLS workspace is the solver's followed by the step's own
-size_t solver_bytes(ff_spectra h, int which, int solver, int tp) {
+// (basis: FF_F64 or FF_F32 storage of the GKB bases)
+size_t solver_bytes(ff_spectra h, int which, int solver, int basis, int tp) {
   Arena ar{nullptr, 0, 0, true};
   const int sol = which == FF_WS_IRLS ? solver : (which == FF_WS_RSVD ? 1 : 0);
   if (sol == 1) {
     RsvdWs W;
     W.carve(ar, h->n, h->m, tp);
+  } else if (basis == FF_F32) {
+    GkbWs<float> W;
+    W.carve(ar, h->n, h->m, tp);
   } else {
-    GkbWs W;
+    GkbWs<double> W;
     W.carve(ar, h->n, h->m, tp);
   }
   size_t b = ar.used + 256;
@@ -942,22 +991,30 @@ using namespace ff;
 
 extern "C" {
 
-ff_status ff_workspace_size(ff_spectra h, int32_t which, int32_t solver, int32_t tp, size_t *bytes) {
+ff_status ff_workspace_size(ff_spectra h, int32_t which, int32_t solver, int32_t basis_dtype, int32_t tp,
+                            size_t *bytes) {
   if (!h || !bytes) return fail(FF_EINVAL, "ff_workspace_size: NULL argument");
   if (which < FF_WS_GKB || which > FF_WS_IRLS) return fail(FF_EINVAL, "ff_workspace_size: unknown solver");
   if (tp < 1 || tp > h->m) return fail(FF_ESHAPE, "ff_workspace_size: need 1 <= tp <= m");
   if (which == FF_WS_IRLS && solver != 0 && solver != 1) return fail(FF_EINVAL, "ff_workspace_size: solver must be 0 or 1");
-  *bytes = solver_bytes(h, which, solver, tp);
+  if (basis_dtype != FF_F64 && basis_dtype != FF_F32) return fail(FF_EDTYPE, "ff_workspace_size: basis dtype");
+  *bytes = solver_bytes(h, which, solver, basis_dtype, tp);
   return FF_OK;
 }
 
 ff_status gkb_project(ff_spectra h, const double *r_tilde, const double *wd, const double *winv, int32_t t,
-                      int32_t tp, int32_t alpha_mode, double *y, double *alpha, double *sigma, void *workspace,
-                      size_t ws_bytes, ff_stream stream) {
+                      int32_t tp, int32_t alpha_mode, int32_t basis_dtype, double *y, double *alpha, double *sigma,
+                      void *workspace, size_t ws_bytes, ff_stream stream) {
   ff_status st = check_solver_args(h, t, tp, r_tilde, wd, winv, y, alpha, sigma, workspace);
   if (st) return st;
   if (alpha_mode < 0 || alpha_mode > 2) return fail(FF_EINVAL, "gkb_project: alpha_mode must be 0, 1 or 2");
-  return gkb_run(h, r_tilde, wd, winv, t, tp, alpha_mode, y, alpha, sigma, workspace, ws_bytes, (hipStream_t)stream);
+  if (basis_dtype == FF_F64)
+    return gkb_run<double>(h, r_tilde, wd, winv, t, tp, alpha_mode, y, alpha, sigma, workspace, ws_bytes,
+                           (hipStream_t)stream);
+  if (basis_dtype == FF_F32)
+    return gkb_run<float>(h, r_tilde, wd, winv, t, tp, alpha_mode, y, alpha, sigma, workspace, ws_bytes,
+                          (hipStream_t)stream);
+  return fail(FF_EDTYPE, "gkb_project: basis_dtype must be FF_F64 or FF_F32");
 }
 
 ff_status rsvd_project(ff_spectra h, const double *r_tilde, const double *wd, const double *winv, int32_t t,
@@ -984,15 +1041,17 @@ ff_status irls_step(ff_spectra h, const ff_irls_params *p, const double *d_obs, 
     return fail(FF_EINVAL, "irls_step: power_iters must lie in [0, 8]");
   if (!(p->eps2 > 0) || !(p->m_max >= p->m_min)) return fail(FF_EINVAL, "irls_step: need eps2 > 0, m_max >= m_min");
   if (p->t < 1 || p->tp < p->t || p->tp > h->m) return fail(FF_ESHAPE, "irls_step: need 1 <= t <= tp <= m");
+  if (p->basis_dtype != FF_F64 && p->basis_dtype != FF_F32)
+    return fail(FF_EDTYPE, "irls_step: basis_dtype must be FF_F64 or FF_F32");
   int cur = -1;
   hipGetDevice(&cur);
   if (cur != h->device) return fail(FF_EDEVICE, "irls_step: current device differs from the handle's device");
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = h->n, m = h->m;
-  const size_t need = solver_bytes(h, FF_WS_IRLS, p->solver, p->tp);
+  const size_t need = solver_bytes(h, FF_WS_IRLS, p->solver, p->basis_dtype, p->tp);
   if (ws_bytes < need) return fail(FF_ENOMEM, "irls_step: workspace too small");
   // the solver's workspace first, the step's own vectors after it
-  const size_t sol = solver_bytes(h, p->solver == 1 ? FF_WS_RSVD : FF_WS_GKB, 0, p->tp);
+  const size_t sol = solver_bytes(h, p->solver == 1 ? FF_WS_RSVD : FF_WS_GKB, 0, p->basis_dtype, p->tp);
   Arena ar{(char *)workspace + sol, ws_bytes - sol, 0, false};
   IrlsWs I;
   I.carve(ar, n, m, h->nz, p->tp);
@@ -1012,7 +1071,8 @@ ff_status irls_step(ff_spectra h, const ff_irls_params *p, const double *d_obs, 
   double a = p->alpha_fixed;
   // the solvers synchronize the stream before returning, so zw (host) has been consumed
   if (p->solver == 0)
-    st = gkb_run(h, I.r, wd, I.winv, p->t, p->tp, mode, I.y, &a, I.sig, workspace, sol, s);
+    st = p->basis_dtype == FF_F32 ? gkb_run<float>(h, I.r, wd, I.winv, p->t, p->tp, mode, I.y, &a, I.sig, workspace, sol, s)
+                                  : gkb_run<double>(h, I.r, wd, I.winv, p->t, p->tp, mode, I.y, &a, I.sig, workspace, sol, s);
   else
     st = rsvd_run(h, I.r, wd, I.winv, p->t, p->tp, omega, p->seed, (uint32_t)p->k, p->power_iters, mode, I.y, &a,
                   I.sig, workspace, sol, s);

@@ -24,31 +24,36 @@ def _f64(op, t, numel, name):
     return op._vec(t, numel, name, dtype=torch.float64)
 
 
-def workspace_bytes(op, which, tp, solver=0):
+BASIS = {"f64": 1, "f32": 0}   # FF_F64, FF_F32
+
+
+def workspace_bytes(op, which, tp, solver=0, basis="f64"):
     b = C.c_size_t()
     code = {"gkb": 0, "rsvd": 1, "irls": 2}[which]
-    L.call("ff_workspace_size", op.h, code, int(solver), int(tp), C.byref(b))
+    L.call("ff_workspace_size", op.h, code, int(solver), BASIS[basis], int(tp), C.byref(b))
     return b.value
 
 
-def _workspace(op, which, tp, solver=0, ws=None):
-    need = workspace_bytes(op, which, tp, solver)
+def _workspace(op, which, tp, solver=0, ws=None, basis="f64"):
+    need = workspace_bytes(op, which, tp, solver, basis)
     if ws is None or ws.numel() < need:
         ws = torch.empty(need, dtype=torch.uint8, device=op.device)
     return ws
 
 
-def gkb_project(op, r_tilde, wd, winv, t, tp, alpha_mode="upre", alpha=None, ws=None, stream=None):
-    """Returns (y, alpha, sigma): y standard-form (model update winv * y), sigma (tp,)."""
+def gkb_project(op, r_tilde, wd, winv, t, tp, alpha_mode="upre", alpha=None, ws=None, stream=None,
+                basis="f64"):
+    """Returns (y, alpha, sigma): y standard-form (model update winv * y), sigma (tp,).
+    basis: "f64" (default) or "f32" storage of the GKB bases."""
     _f64(op, r_tilde, op.m, "gkb_project")
     _f64(op, wd, op.m, "gkb_project")
     _f64(op, winv, op.n, "gkb_project")
-    ws = _workspace(op, "gkb", tp, 0, ws)
+    ws = _workspace(op, "gkb", tp, 0, ws, basis)
     y = torch.empty(op.n, dtype=torch.float64, device=op.device)
     sigma = torch.empty(tp, dtype=torch.float64, device=op.device)
     a = C.c_double(float(alpha) if alpha is not None else 0.0)
     L.call("gkb_project", op.h, _ptr(r_tilde), _ptr(wd), _ptr(winv), int(t), int(tp),
-           ALPHA_MODES[alpha_mode], _ptr(y), C.byref(a), _ptr(sigma), _ptr(ws), ws.numel(),
+           ALPHA_MODES[alpha_mode], BASIS[basis], _ptr(y), C.byref(a), _ptr(sigma), _ptr(ws), ws.numel(),
            _stream(stream))
     return y, a.value, sigma
 
@@ -85,6 +90,7 @@ class IrlsParams:
     alpha_fixed: float = -1.0
     power_iters: int = 1
     seed: int = 0
+    basis: str = "f64"
 
 
 def irls_step(op, p: IrlsParams, k, d_obs, wd, m_prev, m_prev2=None, omega=None, ws=None,
@@ -98,10 +104,10 @@ def irls_step(op, p: IrlsParams, k, d_obs, wd, m_prev, m_prev2=None, omega=None,
     solver = 0 if p.solver == "gkb" else 1
     if omega is not None:
         _f64(op, omega, p.tp * op.m, "irls_step")
-    ws = _workspace(op, "irls", p.tp, solver, ws)
+    ws = _workspace(op, "irls", p.tp, solver, ws, p.basis)
     prm = L.FFIrlsParams(solver, int(p.t), int(p.tp), int(k), float(p.lam), float(p.eps2),
                          float(p.beta_depth), float(p.m_min), float(p.m_max), float(p.alpha_fixed),
-                         int(p.power_iters), int(p.seed))
+                         int(p.power_iters), int(p.seed), BASIS[p.basis])
     m_new = torch.empty(op.n, dtype=torch.float64, device=op.device)
     a, chi2 = C.c_double(), C.c_double()
     L.call("irls_step", op.h, C.byref(prm), _ptr(d_obs), _ptr(wd), _ptr(m_prev), _ptr(m_prev2),
@@ -117,7 +123,7 @@ def irls(op, p: IrlsParams, d_obs, wd, k_max=25, omega_fn=None, callback=None, s
     Returns (m, history) with history a list of (k, alpha, chi2)."""
     m_prev = torch.zeros(op.n, dtype=torch.float64, device=op.device)
     m_prev2 = torch.zeros_like(m_prev)
-    ws = _workspace(op, "irls", p.tp, 0 if p.solver == "gkb" else 1)
+    ws = _workspace(op, "irls", p.tp, 0 if p.solver == "gkb" else 1, None, p.basis)
     hist = []
     for k in range(1, k_max + 1):
         omega = omega_fn(k) if (p.solver == "rsvd" and omega_fn is not None) else None

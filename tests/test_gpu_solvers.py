@@ -114,6 +114,23 @@ def test_rsvd_matches_oracle_algorithm(mode, dtype):
     assert rel(to_host(y), y0) <= (1e-8 if dtype == F64 else 1e-4) + 2 * abs(a - a0) / a0
 
 
+@pytest.mark.parametrize("kernel", ["gravity", "magnetic"])
+def test_gkb_single_precision_basis(kernel):
+    # the bases stored in FP32 (every product and sum in FP64): the oracle's Algorithm 1 to the
+    # level of the basis rounding
+    s, g, G, wd, winv, Gt, r = problem("mid", kernel=kernel, seed=1)
+    t, tp = 60, 63
+    announce("gkb f32 basis", kernel)
+    y0, a0, s0, F = osol.gkb(*dense_ops(Gt), r, g.n, t, tp, "fixed", 2.0, return_factors=True)
+    A = Operator(s, F64)
+    y, a, sig = S.gkb_project(A, to_dev(r, F64), to_dev(wd, F64), to_dev(winv, F64), t, tp, "fixed", 2.0,
+                              basis="f32")
+    assert rel(to_host(sig), s0) <= 1e-6
+    assert rel(to_host(y), y0) <= 2e-5
+    # half the basis memory
+    assert S.workspace_bytes(A, "gkb", tp, basis="f32") < 0.75 * S.workspace_bytes(A, "gkb", tp)
+
+
 @pytest.mark.parametrize("q", [0, 2])
 def test_rsvd_power_iterations_and_device_omega(q):
     # Omega drawn on the device from a seed (Philox4x32-10) and q power iterations, against the
@@ -211,6 +228,6 @@ def test_workspace_errors():
     a = __import__("ctypes").c_double(1.0)
     lib = L.load()
     from paper_2004_13904_amd.operator import _ptr, _stream
-    rc = lib.gkb_project(A.h, _ptr(r), _ptr(r), _ptr(torch.ones(A.n, dtype=F64, device="cuda")), 2, 4, 2,
+    rc = lib.gkb_project(A.h, _ptr(r), _ptr(r), _ptr(torch.ones(A.n, dtype=F64, device="cuda")), 2, 4, 2, 1,
                          _ptr(y), __import__("ctypes").byref(a), _ptr(sig), _ptr(small), 16, _stream())
     assert rc == -4
