@@ -66,12 +66,19 @@ def main(argv=None):
     ap.add_argument("--no-extra", action="store_true", help="skip the batched / RSVD-block / IRLS legs")
     ap.add_argument("--legs", default="batched,rsvd,multi,autograd,table3,irls",
                     help="comma list of extra legs (batched, rsvd, multi, autograd, table3, irls; "
-                         "opt-in: irls_c2)")
+                         "opt-in: irls_c2, study)")
     ap.add_argument("--irls-c2-steps", type=int, default=1,
                     help="IRLS steps of the opt-in n = 1e6 magnetic leg (each step ~10 s)")
     ap.add_argument("--irls-c2-basis", default="f64", choices=("f64", "f32"),
                     help="GKB basis storage of the opt-in n = 1e6 magnetic leg")
     ap.add_argument("--irls-steps", type=int, default=25)
+    ap.add_argument("--study-ells", default="4,5", help="ladder sizes l of the opt-in study leg")
+    ap.add_argument("--study-s", default="40,25,20,8,6,4,3", help="t = floor(m/s) of the study leg")
+    ap.add_argument("--study-kinds", default="gravity,magnetic")
+    ap.add_argument("--study-solvers", default="gkb,rsvd")
+    ap.add_argument("--study-basis", default="f64", choices=("f64", "f32"))
+    ap.add_argument("--study-pad", type=float, default=0.0, help="padding fraction of the study grids")
+    ap.add_argument("--study-kmax", type=int, default=25, help="IRLS step limit of the study leg")
     ap.add_argument("--calib", action="store_true",
                     help="end with a plain 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     a = ap.parse_args(argv)
@@ -276,6 +283,10 @@ def main(argv=None):
         result["irls_l1_f32basis"] = irls_leg(a.irls_steps, lam=1.0, stop=True, basis="f32")
     if "irls_c2" in legs:
         result["irls_magnetic_1m"] = irls_c2_leg(a.irls_c2_steps, a.irls_c2_basis)
+    if "study" in legs:
+        result["study"] = study_leg([int(v) for v in a.study_ells.split(",")],
+                                    [int(v) for v in a.study_s.split(",")], a.study_kinds.split(","),
+                                    a.study_solvers.split(","), a.study_basis, a.study_pad, a.study_kmax)
 
     if a.calib:
         src = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
@@ -289,6 +300,84 @@ def main(argv=None):
         result["cpu_baseline"], result["rel_err"] = cpu_baseline(s, x_h, d_h, A, x, d)
     print(json.dumps(result), flush=True)
     return 0
+
+
+def study_leg(ells, s_list, kinds, solvers, basis="f64", pad=0.0, kmax=25):
+    """GKB against RSVD to convergence over the size ladder (Sec. 3.3.2, the timing-to-convergence
+    table of the appendix): for each l, data kind and t = min(floor(m/s), 5000), t_p = floor(1.05 t),
+    IRLS with lambda = 1, eps^2 = 1e-9, depth weighting beta = 0.8 (gravity) / 1.4 (magnetic), bounds
+    [0, 1] / [0, 0.1], RSVD with one power iteration and a device-drawn Omega, stopped by the scaled
+    chi^2 test or after kmax steps.  Data: the ladder structure through the FP64 operator, noise of
+    eq. (noisydata) with tau1 = 0.02 and the paper's tau2 for l.  FP32 operator, FP64 solves.
+    Returns one record per run (K, seconds, RE, final scaled chi^2, alpha)."""
+    import torch
+
+    from paper_2004_13904_amd import solvers as SV
+    from paper_2004_13904_amd import workloads as W
+    from paper_2004_13904_amd.operator import Operator
+    rows = []
+    for ell in ells:
+        for kind in kinds:
+            s = W.ladder_survey(ell, kind, pad_fraction=pad)
+            grav = kind == "gravity"
+            m_true = torch.tensor(W.ladder_structure(s, kind), dtype=torch.float64, device="cuda")
+            A64 = Operator(s, torch.float64)
+            d_exact = A64.G(m_true).cpu().numpy()
+            A64.close()
+            del A64
+            eta, sd = W.noise(d_exact, W.LADDER_TAU1, W.LADDER_TAU2[ell][0 if grav else 1], 100 + ell)
+            snr = W.snr_db(d_exact, eta)
+            A = Operator(s, torch.float32)
+            d_obs = torch.tensor(d_exact + eta, dtype=torch.float64, device="cuda")
+            wd = torch.tensor(1.0 / sd, dtype=torch.float64, device="cuda")
+            m = A.m
+            log(f"study l={ell} {kind}: m {m} n {A.n} NX x NY {A.nfft} SNR {snr:.2f} dB")
+
+            def params(solver, t, tp, sdiv):
+                return SV.IrlsParams(solver=solver, t=t, tp=tp, lam=1.0, eps2=1e-9,
+                                     beta_depth=0.8 if grav else 1.4, m_min=0.0,
+                                     m_max=1.0 if grav else 0.1, basis=basis, power_iters=1,
+                                     seed=1000 * ell + sdiv)
+            for solver in solvers:   # untimed warm-up of the solver's library paths
+                t0_ = min(m // max(s_list), 5000)
+                SV.irls(A, params(solver, t0_, 21 * t0_ // 20, 0), d_obs, wd, k_max=1, stop_at_chi2=False)
+            for sdiv in s_list:
+                t = min(m // sdiv, 5000)
+                tp = 21 * t // 20
+                for solver in solvers:
+                    p = params(solver, t, tp, sdiv)
+                    step_t = []
+                    t_last = [0.0]
+
+                    def cb(k, mk, alpha, chi2):
+                        torch.cuda.synchronize()
+                        now = time.perf_counter()
+                        step_t.append(now - t_last[0])
+                        t_last[0] = now
+                        log(f"study l={ell} {kind} {solver} t={t}: step {k} alpha {alpha:.4g} "
+                            f"chi2 {chi2:.4f} ({step_t[-1]:.3f} s)")
+                    qr0 = A.qr_counts
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    t_last[0] = t0
+                    mk, hist = SV.irls(A, p, d_obs, wd, k_max=kmax, callback=cb, stop_at_chi2=True)
+                    torch.cuda.synchronize()
+                    total = time.perf_counter() - t0
+                    re = float(torch.linalg.norm(m_true - mk) / torch.linalg.norm(m_true))
+                    rows.append({"ell": ell, "kind": kind, "solver": solver, "s": sdiv, "t": t, "tp": tp,
+                                 "m": m, "n": A.n, "pad": pad, "basis": basis, "snr_db": round(snr, 2),
+                                 "K": len(hist), "converged": hist[-1][2] <= 1.0,
+                                 "seconds": round(total, 3),
+                                 "seconds_per_step": round(total / len(hist), 4),
+                                 "first_step_s": round(step_t[0], 4), "RE": round(re, 4),
+                                 "chi2_scaled": round(hist[-1][2], 4), "alpha_1": hist[0][1],
+                                 "alpha_K": hist[-1][1],
+                                 "qr_householder_fallbacks": A.qr_counts["householder"] - qr0["householder"]})
+                    del mk
+            A.close()
+            del A
+            torch.cuda.empty_cache()
+    return rows
 
 
 # the sources that define the operator's pass kernels and their launches

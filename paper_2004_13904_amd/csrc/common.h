@@ -102,11 +102,14 @@ struct ff_spectra_s {
   int batch_max = ff::kMinBatch;      // vectors the pass workspace holds
   int row_tile = 0;                   // 0 auto, 1 one transform per row block, 2 largest tile
   int col_batched = 1;                // 4-vectors-per-block column passes for block applies
+  int rsvd_qr = 0;                    // RSVD orthonormalization: 0 Cholesky QR (+ fallback), 1 Householder
   void *ws_rows = nullptr;           // batch x nz x H x max(ny, sy) complex: row-pass <-> column-pass
   void *ws_cols = nullptr;           // batch x LG x H x max(sy, ...) complex: column-pass partials / D1
   size_t ws_rows_bytes = 0, ws_cols_bytes = 0;
   int lg_G = 1;                      // layer groups of the G column pass (partial sums)
   int lg_GT = 1;                     // layer groups of the G^T column pass
+  // RSVD orthonormalizations so far: by shifted Cholesky QR, and by the Householder fallback
+  int64_t qr_cholesky = 0, qr_householder = 0;
   // pass profiling: 4 events per profiled call (before pass 1, after passes 1-3)
   std::vector<hipEvent_t> prof_ev;
   std::vector<int> prof_kind;        // transpose flag of each profiled call

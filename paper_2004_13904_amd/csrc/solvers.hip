@@ -515,22 +515,69 @@ __global__ void k_filter(const double *__restrict__ s, const double *__restrict_
 
 // RSVD: S = sqrt(|lambda|) sorted descending (lambda ascending from the eigensolver), and the
 // eigenvector columns in the same order: Vs[:, i] = V[:, perm(i)]
+// S = sqrt|lambda| in descending order with perm its source indices; equal magnitudes keep their
+// ascending eigenvalue order (NaN ranks last).  One thread per value counts the values ranked
+// before it.
 __global__ void k_rsvd_sort(const double *__restrict__ lam, int tp, double *__restrict__ S, int *__restrict__ perm) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  // rank sort: stable in the ascending eigenvalue order for equal magnitudes
-  for (int i = 0; i < tp; ++i) perm[i] = i;
-  // insertion sort by descending sqrt|lambda| (tp is small; runs once per solve)
-  for (int i = 1; i < tp; ++i) {
-    const int pi = perm[i];
-    const double v = sqrt(fabs(lam[pi]));
-    int j = i - 1;
-    while (j >= 0 && sqrt(fabs(lam[perm[j]])) < v) {
-      perm[j + 1] = perm[j];
-      --j;
-    }
-    perm[j + 1] = pi;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= tp) return;
+  const double li = lam[i];
+  const double v = isnan(li) ? -1.0 : sqrt(fabs(li));
+  int rank = 0;
+  for (int j = 0; j < tp; ++j) {
+    const double lj = lam[j];
+    const double u = isnan(lj) ? -1.0 : sqrt(fabs(lj));
+    rank += (u > v) || (u == v && j < i);
   }
-  for (int i = 0; i < tp; ++i) S[i] = sqrt(fabs(lam[perm[i]]));
+  perm[rank] = i;
+  S[rank] = li != li ? 0.0 : v;
+}
+
+// Shifted Cholesky QR helpers (Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa, SIAM J. Sci.
+// Comput. 2020).  k_gram_shift adds s = 11 (rows cols + cols (cols + 1)) u trace(G) to the
+// diagonal of the Gram matrix G (cols x cols): trace(G) = ||Y||_F^2 bounds ||Y||_2^2.
+__global__ void __launch_bounds__(kThreads) k_gram_shift(double *__restrict__ G, int cols, int64_t rows) {
+  __shared__ double red[kThreads / 64];
+  double tr = 0.0;
+  for (int i = threadIdx.x; i < cols; i += kThreads) tr += G[(int64_t)i * cols + i];
+  tr = block_sum(tr, red);
+  __shared__ double trs;
+  if (threadIdx.x == 0) trs = tr;
+  __syncthreads();
+  tr = trs;
+  const double u = 1.1102230246251565e-16;   // 2^-53
+  const double shift = 11.0 * ((double)rows * cols + (double)cols * (cols + 1)) * u * tr;
+  for (int i = threadIdx.x; i < cols; i += kThreads) G[(int64_t)i * cols + i] += shift;
+}
+
+// zero the strictly lower triangle of the column-major cols x cols R^-1, so that a plain product
+// with it reads only the triangle
+__global__ void k_zero_lower(double *__restrict__ A, int cols) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)cols * cols) return;
+  const int r = (int)(idx % cols), c = (int)(idx / cols);
+  if (r > c) A[idx] = 0.0;
+}
+
+// out[0] = max |G - I| over the cols x cols Gram matrix (NaN counts as +inf), as the bits of a
+// non-negative double (whose integer order is its numeric order); out[0] must start at 0.
+// Block b takes the columns b, b + gridDim.x, ...
+__global__ void __launch_bounds__(kThreads) k_orth_defect(const double *__restrict__ G, int cols,
+                                                          unsigned long long *__restrict__ out) {
+  __shared__ double red[kThreads];
+  double mx = 0.0;
+  for (int c = blockIdx.x; c < cols; c += gridDim.x)
+    for (int r = threadIdx.x; r < cols; r += kThreads) {
+      const double d = fabs(G[(int64_t)c * cols + r] - (r == c ? 1.0 : 0.0));
+      mx = d != d ? INFINITY : fmax(mx, d);
+    }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(red[0]));
 }
 
 __global__ void k_gather_cols(const double *__restrict__ V, int64_t ldv, int nrows, const int *__restrict__ perm, int ncols,
@@ -768,13 +815,16 @@ template <typename TB> struct GkbWs {
 };
 
 struct RsvdWs {
-  double *Q, *Bm, *Y, *lam, *E, *S, *Vs, *btr, *c, *g, *w, *tau, *alpha, *part;
+  double *Q, *Bm, *Y, *lam, *E, *S, *Vs, *btr, *c, *g, *w, *tau, *alpha, *part, *T, *U, *dev;
   int *perm;
   rocblas_int *info;
   void carve(Arena &a, int64_t n, int64_t m, int tp) {
     const int64_t P = ((n > m ? n : m) + kRowsMin - 1) / kRowsMin + 1;   // partial rows at one row per load
     Q = a.take<double>((size_t)n * tp);     // n x tp (also holds the m x tp factors)
     Bm = a.take<double>((size_t)m * tp);    // G~ Q
+    T = a.take<double>((size_t)(n > m ? n : m) * tp);   // QR scratch
+    U = a.take<double>((size_t)(n > m ? n : m) * tp);
+    dev = a.take<double>(1);
     Y = a.take<double>((size_t)tp * tp);    // B^T B, then its eigenvectors
     lam = a.take<double>(tp);
     E = a.take<double>(tp);
@@ -788,7 +838,7 @@ struct RsvdWs {
     alpha = a.take<double>(2);
     part = a.take<double>((size_t)((P > 256 ? P : 256) + 1) * (tp + 2));
     perm = a.take<int>(tp);
-    info = a.take<rocblas_int>(4);
+    info = a.take<rocblas_int>(8);
   }
 };
 
@@ -894,10 +944,71 @@ ff_status gkb_run(ff_spectra h, const double *rt, const double *wd, const double
   return FF_OK;
 }
 
-ff_status qr_inplace(rocblas_handle bh, double *M, int64_t rows, int cols, double *tau) {
+ff_status householder_qr(rocblas_handle bh, double *M, int64_t rows, int cols, double *tau) {
   FF_BLAS(rocsolver_dgeqrf(bh, (rocblas_int)rows, cols, M, (rocblas_int)rows, tau), "rocsolver_dgeqrf");
   FF_BLAS(rocsolver_dorgqr(bh, (rocblas_int)rows, cols, cols, M, (rocblas_int)rows, tau), "rocsolver_dorgqr");
   return FF_OK;
+}
+
+// Orthonormal basis of the columns of the tall rows x cols matrix M, in place.  Shifted Cholesky
+// QR three times (one shifted pass, then two plain ones): each pass forms the Gram matrix with
+// one product, factors it (potrf), inverts the factor (trtri) and multiplies, so the work is
+// matrix-matrix products.  M is kept until the end; if a factorization fails or the result's
+// Gram matrix is more than 1e-8 from the identity (columns dependent beyond what the shift
+// covers), the Householder QR (geqrf + orgqr) runs on M instead.  T and U are rows x cols
+// scratch, G is cols x cols, dev holds one double and info eight ints.
+ff_status qr_inplace(ff_spectra h, rocblas_handle bh, double *M, int64_t rows, int cols, double *tau, double *T,
+                     double *U, double *G, double *dev, rocblas_int *info, hipStream_t s) {
+  if (h->rsvd_qr == 1) {
+    h->qr_householder += 1;
+    return householder_qr(bh, M, rows, cols, tau);
+  }
+  const double one = 1.0, zero = 0.0;
+  const rocblas_int r = (rocblas_int)rows, c = cols;
+  FF_HIP(hipMemsetAsync(info, 0, 8 * sizeof(rocblas_int), s));
+  const double *in = M;
+  double *outs[3] = {T, U, T};
+  for (int p = 0; p < 3; ++p) {
+    double *out = outs[p];
+    FF_BLAS(rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, c, c, r, &one, in, r, in, r, &zero,
+                          G, c),
+            "rocblas_dgemm (Gram)");
+    if (p == 0) {
+      k_gram_shift<<<1, kThreads, 0, s>>>(G, c, rows);
+      FF_LAUNCH_CHECK("gram shift");
+    }
+    FF_BLAS(rocsolver_dpotrf(bh, rocblas_fill_upper, c, G, c, info + 2 * p), "rocsolver_dpotrf");
+    FF_BLAS(rocsolver_dtrtri(bh, rocblas_fill_upper, rocblas_diagonal_non_unit, c, G, c, info + 2 * p + 1),
+            "rocsolver_dtrtri");
+    k_zero_lower<<<grid_for((int64_t)c * c, 256, 1 << 30), 256, 0, s>>>(G, c);
+    FF_LAUNCH_CHECK("zero lower");
+    FF_BLAS(rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_none, r, c, c, &one, in, r, G, c, &zero, out,
+                          r),
+            "rocblas_dgemm (Q R^-1)");
+    in = out;
+  }
+  FF_BLAS(rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, c, c, r, &one, in, r, in, r, &zero, G,
+                        c),
+          "rocblas_dgemm (check)");
+  FF_HIP(hipMemsetAsync(dev, 0, sizeof(double), s));
+  k_orth_defect<<<c < 1024 ? c : 1024, kThreads, 0, s>>>(G, c, (unsigned long long *)dev);
+  FF_LAUNCH_CHECK("orthogonality check");
+  struct {
+    rocblas_int info[8];
+    double defect;
+  } hs;
+  FF_HIP(hipMemcpyAsync(hs.info, info, sizeof(hs.info), hipMemcpyDeviceToHost, s));
+  FF_HIP(hipMemcpyAsync(&hs.defect, dev, sizeof(double), hipMemcpyDeviceToHost, s));
+  FF_HIP(hipStreamSynchronize(s));
+  bool ok = hs.defect <= 1e-8;
+  for (int i = 0; i < 6; ++i) ok = ok && hs.info[i] == 0;
+  if (ok) {
+    FF_HIP(hipMemcpyAsync(M, in, sizeof(double) * rows * cols, hipMemcpyDeviceToDevice, s));
+    h->qr_cholesky += 1;
+    return FF_OK;
+  }
+  h->qr_householder += 1;
+  return householder_qr(bh, M, rows, cols, tau);
 }
 
 ff_status rsvd_run(ff_spectra h, const double *rt, const double *wd, const double *winv, int t, int tp,
@@ -922,13 +1033,13 @@ ff_status rsvd_run(ff_spectra h, const double *rt, const double *wd, const doubl
   }
   // Y^T = G~^T Omega^T (n x tp), Q = qr(Y^T)
   if ((st = op_apply(h, 1, tp, omega, m, W.Q, n, wd, winv, FF_F64, s))) return st;
-  if ((st = qr_inplace(bh, W.Q, n, tp, W.tau))) return st;
+  if ((st = qr_inplace(h, bh, W.Q, n, tp, W.tau, W.T, W.U, W.Y, W.dev, W.info, s))) return st;
   for (int q = 0; q < power_iters; ++q) {
     // Y = G~ Q (m x tp), Q = qr(Y); Y^T = G~^T Q (n x tp), Q = qr(Y^T)
     if ((st = op_apply(h, 0, tp, W.Q, n, W.Bm, m, winv, wd, FF_F64, s))) return st;
-    if ((st = qr_inplace(bh, W.Bm, m, tp, W.tau))) return st;
+    if ((st = qr_inplace(h, bh, W.Bm, m, tp, W.tau, W.T, W.U, W.Y, W.dev, W.info, s))) return st;
     if ((st = op_apply(h, 1, tp, W.Bm, m, W.Q, n, wd, winv, FF_F64, s))) return st;
-    if ((st = qr_inplace(bh, W.Q, n, tp, W.tau))) return st;
+    if ((st = qr_inplace(h, bh, W.Q, n, tp, W.tau, W.T, W.U, W.Y, W.dev, W.info, s))) return st;
   }
   // B = G~ Q
   if ((st = op_apply(h, 0, tp, W.Q, n, W.Bm, m, winv, wd, FF_F64, s))) return st;
@@ -940,7 +1051,7 @@ ff_status rsvd_run(ff_spectra h, const double *rt, const double *wd, const doubl
           "rocblas_dgemm");
   FF_BLAS(rocsolver_dsyevd(bh, rocblas_evect_original, rocblas_fill_lower, tp, W.Y, tp, W.lam, W.E, W.info),
           "rocsolver_dsyevd");
-  k_rsvd_sort<<<1, 1, 0, s>>>(W.lam, tp, W.S, W.perm);
+  k_rsvd_sort<<<(tp + 255) / 256, 256, 0, s>>>(W.lam, tp, W.S, W.perm);
   k_gather_cols<<<grid_for((int64_t)tp * t, 256, 1 << 30), 256, 0, s>>>(W.Y, tp, tp, W.perm, t, W.Vs);
   // B^T r~, c = U~^T (B^T r~)
   if ((st = gemv_t(W.Bm, m, m, tp, rt, W.btr, W.part, s))) return st;
@@ -1015,6 +1126,13 @@ ff_status gkb_project(ff_spectra h, const double *r_tilde, const double *wd, con
     return gkb_run<float>(h, r_tilde, wd, winv, t, tp, alpha_mode, y, alpha, sigma, workspace, ws_bytes,
                           (hipStream_t)stream);
   return fail(FF_EDTYPE, "gkb_project: basis_dtype must be FF_F64 or FF_F32");
+}
+
+ff_status ff_solver_stats(ff_spectra h, int64_t *qr_cholesky, int64_t *qr_householder) {
+  if (!h || !qr_cholesky || !qr_householder) return fail(FF_EINVAL, "ff_solver_stats: NULL argument");
+  *qr_cholesky = h->qr_cholesky;
+  *qr_householder = h->qr_householder;
+  return FF_OK;
 }
 
 ff_status rsvd_project(ff_spectra h, const double *r_tilde, const double *wd, const double *winv, int32_t t,

@@ -75,7 +75,7 @@ class Operator:
         op._attach(h, survey)
         return op
 
-    TUNING_KEYS = ("lg_G", "lg_GT", "row_tile", "batch", "col_batched")
+    TUNING_KEYS = ("lg_G", "lg_GT", "row_tile", "batch", "col_batched", "rsvd_qr")
 
     @property
     def batch_max(self):
@@ -88,6 +88,13 @@ class Operator:
         t = L.FFTuning()
         L.call("ff_get_tuning", self.h, C.byref(t))
         return {k: getattr(t, k) for k in self.TUNING_KEYS}
+
+    @property
+    def qr_counts(self):
+        """RSVD orthonormalizations on this handle so far: {"cholesky": .., "householder": ..}."""
+        a, b = C.c_int64(), C.c_int64()
+        L.call("ff_solver_stats", self.h, C.byref(a), C.byref(b))
+        return {"cholesky": a.value, "householder": b.value}
 
     def set_tuning(self, **changes):
         """Change some tuning values (keys of ``tuning``); the others are kept."""

@@ -29,6 +29,12 @@ plane.  Sizes and models:
 * ``ladder_survey(l)`` the size ladder of Sec. 3.2 / Table 2: l (25, 15, 2) stations and
                  layers over 2000 x 1200 x 400 m, padded by round(0.05 s) cells per side
                  (round half away from zero).
+* ``ladder_structure(s, kind)`` a stand-in for the volume structure of Sec. 3.2 on any ladder
+                 grid: three boxes, an elongated well, a very small well and a dike dipping at
+                 45 degrees over six 50 m depth bands, fixed in metres so that every l sees the
+                 same bodies; density 1 for gravity; susceptibility 0.06 (dike and wells) and
+                 0.04 (boxes) for magnetic data.  ``LADDER_TAU2`` holds the paper's noise
+                 levels tau2 per l (tau1 = 0.02).
 
 The paper's own synthetic structure exists only in its figures and its field data
 set is not available; the models here stand in for them.
@@ -74,6 +80,50 @@ def ladder_survey(ell, kernel="gravity", pad_fraction=0.05, incl=45.0, decl=45.0
     px, py = _round_half_away(pad_fraction * sx), _round_half_away(pad_fraction * sy)
     return survey(sx, sy, nz, 2000.0 / sx, 1200.0 / sy, 400.0 / nz, kernel=kernel, incl=incl, decl=decl,
                   pad=(px, px, py, py))
+
+
+# tau2 of eq. (noisydata) per ladder size l, gravity and magnetic, with tau1 = 0.02 (the table of
+# problem dimensions in Sec. 3.2; chosen there to give an SNR of about 24 dB for the paper's structure)
+LADDER_TAU1 = 0.02
+LADDER_TAU2 = {4: (0.0138, 0.0081), 5: (0.0147, 0.0083), 6: (0.0133, 0.0074), 7: (0.0133, 0.0070),
+               8: (0.0133, 0.0071), 9: (0.0133, 0.0069), 10: (0.0132, 0.0070), 11: (0.0135, 0.0075),
+               12: (0.0135, 0.0075)}
+
+# Bodies of the ladder structure in metres over the 2000 x 1200 x 400 m station domain (x along the
+# sx stations, y along sy, z down).  Boxes: (x0, x1, y0, y1, z0, z1, susceptibility); the dike's top
+# x-range [x0, x1) moves by +1 m per metre of depth between z0 and z1.
+LADDER_BOXES = [(250.0, 600.0, 250.0, 550.0, 50.0, 150.0, 0.04),
+                (1300.0, 1700.0, 650.0, 1000.0, 100.0, 250.0, 0.04),
+                (700.0, 1000.0, 800.0, 1000.0, 25.0, 100.0, 0.04),
+                (400.0, 475.0, 700.0, 1100.0, 50.0, 300.0, 0.06),      # elongated well
+                (1750.0, 1800.0, 250.0, 300.0, 25.0, 75.0, 0.06)]      # very small well
+LADDER_DIKE = (1000.0, 1100.0, 200.0, 550.0, 50.0, 350.0, 0.06)
+
+
+def ladder_structure(s, kind="gravity"):
+    """Model vector (layer, row, column) of the ladder structure on survey s: a cell takes a body's
+    value when its centre lies inside the body (half-open extents); gravity uses 1 for every body.
+    Padding cells lie outside the station domain and stay 0."""
+    nx, ny, nz, _, _ = sizes(s)
+    xc = (np.arange(nx) - s["pad_xl"] + 0.5) * s["dx"]
+    yc = (np.arange(ny) - s["pad_yl"] + 0.5) * s["dy"]
+    ze = np.asarray(s["z_edges"])
+    zc = 0.5 * (ze[:-1] + ze[1:])
+    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+    out = np.zeros((nz, ny, nx))
+    for x0, x1, y0, y1, z0, z1, v in LADDER_BOXES:
+        inside = (X >= x0) & (X < x1) & (Y >= y0) & (Y < y1) & (Z >= z0) & (Z < z1)
+        out[inside] = 1.0 if kind == "gravity" else v
+    x0, x1, y0, y1, z0, z1, v = LADDER_DIKE
+    shift = Z - z0
+    inside = (X >= x0 + shift) & (X < x1 + shift) & (Y >= y0) & (Y < y1) & (Z >= z0) & (Z < z1)
+    out[inside] = 1.0 if kind == "gravity" else v
+    return out.reshape(-1)
+
+
+def snr_db(d_exact, eta):
+    """eq. (SNR): 20 log10(||d_exact|| / ||d_obs - d_exact||)."""
+    return float(20.0 * np.log10(np.linalg.norm(d_exact) / np.linalg.norm(eta)))
 
 
 UNEVEN = [(32, 32, 6), (48, 48, 8), (64, 48, 8), (80, 64, 10), (100, 60, 10),

@@ -95,13 +95,16 @@ def test_rsvd_full_space_is_tikhonov(kernel):
 
 @pytest.mark.parametrize("mode", ["fixed", "upre", "alpha1"])
 @pytest.mark.parametrize("dtype", [F64, F32])
-def test_rsvd_matches_oracle_algorithm(mode, dtype):
+@pytest.mark.parametrize("qr", [0, 1])
+def test_rsvd_matches_oracle_algorithm(mode, dtype, qr):
+    # qr 0: shifted Cholesky QR (with its Householder fallback); 1: Householder QR always
     s, g, G, wd, winv, Gt, r = problem("mid", kernel="gravity", seed=2)
     t, tp = 60, 63
-    announce("rsvd", mode, dtype)
+    announce("rsvd", mode, dtype, "qr", qr)
     omega = np.random.default_rng(4).standard_normal((tp, g.m))
     y0, a0, s0, F = osol.rsvd(*dense_ops(Gt), r, g.n, t, tp, omega, mode, 2.0, return_factors=True)
     A = Operator(s, dtype)
+    A.set_tuning(rsvd_qr=qr)
     y, a, sig = S.rsvd_project(A, to_dev(r, F64), to_dev(wd, F64), to_dev(winv, F64), t, tp,
                                to_dev(omega, F64), mode, 2.0)
     tol = 1e-8 if dtype == F64 else 2e-5
@@ -112,6 +115,13 @@ def test_rsvd_matches_oracle_algorithm(mode, dtype):
                         to_dev(omega, F64), "fixed", a0)[0]
     assert rel(to_host(ya), y0) <= (1e-8 if dtype == F64 else 1e-4)
     assert rel(to_host(y), y0) <= (1e-8 if dtype == F64 else 1e-4) + 2 * abs(a - a0) / a0
+    counts = A.qr_counts
+    # three factorizations per call (one power iteration), two calls
+    assert counts["cholesky"] + counts["householder"] == 6
+    if qr == 1:
+        assert counts["householder"] == 6
+    else:
+        assert counts["cholesky"] >= 1
 
 
 @pytest.mark.parametrize("kernel", ["gravity", "magnetic"])
