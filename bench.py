@@ -372,7 +372,7 @@ def study_leg(ells, s_list, kinds, solvers, basis="f64", pad=0.0, kmax=25):
                                  "first_step_s": round(step_t[0], 4), "RE": round(re, 4),
                                  "chi2_scaled": round(hist[-1][2], 4), "alpha_1": hist[0][1],
                                  "alpha_K": hist[-1][1],
-                                 "qr_householder_fallbacks": A.qr_counts["householder"] - qr0["householder"]})
+                                 "qr": {k: A.qr_counts[k] - qr0[k] for k in qr0}})
                     del mk
             A.close()
             del A

@@ -165,18 +165,19 @@ ff_status gkb_project(ff_spectra h, const double *r_tilde, const double *wd, con
    counter-based Philox4x32-10 generator (Salmon et al., SC 2011): element pair p from the
    counter (p mod 2^32, p div 2^32, 0, 0) and the key (seed mod 2^32, seed div 2^32), two
    53-bit uniforms and a Box-Muller transform (see k_gaussian in the sources).
-   The QR factorizations of Algorithm 2 keep only Q; it is formed by shifted Cholesky QR
-   (three passes of Gram product, Cholesky, triangular inverse and product), checked to be
-   orthonormal to 1e-8, and formed by Householder QR (geqrf + orgqr) when that check fails.
-   The call synchronizes `stream` after each factorization. */
+   The QR factorizations of Algorithm 2 keep only Q.  It is formed by Cholesky QR (passes of
+   Gram product, Cholesky, triangular inverse and product): two plain passes (CholeskyQR2),
+   else three passes with a shifted first one (shifted CholeskyQR3), else Householder QR
+   (geqrf + orgqr); a Cholesky result is accepted when every factorization succeeded and
+   max |Q^T Q - I| <= 1e-8.  The call synchronizes `stream` after each attempt. */
 ff_status rsvd_project(ff_spectra h, const double *r_tilde, const double *wd, const double *winv,
                        int32_t t, int32_t tp, const double *omega, uint64_t seed, int32_t power_iters,
                        int32_t alpha_mode, double *y, double *alpha, double *sigma, void *workspace,
                        size_t ws_bytes, ff_stream stream);
 
-/* Counts of the RSVD orthonormalizations done on handle h so far: by shifted Cholesky QR and by
-   the Householder fallback (see rsvd_project). */
-ff_status ff_solver_stats(ff_spectra h, int64_t *qr_cholesky, int64_t *qr_householder);
+/* Counts of the RSVD orthonormalizations done on handle h so far: by CholeskyQR2, by shifted
+   CholeskyQR3 and by Householder QR (see rsvd_project). */
+ff_status ff_solver_stats(ff_spectra h, int64_t *qr_cholesky2, int64_t *qr_cholesky3, int64_t *qr_householder);
 
 /* Parameters of one IRLS step (Sec. 2.2-2.3, Sec. 3.1). */
 typedef struct {
@@ -218,8 +219,8 @@ ff_status irls_step(ff_spectra h, const ff_irls_params *p, const double *d_obs, 
                    workspace was sized for (the value build_spectra sets).
      col_batched   1 = block applies use the 4-vectors-per-block column passes (single
                    precision), 0 = one vector per column block.
-     rsvd_qr       orthonormalization inside rsvd_project: 0 = shifted Cholesky QR with the
-                   Householder fallback, 1 = always Householder QR (geqrf + orgqr). */
+     rsvd_qr       orthonormalization inside rsvd_project: 0 = Cholesky QR with the fallbacks
+                   described there, 1 = always Householder QR (geqrf + orgqr). */
 typedef struct {
     int32_t lg_G, lg_GT;
     int32_t row_tile;

@@ -92,7 +92,7 @@ def load(path=None):
         "ff_spectra_save": [vp, C.c_char_p],
         "ff_spectra_load": [C.c_char_p, vp, C.POINTER(vp)],
         "ff_spectra_geometry": [vp, C.POINTER(FFGeometry), C.POINTER(C.c_double)],
-        "ff_solver_stats": [vp, C.POINTER(i64), C.POINTER(i64)],
+        "ff_solver_stats": [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

@@ -108,8 +108,8 @@ struct ff_spectra_s {
   size_t ws_rows_bytes = 0, ws_cols_bytes = 0;
   int lg_G = 1;                      // layer groups of the G column pass (partial sums)
   int lg_GT = 1;                     // layer groups of the G^T column pass
-  // RSVD orthonormalizations so far: by shifted Cholesky QR, and by the Householder fallback
-  int64_t qr_cholesky = 0, qr_householder = 0;
+  // RSVD orthonormalizations so far: by CholeskyQR2, by shifted CholeskyQR3, by Householder QR
+  int64_t qr_cholesky2 = 0, qr_cholesky3 = 0, qr_householder = 0;
   // pass profiling: 4 events per profiled call (before pass 1, after passes 1-3)
   std::vector<hipEvent_t> prof_ev;
   std::vector<int> prof_kind;        // transpose flag of each profiled call

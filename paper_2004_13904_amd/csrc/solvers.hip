@@ -152,18 +152,21 @@ __global__ void k_scale_from(const double *__restrict__ x, const double *__restr
   }
 }
 
-// After the first Gram-Schmidt pass: n1 = ||v1|| from the partials, the second-pass test
-// against n0 = *dg (flag = n1 < n0 / sqrt 2, Daniel-Gragg-Kaufman-Stewart), and the norm
-// and its inverse as they stand if the second pass is skipped.
-__global__ void k_norm_flag(const double *__restrict__ part, int P, const double *__restrict__ n0,
+// After the first Gram-Schmidt pass: n0 = ||v0|| (before the pass) and n1 = ||v1|| (after it)
+// from their partial sums of squares, the second-pass test flag = n1 < n0 / sqrt 2
+// (Daniel-Gragg-Kaufman-Stewart), and the norm and its inverse as they stand if the second
+// pass is skipped.
+__global__ void k_norm_flag(const double *__restrict__ part0, int P0, const double *__restrict__ part1, int P1,
                             int *__restrict__ flag, double *__restrict__ nrm, double *__restrict__ inv) {
   __shared__ double red[16];
-  double s = 0.0;
-  for (int i = threadIdx.x; i < P; i += blockDim.x) s += part[i];
-  s = block_sum(s, red);
+  double s0 = 0.0, s1 = 0.0;
+  for (int i = threadIdx.x; i < P0; i += blockDim.x) s0 += part0[i];
+  for (int i = threadIdx.x; i < P1; i += blockDim.x) s1 += part1[i];
+  s0 = block_sum(s0, red);
+  s1 = block_sum(s1, red);
   if (threadIdx.x == 0) {
-    const double v = sqrt(s);
-    *flag = (v < 0.70710678118654752 * *n0) ? 1 : 0;
+    const double v = sqrt(s1);
+    *flag = (v < 0.70710678118654752 * sqrt(s0)) ? 1 : 0;
     *nrm = v;
     *inv = v > 0.0 ? 1.0 / v : 0.0;
   }
@@ -550,6 +553,15 @@ __global__ void __launch_bounds__(kThreads) k_gram_shift(double *__restrict__ G,
   for (int i = threadIdx.x; i < cols; i += kThreads) G[(int64_t)i * cols + i] += shift;
 }
 
+// G[i] = sum over p < P of Gs[p * cc + i], in slice order (cc = cols^2 entries)
+__global__ void k_sum_slices(const double *__restrict__ Gs, int P, int64_t cc, double *__restrict__ G) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cc; i += (int64_t)gridDim.x * blockDim.x) {
+    double t = 0.0;
+    for (int p = 0; p < P; ++p) t += Gs[p * cc + i];
+    G[i] = t;
+  }
+}
+
 // zero the strictly lower triangle of the column-major cols x cols R^-1, so that a plain product
 // with it reads only the triangle
 __global__ void k_zero_lower(double *__restrict__ A, int cols) {
@@ -729,26 +741,25 @@ int launch_gemv_n(const TB *Q, int64_t ld, int64_t nrows, int ncols, const doubl
 
 // v <- (I - Q Q^T) v over the first ncols columns of Q (classical Gram-Schmidt), repeated once
 // when the first pass cancelled most of v (k_norm_flag); the test stays on the device.  On
-// return *nrm = ||v|| and *inv = 1/||v|| (0 for a zero vector).  `part` holds, on entry when
-// have_sq, the kNormBlocks partial sums of v^2 (else they are formed here); it is also the
-// scratch of the products.  dg: 1 double, flag: 1 int of scratch.
+// return *nrm = ||v|| and *inv = 1/||v|| (0 for a zero vector).  sq0 holds, on entry when
+// have_sq, the kNormBlocks partial sums of v^2 (else they are formed here); sq1 receives the
+// block sums of the updated v^2 (one per A c block); part is the scratch of the products.
+// flag: 1 int of scratch.
 template <typename TB>
 ff_status reorth_norm(const TB *Q, int64_t ld, int64_t nrows, int ncols, double *v, double *coef, double *part,
-                      bool have_sq, double *dg, int *flag, double *nrm, double *inv, hipStream_t s) {
-  if (!have_sq) k_sumsq_partial<<<kNormBlocks, kThreads, 0, s>>>(v, nrows, part);
+                      double *sq0, bool have_sq, double *sq1, int *flag, double *nrm, double *inv, hipStream_t s) {
+  if (!have_sq) k_sumsq_partial<<<kNormBlocks, kThreads, 0, s>>>(v, nrows, sq0);
   if (ncols <= 0) {
-    k_norm_finalize<<<1, kThreads, 0, s>>>(part, kNormBlocks, nrm, inv);
+    k_norm_finalize<<<1, kThreads, 0, s>>>(sq0, kNormBlocks, nrm, inv);
     FF_LAUNCH_CHECK("norm");
     return FF_OK;
   }
-  k_norm_finalize<<<1, kThreads, 0, s>>>(part, kNormBlocks, dg, nullptr);
   launch_gemv_t(Q, ld, nrows, ncols, v, coef, part, s);
-  launch_gemv_n(Q, ld, nrows, ncols, coef, v, -1.0, 1.0, s);
-  k_sumsq_partial<<<kNormBlocks, kThreads, 0, s>>>(v, nrows, part);
-  k_norm_flag<<<1, kThreads, 0, s>>>(part, kNormBlocks, dg, flag, nrm, inv);
+  const int nb1 = launch_gemv_n(Q, ld, nrows, ncols, coef, v, -1.0, 1.0, s, nullptr, sq1);
+  k_norm_flag<<<1, kThreads, 0, s>>>(sq0, kNormBlocks, sq1, nb1, flag, nrm, inv);
   launch_gemv_t(Q, ld, nrows, ncols, v, coef, part, s, flag);
-  const int nb = launch_gemv_n(Q, ld, nrows, ncols, coef, v, -1.0, 1.0, s, flag, part);
-  k_norm_cond<<<1, kThreads, 0, s>>>(part, nb, flag, nrm, inv);
+  const int nb2 = launch_gemv_n(Q, ld, nrows, ncols, coef, v, -1.0, 1.0, s, flag, sq1);
+  k_norm_cond<<<1, kThreads, 0, s>>>(sq1, nb2, flag, nrm, inv);
   FF_LAUNCH_CHECK("reorthogonalization");
   return FF_OK;
 }
@@ -782,7 +793,7 @@ ff_status norm2(const double *x, int64_t n, double *nrm, double *inv, double *pa
 // (n x tp) and H (m x (tp + 1)) are stored as TB.
 template <typename TB> struct GkbWs {
   TB *A, *H;
-  double *b, *c, *gamma, *beta, *ginv, *binv, *coef, *part, *dT, *eT, *C, *S, *V, *u0, *g, *w, *alpha, *dg;
+  double *b, *c, *gamma, *beta, *ginv, *binv, *coef, *part, *dT, *eT, *C, *S, *V, *u0, *g, *w, *alpha, *sq0, *sq1;
   int *flag;
   rocblas_int *info;
   void carve(Arena &a, int64_t n, int64_t m, int tp) {
@@ -808,14 +819,32 @@ template <typename TB> struct GkbWs {
     g = a.take<double>(tp);
     w = a.take<double>(tp);
     alpha = a.take<double>(2);
-    dg = a.take<double>(1);
+    sq0 = a.take<double>(kNormBlocks);
+    sq1 = a.take<double>((size_t)Pn);
     flag = a.take<int>(1);
     info = a.take<rocblas_int>(4);
   }
 };
 
+// Row chunks of a split Gram product Y^T Y (rows x cols Y): a single product has only
+// (cols / tile)^2 output tiles, too few for the chip when cols is small, so the rows are cut into
+// S chunks of at least 4 max(cols, 256) rows whose Gram matrices come from one batched product;
+// at most 64 chunks and 2^25 doubles of partial matrices.
+constexpr int64_t kGramScratch = (int64_t)1 << 25;
+int gram_chunks(int64_t rows, int cols) {
+  int64_t S = rows / (4 * (int64_t)(cols > 256 ? cols : 256));
+  if (S > 64) S = 64;
+  const int64_t budget = kGramScratch / ((int64_t)cols * cols) - 1;
+  if (S > budget) S = budget;
+  return S < 2 ? 1 : (int)S;
+}
+size_t gram_scratch(int64_t rows, int cols) {
+  const int S = gram_chunks(rows, cols);
+  return S > 1 ? (size_t)(S + 1) * cols * cols : 1;
+}
+
 struct RsvdWs {
-  double *Q, *Bm, *Y, *lam, *E, *S, *Vs, *btr, *c, *g, *w, *tau, *alpha, *part, *T, *U, *dev;
+  double *Q, *Bm, *Y, *lam, *E, *S, *Vs, *btr, *c, *g, *w, *tau, *alpha, *part, *T, *U, *Gs, *dev;
   int *perm;
   rocblas_int *info;
   void carve(Arena &a, int64_t n, int64_t m, int tp) {
@@ -824,6 +853,7 @@ struct RsvdWs {
     Bm = a.take<double>((size_t)m * tp);    // G~ Q
     T = a.take<double>((size_t)(n > m ? n : m) * tp);   // QR scratch
     U = a.take<double>((size_t)(n > m ? n : m) * tp);
+    Gs = a.take<double>(gram_scratch(n > m ? n : m, tp));
     dev = a.take<double>(1);
     Y = a.take<double>((size_t)tp * tp);    // B^T B, then its eigenvectors
     lam = a.take<double>(tp);
@@ -907,15 +937,16 @@ ff_status gkb_run(ff_spectra h, const double *rt, const double *wd, const double
     // b = G~^T h_i - beta_i a_{i-1}, reorthogonalized; gamma_i = ||b||
     if ((st = op_apply(h, 1, 1, W.c, m, W.b, n, wd, winv, FF_F64, s))) return st;
     if (i > 0)
-      k_axpy_sumsq<TB><<<kNormBlocks, kThreads, 0, s>>>(W.b, W.A + (int64_t)(i - 1) * n, W.beta + i, -1.0, n, W.part);
-    if ((st = reorth_norm<TB>(W.A, n, n, i, W.b, W.coef, W.part, i > 0, W.dg, W.flag, W.gamma + i, W.ginv + i, s)))
+      k_axpy_sumsq<TB><<<kNormBlocks, kThreads, 0, s>>>(W.b, W.A + (int64_t)(i - 1) * n, W.beta + i, -1.0, n, W.sq0);
+    if ((st = reorth_norm<TB>(W.A, n, n, i, W.b, W.coef, W.part, W.sq0, i > 0, W.sq1, W.flag, W.gamma + i,
+                              W.ginv + i, s)))
       return st;
     k_scale_store<TB><<<grid_for(n), kThreads, 0, s>>>(W.b, W.ginv + i, ai, n);     // b = a_i as stored
     // c = G~ a_i - gamma_i h_i, reorthogonalized; beta_{i+1} = ||c||
     if ((st = op_apply(h, 0, 1, W.b, n, W.c, m, winv, wd, FF_F64, s))) return st;
-    k_axpy_sumsq<TB><<<kNormBlocks, kThreads, 0, s>>>(W.c, hi, W.gamma + i, -1.0, m, W.part);
-    if ((st = reorth_norm<TB>(W.H, m, m, i + 1, W.c, W.coef, W.part, true, W.dg, W.flag, W.beta + i + 1,
-                              W.binv + i + 1, s)))
+    k_axpy_sumsq<TB><<<kNormBlocks, kThreads, 0, s>>>(W.c, hi, W.gamma + i, -1.0, m, W.sq0);
+    if ((st = reorth_norm<TB>(W.H, m, m, i + 1, W.c, W.coef, W.part, W.sq0, true, W.sq1, W.flag,
+                              W.beta + i + 1, W.binv + i + 1, s)))
       return st;
     k_scale_store<TB><<<grid_for(m), kThreads, 0, s>>>(W.c, W.binv + i + 1, W.H + (int64_t)(i + 1) * m, m);
   }
@@ -944,36 +975,60 @@ ff_status gkb_run(ff_spectra h, const double *rt, const double *wd, const double
   return FF_OK;
 }
 
+// G = Y^T Y (cols x cols, full) for the column-major rows x cols Y; Gs is the scratch of
+// gram_scratch(rows, cols) doubles.  The chunk products and the remainder rows' product are
+// summed in chunk order.
+ff_status gram(rocblas_handle bh, const double *Y, int64_t rows, int cols, double *G, double *Gs, hipStream_t s) {
+  const double one = 1.0, zero = 0.0;
+  const int S = gram_chunks(rows, cols);
+  const rocblas_int r = (rocblas_int)rows, c = cols;
+  if (S == 1) {
+    FF_BLAS(rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, c, c, r, &one, Y, r, Y, r, &zero, G,
+                          c),
+            "rocblas_dgemm (Gram)");
+    return FF_OK;
+  }
+  const int64_t K = rows / S, rem = rows - K * S, cc = (int64_t)cols * cols;
+  FF_BLAS(rocblas_dgemm_strided_batched(bh, rocblas_operation_transpose, rocblas_operation_none, c, c, (rocblas_int)K,
+                                        &one, Y, r, K, Y, r, K, &zero, Gs, c, cc, S),
+          "rocblas_dgemm_strided_batched (Gram chunks)");
+  int P = S;
+  if (rem > 0) {
+    const double *Yr = Y + K * S;
+    FF_BLAS(rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, c, c, (rocblas_int)rem, &one, Yr, r,
+                          Yr, r, &zero, Gs + cc * S, c),
+            "rocblas_dgemm (Gram remainder)");
+    P = S + 1;
+  }
+  k_sum_slices<<<grid_for(cc), kThreads, 0, s>>>(Gs, P, cc, G);
+  FF_LAUNCH_CHECK("Gram sum");
+  return FF_OK;
+}
+
 ff_status householder_qr(rocblas_handle bh, double *M, int64_t rows, int cols, double *tau) {
   FF_BLAS(rocsolver_dgeqrf(bh, (rocblas_int)rows, cols, M, (rocblas_int)rows, tau), "rocsolver_dgeqrf");
   FF_BLAS(rocsolver_dorgqr(bh, (rocblas_int)rows, cols, cols, M, (rocblas_int)rows, tau), "rocsolver_dorgqr");
   return FF_OK;
 }
 
-// Orthonormal basis of the columns of the tall rows x cols matrix M, in place.  Shifted Cholesky
-// QR three times (one shifted pass, then two plain ones): each pass forms the Gram matrix with
-// one product, factors it (potrf), inverts the factor (trtri) and multiplies, so the work is
-// matrix-matrix products.  M is kept until the end; if a factorization fails or the result's
-// Gram matrix is more than 1e-8 from the identity (columns dependent beyond what the shift
-// covers), the Householder QR (geqrf + orgqr) runs on M instead.  T and U are rows x cols
-// scratch, G is cols x cols, dev holds one double and info eight ints.
-ff_status qr_inplace(ff_spectra h, rocblas_handle bh, double *M, int64_t rows, int cols, double *tau, double *T,
-                     double *U, double *G, double *dev, rocblas_int *info, hipStream_t s) {
-  if (h->rsvd_qr == 1) {
-    h->qr_householder += 1;
-    return householder_qr(bh, M, rows, cols, tau);
-  }
+// One Cholesky QR attempt on the rows x cols matrix M (kept): `passes` passes of Gram product,
+// Cholesky (potrf), triangular inverse (trtri) and product, the first one with the Gram matrix
+// shifted when `shift`; then the Gram matrix of the result.  Returns through *ok whether every
+// factorization succeeded and max |Q^T Q - I| <= 1e-8, and through *q the buffer (T or U)
+// holding Q.
+ff_status cholesky_qr(rocblas_handle bh, const double *M, int64_t rows, int cols, int passes, bool shift, double *T,
+                      double *U, double *G, double *Gs, double *dev, rocblas_int *info, hipStream_t s, bool *ok,
+                      const double **q) {
   const double one = 1.0, zero = 0.0;
   const rocblas_int r = (rocblas_int)rows, c = cols;
   FF_HIP(hipMemsetAsync(info, 0, 8 * sizeof(rocblas_int), s));
   const double *in = M;
   double *outs[3] = {T, U, T};
-  for (int p = 0; p < 3; ++p) {
+  for (int p = 0; p < passes; ++p) {
     double *out = outs[p];
-    FF_BLAS(rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, c, c, r, &one, in, r, in, r, &zero,
-                          G, c),
-            "rocblas_dgemm (Gram)");
-    if (p == 0) {
+    ff_status st = gram(bh, in, rows, cols, G, Gs, s);
+    if (st) return st;
+    if (p == 0 && shift) {
       k_gram_shift<<<1, kThreads, 0, s>>>(G, c, rows);
       FF_LAUNCH_CHECK("gram shift");
     }
@@ -987,9 +1042,8 @@ ff_status qr_inplace(ff_spectra h, rocblas_handle bh, double *M, int64_t rows, i
             "rocblas_dgemm (Q R^-1)");
     in = out;
   }
-  FF_BLAS(rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, c, c, r, &one, in, r, in, r, &zero, G,
-                        c),
-          "rocblas_dgemm (check)");
+  ff_status st = gram(bh, in, rows, cols, G, Gs, s);
+  if (st) return st;
   FF_HIP(hipMemsetAsync(dev, 0, sizeof(double), s));
   k_orth_defect<<<c < 1024 ? c : 1024, kThreads, 0, s>>>(G, c, (unsigned long long *)dev);
   FF_LAUNCH_CHECK("orthogonality check");
@@ -1000,12 +1054,36 @@ ff_status qr_inplace(ff_spectra h, rocblas_handle bh, double *M, int64_t rows, i
   FF_HIP(hipMemcpyAsync(hs.info, info, sizeof(hs.info), hipMemcpyDeviceToHost, s));
   FF_HIP(hipMemcpyAsync(&hs.defect, dev, sizeof(double), hipMemcpyDeviceToHost, s));
   FF_HIP(hipStreamSynchronize(s));
-  bool ok = hs.defect <= 1e-8;
-  for (int i = 0; i < 6; ++i) ok = ok && hs.info[i] == 0;
-  if (ok) {
-    FF_HIP(hipMemcpyAsync(M, in, sizeof(double) * rows * cols, hipMemcpyDeviceToDevice, s));
-    h->qr_cholesky += 1;
-    return FF_OK;
+  bool good = hs.defect <= 1e-8;
+  for (int i = 0; i < 2 * passes; ++i) good = good && hs.info[i] == 0;
+  *ok = good;
+  *q = in;
+  return FF_OK;
+}
+
+// Orthonormal basis of the columns of the tall rows x cols matrix M, in place, by Cholesky QR:
+// first plain CholeskyQR2 (two passes; enough while the columns' condition number stays below
+// about 1e7), then, if its result is not orthonormal, shifted CholeskyQR3 (Fukaya, Kannan,
+// Nakatsukasa, Yamamoto, Yanagisawa, SIAM J. Sci. Comput. 2020: the first of three passes
+// factors the Gram matrix plus 11 (rows cols + cols (cols + 1)) u ||M||_F^2 I), then Householder
+// QR (geqrf + orgqr).  Each attempt is accepted only if max |Q^T Q - I| <= 1e-8 and all of its
+// factorizations succeeded.  T and U are rows x cols scratch, G is cols x cols, Gs the Gram
+// scratch, dev one double and info eight ints.  Synchronizes s after each attempt.
+ff_status qr_inplace(ff_spectra h, rocblas_handle bh, double *M, int64_t rows, int cols, double *tau, double *T,
+                     double *U, double *G, double *Gs, double *dev, rocblas_int *info, hipStream_t s) {
+  if (h->rsvd_qr == 0) {
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      bool ok = false;
+      const double *q = nullptr;
+      ff_status st = cholesky_qr(bh, M, rows, cols, attempt == 0 ? 2 : 3, attempt == 1, T, U, G, Gs, dev, info, s,
+                                 &ok, &q);
+      if (st) return st;
+      if (ok) {
+        FF_HIP(hipMemcpyAsync(M, q, sizeof(double) * rows * cols, hipMemcpyDeviceToDevice, s));
+        (attempt == 0 ? h->qr_cholesky2 : h->qr_cholesky3) += 1;
+        return FF_OK;
+      }
+    }
   }
   h->qr_householder += 1;
   return householder_qr(bh, M, rows, cols, tau);
@@ -1033,13 +1111,13 @@ ff_status rsvd_run(ff_spectra h, const double *rt, const double *wd, const doubl
   }
   // Y^T = G~^T Omega^T (n x tp), Q = qr(Y^T)
   if ((st = op_apply(h, 1, tp, omega, m, W.Q, n, wd, winv, FF_F64, s))) return st;
-  if ((st = qr_inplace(h, bh, W.Q, n, tp, W.tau, W.T, W.U, W.Y, W.dev, W.info, s))) return st;
+  if ((st = qr_inplace(h, bh, W.Q, n, tp, W.tau, W.T, W.U, W.Y, W.Gs, W.dev, W.info, s))) return st;
   for (int q = 0; q < power_iters; ++q) {
     // Y = G~ Q (m x tp), Q = qr(Y); Y^T = G~^T Q (n x tp), Q = qr(Y^T)
     if ((st = op_apply(h, 0, tp, W.Q, n, W.Bm, m, winv, wd, FF_F64, s))) return st;
-    if ((st = qr_inplace(h, bh, W.Bm, m, tp, W.tau, W.T, W.U, W.Y, W.dev, W.info, s))) return st;
+    if ((st = qr_inplace(h, bh, W.Bm, m, tp, W.tau, W.T, W.U, W.Y, W.Gs, W.dev, W.info, s))) return st;
     if ((st = op_apply(h, 1, tp, W.Bm, m, W.Q, n, wd, winv, FF_F64, s))) return st;
-    if ((st = qr_inplace(h, bh, W.Q, n, tp, W.tau, W.T, W.U, W.Y, W.dev, W.info, s))) return st;
+    if ((st = qr_inplace(h, bh, W.Q, n, tp, W.tau, W.T, W.U, W.Y, W.Gs, W.dev, W.info, s))) return st;
   }
   // B = G~ Q
   if ((st = op_apply(h, 0, tp, W.Q, n, W.Bm, m, winv, wd, FF_F64, s))) return st;
@@ -1128,9 +1206,10 @@ ff_status gkb_project(ff_spectra h, const double *r_tilde, const double *wd, con
   return fail(FF_EDTYPE, "gkb_project: basis_dtype must be FF_F64 or FF_F32");
 }
 
-ff_status ff_solver_stats(ff_spectra h, int64_t *qr_cholesky, int64_t *qr_householder) {
-  if (!h || !qr_cholesky || !qr_householder) return fail(FF_EINVAL, "ff_solver_stats: NULL argument");
-  *qr_cholesky = h->qr_cholesky;
+ff_status ff_solver_stats(ff_spectra h, int64_t *qr_cholesky2, int64_t *qr_cholesky3, int64_t *qr_householder) {
+  if (!h || !qr_cholesky2 || !qr_cholesky3 || !qr_householder) return fail(FF_EINVAL, "ff_solver_stats: NULL argument");
+  *qr_cholesky2 = h->qr_cholesky2;
+  *qr_cholesky3 = h->qr_cholesky3;
   *qr_householder = h->qr_householder;
   return FF_OK;
 }

@@ -91,10 +91,11 @@ class Operator:
 
     @property
     def qr_counts(self):
-        """RSVD orthonormalizations on this handle so far: {"cholesky": .., "householder": ..}."""
-        a, b = C.c_int64(), C.c_int64()
-        L.call("ff_solver_stats", self.h, C.byref(a), C.byref(b))
-        return {"cholesky": a.value, "householder": b.value}
+        """RSVD orthonormalizations on this handle so far: {"cholesky2": .., "cholesky3": ..,
+        "householder": ..} (see rsvd_project in include/fastfocus.h)."""
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        L.call("ff_solver_stats", self.h, C.byref(a), C.byref(b), C.byref(c))
+        return {"cholesky2": a.value, "cholesky3": b.value, "householder": c.value}
 
     def set_tuning(self, **changes):
         """Change some tuning values (keys of ``tuning``); the others are kept."""
