@@ -64,15 +64,15 @@ def main(argv=None):
     ap.add_argument("--cold-reps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched / RSVD-block / IRLS legs")
-    ap.add_argument("--legs", default="batched,rsvd,multi,autograd,table3,irls",
-                    help="comma list of extra legs (batched, rsvd, multi, autograd, table3, irls; "
-                         "opt-in: irls_c2, study)")
+    ap.add_argument("--legs", default="batched,rsvd,multi,autograd,table3,irls,study",
+                    help="comma list of extra legs (batched, rsvd, multi, autograd, table3, irls, study; "
+                         "opt-in: irls_c2)")
     ap.add_argument("--irls-c2-steps", type=int, default=1,
                     help="IRLS steps of the opt-in n = 1e6 magnetic leg (each step ~10 s)")
     ap.add_argument("--irls-c2-basis", default="f64", choices=("f64", "f32"),
                     help="GKB basis storage of the opt-in n = 1e6 magnetic leg")
     ap.add_argument("--irls-steps", type=int, default=25)
-    ap.add_argument("--study-ells", default="4,5", help="ladder sizes l of the opt-in study leg")
+    ap.add_argument("--study-ells", default="4", help="ladder sizes l of the study leg")
     ap.add_argument("--study-s", default="40,25,20,8,6,4,3", help="t = floor(m/s) of the study leg")
     ap.add_argument("--study-kinds", default="gravity,magnetic")
     ap.add_argument("--study-solvers", default="gkb,rsvd")
