@@ -142,6 +142,17 @@ def main(argv=None):
     ms_step = ev0.elapsed_time(ev1) / steps_done
     log(f"timed {steps_done} graph-replayed pairs: {ms_step * 1e3:.2f} us/pair (wall {wall:.3f} s)")
 
+    # spread of the replays (each replay of R pairs between its own events; not the headline)
+    per_replay = []
+    for _ in range(min(reps, 50)):
+        r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        r0.record()
+        graph.replay()
+        r1.record()
+        torch.cuda.synchronize()
+        per_replay.append(r0.elapsed_time(r1) / R * 1e3)
+    pct = {f"p{q}": round(float(np.percentile(per_replay, q)), 3) for q in (10, 50, 90)}
+
     # eager launches (no graph), same K
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -257,6 +268,7 @@ def main(argv=None):
                           "cold_ms_per_pair": round(cold_ms, 5),
                           "cold_frac": round(b_alg_pair / (cold_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "passes": passes,
+        "pair_us_spread": dict(pct, replays=len(per_replay), pairs_per_replay=R),
         "eager_ms_per_step": round(ms_eager, 6),
         "pair_grouped": {"ms_per_pair": round(ms_grouped, 6), "pairs_per_s": round(1e3 / ms_grouped, 1),
                          "results_equal_separate_calls": same_grouped,

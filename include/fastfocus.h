@@ -212,9 +212,11 @@ ff_status irls_step(ff_spectra h, const ff_irls_params *p, const double *d_obs, 
      lg_G, lg_GT   the layers of every column are split over this many groups of column-pass
                    blocks (1 <= lg <= nz); the G partial sums of the groups are added in the
                    inverse row pass.
-     row_tile      transforms per row-pass block: 0 = automatic (the largest tile that fits
-                   64 KB of LDS when a pass has at least 2048 rows, one transform otherwise),
-                   1 = always one transform (two rows), 2 = always the largest tile.
+     row_tile      transforms per row-pass block: 0 = automatic by the rows of the pass (one
+                   transform below 512 rows, two below 1024, else four; inverse passes of at
+                   least 2048 rows take the largest tile that fits 64 KB of LDS), 1 = always one
+                   transform (two rows), 2 = always the largest tile, 3 = four transforms, 4 = two
+                   transforms (3 and 4 capped by the largest tile).
      batch         vectors per launch of apply_G_block, 1 <= batch <= the batch the handle's
                    workspace was sized for (the value build_spectra sets).
      col_batched   1 = block applies use the 4-vectors-per-block column passes (single

@@ -5,7 +5,7 @@ embedding sizes) are:
 
 * ``lg_G``, ``lg_GT``: layer groups of the two column passes (more groups give more waves but more
   partial sums for G, more forward transforms for G^T);
-* ``row_tile``: transforms per row-pass block (automatic, one, or the largest that fits LDS);
+* ``row_tile``: transforms per row-pass block (automatic, one, two, four, or the largest that fits LDS);
 * ``batch`` and ``col_batched`` (block applies only): vectors per launch, and whether the column
   passes take 4 vectors per block.
 
@@ -49,7 +49,7 @@ def _time(fn, reps=20):
 
 def candidates(op, batched):
     """The values tried for each tuning key (dict key -> list), in search order."""
-    c = {"lg_G": _lg_candidates(op.nz), "lg_GT": _lg_candidates(op.nz), "row_tile": [0, 1, 2]}
+    c = {"lg_G": _lg_candidates(op.nz), "lg_GT": _lg_candidates(op.nz), "row_tile": [0, 1, 2, 3, 4]}
     if batched:
         bmax = op.batch_max
         c["batch"] = sorted({b for b in (4, 8, 16, 32, 64, bmax) if b <= bmax})

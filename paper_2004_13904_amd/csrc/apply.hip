@@ -9,40 +9,68 @@ namespace ff {
 namespace {
 
 
-// Row-pass tile: full-size blocks (RowMax transforms, 2*NF rows, written back as 2*NF-row
-// contiguous segments) when the pass has at least 2048 rows, else one transform (two rows)
-// per block so that small passes still spread over the chip; `tile` (the handle's row_tile)
-// can force either.
-inline bool big_row_tile(int tile, int64_t rows) { return tile == 2 || (tile == 0 && rows >= 2048); }
+// Row-pass tile: transforms per block (a block of NF transforms writes 2*NF-row contiguous
+// segments).  `tile` is the handle's row_tile: 1 = one transform, 2 = the largest that fits LDS,
+// 3 = four, 4 = two (capped by the largest); 0 = automatic by the rows of the pass (measured on
+// 512- and 256-point rows): one transform below 512 rows and two below 1024, so that small passes
+// still spread over the chip; four for larger forward passes; four for inverse passes below 2048
+// rows and the largest above (its 2*NF-row write segments fetch fewer partial cache lines).
+inline int row_nf(int tile, int64_t rows, int nfm, bool inverse) {
+  int nf;
+  if (tile == 1) nf = 1;
+  else if (tile == 2) nf = nfm;
+  else if (tile == 3) nf = 4;
+  else if (tile == 4) nf = 2;
+  else nf = rows < 512 ? 1 : rows < 1024 ? 2 : (inverse && rows >= 2048) ? nfm : 4;
+  return nf < nfm ? nf : nfm;
+}
+
+template <typename T, typename TI, int N, int NF>
+void launch_r2c_nf(int nrows, int nb, int kb, const TI *in, Idx3 ii, const TI *pre, Idx3 pi, int len, int off,
+                   cplx<T> *out, Idx3 oi, int64_t out_kx, const cplx<T> *tw, hipStream_t s) {
+  using C = RowCfg<T, N, NF>;
+  dim3 g((nrows * nb + C::ROWS - 1) / C::ROWS, 1, kb);
+  k_row_r2c<T, TI, N, NF><<<g, C::THREADS, 0, s>>>(in, ii, pre, pi, nrows, nb, len, off, out, oi, out_kx, tw);
+}
 
 template <typename T, typename TI, int N>
 void launch_r2c(int tile, int nrows, int nb, int kb, const TI *in, Idx3 ii, const TI *pre, Idx3 pi, int len, int off,
                 cplx<T> *out, Idx3 oi, int64_t out_kx, const cplx<T> *tw, hipStream_t s) {
   constexpr int NFM = RowMax<T, N>::NF;
-  if (NFM == 1 || big_row_tile(tile, (int64_t)nrows * nb * kb)) {
-    using C = RowCfg<T, N, NFM>;
-    dim3 g((nrows * nb + C::ROWS - 1) / C::ROWS, 1, kb);
-    k_row_r2c<T, TI, N, NFM><<<g, C::THREADS, 0, s>>>(in, ii, pre, pi, nrows, nb, len, off, out, oi, out_kx, tw);
-  } else {
-    using C = RowCfg<T, N, 1>;
-    dim3 g((nrows * nb + C::ROWS - 1) / C::ROWS, 1, kb);
-    k_row_r2c<T, TI, N, 1><<<g, C::THREADS, 0, s>>>(in, ii, pre, pi, nrows, nb, len, off, out, oi, out_kx, tw);
-  }
+  constexpr int NF4 = NFM < 4 ? NFM : 4, NF2 = NFM < 2 ? NFM : 2;
+  const int nf = row_nf(tile, (int64_t)nrows * nb * kb, NFM, false);
+  if (nf == NFM)
+    launch_r2c_nf<T, TI, N, NFM>(nrows, nb, kb, in, ii, pre, pi, len, off, out, oi, out_kx, tw, s);
+  else if (nf == NF4)
+    launch_r2c_nf<T, TI, N, NF4>(nrows, nb, kb, in, ii, pre, pi, len, off, out, oi, out_kx, tw, s);
+  else if (nf == NF2)
+    launch_r2c_nf<T, TI, N, NF2>(nrows, nb, kb, in, ii, pre, pi, len, off, out, oi, out_kx, tw, s);
+  else
+    launch_r2c_nf<T, TI, N, 1>(nrows, nb, kb, in, ii, pre, pi, len, off, out, oi, out_kx, tw, s);
+}
+
+template <typename T, typename TO, int N, int NF>
+void launch_c2r_nf(int nrows, int nb, int kb, const cplx<T> *in, Idx3 ii, int64_t in_kx, int64_t pstride, int P,
+                   TO *out, Idx3 oi, const TO *post, Idx3 qi, int len, int off, const cplx<T> *tw, hipStream_t s) {
+  using C = RowCfg<T, N, NF>;
+  dim3 g((nrows * nb + C::ROWS - 1) / C::ROWS, 1, kb);
+  k_row_c2r<T, TO, N, NF><<<g, C::THREADS, 0, s>>>(in, ii, in_kx, pstride, P, nrows, nb, out, oi, post, qi, len, off, tw);
 }
 
 template <typename T, typename TO, int N>
 void launch_c2r(int tile, int nrows, int nb, int kb, const cplx<T> *in, Idx3 ii, int64_t in_kx, int64_t pstride,
                 int P, TO *out, Idx3 oi, const TO *post, Idx3 qi, int len, int off, const cplx<T> *tw, hipStream_t s) {
   constexpr int NFM = RowMax<T, N>::NF;
-  if (NFM == 1 || big_row_tile(tile, (int64_t)nrows * nb * kb)) {
-    using C = RowCfg<T, N, NFM>;
-    dim3 g((nrows * nb + C::ROWS - 1) / C::ROWS, 1, kb);
-    k_row_c2r<T, TO, N, NFM><<<g, C::THREADS, 0, s>>>(in, ii, in_kx, pstride, P, nrows, nb, out, oi, post, qi, len, off, tw);
-  } else {
-    using C = RowCfg<T, N, 1>;
-    dim3 g((nrows * nb + C::ROWS - 1) / C::ROWS, 1, kb);
-    k_row_c2r<T, TO, N, 1><<<g, C::THREADS, 0, s>>>(in, ii, in_kx, pstride, P, nrows, nb, out, oi, post, qi, len, off, tw);
-  }
+  constexpr int NF4 = NFM < 4 ? NFM : 4, NF2 = NFM < 2 ? NFM : 2;
+  const int nf = row_nf(tile, (int64_t)nrows * nb * kb, NFM, true);
+  if (nf == NFM)
+    launch_c2r_nf<T, TO, N, NFM>(nrows, nb, kb, in, ii, in_kx, pstride, P, out, oi, post, qi, len, off, tw, s);
+  else if (nf == NF4)
+    launch_c2r_nf<T, TO, N, NF4>(nrows, nb, kb, in, ii, in_kx, pstride, P, out, oi, post, qi, len, off, tw, s);
+  else if (nf == NF2)
+    launch_c2r_nf<T, TO, N, NF2>(nrows, nb, kb, in, ii, in_kx, pstride, P, out, oi, post, qi, len, off, tw, s);
+  else
+    launch_c2r_nf<T, TO, N, 1>(nrows, nb, kb, in, ii, in_kx, pstride, P, out, oi, post, qi, len, off, tw, s);
 }
 
 // One pass of G (transpose = 0) or G^T (transpose = 1) for kb vectors: pass 0 = row

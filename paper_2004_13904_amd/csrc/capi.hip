@@ -369,7 +369,7 @@ ff_status ff_set_tuning(ff_spectra h, const ff_tuning *t) {
   if (!h || !t) return fail(FF_EINVAL, "ff_set_tuning: NULL argument");
   if (t->lg_G < 1 || t->lg_G > h->nz || t->lg_GT < 1 || t->lg_GT > h->nz)
     return fail(FF_EINVAL, "ff_set_tuning: layer groups must lie in [1, nz]");
-  if (t->row_tile < 0 || t->row_tile > 2) return fail(FF_EINVAL, "ff_set_tuning: row_tile must be 0, 1 or 2");
+  if (t->row_tile < 0 || t->row_tile > 4) return fail(FF_EINVAL, "ff_set_tuning: row_tile must lie in [0, 4]");
   if (t->batch < 1 || t->batch > h->batch_max)
     return fail(FF_EINVAL, "ff_set_tuning: batch must lie in [1, the handle's workspace batch]");
   if (t->col_batched != 0 && t->col_batched != 1) return fail(FF_EINVAL, "ff_set_tuning: col_batched must be 0 or 1");
