@@ -84,7 +84,7 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the operator and solvers run on a single MI355X "
-              "(multi-GPU sharding is a design note, not part of this build).", file=sys.stderr)
+              "(sharding over several GPUs is not implemented).", file=sys.stderr)
         return 2
 
     import torch
