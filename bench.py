@@ -797,11 +797,13 @@ def cpu_baseline(s, x_h, d_h, A, x, d):
     g = geometry.Geometry(**s)
     log("oracle kernel table (not timed: precomputed, like the spectra)")
     T = op.kernel_table(g)
-    reps = 2
+    # pairs until at least 10 s of host time (at least 2, at most 8)
+    reps = 0
     t0 = time.perf_counter()
-    for _ in range(reps):
+    while reps < 2 or (reps < 8 and time.perf_counter() - t0 < 10.0):
         ref_d = op.apply_G(g, x_h, T)
         ref_x = op.apply_GT(g, d_h, T)
+        reps += 1
     dt = time.perf_counter() - t0
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
     gx = A.G(x).double().cpu().numpy()
