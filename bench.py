@@ -381,7 +381,8 @@ def study_leg(ells, s_list, kinds, solvers, basis="f64", pad=0.0, kmax=25):
                                  "K": len(hist), "converged": hist[-1][2] <= 1.0,
                                  "seconds": round(total, 3),
                                  "seconds_per_step": round(total / len(hist), 4),
-                                 "first_step_s": round(step_t[0], 4), "RE": round(re, 4),
+                                 "first_step_s": round(step_t[0], 4), "last_step_s": round(step_t[-1], 4),
+                                 "RE": round(re, 4),
                                  "chi2_scaled": round(hist[-1][2], 4), "alpha_1": hist[0][1],
                                  "alpha_K": hist[-1][1],
                                  "qr": {k: A.qr_counts[k] - qr0[k] for k in qr0}})
