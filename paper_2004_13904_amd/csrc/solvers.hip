@@ -791,8 +791,13 @@ ff_status norm2(const double *x, int64_t n, double *nrm, double *inv, double *pa
 
 // Workspace of Algorithm 1 for a handle and tp (also used for sizing when a.dry); the bases A
 // (n x tp) and H (m x (tp + 1)) are stored as TB.
+// Leading dimension of a stored basis: the rows rounded up to 64 elements, so that every column
+// starts on a 256-byte boundary and the products use 16-byte loads for any n and m.
+inline int64_t basis_ld(int64_t rows) { return (rows + 63) / 64 * 64; }
+
 template <typename TB> struct GkbWs {
   TB *A, *H;
+  int64_t ldA, ldH;
   double *b, *c, *gamma, *beta, *ginv, *binv, *coef, *part, *dT, *eT, *C, *S, *V, *u0, *g, *w, *alpha, *sq0, *sq1;
   int *flag;
   rocblas_int *info;
@@ -800,8 +805,10 @@ template <typename TB> struct GkbWs {
     const int64_t P = ((n > m ? n : m) + kRowsMin - 1) / kRowsMin + 1;   // partial rows at one row per load
     const int64_t Pn = ((n > m ? n : m) + 63) / 64 + 1;                  // blocks of the A c products
     const int64_t npart = ((P > 256 ? P : 256) + 1) * (tp + 2);
-    A = a.take<TB>((size_t)n * tp);
-    H = a.take<TB>((size_t)m * (tp + 1));
+    ldA = basis_ld(n);
+    ldH = basis_ld(m);
+    A = a.take<TB>((size_t)ldA * tp);
+    H = a.take<TB>((size_t)ldH * (tp + 1));
     b = a.take<double>(n);
     c = a.take<double>(m);
     gamma = a.take<double>(tp + 1);
@@ -932,23 +939,24 @@ ff_status gkb_run(ff_spectra h, const double *rt, const double *wd, const double
   k_scale_from<TB><<<grid_for(m), kThreads, 0, s>>>(rt, W.binv, W.H, W.c, m);
   FF_HIP(hipMemsetAsync(W.b, 0, sizeof(double) * n, s));
   for (int i = 0; i < tp; ++i) {
-    TB *ai = W.A + (int64_t)i * n;
-    const TB *hi = W.H + (int64_t)i * m;
+    TB *ai = W.A + (int64_t)i * W.ldA;
+    const TB *hi = W.H + (int64_t)i * W.ldH;
     // b = G~^T h_i - beta_i a_{i-1}, reorthogonalized; gamma_i = ||b||
     if ((st = op_apply(h, 1, 1, W.c, m, W.b, n, wd, winv, FF_F64, s))) return st;
     if (i > 0)
-      k_axpy_sumsq<TB><<<kNormBlocks, kThreads, 0, s>>>(W.b, W.A + (int64_t)(i - 1) * n, W.beta + i, -1.0, n, W.sq0);
-    if ((st = reorth_norm<TB>(W.A, n, n, i, W.b, W.coef, W.part, W.sq0, i > 0, W.sq1, W.flag, W.gamma + i,
+      k_axpy_sumsq<TB><<<kNormBlocks, kThreads, 0, s>>>(W.b, W.A + (int64_t)(i - 1) * W.ldA, W.beta + i, -1.0, n,
+                                                        W.sq0);
+    if ((st = reorth_norm<TB>(W.A, W.ldA, n, i, W.b, W.coef, W.part, W.sq0, i > 0, W.sq1, W.flag, W.gamma + i,
                               W.ginv + i, s)))
       return st;
     k_scale_store<TB><<<grid_for(n), kThreads, 0, s>>>(W.b, W.ginv + i, ai, n);     // b = a_i as stored
     // c = G~ a_i - gamma_i h_i, reorthogonalized; beta_{i+1} = ||c||
     if ((st = op_apply(h, 0, 1, W.b, n, W.c, m, winv, wd, FF_F64, s))) return st;
     k_axpy_sumsq<TB><<<kNormBlocks, kThreads, 0, s>>>(W.c, hi, W.gamma + i, -1.0, m, W.sq0);
-    if ((st = reorth_norm<TB>(W.H, m, m, i + 1, W.c, W.coef, W.part, W.sq0, true, W.sq1, W.flag,
+    if ((st = reorth_norm<TB>(W.H, W.ldH, m, i + 1, W.c, W.coef, W.part, W.sq0, true, W.sq1, W.flag,
                               W.beta + i + 1, W.binv + i + 1, s)))
       return st;
-    k_scale_store<TB><<<grid_for(m), kThreads, 0, s>>>(W.c, W.binv + i + 1, W.H + (int64_t)(i + 1) * m, m);
+    k_scale_store<TB><<<grid_for(m), kThreads, 0, s>>>(W.c, W.binv + i + 1, W.H + (int64_t)(i + 1) * W.ldH, m);
   }
   FF_LAUNCH_CHECK("gkb iteration");
   // SVD of the (tp+1) x tp bidiagonal through its Golub-Kahan tridiagonal
@@ -967,7 +975,7 @@ ff_status gkb_run(ff_spectra h, const double *rt, const double *wd, const double
   qa.t = tp;
   k_filter<<<(tp + 255) / 256, 256, 0, s>>>(W.S, W.alpha, qa, tp, W.g);
   if ((st = gemv_n(W.V, tp, tp, tp, W.g, W.w, 1.0, s))) return st;
-  launch_gemv_n<TB>(W.A, n, n, tp, W.w, y, 1.0, 0.0, s);
+  launch_gemv_n<TB>(W.A, W.ldA, n, tp, W.w, y, 1.0, 0.0, s);
   FF_LAUNCH_CHECK("gkb solution");
   FF_HIP(hipMemcpyAsync(sigma, W.S, sizeof(double) * tp, hipMemcpyDeviceToDevice, s));
   FF_HIP(hipMemcpyAsync(alpha, W.alpha, sizeof(double), hipMemcpyDeviceToHost, s));
