@@ -599,6 +599,47 @@ def autograd_leg(check=True, alpha=1.0, eps2=1e-9):
     else:
         out["ms_forward_backward_graph"] = None
         log("autograd graph replay differs from eager: not timed")
+    # the fused objective: the misfit and stabilizer around the operator in library kernels
+    # (ff_focusing_loss / ff_focusing_grad), eager and in a graph, against the unfused gradient
+    from paper_2004_13904_amd.operator import FocusingLoss
+
+    def fwd_bwd_fused():
+        m = m0.clone().requires_grad_(True)
+        FocusingLoss.apply(A, m, d_obs, wd, alpha, eps2).backward()
+        return m.grad
+    gf = fwd_bwd_fused()
+    out["fused_grad_rel_diff_vs_unfused"] = float((torch.linalg.norm((gf - ref).double()) /
+                                                   torch.linalg.norm(ref.double())).item())
+    ms_f = timed(fwd_bwd_fused, 20)
+    out["ms_forward_backward_fused"] = round(ms_f, 5)
+    out["fused_overhead_vs_plain"] = round(ms_f / ms_plain, 3)
+    fm = m0.clone().requires_grad_(True)
+
+    def fused_backward():
+        FocusingLoss.apply(A, fm, d_obs, wd, alpha, eps2).backward()
+    with torch.cuda.stream(side):
+        for _ in range(3):
+            fm.grad = None
+            fused_backward()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    fm.grad = None
+    fgraph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(fgraph):
+        fused_backward()
+    fsame = True
+    for _ in range(3):
+        plain()
+        fgraph.replay()
+        torch.cuda.synchronize()
+        fsame = fsame and bool(torch.equal(fm.grad, gf))
+    if fsame:
+        ms_fg = timed(fgraph.replay, 20)
+        out["ms_forward_backward_fused_graph"] = round(ms_fg, 5)
+        out["fused_graph_overhead_vs_plain"] = round(ms_fg / ms_plain, 3)
+    else:
+        out["ms_forward_backward_fused_graph"] = None
+    log(f"autograd fused: {ms_f * 1e3:.1f} us eager, graph {out['ms_forward_backward_fused_graph']}")
     if check:
         from oracle import geometry, operator as op
         grad = fwd_bwd()[0].double().cpu().numpy()

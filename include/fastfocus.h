@@ -130,6 +130,22 @@ ff_status apply_G_block(ff_spectra h, int32_t transpose, int64_t k, const void *
                         void *Y, int64_t ldy, const void *w_pre, const void *w_post,
                         ff_stream stream);
 
+/* The focusing objective of the differentiable form, with the operator products inside:
+   L = sum over the k models of ||wd .* (G m - d_obs)||^2 + alpha * sum_i m_i^2 / (m_i^2 + eps2),
+   the data misfit of eq. (dfandstab) and the minimum-support stabilizer (eq. (WLdefn) with
+   lambda = 0, W_h = W_z = I, D = I, m_apr = 0).  m: k x n, d_obs, wd, rw: k x m, all column-major
+   with leading dimensions n and m, in the handle's dtype; alpha >= 0, eps2 > 0.
+   ff_focusing_loss writes rw = 2 wd .* wd .* (G m - d_obs) (the misfit's gradient with respect to
+   G m, kept for the gradient call) and, in the caller's device buffer `work` of 513 doubles,
+   work[0] = L (summed in double, in a fixed order).
+   ff_focusing_grad writes grad (k x n) = scale * (G^T rw + alpha * 2 m eps2 / (m^2 + eps2)^2),
+   with scale a device double (NULL = 1): dL/dm times the caller's upstream factor.
+   Both are asynchronous on `stream`. */
+ff_status ff_focusing_loss(ff_spectra h, int64_t k, const void *m, const void *d_obs, const void *wd,
+                           double alpha, double eps2, void *rw, double *work, ff_stream stream);
+ff_status ff_focusing_grad(ff_spectra h, int64_t k, const void *m, const void *rw, double alpha,
+                           double eps2, const double *scale, void *grad, ff_stream stream);
+
 /* ---------------------------------------------------------------------------------------
    Projected solvers and IRLS (Sec. 2.3).  All vectors below are FP64 device arrays; the
    operator applications inside run in the handle's dtype.  `workspace` is a caller-owned

@@ -199,6 +199,43 @@ class GOp(torch.autograd.Function):
         return None, gx
 
 
+class FocusingLoss(torch.autograd.Function):
+    """L = sum over models of ||wd (G m - d_obs)||^2 + alpha * sum m^2 / (m^2 + eps2), with the
+    operator products and everything around them in the library (ff_focusing_loss / _grad):
+    m is (n,) or (k, n); d_obs and wd have the shape of G m.  Returns a float64 scalar; the
+    gradient flows to m only."""
+
+    @staticmethod
+    def forward(ctx, op, m, d_obs, wd, alpha=1.0, eps2=1e-9):
+        m = m.contiguous()
+        if m.dim() not in (1, 2) or m.shape[-1] != op.n:
+            raise L.FastFocusError("FocusingLoss", -2, f"m must be (n,) or (k, n) with n = {op.n}")
+        k = 1 if m.dim() == 1 else m.shape[0]
+        op._vec(m, k * op.n, "FocusingLoss m")
+        shape = (op.m,) if m.dim() == 1 else (k, op.m)
+        d_obs = d_obs.contiguous()
+        wd = wd.contiguous()
+        for name, t in (("d_obs", d_obs), ("wd", wd)):
+            if tuple(t.shape) != shape or t.dtype != m.dtype or t.device != m.device:
+                raise L.FastFocusError("FocusingLoss", -2, f"{name} must be {shape} {m.dtype} on {m.device}")
+        rw = torch.empty(shape, dtype=m.dtype, device=m.device)
+        work = torch.empty(513, dtype=torch.float64, device=m.device)
+        L.call("ff_focusing_loss", op.h, k, _ptr(m), _ptr(d_obs), _ptr(wd), float(alpha), float(eps2), _ptr(rw),
+               _ptr(work), _stream())
+        ctx.op, ctx.k, ctx.alpha, ctx.eps2 = op, k, float(alpha), float(eps2)
+        ctx.save_for_backward(m, rw)
+        return work[0]
+
+    @staticmethod
+    def backward(ctx, g):
+        m, rw = ctx.saved_tensors
+        g = g.to(torch.float64).contiguous()
+        grad = torch.empty_like(m)
+        L.call("ff_focusing_grad", ctx.op.h, ctx.k, _ptr(m), _ptr(rw), ctx.alpha, ctx.eps2, _ptr(g), _ptr(grad),
+               _stream())
+        return None, grad, None, None, None, None
+
+
 class GTOp(torch.autograd.Function):
     """x = G^T d; backward applies G."""
 

@@ -8,7 +8,8 @@ import torch
 from gpu_common import ogeom, rel, same, to_dev, to_host
 from oracle import operator as op
 from paper_2004_13904_amd import workloads as W
-from paper_2004_13904_amd.operator import GOp, GTOp, Operator
+from paper_2004_13904_amd import _lib as L
+from paper_2004_13904_amd.operator import FocusingLoss, GOp, GTOp, Operator
 
 pytestmark = pytest.mark.gpu
 F64, F32 = torch.float64, torch.float32
@@ -116,3 +117,57 @@ def test_batched_forward_backward_equals_per_vector():
     for c in range(4):
         same(Y[c], A.G(models[c].contiguous()))
         same(X.grad[c], A.GT(w[c].contiguous()))
+
+
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_fused_focusing_loss_matches_dense_reference(dtype):
+    # the library's fused objective (misfit + minimum support with the operator inside) against the
+    # dense FP64 loss and gradient on the crop
+    s, g, G, m0, d_obs, wd = crop_problem(dtype)
+    alpha = 1.0
+    A = Operator(s, dtype)
+    m = to_dev(m0, dtype).requires_grad_(True)
+    Lf = FocusingLoss.apply(A, m, to_dev(d_obs, dtype), to_dev(wd, dtype), alpha, EPS2)
+    Lf.backward()
+    r = wd * (m0 @ G.T - d_obs)
+    ref = 2.0 * (wd * r) @ G + alpha * 2.0 * m0 * EPS2 / (m0 * m0 + EPS2) ** 2
+    ref_L = float((r * r).sum() + alpha * (m0 * m0 / (m0 * m0 + EPS2)).sum())
+    tol = 1e-10 if dtype == F64 else 1e-5
+    assert Lf.dtype == F64 and abs(float(Lf) - ref_L) <= tol * abs(ref_L)
+    assert rel(to_host(m.grad), ref) <= tol
+
+
+def test_fused_focusing_loss_equals_unfused_and_gradchecks():
+    s = W.survey(7, 6, 3, 25, 25, 25, kernel="magnetic", incl=45, decl=45)
+    A = Operator(s, F64)
+    rng = np.random.default_rng(3)
+    m0 = rng.random((2, A.n)) * (rng.random((2, A.n)) > 0.5)
+    d_obs = to_dev(rng.standard_normal((2, A.m)), F64)
+    wd = to_dev(0.5 + rng.random((2, A.m)), F64)
+    alpha, eps2 = 0.7, 1e-3          # a smooth stabilizer at the scale of the finite differences
+    m1 = to_dev(m0, F64).requires_grad_(True)
+    m2 = to_dev(m0, F64).requires_grad_(True)
+    L1 = FocusingLoss.apply(A, m1, d_obs, wd, alpha, eps2)
+    r = wd * (GOp.apply(A, m2) - d_obs)
+    L2 = (r * r).sum() + alpha * (m2 * m2 / (m2 * m2 + eps2)).sum()
+    (3.0 * L1).backward()           # an upstream factor reaches the gradient
+    (3.0 * L2).backward()
+    assert abs(float(L1) - float(L2)) <= 1e-12 * abs(float(L2))
+    assert rel(to_host(m1.grad), to_host(m2.grad)) <= 1e-12
+    x = to_dev(m0[0], F64).requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda v: FocusingLoss.apply(A, v, d_obs[0], wd[0], alpha, eps2), (x,),
+                                    eps=1e-6, atol=1e-7)
+
+
+def test_fused_focusing_loss_rejects_bad_arguments():
+    s = W.survey(7, 6, 3, 25, 25, 25)
+    A = Operator(s, F32)
+    m = torch.rand(2, A.n, device="cuda")
+    d = torch.randn(2, A.m, device="cuda")
+    w = torch.ones(2, A.m, device="cuda")
+    with pytest.raises(L.FastFocusError):
+        FocusingLoss.apply(A, m, d[:, :-1].contiguous(), w, 1.0, 1e-9)      # wrong data shape
+    with pytest.raises(L.FastFocusError):
+        FocusingLoss.apply(A, m.double(), d.double(), w.double(), 1.0, 1e-9)   # wrong dtype
+    with pytest.raises(L.FastFocusError):
+        FocusingLoss.apply(A, m, d, w, 1.0, 0.0)                            # eps2 must be > 0
