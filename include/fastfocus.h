@@ -238,7 +238,8 @@ ff_status irls_step(ff_spectra h, const ff_irls_params *p, const double *d_obs, 
      col_batched   1 = block applies use the 4-vectors-per-block column passes (single
                    precision), 0 = one vector per column block.
      rsvd_qr       orthonormalization inside rsvd_project: 0 = Cholesky QR with the fallbacks
-                   described there, 1 = always Householder QR (geqrf + orgqr). */
+                   described there, 1 = always Householder QR (geqrf + orgqr), 2 = start at the
+                   shifted CholeskyQR3 (then Householder). */
 typedef struct {
     int32_t lg_G, lg_GT;
     int32_t row_tile;

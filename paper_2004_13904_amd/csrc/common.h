@@ -102,7 +102,7 @@ struct ff_spectra_s {
   int batch_max = ff::kMinBatch;      // vectors the pass workspace holds
   int row_tile = 0;                   // 0 auto, 1 one transform per row block, 2 largest tile
   int col_batched = 1;                // 4-vectors-per-block column passes for block applies
-  int rsvd_qr = 0;                    // RSVD orthonormalization: 0 Cholesky QR (+ fallback), 1 Householder
+  int rsvd_qr = 0;                    // RSVD orthonormalization: 0 CholQR2 first, 1 Householder, 2 CholQR3 first
   void *ws_rows = nullptr;           // batch x nz x H x max(ny, sy) complex: row-pass <-> column-pass
   void *ws_cols = nullptr;           // batch x LG x H x max(sy, ...) complex: column-pass partials / D1
   size_t ws_rows_bytes = 0, ws_cols_bytes = 0;

@@ -1079,8 +1079,8 @@ ff_status cholesky_qr(rocblas_handle bh, const double *M, int64_t rows, int cols
 // scratch, dev one double and info eight ints.  Synchronizes s after each attempt.
 ff_status qr_inplace(ff_spectra h, rocblas_handle bh, double *M, int64_t rows, int cols, double *tau, double *T,
                      double *U, double *G, double *Gs, double *dev, rocblas_int *info, hipStream_t s) {
-  if (h->rsvd_qr == 0) {
-    for (int attempt = 0; attempt < 2; ++attempt) {
+  if (h->rsvd_qr != 1) {
+    for (int attempt = h->rsvd_qr == 2 ? 1 : 0; attempt < 2; ++attempt) {
       bool ok = false;
       const double *q = nullptr;
       ff_status st = cholesky_qr(bh, M, rows, cols, attempt == 0 ? 2 : 3, attempt == 1, T, U, G, Gs, dev, info, s,

@@ -95,9 +95,10 @@ def test_rsvd_full_space_is_tikhonov(kernel):
 
 @pytest.mark.parametrize("mode", ["fixed", "upre", "alpha1"])
 @pytest.mark.parametrize("dtype", [F64, F32])
-@pytest.mark.parametrize("qr", [0, 1])
+@pytest.mark.parametrize("qr", [0, 1, 2])
 def test_rsvd_matches_oracle_algorithm(mode, dtype, qr):
-    # qr 0: shifted Cholesky QR (with its Householder fallback); 1: Householder QR always
+    # qr 0: CholeskyQR2 first (then shifted CholeskyQR3, then Householder); 1: Householder QR
+    # always; 2: shifted CholeskyQR3 first
     s, g, G, wd, winv, Gt, r = problem("mid", kernel="gravity", seed=2)
     t, tp = 60, 63
     announce("rsvd", mode, dtype, "qr", qr)
@@ -120,6 +121,8 @@ def test_rsvd_matches_oracle_algorithm(mode, dtype, qr):
     assert sum(counts.values()) == 6
     if qr == 1:
         assert counts["householder"] == 6
+    elif qr == 2:
+        assert counts["cholesky2"] == 0 and counts["cholesky3"] >= 1
     else:
         assert counts["cholesky2"] + counts["cholesky3"] >= 1
 
