@@ -90,24 +90,16 @@ __global__ void k_scale(const double *__restrict__ x, const double *__restrict__
 
 // Basis storage of the GKB factors: FP64 (default) or FP32 (half the memory and traffic; the
 // arithmetic stays FP64).  load_rows reads RPL consecutive rows of a basis column with one
-// vector load (16 bytes: RPL = 2 for double, 4 for float) and widens them to double.
-template <typename TB, int RPL> struct Vec { using type = TB; };
-template <> struct Vec<double, 2> { using type = double2; };
-template <> struct Vec<float, 2> { using type = float2; };
-template <> struct Vec<float, 4> { using type = float4; };
-
+// vector load (16 bytes: RPL = 2 for double, 4 for float) and widens them to double.  The bases
+// are streamed once per pass, so the loads carry the non-temporal hint.
 template <typename TB, int RPL> __device__ __forceinline__ void load_rows(const TB *p, double (&o)[RPL]) {
-  const typename Vec<TB, RPL>::type v = *(const typename Vec<TB, RPL>::type *)p;
   if constexpr (RPL == 1) {
-    o[0] = (double)v;
-  } else if constexpr (RPL == 2) {
-    o[0] = (double)v.x;
-    o[1] = (double)v.y;
+    o[0] = (double)__builtin_nontemporal_load(p);
   } else {
-    o[0] = (double)v.x;
-    o[1] = (double)v.y;
-    o[2] = (double)v.z;
-    o[3] = (double)v.w;
+    typedef TB V __attribute__((ext_vector_type(RPL)));
+    const V v = __builtin_nontemporal_load((const V *)p);
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) o[q] = (double)v[q];
   }
 }
 
