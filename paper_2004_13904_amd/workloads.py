@@ -1,7 +1,8 @@
 """Seeded synthetic workloads shared by the tests, the benchmark and the checks.
 
-This module holds only geometry *parameters* and random draws; it contains none of
-the method's arithmetic (no kernel integrals, no operator, no solver).  Both the CPU
+This module holds geometry *parameters*, synthetic models and random draws, plus the noise
+model and the SNR of the paper's experiments; it contains none of the method's arithmetic (no
+kernel integrals, no operator, no solver).  Both the CPU
 oracle and the HIP path build their own geometry objects from the plain dicts here.
 
 Survey geometries follow the paper's setting (Sec. 2.1, Fig. 1): stations at the
