@@ -11,6 +11,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kLossBlocks = 256;   // partial sums per term
+static_assert(kLossBlocks == kThreads, "k_loss_final sums one partial per thread");
 
 __device__ double block_sum256(double v, double *red) {
   red[threadIdx.x] = v;
