@@ -23,8 +23,8 @@ __device__ double block_sum256(double v, double *red) {
   return red[0];
 }
 
-// Blocks [0, kLossBlocks): rw = 2 wd (gm - d) in place of gm (the misfit's gradient with respect
-// to G m) and partial sums of (wd (gm - d))^2 into part[b].  Blocks [kLossBlocks, 2 kLossBlocks):
+// Blocks [0, kLossBlocks): rw = 2 wd^2 (gm - d) in place of gm (the misfit's gradient with
+// respect to G m) and partial sums of (wd (gm - d))^2 into part[b].  Blocks [kLossBlocks, 2 kLossBlocks):
 // partial sums of m^2 / (m^2 + eps2) into part[b].  Grid-stride over the km and kn elements.
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
