@@ -732,9 +732,42 @@ def multi_survey_leg():
     ms_eager = timed(B.eager, 50)
     log(f"multi-survey: grouped graph {ms_graph * 1e3:.1f} us, grouped {ms_grouped * 1e3:.1f} us, "
         f"per-survey launches {ms_eager * 1e3:.1f} us")
-    return {"surveys": [list(x) for x in W.UNEVEN], "grouped_launches": B.grouped_launches,
-            "ms_graph": round(ms_graph, 5), "ms_grouped_eager": round(ms_grouped, 5),
-            "ms_sequential_launches": round(ms_eager, 5), "speedup": round(ms_eager / ms_graph, 3)}
+    out = {"surveys": [list(x) for x in W.UNEVEN], "grouped_launches": B.grouped_launches,
+           "ms_graph": round(ms_graph, 5), "ms_grouped_eager": round(ms_grouped, 5),
+           "ms_sequential_launches": round(ms_eager, 5), "speedup": round(ms_eager / ms_graph, 3)}
+    # k = 64 vectors per survey: every survey's block pair (G X, G^T D), replayed from one graph,
+    # against the per-vector loop (timed on 8 of the 64 vectors and scaled)
+    k = 64
+    Xs = [torch.rand(k, o.n, device="cuda", generator=g) for o in B.ops]
+    Ds = [torch.randn(k, o.m, device="cuda", generator=g) for o in B.ops]
+    Ys = [torch.empty(k, o.m, device="cuda") for o in B.ops]
+    Zs = [torch.empty(k, o.n, device="cuda") for o in B.ops]
+
+    def blocks():
+        for o, X, D, Y, Z in zip(B.ops, Xs, Ds, Ys, Zs):
+            o.G_block(X, out=Y)
+            o.G_block(D, transpose=True, out=Z)
+
+    def loop8():
+        for o, X, D, Y, Z in zip(B.ops, Xs, Ds, Ys, Zs):
+            for c in range(8):
+                o.G(X[c], out=Y[c])
+                o.GT(D[c], out=Z[c])
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        blocks()
+    torch.cuda.current_stream().wait_stream(side)
+    bg = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(bg):
+        blocks()
+    ms_blocks = timed(bg.replay, 20)
+    ms_loop = timed(loop8, 5) * (k / 8)
+    log(f"multi-survey k=64: block pairs in a graph {ms_blocks:.3f} ms, per-vector loop {ms_loop:.3f} ms")
+    out["k64"] = {"vectors_per_survey": k, "ms_block_pairs_graph": round(ms_blocks, 4),
+                  "ms_per_vector_loop": round(ms_loop, 4), "speedup": round(ms_loop / ms_blocks, 3),
+                  "pairs_per_s": round(8 * k / (ms_blocks * 1e-3), 1)}
+    return out
 
 
 def irls_leg(steps, lam=0.0, stop=False, basis="f64"):
