@@ -493,6 +493,20 @@ def geometry_leg(name, s, check=True, R=20, reps=10):
            "us_per_pair": round(ms * 1e3, 3), "pairs_per_s": round(1e3 / ms, 1),
            "path_GBs": round(balg / (ms * 1e-3) / 1e9, 1), "path_frac": round(balg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     log(f"{name}: {ms * 1e3:.1f} us per pair")
+    # the same pair after the autotuner has picked the layer groups and row tile for it
+    from paper_2004_13904_amd.autotune import autotune
+    choice = autotune(A, x, d, cache=None, use_cache=False, reps=20)
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    tgraph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(tgraph):
+        for _ in range(R):
+            step()
+    ms_t = timed(tgraph.replay, reps) / R
+    out["autotuned"] = {"tuning": {k: choice[k] for k in ("lg_G", "lg_GT", "row_tile")},
+                        "us_per_pair": round(ms_t * 1e3, 3), "pairs_per_s": round(1e3 / ms_t, 1)}
+    log(f"{name}: autotuned {choice} {ms_t * 1e3:.1f} us per pair")
     if check:
         out["rel_err_vs_oracle"] = oracle_errors(s, x, d, gx, gtd)
     A.close()
