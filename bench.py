@@ -71,6 +71,9 @@ def main(argv=None):
                     help="IRLS steps of the opt-in n = 1e6 magnetic leg (each step ~10 s)")
     ap.add_argument("--irls-c2-basis", default="f64", choices=("f64", "f32"),
                     help="GKB basis storage of the opt-in n = 1e6 magnetic leg")
+    ap.add_argument("--irls-c2-lambda", type=float, default=0.0,
+                    help="stabilizer of the n = 1e6 leg: 0 = minimum support, 1 = the paper's L1 choice")
+    ap.add_argument("--irls-c2-stop", action="store_true", help="stop the n = 1e6 leg at the chi^2 test")
     ap.add_argument("--irls-steps", type=int, default=25)
     ap.add_argument("--study-ells", default="4", help="ladder sizes l of the study leg")
     ap.add_argument("--study-s", default="40,25,20,8,6,4,3", help="t = floor(m/s) of the study leg")
@@ -294,7 +297,7 @@ def main(argv=None):
         result["irls_l1"] = irls_leg(a.irls_steps, lam=1.0, stop=True)
         result["irls_l1_f32basis"] = irls_leg(a.irls_steps, lam=1.0, stop=True, basis="f32")
     if "irls_c2" in legs:
-        result["irls_magnetic_1m"] = irls_c2_leg(a.irls_c2_steps, a.irls_c2_basis)
+        result["irls_magnetic_1m"] = irls_c2_leg(a.irls_c2_steps, a.irls_c2_basis, a.irls_c2_lambda, a.irls_c2_stop)
     if "study" in legs:
         result["study"] = study_leg([int(v) for v in a.study_ells.split(",")],
                                     [int(v) for v in a.study_s.split(",")], a.study_kinds.split(","),
@@ -827,7 +830,7 @@ def irls_leg(steps, lam=0.0, stop=False, basis="f64"):
             "alpha_1": hist[0][1], "alpha_K": hist[-1][1], "RE": round(re, 4)}
 
 
-def irls_c2_leg(steps, basis="f64"):
+def irls_c2_leg(steps, basis="f64", lam=0.0, stop=False):
     """IRLS on the n = 1e6 magnetic survey (250 x 200 x 20, TFA with I = D = 45 deg): a 0.1 SI cube
     and a 45-degree dipping dike, 2 % noise (tau1 = 0.02, tau2 = 0.002), minimum support
     (lambda = 0, eps^2 = 1e-9), depth weighting beta = 1.4, bounds [0, 0.1], GKB with
@@ -846,7 +849,7 @@ def irls_c2_leg(steps, basis="f64"):
     eta, sd = W.noise(d_exact, 0.02, 0.002, 2)
     d_obs = torch.tensor(d_exact + eta, dtype=torch.float64, device="cuda")
     wd = torch.tensor(1.0 / sd, dtype=torch.float64, device="cuda")
-    p = SV.IrlsParams(solver="gkb", t=2500, tp=2625, lam=0.0, eps2=1e-9, beta_depth=1.4, m_min=0.0,
+    p = SV.IrlsParams(solver="gkb", t=2500, tp=2625, lam=lam, eps2=1e-9, beta_depth=1.4, m_min=0.0,
                       m_max=0.1, basis=basis)
     times = []
     t_last = [0.0]
@@ -860,16 +863,19 @@ def irls_c2_leg(steps, basis="f64"):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     t_last[0] = t0
-    m, hist = SV.irls(A, p, d_obs, wd, k_max=steps, callback=cb, stop_at_chi2=False)
+    m, hist = SV.irls(A, p, d_obs, wd, k_max=steps, callback=cb, stop_at_chi2=stop)
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     tp, n, mm = p.tp, A.n, A.m
     # one Gram-Schmidt pass (Q^T v, then v - Q c) over both bases per iteration; the second pass
     # runs only when the first cancels most of the vector
     reorth_bytes = 2 * (8 if basis == "f64" else 4) * (n + mm) * tp * (tp + 1) / 2
+    mt = m_true.double()
+    re = float(torch.linalg.norm(mt - m) / torch.linalg.norm(mt))
     return {"workload": "magnetic_1m: 250x200 stations, nz=20, cube + dipping dike, 2% noise, GKB t=2500 "
                         "t_p=2625, FP32 operator, FP64 solve",
-            "basis": basis, "steps": len(hist), "seconds_per_step": [round(x, 3) for x in times],
+            "lambda": lam, "basis": basis, "steps": len(hist), "converged": hist[-1][2] <= 1.0, "RE": round(re, 4),
+            "seconds_per_step": [round(x, 3) for x in times],
             "seconds_total": round(total, 3), "chi2_scaled": [round(h[2], 4) for h in hist],
             "reorth_bytes_per_step": reorth_bytes,
             "reorth_GBs_if_all_time": round(reorth_bytes / (total / len(hist)) / 1e9, 1)}
