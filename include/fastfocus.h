@@ -106,6 +106,15 @@ ff_status ff_spectra_info(ff_spectra h, int64_t *m, int64_t *n, int32_t *nfft_x,
    u0 = pad_xl - nx + 1, v0 = pad_yl - ny + 1.  For verification of the prism kernels. */
 ff_status ff_kernel_table(ff_spectra h, double *table, ff_stream stream);
 
+/* The device FFT of the operator's passes (App. A: the 2DFFT is applied as 1-D transforms along
+   rows and columns) applied stand-alone, for verification against a reference FFT: count
+   transforms of length n (a power of two in [8, 2048]), out[b] = sum_k in[b][k] exp(-+2 pi i j k / n)
+   (minus for inverse = 0, plus and unnormalized for inverse = 1).  in, out: count x n complex
+   values (interleaved re, im) of dtype FF_F32 or FF_F64; twiddles: device scratch of n complex
+   values of the same dtype (filled here).  Asynchronous on `stream`. */
+ff_status ff_fft_1d(int32_t n, int32_t dtype, int32_t inverse, int64_t count, const void *in, void *out,
+                    void *twiddles, ff_stream stream);
+
 /* Appendix A, eq. (costGx): d = w_post .* G (w_pre .* x).  x: n values, d: m values, both of
    the handle's dtype (float or double).  w_pre (n) and w_post (m) are optional diagonal
    weights of the same dtype (NULL = identity); with w_pre = W^{-1} and w_post = W_d this is

@@ -23,7 +23,8 @@ EXPORTS = ["build_spectra", "ff_free_spectra", "ff_spectra_info", "ff_kernel_tab
            "apply_GT", "apply_G_block", "ff_workspace_size", "gkb_project", "rsvd_project",
            "irls_step", "ff_get_tuning", "ff_set_tuning", "ff_profile_begin", "ff_profile_end", "ff_time_pass",
            "ff_multi_create", "ff_multi_apply", "ff_multi_free", "ff_spectra_save", "ff_spectra_load",
-           "ff_spectra_geometry", "ff_solver_stats", "ff_focusing_loss", "ff_focusing_grad", "ff_last_error"]
+           "ff_spectra_geometry", "ff_solver_stats", "ff_focusing_loss", "ff_focusing_grad", "ff_fft_1d",
+           "ff_last_error"]
 
 
 class FFGeometry(C.Structure):
@@ -95,6 +96,7 @@ def load(path=None):
         "ff_solver_stats": [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)],
         "ff_focusing_loss": [vp, i64, vp, vp, vp, C.c_double, C.c_double, vp, vp, vp],
         "ff_focusing_grad": [vp, i64, vp, vp, C.c_double, C.c_double, vp, vp, vp],
+        "ff_fft_1d": [i32, i32, i32, i64, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

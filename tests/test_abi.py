@@ -93,3 +93,19 @@ def test_spectra_load_rejects_foreign_and_missing_files(tmp_path):
     assert lib.ff_spectra_load(str(junk).encode(), None, C.byref(h)) == L.FF_EINVAL
     assert b"not a spectra file" in lib.ff_last_error()
     assert lib.ff_spectra_save(None, b"x") == L.FF_EINVAL
+
+
+@pytest.mark.parametrize("n,dtype,inverse,count,code", [
+    (12, 0, 0, 1, -2),        # not a power of two
+    (4, 0, 0, 1, -2),         # below the smallest transform
+    (4096, 1, 0, 1, -2),      # above the largest
+    (64, 2, 0, 1, -3),        # unknown dtype
+    (64, 0, 2, 1, -1),        # inverse must be 0 or 1
+    (64, 0, 0, -1, -2),       # negative count
+    (64, 0, 0, 0, 0),         # nothing to do
+])
+def test_fft_1d_rejects_bad_arguments_before_launching(n, dtype, inverse, count, code):
+    L, lib = _lib()
+    p = C.c_void_p(16)        # never dereferenced: validation precedes any device work
+    assert lib.ff_fft_1d(n, dtype, inverse, count, p, p, p, None) == code
+    assert lib.ff_fft_1d(64, 0, 0, 1, None, p, p, None) == -1
