@@ -109,3 +109,16 @@ def test_fft_1d_rejects_bad_arguments_before_launching(n, dtype, inverse, count,
     p = C.c_void_p(16)        # never dereferenced: validation precedes any device work
     assert lib.ff_fft_1d(n, dtype, inverse, count, p, p, p, None) == code
     assert lib.ff_fft_1d(64, 0, 0, 1, None, p, p, None) == -1
+
+
+@pytest.mark.parametrize("compiler,lang", [("gcc", "c"), ("g++", "c++")])
+def test_header_compiles_as_plain_c_and_cpp(compiler, lang, tmp_path):
+    """The boundary header is self-contained C (plain pointers, fixed-width integers, no torch or
+    HIP types) and also valid C++."""
+    import shutil
+    import subprocess
+    if shutil.which(compiler) is None:
+        pytest.skip(f"{compiler} not available")
+    r = subprocess.run([compiler, "-fsyntax-only", "-x", lang, "-Wall", "-Wextra", "-Werror", HEADER],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
