@@ -224,7 +224,9 @@ typedef struct {
    `omega` tp x m, or omega = NULL for the generator of rsvd_project with the third counter
    word set to k), m_new = clip(m_prev + W^{-1} y, m_min, m_max) and the
    scaled chi^2 of eq. (scaledchi2).  d_obs, wd: m; m_prev, m_prev2, m_new: n (FP64 device).
-   *alpha and *chi2_scaled are host outputs; the call synchronizes `stream` once at the end. */
+   *alpha and *chi2_scaled are host outputs.  A non-finite residual r~ (NaN or Inf in d_obs, wd
+   or m_prev) returns FF_EINVAL before the solve, as does a step that produces non-finite values.
+   The call synchronizes `stream` (after r~ and at the end). */
 ff_status irls_step(ff_spectra h, const ff_irls_params *p, const double *d_obs, const double *wd,
                     const double *m_prev, const double *m_prev2, const double *omega,
                     double *m_new, double *alpha, double *chi2_scaled, void *workspace,

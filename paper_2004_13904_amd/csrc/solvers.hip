@@ -1264,6 +1264,14 @@ ff_status irls_step(ff_spectra h, const ff_irls_params *p, const double *d_obs, 
   if ((st = op_apply(h, 0, 1, m_prev, n, I.gm, m, nullptr, nullptr, FF_F64, s))) return st;
   k_residual<<<grid_for(m), kThreads, 0, s>>>(wd, d_obs, I.gm, m, I.r);
   FF_LAUNCH_CHECK("irls_step setup");
+  {
+    // a non-finite r~ (NaN or Inf in d_obs, wd or m_prev) is rejected before the solve
+    if ((st = norm2(I.r, m, I.nrm, nullptr, I.part, s))) return st;
+    double r0 = 0.0;
+    FF_HIP(hipMemcpyAsync(&r0, I.nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+    FF_HIP(hipStreamSynchronize(s));
+    if (!std::isfinite(r0)) return fail(FF_EINVAL, "irls_step: non-finite residual (NaN or Inf in d_obs, wd or m_prev)");
+  }
   const int mode = p->alpha_fixed > 0 ? ALPHA_FIXED : (p->k == 1 ? ALPHA_ONE : ALPHA_UPRE);
   double a = p->alpha_fixed;
   // the solvers synchronize the stream before returning, so zw (host) has been consumed
@@ -1284,6 +1292,8 @@ ff_status irls_step(ff_spectra h, const ff_irls_params *p, const double *d_obs, 
   FF_HIP(hipStreamSynchronize(s));
   *alpha = a;
   *chi2_scaled = nrm * nrm / ((double)m + std::sqrt(2.0 * (double)m));
+  if (!std::isfinite(*chi2_scaled) || !std::isfinite(a))
+    return fail(FF_EINVAL, "irls_step: the step produced non-finite values");
   return FF_OK;
 }
 

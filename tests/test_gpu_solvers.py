@@ -266,3 +266,22 @@ def test_workspace_errors():
     rc = lib.gkb_project(A.h, _ptr(r), _ptr(r), _ptr(torch.ones(A.n, dtype=F64, device="cuda")), 2, 4, 2, 1,
                          _ptr(y), __import__("ctypes").byref(a), _ptr(sig), _ptr(small), 16, _stream())
     assert rc == -4
+
+
+@pytest.mark.parametrize("where", ["d_obs", "wd", "m_prev"])
+def test_irls_step_rejects_non_finite_inputs(where):
+    # a NaN in the data, the weights or the previous iterate is reported before the solve
+    s = W.survey(8, 8, 2, 25, 25, 25)
+    A = Operator(s, F64)
+    d = torch.randn(A.m, dtype=F64, device="cuda")
+    wd = torch.ones(A.m, dtype=F64, device="cuda")
+    m0 = torch.zeros(A.n, dtype=F64, device="cuda")
+    {"d_obs": d, "wd": wd, "m_prev": m0}[where][3] = float("nan")
+    p = S.IrlsParams(solver="gkb", t=8, tp=9, lam=1.0)
+    with pytest.raises(L.FastFocusError) as e:
+        S.irls_step(A, p, 1, d, wd, m0)
+    assert e.value.code == L.FF_EINVAL and "non-finite" in str(e.value)
+    d[3] = 0.0 if where == "d_obs" else d[3]
+    wd[3] = 1.0
+    m0[3] = 0.0
+    S.irls_step(A, p, 1, d, wd, m0)      # the same call with finite inputs succeeds
