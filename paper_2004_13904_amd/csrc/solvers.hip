@@ -132,6 +132,41 @@ __global__ void k_scale_store(double *__restrict__ b, const double *__restrict__
   }
 }
 
+// k_norm_cond fused into k_scale_store: when the second Gram-Schmidt pass ran (*flag), every
+// block forms the norm from the pass's P partial sums (the same order as k_norm_cond) and block 0
+// writes *nrm and *inv; otherwise the blocks take *inv as k_norm_flag left it.  Then as
+// k_scale_store with that inverse norm.
+template <typename TB>
+__global__ void __launch_bounds__(kThreads)
+k_scale_store_cond(double *__restrict__ b, TB *__restrict__ col, int64_t n, const double *__restrict__ part, int P,
+                   const int *__restrict__ flag, double *__restrict__ nrm, double *__restrict__ inv) {
+  __shared__ double red[16];
+  __shared__ double a_sh;
+  if (*flag) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < P; i += blockDim.x) s += part[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) {
+      const double v = sqrt(s);
+      const double a = v > 0.0 ? 1.0 / v : 0.0;
+      a_sh = a;
+      if (blockIdx.x == 0) {
+        *nrm = v;
+        *inv = a;
+      }
+    }
+  } else if (threadIdx.x == 0) {
+    a_sh = *inv;
+  }
+  __syncthreads();
+  const double a = a_sh;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const TB t = (TB)(a * b[i]);
+    col[i] = t;
+    b[i] = (double)t;
+  }
+}
+
 // out = (*sc) * x with x given in double, stored as TB and (rounded) as double
 template <typename TB>
 __global__ void k_scale_from(const double *__restrict__ x, const double *__restrict__ sc, TB *__restrict__ col,
@@ -737,9 +772,14 @@ int launch_gemv_n(const TB *Q, int64_t ld, int64_t nrows, int ncols, const doubl
 // have_sq, the kNormBlocks partial sums of v^2 (else they are formed here); sq1 receives the
 // block sums of the updated v^2 (one per A c block); part is the scratch of the products.
 // flag: 1 int of scratch.
+// When deferred is non-NULL and the second pass has at most kDeferMax partial sums, its final
+// norm is left to k_scale_store_cond: *deferred receives that count (0 when the norm is final).
+constexpr int kDeferMax = 2048;
 template <typename TB>
 ff_status reorth_norm(const TB *Q, int64_t ld, int64_t nrows, int ncols, double *v, double *coef, double *part,
-                      double *sq0, bool have_sq, double *sq1, int *flag, double *nrm, double *inv, hipStream_t s) {
+                      double *sq0, bool have_sq, double *sq1, int *flag, double *nrm, double *inv, hipStream_t s,
+                      int *deferred = nullptr) {
+  if (deferred) *deferred = 0;
   if (!have_sq) k_sumsq_partial<<<kNormBlocks, kThreads, 0, s>>>(v, nrows, sq0);
   if (ncols <= 0) {
     k_norm_finalize<<<1, kThreads, 0, s>>>(sq0, kNormBlocks, nrm, inv);
@@ -751,7 +791,10 @@ ff_status reorth_norm(const TB *Q, int64_t ld, int64_t nrows, int ncols, double 
   k_norm_flag<<<1, kThreads, 0, s>>>(sq0, kNormBlocks, sq1, nb1, flag, nrm, inv);
   launch_gemv_t(Q, ld, nrows, ncols, v, coef, part, s, flag);
   const int nb2 = launch_gemv_n(Q, ld, nrows, ncols, coef, v, -1.0, 1.0, s, flag, sq1);
-  k_norm_cond<<<1, kThreads, 0, s>>>(sq1, nb2, flag, nrm, inv);
+  if (deferred && nb2 <= kDeferMax)
+    *deferred = nb2;
+  else
+    k_norm_cond<<<1, kThreads, 0, s>>>(sq1, nb2, flag, nrm, inv);
   FF_LAUNCH_CHECK("reorthogonalization");
   return FF_OK;
 }
@@ -938,17 +981,26 @@ ff_status gkb_run(ff_spectra h, const double *rt, const double *wd, const double
     if (i > 0)
       k_axpy_sumsq<TB><<<kNormBlocks, kThreads, 0, s>>>(W.b, W.A + (int64_t)(i - 1) * W.ldA, W.beta + i, -1.0, n,
                                                         W.sq0);
+    int dn = 0;
     if ((st = reorth_norm<TB>(W.A, W.ldA, n, i, W.b, W.coef, W.part, W.sq0, i > 0, W.sq1, W.flag, W.gamma + i,
-                              W.ginv + i, s)))
+                              W.ginv + i, s, &dn)))
       return st;
-    k_scale_store<TB><<<grid_for(n), kThreads, 0, s>>>(W.b, W.ginv + i, ai, n);     // b = a_i as stored
+    if (dn > 0)     // b = a_i as stored
+      k_scale_store_cond<TB><<<grid_for(n), kThreads, 0, s>>>(W.b, ai, n, W.sq1, dn, W.flag, W.gamma + i, W.ginv + i);
+    else
+      k_scale_store<TB><<<grid_for(n), kThreads, 0, s>>>(W.b, W.ginv + i, ai, n);
     // c = G~ a_i - gamma_i h_i, reorthogonalized; beta_{i+1} = ||c||
     if ((st = op_apply(h, 0, 1, W.b, n, W.c, m, winv, wd, FF_F64, s))) return st;
     k_axpy_sumsq<TB><<<kNormBlocks, kThreads, 0, s>>>(W.c, hi, W.gamma + i, -1.0, m, W.sq0);
     if ((st = reorth_norm<TB>(W.H, W.ldH, m, i + 1, W.c, W.coef, W.part, W.sq0, true, W.sq1, W.flag,
-                              W.beta + i + 1, W.binv + i + 1, s)))
+                              W.beta + i + 1, W.binv + i + 1, s, &dn)))
       return st;
-    k_scale_store<TB><<<grid_for(m), kThreads, 0, s>>>(W.c, W.binv + i + 1, W.H + (int64_t)(i + 1) * W.ldH, m);
+    TB *hn = W.H + (int64_t)(i + 1) * W.ldH;
+    if (dn > 0)
+      k_scale_store_cond<TB><<<grid_for(m), kThreads, 0, s>>>(W.c, hn, m, W.sq1, dn, W.flag, W.beta + i + 1,
+                                                              W.binv + i + 1);
+    else
+      k_scale_store<TB><<<grid_for(m), kThreads, 0, s>>>(W.c, W.binv + i + 1, hn, m);
   }
   FF_LAUNCH_CHECK("gkb iteration");
   // SVD of the (tp+1) x tp bidiagonal through its Golub-Kahan tridiagonal
