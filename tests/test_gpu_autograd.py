@@ -60,7 +60,7 @@ def test_loss_gradient_matches_dense_reference(dtype):
     ref = 2.0 * (wd * r) @ G + alpha * 2.0 * m0 * EPS2 / (m0 * m0 + EPS2) ** 2
     assert rel(to_host(m.grad), ref) <= (1e-10 if dtype == F64 else 1e-5)
     ref_L = float((r * r).sum() + alpha * (m0 * m0 / (m0 * m0 + EPS2)).sum())
-    assert abs(float(L) - ref_L) <= (1e-10 if dtype == F64 else 1e-5) * abs(ref_L)
+    assert abs(float(L.detach()) - ref_L) <= (1e-10 if dtype == F64 else 1e-5) * abs(ref_L)
 
 
 def test_loss_gradient_finite_differences_full_size():
