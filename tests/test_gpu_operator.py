@@ -90,6 +90,32 @@ def test_embedding_size_invariance(nfft):
     assert rel(a, b) <= 1e-13
 
 
+@pytest.mark.parametrize("nfft", [(1024, 32), (32, 1024), (2048, 32), (32, 2048)])
+@pytest.mark.parametrize("name", ["tiny", "mag_padded"])
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_large_embeddings_against_dense_G(nfft, name, dtype):
+    # rows and columns of 1024 and 2048 points: transforms that span several wavefronts, one row
+    # or column per block; one vector and a block of three (the per-vector column kernels over
+    # the batch) against the dense definition
+    s = SMALL[name]
+    announce("embedding", name, nfft, dtype)
+    g = ogeom(s)
+    G = op.dense_G(g)
+    rng = np.random.default_rng(7)
+    X = rng.random((3, g.n))
+    D = rng.standard_normal((3, g.m))
+    A = Operator(s, dtype, nfft=nfft)
+    assert A.nfft == nfft
+    assert rel(to_host(A.G(to_dev(X[0], dtype))), G @ X[0]) <= TOL[dtype]
+    assert rel(to_host(A.GT(to_dev(D[0], dtype))), G.T @ D[0]) <= TOL[dtype]
+    Y = to_host(A.G_block(to_dev(X, dtype)))
+    Z = to_host(A.G_block(to_dev(D, dtype), transpose=True))
+    for i in range(3):
+        assert rel(Y[i], G @ X[i]) <= TOL[dtype]
+        assert rel(Z[i], G.T @ D[i]) <= TOL[dtype]
+    A.close()
+
+
 def test_too_small_embedding_is_rejected():
     with pytest.raises(L.FastFocusError) as e:
         Operator(W.SURVEYS["tiny"], F64, nfft=(16, 32))
@@ -254,3 +280,12 @@ def test_padded_size_ladder(ell, kernel):
     # the padded ladder of Sec. 3.2 / Table 2 (pad = round(0.05 s) cells per side)
     announce("ladder", ell, kernel)
     _full_size_check(W.ladder_survey(ell, kernel), ell)
+
+
+@pytest.mark.parametrize("ell,kernel", [(11, "magnetic"), (12, "gravity")])
+def test_high_resolution_ladder(ell, kernel):
+    # the high-resolution sizes of Sec. 3.3.4 (n = 998250 and 1296000, unpadded): 1024-point rows
+    announce("ladder", ell, kernel)
+    s = W.ladder_survey(ell, kernel, pad_fraction=0.0)
+    assert W.sizes(s)[4] == {11: 998250, 12: 1296000}[ell]
+    _full_size_check(s, ell)
