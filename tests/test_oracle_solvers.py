@@ -135,3 +135,42 @@ def test_irls_step_matches_dense_closed_form():
     assert np.linalg.norm(m_new - ref) <= 1e-7 * np.linalg.norm(ref)
     res = wd * (G @ m_new - d_obs)
     assert abs(chi2 - res @ res / (g.m + math.sqrt(2 * g.m))) <= 1e-12 * chi2
+
+
+def test_depth_weights_values_and_layout():
+    # Sec. 2.2: one weight per layer, (mean depth of the layer)^(-beta), repeated over the layer's
+    # cells in the model's (layer, row, column) order.  Uneven layers 0-10-40-100 m have mean
+    # depths 5, 25 and 70 m; with beta = 1 the weights are 0.2, 0.04 and 1/70, with beta = 2
+    # 0.04, 0.0016 and 1/4900.
+    g = geometry.Geometry(sx=3, sy=2, nz=3, dx=10.0, dy=10.0, z_edges=(0.0, 10.0, 40.0, 100.0))
+    for beta, want in ((1.0, (0.2, 0.04, 1.0 / 70.0)), (2.0, (0.04, 0.0016, 1.0 / 4900.0))):
+        w = irls.depth_weights(g, beta).reshape(3, 2 * 3)
+        for r in range(3):
+            assert np.allclose(w[r], want[r], rtol=1e-15, atol=0.0)
+    assert np.array_equal(irls.depth_weights(g, 0.0), np.ones(g.n))
+    # deeper layers get smaller weights for beta > 0, so W^{-1} lets deep cells take larger values
+    w = irls.depth_weights(g, 0.8).reshape(3, -1)[:, 0]
+    assert w[0] > w[1] > w[2]
+
+
+def test_focusing_weights_reproduce_the_stabilizers():
+    # eq. (WLdefn) is chosen so that sum_i (W_L)_ii^2 x_i^2 equals the stabilizer at x: the
+    # minimum-support sum x^2 / (x^2 + eps^2) for lambda = 0, the smoothed l1 norm
+    # x^2 / sqrt(x^2 + eps^2) for lambda = 1 (|x| as eps -> 0), and ||x||^2 (W_L = I) for lambda = 2.
+    rng = np.random.default_rng(3)
+    m1 = rng.standard_normal(200)
+    m0 = rng.standard_normal(200)
+    x = m1 - m0
+    eps2 = 1e-3
+    w0 = irls.focusing_weights(m1, m0, 0.0, eps2, 2)
+    assert np.allclose(w0 * w0 * x * x, x * x / (x * x + eps2), rtol=1e-14, atol=0.0)
+    w1 = irls.focusing_weights(m1, m0, 1.0, eps2, 2)
+    assert np.allclose(w1 * w1 * x * x, x * x / np.sqrt(x * x + eps2), rtol=1e-14, atol=0.0)
+    w1s = irls.focusing_weights(m1, m0, 1.0, 1e-14, 5)
+    assert abs(np.sum(w1s * w1s * x * x) - np.sum(np.abs(x))) <= 1e-6 * np.sum(np.abs(x))
+    assert np.allclose(irls.focusing_weights(m1, m0, 2.0, eps2, 3), 1.0, rtol=1e-15, atol=0.0)
+    # the first step has no previous increment: W_L^(1) = I for any lambda
+    assert np.array_equal(irls.focusing_weights(m1, m0, 0.0, eps2, 1), np.ones(200))
+    # the weight depends on the increment only: no change at a cell gives eps^((lambda - 2) / 2)
+    w = irls.focusing_weights(np.ones(3), np.ones(3), 0.0, 1e-4, 4)
+    assert np.allclose(w, 1e-4 ** -0.5, rtol=1e-15)
