@@ -1,0 +1,26 @@
+"""Galerkin conditions of a projected Tikhonov solution (test helper, numpy only).
+
+Algorithm 1's solution y = A_tp w minimizes ||G~ y - r~||^2 + alpha^2 ||y||^2 over the span of
+the basis A_tp, the Krylov space of G~^T G~ started at G~^T r~.  So the normal-equation residual
+g = G~^T (G~ y - r~) + alpha^2 y is orthogonal to every vector of that space: to y itself and to
+(G~^T G~)^j G~^T r~ for j < t_p.  These conditions hold at any size and need only products with
+G~ and G~^T, which the oracle's direct sums supply where its own Algorithm 1 would take minutes.
+"""
+import numpy as np
+
+
+def galerkin_defects(apply_Gt, apply_GtT, r_tilde, y, alpha, powers=3):
+    """|v^T g| / (||v|| * scale) for v = y and v = (G~^T G~)^j G~^T r~, j < powers, where scale
+    sums the norms of the three terms of g (so that rounding in them gives small values)."""
+    y = np.asarray(y, dtype=np.float64)
+    gy = apply_Gt(y)
+    gtgy = apply_GtT(gy)
+    gtr = apply_GtT(r_tilde)
+    g = gtgy - gtr + alpha * alpha * y
+    scale = np.linalg.norm(gtgy) + np.linalg.norm(gtr) + alpha * alpha * np.linalg.norm(y)
+    out = [abs(y @ g) / (np.linalg.norm(y) * scale)]
+    v = gtr
+    for _ in range(powers):
+        out.append(abs(v @ g) / (np.linalg.norm(v) * scale))
+        v = apply_GtT(apply_Gt(v))
+    return np.array(out)

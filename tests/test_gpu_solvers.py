@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 import torch
 
+from galerkin import galerkin_defects
 from gpu_common import announce, ogeom, rel, to_dev, to_host
 from oracle import irls as oirls, operator as op, philox, solvers as osol
 from paper_2004_13904_amd import _lib as L
@@ -249,6 +250,47 @@ def test_irls_step_matches_oracle(solver):
     assert abs(a2 - a2o) <= 1e-5 * a2o
     assert rel(to_host(m2), m2o) <= 1e-6 + 2 * abs(a2 - a2o) / a2o
     assert abs(c2 - c2o) <= (1e-6 + 4 * abs(a2 - a2o) / a2o) * c2o
+
+
+def test_gkb_full_size_properties():
+    # The timed IRLS configuration: gravity 100 x 60 stations, 10 layers (n = 60000), FP32
+    # operator, FP64 solve, t = 750, t_p = 787, on the first step's weighted problem (W = W_z
+    # with beta = 0.8, 1 % noise).  The oracle's Algorithm 1 takes minutes at this size, so the
+    # result is checked by what holds at any size, with the oracle's direct sums:
+    # eq. (eq:alpha1) on the returned spectrum, sigma_1 by power iteration on G~^T G~, and the
+    # Galerkin conditions of the projected Tikhonov solution at a fixed alpha.
+    s = W.SURVEYS["gravity_l4"]
+    announce("gkb full size", "gravity_l4", 750, 787)
+    g = ogeom(s)
+    T = op.kernel_table(g)
+    d_exact = op.apply_G(g, W.block_model(s, W.GRAVITY_L4_BLOCKS), T)
+    eta, sd = W.noise(d_exact, 0.01, 0.001, 2)
+    wd = 1.0 / sd
+    winv = 1.0 / oirls.depth_weights(g, 0.8)
+    r = wd * (d_exact + eta)
+    Gt = lambda v: wd * op.apply_G(g, winv * v, T)
+    GtT = lambda y: winv * op.apply_GT(g, wd * y, T)
+    A = Operator(s, F32)
+    t, tp = 750, 787
+    args = (to_dev(r, F64), to_dev(wd, F64), to_dev(winv, F64), t, tp)
+    _, a1, sig = S.gkb_project(A, *args, alpha_mode="alpha1")
+    sig = to_host(sig)
+    assert np.all(np.diff(sig) <= 0) and sig[-1] > 0
+    assert abs(a1 - osol.alpha_one(g.n, g.m, sig)) <= 1e-12 * a1
+    v = GtT(r)
+    v /= np.linalg.norm(v)
+    for _ in range(40):        # the Rayleigh quotient settles to ~1e-13 here
+        v = GtT(Gt(v))
+        v /= np.linalg.norm(v)
+    s1 = float(np.linalg.norm(Gt(v)))
+    assert abs(sig[0] - s1) <= 1e-5 * s1
+    alpha = float(sig[t // 2])
+    y, a, _ = S.gkb_project(A, *args, alpha_mode="fixed", alpha=alpha)
+    assert a == alpha
+    # exact GKB gives ~1e-16, FP32-sized errors in every product ~1e-8; a solution for alpha
+    # 1 % off gives ~1e-2
+    assert galerkin_defects(Gt, GtT, r, to_host(y), alpha).max() <= 2e-5
+    A.close()
 
 
 def test_workspace_errors():

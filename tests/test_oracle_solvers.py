@@ -4,6 +4,7 @@ import math
 import numpy as np
 import pytest
 
+from galerkin import galerkin_defects
 from oracle import geometry, irls, operator as op, solvers
 
 
@@ -174,3 +175,28 @@ def test_focusing_weights_reproduce_the_stabilizers():
     # the weight depends on the increment only: no change at a cell gives eps^((lambda - 2) / 2)
     w = irls.focusing_weights(np.ones(3), np.ones(3), 0.0, 1e-4, 4)
     assert np.allclose(w, 1e-4 ** -0.5, rtol=1e-15)
+
+
+@pytest.mark.parametrize("kernel", ["gravity", "magnetic"])
+def test_gkb_solution_satisfies_galerkin_conditions(kernel):
+    # Algorithm 1's y is the Tikhonov solution over its Krylov space (t_p well below m): the
+    # normal-equation residual is orthogonal to y and to (G~^T G~)^j G~^T r~.  A solution for
+    # alpha 1 % off, or y scaled by 1.001, breaks the conditions by orders of magnitude.
+    g = geometry.uniform_geometry(20, 16, 4, 25.0, 25.0, 25.0, kernel=kernel, incl_deg=45.0,
+                                  decl_deg=45.0)
+    G = op.dense_G(g)
+    rng = np.random.default_rng(8)
+    wd = 1.0 / (0.05 + rng.random(g.m))
+    winv = 0.5 + rng.random(g.n)
+    Gt = wd[:, None] * G * winv[None, :]
+    r = rng.standard_normal(g.m)
+    f, fT = ops(Gt)
+    t, tp = 60, 63
+    _, _, S = solvers.gkb(f, fT, r, g.n, t, tp, "alpha1")
+    alpha = float(S[t // 2])
+    y, a, _ = solvers.gkb(f, fT, r, g.n, t, tp, "fixed", alpha)
+    assert a == alpha
+    assert galerkin_defects(f, fT, r, y, alpha).max() <= 1e-12
+    y_off, _, _ = solvers.gkb(f, fT, r, g.n, t, tp, "fixed", 1.01 * alpha)
+    assert galerkin_defects(f, fT, r, y_off, alpha).max() >= 1e-4
+    assert galerkin_defects(f, fT, r, 1.001 * y, alpha).max() >= 1e-4
