@@ -24,3 +24,22 @@ def galerkin_defects(apply_Gt, apply_GtT, r_tilde, y, alpha, powers=3):
         out.append(abs(v @ g) / (np.linalg.norm(v) * scale))
         v = apply_GtT(apply_Gt(v))
     return np.array(out)
+
+
+def rsvd_galerkin_defects(apply_Gt, apply_GtT, r_tilde, y, alpha, omega, power_iters=1, combos=2, seed=0):
+    """Algorithm 2 with t = t_p: y is the Tikhonov solution over range(Q), the span of
+    (G~^T G~)^q G~^T Omega^T.  Defects as in galerkin_defects for v = y and for v =
+    (G~^T G~)^q G~^T Omega^T c with `combos` standard normal c (omega: t_p x m)."""
+    y = np.asarray(y, dtype=np.float64)
+    gtgy = apply_GtT(apply_Gt(y))
+    gtr = apply_GtT(r_tilde)
+    g = gtgy - gtr + alpha * alpha * y
+    scale = np.linalg.norm(gtgy) + np.linalg.norm(gtr) + alpha * alpha * np.linalg.norm(y)
+    out = [abs(y @ g) / (np.linalg.norm(y) * scale)]
+    rng = np.random.default_rng(seed)
+    for _ in range(combos):
+        v = apply_GtT(omega.T @ rng.standard_normal(omega.shape[0]))
+        for _ in range(power_iters):
+            v = apply_GtT(apply_Gt(v))
+        out.append(abs(v @ g) / (np.linalg.norm(v) * scale))
+    return np.array(out)

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 import torch
 
-from galerkin import galerkin_defects
+from galerkin import galerkin_defects, rsvd_galerkin_defects
 from gpu_common import announce, ogeom, rel, to_dev, to_host
 from oracle import irls as oirls, operator as op, philox, solvers as osol
 from paper_2004_13904_amd import _lib as L
@@ -252,15 +252,11 @@ def test_irls_step_matches_oracle(solver):
     assert abs(c2 - c2o) <= (1e-6 + 4 * abs(a2 - a2o) / a2o) * c2o
 
 
-def test_gkb_full_size_properties():
-    # The timed IRLS configuration: gravity 100 x 60 stations, 10 layers (n = 60000), FP32
-    # operator, FP64 solve, t = 750, t_p = 787, on the first step's weighted problem (W = W_z
-    # with beta = 0.8, 1 % noise).  The oracle's Algorithm 1 takes minutes at this size, so the
-    # result is checked by what holds at any size, with the oracle's direct sums:
-    # eq. (eq:alpha1) on the returned spectrum, sigma_1 by power iteration on G~^T G~, and the
-    # Galerkin conditions of the projected Tikhonov solution at a fixed alpha.
+def c1_weighted_problem():
+    """The timed IRLS configuration's first weighted problem, from the oracle: gravity 100 x 60
+    stations, 10 layers (n = 60000), two 1 g/cc blocks, 1 % noise, W = W_z with beta = 0.8,
+    r~ = W_d d_obs; products with G~ by the oracle's direct sums."""
     s = W.SURVEYS["gravity_l4"]
-    announce("gkb full size", "gravity_l4", 750, 787)
     g = ogeom(s)
     T = op.kernel_table(g)
     d_exact = op.apply_G(g, W.block_model(s, W.GRAVITY_L4_BLOCKS), T)
@@ -270,6 +266,28 @@ def test_gkb_full_size_properties():
     r = wd * (d_exact + eta)
     Gt = lambda v: wd * op.apply_G(g, winv * v, T)
     GtT = lambda y: winv * op.apply_GT(g, wd * y, T)
+    return s, g, wd, winv, r, Gt, GtT
+
+
+def oracle_sigma1(Gt, GtT, r, iters=40):
+    """Largest singular value of G~ by power iteration on G~^T G~ (the Rayleigh quotient settles
+    to ~1e-13 within 40 steps on the problem above)."""
+    v = GtT(r)
+    v /= np.linalg.norm(v)
+    for _ in range(iters):
+        v = GtT(Gt(v))
+        v /= np.linalg.norm(v)
+    return float(np.linalg.norm(Gt(v)))
+
+
+def test_gkb_full_size_properties():
+    # GKB in the timed configuration (FP32 operator, FP64 solve, t = 750, t_p = 787).  The
+    # oracle's Algorithm 1 takes minutes at this size, so the result is checked by what holds at
+    # any size, with the oracle's direct sums: eq. (eq:alpha1) on the returned spectrum, sigma_1
+    # by power iteration, and the Galerkin conditions of the projected Tikhonov solution at a
+    # fixed alpha.
+    announce("gkb full size", "gravity_l4", 750, 787)
+    s, g, wd, winv, r, Gt, GtT = c1_weighted_problem()
     A = Operator(s, F32)
     t, tp = 750, 787
     args = (to_dev(r, F64), to_dev(wd, F64), to_dev(winv, F64), t, tp)
@@ -277,12 +295,7 @@ def test_gkb_full_size_properties():
     sig = to_host(sig)
     assert np.all(np.diff(sig) <= 0) and sig[-1] > 0
     assert abs(a1 - osol.alpha_one(g.n, g.m, sig)) <= 1e-12 * a1
-    v = GtT(r)
-    v /= np.linalg.norm(v)
-    for _ in range(40):        # the Rayleigh quotient settles to ~1e-13 here
-        v = GtT(Gt(v))
-        v /= np.linalg.norm(v)
-    s1 = float(np.linalg.norm(Gt(v)))
+    s1 = oracle_sigma1(Gt, GtT, r)
     assert abs(sig[0] - s1) <= 1e-5 * s1
     alpha = float(sig[t // 2])
     y, a, _ = S.gkb_project(A, *args, alpha_mode="fixed", alpha=alpha)
@@ -290,6 +303,31 @@ def test_gkb_full_size_properties():
     # exact GKB gives ~1e-16, FP32-sized errors in every product ~1e-8; a solution for alpha
     # 1 % off gives ~1e-2
     assert galerkin_defects(Gt, GtT, r, to_host(y), alpha).max() <= 2e-5
+    A.close()
+
+
+def test_rsvd_full_size_properties():
+    # RSVD on the same problem (FP32 operator, FP64 solve, one power iteration, t = t_p = 787,
+    # Omega passed in): eq. (eq:alpha1) on the returned spectrum, sigma_1 by power iteration,
+    # and the Galerkin conditions over range(Q), which holds G~^T G~ G~^T Omega^T c for any c.
+    announce("rsvd full size", "gravity_l4", 787, 787)
+    s, g, wd, winv, r, Gt, GtT = c1_weighted_problem()
+    A = Operator(s, F32)
+    tp = 787
+    omega = W.gaussian_matrix(tp, g.m, 11)
+    args = (to_dev(r, F64), to_dev(wd, F64), to_dev(winv, F64), tp, tp, to_dev(omega, F64))
+    _, a1, sig = S.rsvd_project(A, *args, alpha_mode="alpha1")
+    sig = to_host(sig)
+    assert np.all(np.diff(sig) <= 0) and sig[-1] > 0
+    assert abs(a1 - osol.alpha_one(g.n, g.m, sig)) <= 1e-12 * a1
+    s1 = oracle_sigma1(Gt, GtT, r)
+    assert abs(sig[0] - s1) <= 1e-5 * s1
+    alpha = float(sig[tp // 2])
+    y, a, _ = S.rsvd_project(A, *args, alpha_mode="fixed", alpha=alpha)
+    assert a == alpha
+    # exact Algorithm 2 gives ~1e-16, FP32-sized errors in every product ~1e-8; alpha 1 % off
+    # gives >= 3e-3
+    assert rsvd_galerkin_defects(Gt, GtT, r, to_host(y), alpha, omega).max() <= 2e-5
     A.close()
 
 

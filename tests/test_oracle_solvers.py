@@ -4,7 +4,7 @@ import math
 import numpy as np
 import pytest
 
-from galerkin import galerkin_defects
+from galerkin import galerkin_defects, rsvd_galerkin_defects
 from oracle import geometry, irls, operator as op, solvers
 
 
@@ -200,3 +200,32 @@ def test_gkb_solution_satisfies_galerkin_conditions(kernel):
     y_off, _, _ = solvers.gkb(f, fT, r, g.n, t, tp, "fixed", 1.01 * alpha)
     assert galerkin_defects(f, fT, r, y_off, alpha).max() >= 1e-4
     assert galerkin_defects(f, fT, r, 1.001 * y, alpha).max() >= 1e-4
+
+
+@pytest.mark.parametrize("kernel", ["gravity", "magnetic"])
+def test_rsvd_solution_satisfies_galerkin_conditions(kernel):
+    # Algorithm 2 with t = t_p: y is the Tikhonov solution over range(Q), which holds
+    # G~^T G~ G~^T Omega^T c for every c (one power iteration).  alpha 1 % off, or truncation to
+    # t < t_p, breaks the conditions by orders of magnitude.
+    g = geometry.uniform_geometry(20, 16, 4, 25.0, 25.0, 25.0, kernel=kernel, incl_deg=45.0,
+                                  decl_deg=45.0)
+    G = op.dense_G(g)
+    rng = np.random.default_rng(8)
+    wd = 1.0 / (0.05 + rng.random(g.m))
+    winv = 0.5 + rng.random(g.n)
+    Gt = wd[:, None] * G * winv[None, :]
+    r = rng.standard_normal(g.m)
+    f, fT = ops(Gt)
+    tp = 63
+    omega = rng.standard_normal((tp, g.m))
+    _, _, S = solvers.rsvd(f, fT, r, g.n, tp, tp, omega, "alpha1")
+    alpha = float(S[tp // 2])
+    y, _, _ = solvers.rsvd(f, fT, r, g.n, tp, tp, omega, "fixed", alpha)
+    assert rsvd_galerkin_defects(f, fT, r, y, alpha, omega).max() <= 1e-12
+    y_off, _, _ = solvers.rsvd(f, fT, r, g.n, tp, tp, omega, "fixed", 1.01 * alpha)
+    assert rsvd_galerkin_defects(f, fT, r, y_off, alpha, omega).max() >= 1e-4
+    y_cut, _, _ = solvers.rsvd(f, fT, r, g.n, tp - 10, tp, omega, "fixed", alpha)
+    assert rsvd_galerkin_defects(f, fT, r, y_cut, alpha, omega).max() >= 1e-4
+    # two power iterations: the space moves to (G~^T G~)^2 G~^T Omega^T
+    y2, _, _ = solvers.rsvd(f, fT, r, g.n, tp, tp, omega, "fixed", alpha, power_iters=2)
+    assert rsvd_galerkin_defects(f, fT, r, y2, alpha, omega, power_iters=2).max() <= 1e-12
