@@ -133,7 +133,7 @@ def test_fused_focusing_loss_matches_dense_reference(dtype):
     ref = 2.0 * (wd * r) @ G + alpha * 2.0 * m0 * EPS2 / (m0 * m0 + EPS2) ** 2
     ref_L = float((r * r).sum() + alpha * (m0 * m0 / (m0 * m0 + EPS2)).sum())
     tol = 1e-10 if dtype == F64 else 1e-5
-    assert Lf.dtype == F64 and abs(float(Lf) - ref_L) <= tol * abs(ref_L)
+    assert Lf.dtype == F64 and abs(float(Lf.detach()) - ref_L) <= tol * abs(ref_L)
     assert rel(to_host(m.grad), ref) <= tol
 
 
