@@ -1,9 +1,11 @@
 """The host rendering of the RSVD test-matrix generator (Philox4x32-10 + Box-Muller), pinned by
-properties of its definition: the vectorized rounds equal a plain integer rendering, the map
+the generator's published known-answer vectors and by properties of its definition: the
+vectorized rounds equal a plain integer rendering, the map
 is a permutation of counters, one flipped counter bit changes about half of the output bits,
 streams and seeds give unrelated sequences, and the normals have the moments of N(0, 1)."""
 import numpy as np
 
+from conftest import read_golden
 from oracle import philox
 
 
@@ -46,3 +48,16 @@ def test_gaussian_moments_streams_and_prefixes():
     # other streams and seeds are unrelated
     for y in (philox.gaussian(20000, seed=12345, stream=1), philox.gaussian(20000, seed=12346)):
         assert abs(np.corrcoef(x[:20000], y)[0, 1]) < 0.05
+
+
+def test_published_known_answers():
+    # the generator's published known-answer vectors (tests/golden/philox4x32_10_kat.txt), for
+    # the plain and the vectorized rendering
+    rows = read_golden("philox4x32_10_kat.txt")
+    assert len(rows) == 3
+    for row in rows:
+        w = [int(x, 16) for x in row]
+        ctr, key, want = w[0:4], w[4:6], w[6:10]
+        assert list(philox.philox_scalar(ctr, key)) == want
+        v = philox.philox4x32_10(*(np.array([x], dtype=np.uint64) for x in ctr), key[0], key[1])
+        assert [int(x[0]) for x in v] == want
