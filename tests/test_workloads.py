@@ -67,3 +67,74 @@ def test_snr_and_tau_table():
     assert abs(W.snr_db(d, eta) - 20.0) < 1e-12
     assert sorted(W.LADDER_TAU2) == list(range(4, 13))
     assert all(0 < g < W.LADDER_TAU1 and 0 < mg < W.LADDER_TAU1 for g, mg in W.LADDER_TAU2.values())
+
+
+def _pow2_at_least(v):
+    p = 1
+    while p < v:
+        p *= 2
+    return p
+
+
+def test_named_surveys_sizes_and_embeddings():
+    """Stations m, cells n and the smallest power-of-two embedding N >= s + n - 1 per axis."""
+    want = {"tiny": (256, 1024, (32, 32)), "gravity_l4": (6000, 60000, (256, 128)),
+            "magnetic_1m": (50000, 1000000, (512, 512)), "gravity_rsvd": (30000, 360000, (512, 512)),
+            "gravity_diff": (16384, 262144, (256, 256))}
+    assert sorted(W.SURVEYS) == sorted(want)
+    for name, (m, n, emb) in want.items():
+        s = W.SURVEYS[name]
+        nx, ny, nz, mm, nn = W.sizes(s)
+        assert (mm, nn) == (m, n)
+        assert (_pow2_at_least(s["sx"] + nx - 1), _pow2_at_least(s["sy"] + ny - 1)) == emb
+    assert W.SURVEYS["magnetic_1m"]["kernel"] == "magnetic"
+
+
+def test_uneven_surveys_span_the_embedding_sizes():
+    """Eight gravity surveys of 20 m cubes whose embeddings run from 64 x 64 to 512 x 256."""
+    embs = []
+    for s in W.uneven_surveys():
+        nx, ny, _, _, _ = W.sizes(s)
+        assert s["dx"] == s["dy"] == 20.0 and s["kernel"] == "gravity"
+        embs.append((_pow2_at_least(s["sx"] + nx - 1), _pow2_at_least(s["sy"] + ny - 1)))
+    assert len(embs) == 8 and embs[0] == (64, 64) and embs[-1] == (512, 256)
+    assert len(set(embs)) >= 5
+
+
+def test_block_models_in_metres():
+    """The gravity_l4 blocks (20 m cells, 40 m layers) cover x [500, 800), y [400, 700),
+    z [40, 160) and x [1200, 1500), y [500, 900), z [80, 240) at 1 g/cc."""
+    s = W.SURVEYS["gravity_l4"]
+    nx, ny, nz, _, _ = W.sizes(s)
+    m = W.block_model(s, W.GRAVITY_L4_BLOCKS).reshape(nz, ny, nx)
+    ze = np.asarray(s["z_edges"])
+    boxes = [(500, 800, 400, 700, 40, 160), (1200, 1500, 500, 900, 80, 240)]
+    xc = (np.arange(nx) + 0.5) * s["dx"]
+    yc = (np.arange(ny) + 0.5) * s["dy"]
+    zc = 0.5 * (ze[:-1] + ze[1:])
+    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+    inside = np.zeros_like(m, dtype=bool)
+    for x0, x1, y0, y1, z0, z1 in boxes:
+        inside |= (X >= x0) & (X < x1) & (Y >= y0) & (Y < y1) & (Z >= z0) & (Z < z1)
+    assert np.array_equal(m > 0, inside) and set(np.unique(m)) == {0.0, 1.0}
+
+
+def test_magnetic_1m_cube_and_dike():
+    """A 10-cell cube of 0.1 SI at 60-260 m depth and a 3-cell-thick dike, 100 cells along
+    strike, in layers 2-15, moving one column per 20 m layer (45 degrees on 20 m cubes)."""
+    s = W.SURVEYS["magnetic_1m"]
+    nx, ny, nz, _, _ = W.sizes(s)
+    m = W.block_model(s, W.MAGNETIC_1M_BLOCKS).reshape(nz, ny, nx)
+    cube = W.MAGNETIC_1M_BLOCKS[0]
+    p0, p1, q0, q1, r0, r1, v = cube
+    assert (p1 - p0, q1 - q0, r1 - r0, v) == (10, 10, 10, 0.1)
+    assert (s["z_edges"][r0], s["z_edges"][r1]) == (60.0, 260.0)
+    assert np.all(m[r0:r1, q0:q1, p0:p1] == 0.1)
+    dike = W.MAGNETIC_1M_BLOCKS[1:]
+    assert [b[4] for b in dike] == list(range(2, 16))
+    for (a0, a1, b0, b1, r, _, val), nxt in zip(dike, dike[1:] + [None]):
+        assert (a1 - a0, b1 - b0, val) == (3, 100, 0.1)
+        if nxt is not None:
+            assert nxt[0] == a0 + 1
+    # the cube (columns 60-69) and the dike (columns 152 and beyond) do not overlap
+    assert np.count_nonzero(m) == 10 * 10 * 10 + 14 * 3 * 100
