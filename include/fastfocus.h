@@ -295,6 +295,7 @@ typedef struct ff_multi_s *ff_multi;
 ff_status ff_multi_create(int32_t count, const ff_spectra *handles, const void *const *x, void *const *gx,
                           const void *const *d, void *const *gtd, ff_multi *out);
 ff_status ff_multi_apply(ff_multi plan, ff_stream stream);
+/* Frees the plan's host and device tables; NULL is accepted and does nothing. */
 ff_status ff_multi_free(ff_multi plan);
 
 /* Thread-local message of the last failure ("" if none).  Valid until the next call. */

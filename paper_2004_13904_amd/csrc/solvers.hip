@@ -928,13 +928,14 @@ struct IrlsWs {
   }
 };
 
-ff_status check_solver_args(ff_spectra h, int t, int tp, const void *r, const void *wd, const void *winv,
-                            const void *y, const void *alpha, const void *sigma, const void *ws) {
-  if (!h || !r || !wd || !winv || !y || !alpha || !sigma || !ws) return fail(FF_EINVAL, "NULL argument");
-  if (t < 1 || tp < t || tp > h->m) return fail(FF_ESHAPE, "need 1 <= t <= tp <= m");
+ff_status check_solver_args(const char *who, ff_spectra h, int t, int tp, const void *r, const void *wd,
+                            const void *winv, const void *y, const void *alpha, const void *sigma, const void *ws) {
+  const std::string w(who);
+  if (!h || !r || !wd || !winv || !y || !alpha || !sigma || !ws) return fail(FF_EINVAL, w + ": NULL argument");
+  if (t < 1 || tp < t || tp > h->m) return fail(FF_ESHAPE, w + ": need 1 <= t <= tp <= m");
   int cur = -1;
-  hipGetDevice(&cur);
-  if (cur != h->device) return fail(FF_EDEVICE, "current device differs from the handle's device");
+  if (hipGetDevice(&cur) != hipSuccess) return fail(FF_EHIP, w + ": hipGetDevice failed");
+  if (cur != h->device) return fail(FF_EDEVICE, w + ": current device differs from the handle's device");
   return FF_OK;
 }
 
@@ -1246,7 +1247,7 @@ ff_status ff_workspace_size(ff_spectra h, int32_t which, int32_t solver, int32_t
 ff_status gkb_project(ff_spectra h, const double *r_tilde, const double *wd, const double *winv, int32_t t,
                       int32_t tp, int32_t alpha_mode, int32_t basis_dtype, double *y, double *alpha, double *sigma,
                       void *workspace, size_t ws_bytes, ff_stream stream) {
-  ff_status st = check_solver_args(h, t, tp, r_tilde, wd, winv, y, alpha, sigma, workspace);
+  ff_status st = check_solver_args("gkb_project", h, t, tp, r_tilde, wd, winv, y, alpha, sigma, workspace);
   if (st) return st;
   if (alpha_mode < 0 || alpha_mode > 2) return fail(FF_EINVAL, "gkb_project: alpha_mode must be 0, 1 or 2");
   if (basis_dtype == FF_F64)
@@ -1269,7 +1270,7 @@ ff_status ff_solver_stats(ff_spectra h, int64_t *qr_cholesky2, int64_t *qr_chole
 ff_status rsvd_project(ff_spectra h, const double *r_tilde, const double *wd, const double *winv, int32_t t,
                        int32_t tp, const double *omega, uint64_t seed, int32_t power_iters, int32_t alpha_mode,
                        double *y, double *alpha, double *sigma, void *workspace, size_t ws_bytes, ff_stream stream) {
-  ff_status st = check_solver_args(h, t, tp, r_tilde, wd, winv, y, alpha, sigma, workspace);
+  ff_status st = check_solver_args("rsvd_project", h, t, tp, r_tilde, wd, winv, y, alpha, sigma, workspace);
   if (st) return st;
   if (power_iters < 0 || power_iters > kMaxPowerIters)
     return fail(FF_EINVAL, "rsvd_project: power_iters must lie in [0, 8]");

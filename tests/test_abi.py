@@ -122,3 +122,25 @@ def test_header_compiles_as_plain_c_and_cpp(compiler, lang, tmp_path):
     r = subprocess.run([compiler, "-fsyntax-only", "-x", lang, "-Wall", "-Wextra", "-Werror", HEADER],
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def test_every_entry_point_rejects_null_arguments():
+    # NULL handles and buffers, zero sizes: every entry point returns FF_EINVAL with a message
+    # naming itself, before any device call (so this runs without a GPU); freeing a NULL plan
+    # is a no-op
+    L, lib = _lib()
+    for name in L.EXPORTS:
+        if name in ("ff_last_error", "ff_multi_free"):
+            continue
+        fn = getattr(lib, name)
+        args = []
+        for t in fn.argtypes:
+            if issubclass(t, (C._Pointer, C.c_void_p, C.c_char_p)):
+                args.append(None)
+            elif t in (C.c_double, C.c_float):
+                args.append(0.0)
+            else:
+                args.append(0)
+        assert fn(*args) == -1, name
+        assert lib.ff_last_error().decode().startswith(name + ":"), name
+    assert lib.ff_multi_free(None) == 0
