@@ -170,6 +170,8 @@ class Operator:
             self._vec(w_pre, rin, "apply_G_block")
         if w_post is not None:
             self._vec(w_post, rout, "apply_G_block")
+        if k == 0:      # an empty batch: nothing to launch (its data pointers may be NULL)
+            return out
         L.call("apply_G_block", self.h, int(bool(transpose)), k, _ptr(X), rin, _ptr(out), rout,
                _ptr(w_pre), _ptr(w_post), _stream(stream))
         return out

@@ -192,6 +192,19 @@ def test_batched_full_size_equals_vector_loop(k):
         same(GTD[c], A.GT(D[c].contiguous()))
 
 
+def test_empty_block_apply():
+    # k = 0 vectors: empty results, nothing launched; through the C ABI with valid pointers too
+    A = Operator(SMALL["wide_tail"], F32)
+    assert tuple(A.G_block(torch.empty(0, A.n, device="cuda")).shape) == (0, A.m)
+    assert tuple(A.G_block(torch.empty(0, A.m, device="cuda"), transpose=True).shape) == (0, A.n)
+    x = torch.zeros(A.n, device="cuda")
+    y = torch.full((A.m,), 3.0, device="cuda")
+    L.call("apply_G_block", A.h, 0, 0, x.data_ptr(), A.n, y.data_ptr(), A.m, None, None, None)
+    torch.cuda.synchronize()
+    assert bool((y == 3.0).all())
+    A.close()
+
+
 def test_zero_and_impulse_inputs():
     s = SMALL["mag45"]
     g = ogeom(s)
