@@ -81,6 +81,28 @@ def test_gkb_matches_oracle_algorithm(mode, dtype):
     assert rel(to_host(y), y0) <= (1e-8 if dtype == F64 else 1e-4) + 2 * abs(a - a0) / a0
 
 
+@pytest.mark.parametrize("solver", ["gkb", "rsvd"])
+@pytest.mark.parametrize("t,tp", [(1, 1), (1, 2), (2, 2)])
+@pytest.mark.parametrize("mode", ["fixed", "alpha1"])
+def test_smallest_projected_sizes(solver, t, tp, mode):
+    # the degenerate projected problems: one or two basis vectors (a 2 x 1 or 3 x 2 bidiagonal
+    # for GKB, a 1 x 1 or 2 x 2 Gram matrix for RSVD), FP64 against the oracle's algorithms
+    s, g, G, wd, winv, Gt, r = problem("mid", kernel="gravity", seed=3)
+    announce("smallest", solver, t, tp, mode)
+    A = Operator(s, F64)
+    args = (to_dev(r, F64), to_dev(wd, F64), to_dev(winv, F64), t, tp)
+    if solver == "gkb":
+        y0, a0, s0 = osol.gkb(*dense_ops(Gt), r, g.n, t, tp, mode, 2.0)
+        y, a, sig = S.gkb_project(A, *args, mode, 2.0)
+    else:
+        omega = np.random.default_rng(5).standard_normal((tp, g.m))
+        y0, a0, s0 = osol.rsvd(*dense_ops(Gt), r, g.n, t, tp, omega, mode, 2.0)
+        y, a, sig = S.rsvd_project(A, *args, to_dev(omega, F64), mode, 2.0)
+    assert rel(to_host(sig), s0) <= 1e-9
+    assert abs(a - a0) <= 1e-10 * a0
+    assert rel(to_host(y), y0) <= 1e-8
+
+
 @pytest.mark.parametrize("kernel", ["gravity", "magnetic"])
 def test_rsvd_full_space_is_tikhonov(kernel):
     s, g, G, wd, winv, Gt, r = problem(kernel=kernel)
