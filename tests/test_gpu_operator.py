@@ -192,6 +192,29 @@ def test_batched_full_size_equals_vector_loop(k):
         same(GTD[c], A.GT(D[c].contiguous()))
 
 
+def test_rsvd_block_product_full_size_sampled_columns():
+    # the RSVD block product as the benchmark times it: gravity 200 x 150 x 12 (n = 360000),
+    # k = 3750 FP32 vectors in one call each way; the first, a middle and the last column against
+    # the oracle's direct sums
+    s = W.SURVEYS["gravity_rsvd"]
+    announce("block full size", "gravity_rsvd", 3750)
+    g = ogeom(s)
+    T = op.kernel_table(g)
+    A = Operator(s, F32)
+    k = 3750
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    X = torch.randn(k, A.n, device="cuda", generator=gen)
+    D = torch.randn(k, A.m, device="cuda", generator=gen)
+    Y = A.G_block(X)
+    Z = A.G_block(D, transpose=True)
+    for c in (0, 1877, k - 1):
+        assert rel(to_host(Y[c]), op.apply_G(g, to_host(X[c]), T)) <= 1e-5
+        assert rel(to_host(Z[c]), op.apply_GT(g, to_host(D[c]), T)) <= 1e-5
+    del X, D, Y, Z
+    A.close()
+    torch.cuda.empty_cache()
+
+
 def test_empty_block_apply():
     # k = 0 vectors: empty results, nothing launched; through the C ABI with valid pointers too
     A = Operator(SMALL["wide_tail"], F32)
