@@ -54,10 +54,16 @@ def focusing_weights(m_prev, m_prev2, lam, eps2, k):
     return (dm * dm + eps2) ** ((lam - 2.0) / 4.0)
 
 
-def chi2_scaled(geom: Geometry, m_model, d_obs, wd, table=None):
-    """eq. (scaledchi2): ||W_d (G m - d_obs)||^2 / (m + sqrt(2 m))."""
-    res = wd * (op.apply_G(geom, m_model, table) - d_obs)
-    return float(res @ res) / (geom.m + math.sqrt(2.0 * geom.m))
+def chi2_scaled(Gm, d_obs, wd):
+    """eq. (scaledchi2): ||W_d (G m - d_obs)||^2 / (m + sqrt(2 m)), m = number of data.
+
+    Gm is the predicted data G m of the model being tested.  For pure noise of eq. (noisydata)
+    whitened by W_d the numerator is chi-squared with m degrees of freedom (mean m, variance
+    2 m), which is what the test pins (tests/test_oracle_solvers.py)."""
+    Gm = np.asarray(Gm, dtype=np.float64)
+    res = np.asarray(wd, dtype=np.float64) * (Gm - np.asarray(d_obs, dtype=np.float64))
+    m = res.size
+    return float(res @ res) / (m + math.sqrt(2.0 * m))
 
 
 def irls_step(geom: Geometry, p: IrlsParams, k, d_obs, wd, m_prev, m_prev2, omega=None,
@@ -83,9 +89,7 @@ def irls_step(geom: Geometry, p: IrlsParams, k, d_obs, wd, m_prev, m_prev2, omeg
     else:
         z, alpha, sigma = solvers.rsvd(Gt, GtT, r_tilde, geom.n, p.t, p.tp, omega, mode, af)
     m_new = np.clip(np.asarray(m_prev, dtype=np.float64) + z / W, p.m_min, p.m_max)
-    res = wd * (G(m_new) - d_obs)
-    chi2 = float(res @ res) / (geom.m + math.sqrt(2.0 * geom.m))
-    return m_new, alpha, chi2, sigma
+    return m_new, alpha, chi2_scaled(G(m_new), d_obs, wd), sigma
 
 
 def snr_db(d_exact, d_obs):

@@ -188,3 +188,79 @@ def test_far_corner_cancellation_is_bounded(dist, tol):
     r = np.linalg.norm(c)
     ref = (2 * a) ** 3 * c[2] / r ** 3
     assert abs(val / ref - 1.0) < tol
+
+
+# ---- unit scale of the gravity entries ---------------------------------------------------
+# The entries are in mGal per g/cc.  Two values from outside the oracle fix the scale: the
+# Bouguer slab constant 2 pi G rho h, which the textbooks print as 0.04193 mGal per metre of
+# thickness per g/cc (to four digits, i.e. within 1.2e-4 relative), and Newton's law for a
+# compact body far away, g = G M / r^2 with G = 6.674e-11 (four digits, 6e-5 relative).
+
+def test_gravity_unit_scale_bouguer_slab():
+    for h in (1.0, 50.0, 120.0):
+        W = 1e7
+        val = prism.gravity_entry(-W, W, -W, W, 0.0, h)
+        assert abs(val / (0.04193 * h) - 1.0) < 2e-4, (h, val)
+        # a factor of ten in any unit conversion or a lost 2 pi is far outside that
+        assert abs(val / (0.04193 * h) - 1.0) < 1e-3
+
+
+def test_gravity_unit_scale_point_mass():
+    # a 20 m cube of 1 g/cc = 1000 kg/m^3 holds 8e6 kg; 1 m/s^2 = 1e5 mGal
+    a = 10.0
+    for c in ((0.0, 0.0, 3000.0), (2000.0, -1500.0, 800.0)):
+        val = prism.gravity_entry(c[0] - a, c[0] + a, c[1] - a, c[1] + a, c[2] - a, c[2] + a)
+        r = math.sqrt(c[0] ** 2 + c[1] ** 2 + c[2] ** 2)
+        g_down = 6.674e-11 * 8.0e6 / r ** 2 * (c[2] / r) * 1e5
+        assert abs(val / g_down - 1.0) < 2e-4, (c, val, g_down)
+
+
+# ---- labelling of the field direction ----------------------------------------------------
+# Axes are x = north, y = east, z = down, declination clockwise from north.  These checks do
+# not use the oracle's field_direction: they state what the direction must do.
+
+def test_zero_declination_is_even_in_the_east_offset():
+    # D = 0 puts the field and the magnetization in the x-z plane: reflecting y -> -y maps the
+    # problem onto itself, so the TFA of a prism equals that of its mirror image across y = 0
+    for inc in (30.0, 60.0, 75.0):
+        for b in ((35.0, 85.0, -45.0, 5.0, 20.0, 40.0), (-70.0, -10.0, 15.0, 55.0, 0.0, 30.0)):
+            v = prism.magnetic_entry(*b, inc, 0.0, 50000.0)
+            vm = prism.magnetic_entry(b[0], b[1], -b[3], -b[2], b[4], b[5], inc, 0.0, 50000.0)
+            assert abs(v - vm) <= 1e-12 * abs(v), (inc, b)
+            # and is not even in the north offset (the field has a north component)
+            vx = prism.magnetic_entry(-b[1], -b[0], b[2], b[3], b[4], b[5], inc, 0.0, 50000.0)
+            assert abs(v - vx) > 1e-3 * abs(v)
+
+
+def test_east_declination_is_even_in_the_north_offset():
+    for inc in (30.0, 60.0):
+        b = (35.0, 85.0, -45.0, 5.0, 20.0, 40.0)
+        v = prism.magnetic_entry(*b, inc, 90.0, 50000.0)
+        vm = prism.magnetic_entry(-b[1], -b[0], b[2], b[3], b[4], b[5], inc, 90.0, 50000.0)
+        assert abs(v - vm) <= 1e-12 * abs(v)
+        vy = prism.magnetic_entry(b[0], b[1], -b[3], -b[2], b[4], b[5], inc, 90.0, 50000.0)
+        assert abs(v - vy) > 1e-3 * abs(v)
+
+
+@pytest.mark.parametrize("inc,dec,fhat", [
+    (0.0, 0.0, (1.0, 0.0, 0.0)),       # horizontal field pointing north
+    (0.0, 90.0, (0.0, 1.0, 0.0)),      # horizontal field pointing east
+    (0.0, -90.0, (0.0, -1.0, 0.0)),    # west
+    (90.0, 0.0, (0.0, 0.0, 1.0)),      # vertical, pointing down
+    (30.0, 0.0, (math.sqrt(3) / 2, 0.0, 0.5)),   # northward, dipping down by 30 degrees
+    (0.0, 45.0, (math.sqrt(0.5), math.sqrt(0.5), 0.0)),     # north-east (clockwise from north)
+    (0.0, -45.0, (math.sqrt(0.5), -math.sqrt(0.5), 0.0)),   # north-west
+    (-30.0, 180.0, (-math.sqrt(3) / 2, 0.0, -0.5)),        # southward, pointing up
+])
+def test_tfa_far_field_of_axis_dipoles(inc, dec, fhat):
+    # far from a small cube the TFA is that of a point dipole of moment V kappa F f / mu0:
+    #     dT = F / (4 pi) V (3 (f . r^)^2 - 1) / r^3,
+    # with the direction f written out here for each (I, D)
+    a = 10.0
+    F = 50000.0
+    f = np.array(fhat)
+    for c in (np.array([800.0, 100.0, 300.0]), np.array([-400.0, 600.0, 50.0]), np.array([300.0, -700.0, 200.0])):
+        val = prism.magnetic_entry(c[0] - a, c[0] + a, c[1] - a, c[1] + a, c[2] - a, c[2] + a, inc, dec, F)
+        r = np.linalg.norm(c)
+        ref = F / (4 * math.pi) * (2 * a) ** 3 * (3 * (f @ c / r) ** 2 - 1) / r ** 3
+        assert abs(val / ref - 1.0) < 1e-5, (inc, dec, c, val, ref)

@@ -229,3 +229,31 @@ def test_rsvd_solution_satisfies_galerkin_conditions(kernel):
     # two power iterations: the space moves to (G~^T G~)^2 G~^T Omega^T
     y2, _, _ = solvers.rsvd(f, fT, r, g.n, tp, tp, omega, "fixed", alpha, power_iters=2)
     assert rsvd_galerkin_defects(f, fT, r, y2, alpha, omega, power_iters=2).max() <= 1e-12
+
+
+def test_scaled_chi2_of_pure_noise():
+    # eq. (scaledchi2) on the true model: G m_true - d_obs = -eta with eta drawn per eq. (noisydata)
+    # and W_d = diag(1 / sigma), so the numerator is chi-squared with m degrees of freedom (mean m,
+    # variance 2 m) and the mean of the scaled value over many draws is m / (m + sqrt(2 m)).
+    # Dividing by m instead, by m + sqrt(m), or dropping the square moves the mean by 5 to 50
+    # standard errors.
+    from paper_2004_13904_amd import workloads as W
+    g = geometry.uniform_geometry(16, 16, 2, 30.0, 30.0, 30.0)
+    G = op.dense_G(g)
+    m_true = np.zeros(g.n)
+    m_true[: g.n // 3] = 1.0
+    d_exact = G @ m_true
+    S = 400
+    vals = []
+    for seed in range(S):
+        eta, sd = W.noise(d_exact, 0.01, 0.001, 1000 + seed)
+        vals.append(irls.chi2_scaled(G @ m_true, d_exact + eta, 1.0 / sd))
+    m = g.m
+    expect = m / (m + math.sqrt(2.0 * m))
+    se = math.sqrt(2.0 * m) / (m + math.sqrt(2.0 * m)) / math.sqrt(S)
+    assert abs(np.mean(vals) - expect) < 3.5 * se, (np.mean(vals), expect, se)
+    # the sample variance of the numerator is 2 m as well (within its own sampling error)
+    num = np.array(vals) * (m + math.sqrt(2.0 * m))
+    assert abs(num.var(ddof=1) / (2.0 * m) - 1.0) < 0.25
+    # a noise-free model gives zero
+    assert irls.chi2_scaled(d_exact, d_exact, np.ones(m)) == 0.0
