@@ -139,6 +139,24 @@ ff_status apply_G_block(ff_spectra h, int32_t transpose, int64_t k, const void *
                         void *Y, int64_t ldy, const void *w_pre, const void *w_post,
                         ff_stream stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph capture, tight serving
+   loops and harnesses that forbid hipMalloc.  Computes exactly what apply_G_block computes (same
+   arguments, same pass kernels, results equal to its own), but keeps the pass intermediates in
+   a fixed library array of FF_NOALLOC_SCRATCH_BYTES per device instead of the handle's
+   workspace, and calls no allocating routine.  The array is part of the library's code object:
+   each device the library runs on holds it from load until the process ends.  The k vectors
+   go through in launches of at most the handle's batch, fewer when their intermediates
+   (nz * nfft_x/2 * ny rounded up to 16, plus a data-sized column buffer per layer group of G,
+   complex values of the handle's dtype, per vector) would not fit the array; FF_ENOMEM, before
+   any launch, when a single vector's do not (e.g. nz = 20 at a 512 x 512 embedding needs
+   about 9 MB per vector).  Every call on a device shares that device's array and leaves
+   unspecified contents in it (nothing in it needs to start at zero): calls that may overlap
+   on one device (other streams, threads or handles) race, so the caller must serialize them. */
+#define FF_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+ff_status ff_apply_block_noalloc(ff_spectra h, int32_t transpose, int64_t k, const void *X, int64_t ldx,
+                                 void *Y, int64_t ldy, const void *w_pre, const void *w_post,
+                                 ff_stream stream);
+
 /* The focusing objective of the differentiable form, with the operator products inside:
    L = sum over the k models of ||wd .* (G m - d_obs)||^2 + alpha * sum_i m_i^2 / (m_i^2 + eps2),
    the data misfit of eq. (dfandstab) and the minimum-support stabilizer (eq. (WLdefn) with

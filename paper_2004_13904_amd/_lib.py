@@ -24,7 +24,7 @@ EXPORTS = ["build_spectra", "ff_free_spectra", "ff_spectra_info", "ff_kernel_tab
            "irls_step", "ff_get_tuning", "ff_set_tuning", "ff_profile_begin", "ff_profile_end", "ff_time_pass",
            "ff_multi_create", "ff_multi_apply", "ff_multi_free", "ff_spectra_save", "ff_spectra_load",
            "ff_spectra_geometry", "ff_solver_stats", "ff_focusing_loss", "ff_focusing_grad", "ff_fft_1d",
-           "ff_last_error"]
+           "ff_apply_block_noalloc", "ff_last_error"]
 
 
 class FFGeometry(C.Structure):
@@ -76,6 +76,7 @@ def load(path=None):
         "apply_G": [vp, vp, vp, vp, vp, vp],
         "apply_GT": [vp, vp, vp, vp, vp, vp],
         "apply_G_block": [vp, i32, i64, vp, i64, vp, i64, vp, vp, vp],
+        "ff_apply_block_noalloc": [vp, i32, i64, vp, i64, vp, i64, vp, vp, vp],
         "ff_workspace_size": [vp, i32, i32, i32, i32, C.POINTER(C.c_size_t)],
         "gkb_project": [vp, vp, vp, vp, i32, i32, i32, i32, vp, dp, vp, vp, C.c_size_t, vp],
         "rsvd_project": [vp, vp, vp, vp, i32, i32, vp, C.c_uint64, i32, i32, vp, dp, vp, vp, C.c_size_t, vp],

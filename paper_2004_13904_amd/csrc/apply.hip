@@ -76,12 +76,12 @@ void launch_c2r(int tile, int nrows, int nb, int kb, const cplx<T> *in, Idx3 ii,
 // One pass of G (transpose = 0) or G^T (transpose = 1) for kb vectors: pass 0 = row
 // transforms, 1 = column transforms with the spectral products, 2 = inverse row transforms.
 template <typename T, typename TI, typename TO>
-ff_status run_pass(ff_spectra h, int transpose, int pass, int kb, const TI *X, int64_t ldx, TO *Y, int64_t ldy_out,
-                   const TI *pre, const TO *post, hipStream_t s) {
+ff_status run_pass(ff_spectra h, const OpWs &ws, int transpose, int pass, int kb, const TI *X, int64_t ldx, TO *Y,
+                   int64_t ldy_out, const TI *pre, const TO *post, hipStream_t s) {
   const int HC = h->NX / 2, nz = h->nz, nx = h->nx, ny = h->ny, sx = h->sx, sy = h->sy;
   const int ldy = h->ldy, lds = h->lds;
-  cplx<T> *X1 = (cplx<T> *)h->ws_rows;   // [vec][r][c][row] (ld ldy), HC column slots
-  cplx<T> *C2 = (cplx<T> *)h->ws_cols;   // G: partial sums [vec][g][c][j]; G^T: D1 [vec][c][j] (ld lds)
+  cplx<T> *X1 = (cplx<T> *)ws.rows;   // [vec][r][c][row] (ld ldy), HC column slots
+  cplx<T> *C2 = (cplx<T> *)ws.cols;   // G: partial sums [vec][g][c][j]; G^T: D1 [vec][c][j] (ld lds)
   const cplx<T> *spec = (const cplx<T> *)h->spec;
   const cplx<T> *twx = (const cplx<T> *)h->tw_x, *twy = (const cplx<T> *)h->tw_y;
   const int64_t lay = (int64_t)ny * nx;
@@ -142,11 +142,11 @@ ff_status run_pass(ff_spectra h, int transpose, int pass, int kb, const TI *X, i
 }
 
 template <typename T, typename TI, typename TO>
-ff_status run_op(ff_spectra h, int transpose, int kb, const TI *X, int64_t ldx, TO *Y, int64_t ldy, const TI *pre,
-                 const TO *post, hipStream_t s) {
+ff_status run_op(ff_spectra h, const OpWs &ws, int transpose, int kb, const TI *X, int64_t ldx, TO *Y, int64_t ldy,
+                 const TI *pre, const TO *post, hipStream_t s) {
   for (int pass = 0; pass < 3; ++pass) {
     prof_mark(h, pass, transpose, s);
-    ff_status st = run_pass<T, TI, TO>(h, transpose, pass, kb, X, ldx, Y, ldy, pre, post, s);
+    ff_status st = run_pass<T, TI, TO>(h, ws, transpose, pass, kb, X, ldx, Y, ldy, pre, post, s);
     if (st != FF_OK) return st;
   }
   prof_mark(h, 3, transpose, s);
@@ -154,19 +154,21 @@ ff_status run_op(ff_spectra h, int transpose, int kb, const TI *X, int64_t ldx, 
 }
 
 template <typename T, typename TIO>
-ff_status run(ff_spectra h, int transpose, int64_t k, const void *X, int64_t ldx, void *Y, int64_t ldy,
-              const void *w_pre, const void *w_post, hipStream_t s) {
+ff_status run(ff_spectra h, const OpWs &ws, int transpose, int64_t k, const void *X, int64_t ldx, void *Y,
+              int64_t ldy, const void *w_pre, const void *w_post, hipStream_t s) {
   const TIO *x = (const TIO *)X;
   TIO *y = (TIO *)Y;
-  const int B = h->batch;
+  const int B = ws.batch;
   for (int64_t c0 = 0; c0 < k; c0 += B) {
     const int kb = (int)((k - c0) < B ? (k - c0) : B);
-    ff_status st = run_op<T, TIO, TIO>(h, transpose, kb, x + c0 * ldx, ldx, y + c0 * ldy, ldy, (const TIO *)w_pre,
-                                       (const TIO *)w_post, s);
+    ff_status st = run_op<T, TIO, TIO>(h, ws, transpose, kb, x + c0 * ldx, ldx, y + c0 * ldy, ldy,
+                                       (const TIO *)w_pre, (const TIO *)w_post, s);
     if (st != FF_OK) return st;
   }
   return FF_OK;
 }
+
+OpWs handle_ws(ff_spectra h) { return OpWs{h->ws_rows, h->ws_cols, h->batch}; }
 
 }  // namespace
 
@@ -209,25 +211,39 @@ ff_status op_time_pass(ff_spectra h, int transpose, int pass, int reps, const vo
                           h->dtype, s);
   if (st != FF_OK) return st;
   const int64_t ldx = transpose ? h->m : h->n, ldy = transpose ? h->n : h->m;
+  const OpWs ws = handle_ws(h);
   for (int r = 0; r < reps && st == FF_OK; ++r) {
     if (h->dtype == FF_F32)
-      st = run_pass<float, float, float>(h, transpose, pass, 1, (const float *)X, ldx, (float *)Y, ldy, nullptr, nullptr, s);
+      st = run_pass<float, float, float>(h, ws, transpose, pass, 1, (const float *)X, ldx, (float *)Y, ldy, nullptr,
+                                         nullptr, s);
     else
-      st = run_pass<double, double, double>(h, transpose, pass, 1, (const double *)X, ldx, (double *)Y, ldy, nullptr,
-                                            nullptr, s);
+      st = run_pass<double, double, double>(h, ws, transpose, pass, 1, (const double *)X, ldx, (double *)Y, ldy,
+                                            nullptr, nullptr, s);
   }
   return st;
 }
 
+void op_ws_per_vector(ff_spectra h, int transpose, size_t *rows_bytes, size_t *cols_bytes) {
+  const size_t cs = csize(h->dtype), HC = (size_t)(h->NX / 2);
+  *rows_bytes = cs * (size_t)h->nz * HC * (size_t)h->ldy;
+  *cols_bytes = cs * (transpose ? 1 : (size_t)h->lg_G) * HC * (size_t)h->lds;
+}
+
+ff_status op_apply_ws(ff_spectra h, const OpWs &ws, int transpose, int64_t k, const void *X, int64_t ldx, void *Y,
+                      int64_t ldy, const void *w_pre, const void *w_post, int io_dtype, hipStream_t s) {
+  if (ws.batch < 1 || !ws.rows || !ws.cols) return fail(FF_EINVAL, "operator workspace is empty");
+  if (h->dtype == FF_F32 && io_dtype == FF_F32)
+    return run<float, float>(h, ws, transpose, k, X, ldx, Y, ldy, w_pre, w_post, s);
+  if (h->dtype == FF_F32 && io_dtype == FF_F64)
+    return run<float, double>(h, ws, transpose, k, X, ldx, Y, ldy, w_pre, w_post, s);
+  if (h->dtype == FF_F64 && io_dtype == FF_F64)
+    return run<double, double>(h, ws, transpose, k, X, ldx, Y, ldy, w_pre, w_post, s);
+  return fail(FF_EDTYPE, "vector dtype not supported for this handle");
+}
+
 ff_status op_apply(ff_spectra h, int transpose, int64_t k, const void *X, int64_t ldx, void *Y, int64_t ldy,
                    const void *w_pre, const void *w_post, int io_dtype, hipStream_t s) {
-  if (h->dtype == FF_F32 && io_dtype == FF_F32)
-    return run<float, float>(h, transpose, k, X, ldx, Y, ldy, w_pre, w_post, s);
-  if (h->dtype == FF_F32 && io_dtype == FF_F64)
-    return run<float, double>(h, transpose, k, X, ldx, Y, ldy, w_pre, w_post, s);
-  if (h->dtype == FF_F64 && io_dtype == FF_F64)
-    return run<double, double>(h, transpose, k, X, ldx, Y, ldy, w_pre, w_post, s);
-  return fail(FF_EDTYPE, "vector dtype not supported for this handle");
+  return op_apply_ws(h, handle_ws(h), transpose, k, X, ldx, Y, ldy, w_pre, w_post, io_dtype, s);
 }
 
 }  // namespace ff

@@ -118,10 +118,20 @@ struct ff_spectra_s {
 
 namespace ff {
 size_t csize(int dtype);
-// operator passes (apply.hip)
+// Pass workspace of the operator: row-pass <-> column-pass intermediates (`rows`), column-pass
+// partial sums or transformed data rows (`cols`), and the vectors per launch they hold.
+struct OpWs {
+  void *rows, *cols;
+  int batch;
+};
+// operator passes (apply.hip): op_apply runs on the handle's own workspace, op_apply_ws on the
+// caller's; op_ws_per_vector gives the bytes one vector of a launch needs in each region
 ff_status op_apply(ff_spectra h, int transpose, int64_t k, const void *X, int64_t ldx, void *Y,
                    int64_t ldy, const void *w_pre, const void *w_post, int io_dtype,
                    hipStream_t s);
+ff_status op_apply_ws(ff_spectra h, const OpWs &ws, int transpose, int64_t k, const void *X, int64_t ldx,
+                      void *Y, int64_t ldy, const void *w_pre, const void *w_post, int io_dtype, hipStream_t s);
+void op_ws_per_vector(ff_spectra h, int transpose, size_t *rows_bytes, size_t *cols_bytes);
 ff_status op_time_pass(ff_spectra h, int transpose, int pass, int reps, const void *X, void *Y, hipStream_t s);
 // spectra construction (spectra.hip)
 ff_status make_spectra(ff_spectra h, hipStream_t s);
