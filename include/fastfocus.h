@@ -268,13 +268,19 @@ ff_status irls_step(ff_spectra h, const ff_irls_params *p, const double *d_obs, 
                    precision), 0 = one vector per column block.
      rsvd_qr       orthonormalization inside rsvd_project: 0 = Cholesky QR with the fallbacks
                    described there, 1 = always Householder QR (geqrf + orgqr), 2 = start at the
-                   shifted CholeskyQR3 (then Householder). */
+                   shifted CholeskyQR3 (then Householder).
+     pair_fused    grouped plans (ff_multi_create) of this survey alone that bind both G x and
+                   G^T d: 1 = one column pass for both products, reading each layer spectrum once
+                   (it splits the layers of both over lg_G groups), used when its column blocks
+                   (nfft_x/2 slots, lg_G groups) at least fill the device's compute units;
+                   0 = separate column passes.  The results are the same bit for bit. */
 typedef struct {
     int32_t lg_G, lg_GT;
     int32_t row_tile;
     int32_t batch;
     int32_t col_batched;
     int32_t rsvd_qr;
+    int32_t pair_fused;
 } ff_tuning;
 ff_status ff_get_tuning(ff_spectra h, ff_tuning *t);
 ff_status ff_set_tuning(ff_spectra h, const ff_tuning *t);
@@ -313,6 +319,11 @@ typedef struct ff_multi_s *ff_multi;
 ff_status ff_multi_create(int32_t count, const ff_spectra *handles, const void *const *x, void *const *gx,
                           const void *const *d, void *const *gtd, ff_multi *out);
 ff_status ff_multi_apply(ff_multi plan, ff_stream stream);
+/* Pass timing of a plan (instrumentation for benchmarks): launches only the plan's grouped
+   kernel `pass` (0 = row transforms, 1 = column passes, 2 = inverse row transforms) `reps` times
+   back to back on `stream`, re-reading the intermediates the last ff_multi_apply left.  Events
+   around the call divided by reps give that kernel's own duration. */
+ff_status ff_multi_time_pass(ff_multi plan, int32_t pass, int32_t reps, ff_stream stream);
 /* Frees the plan's host and device tables; NULL is accepted and does nothing. */
 ff_status ff_multi_free(ff_multi plan);
 

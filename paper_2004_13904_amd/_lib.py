@@ -22,7 +22,7 @@ STATUS = {0: "FF_OK", -1: "FF_EINVAL", -2: "FF_ESHAPE", -3: "FF_EDTYPE", -4: "FF
 EXPORTS = ["build_spectra", "ff_free_spectra", "ff_spectra_info", "ff_kernel_table", "apply_G",
            "apply_GT", "apply_G_block", "ff_workspace_size", "gkb_project", "rsvd_project",
            "irls_step", "ff_get_tuning", "ff_set_tuning", "ff_profile_begin", "ff_profile_end", "ff_time_pass",
-           "ff_multi_create", "ff_multi_apply", "ff_multi_free", "ff_spectra_save", "ff_spectra_load",
+           "ff_multi_create", "ff_multi_apply", "ff_multi_time_pass", "ff_multi_free", "ff_spectra_save", "ff_spectra_load",
            "ff_spectra_geometry", "ff_solver_stats", "ff_focusing_loss", "ff_focusing_grad", "ff_fft_1d",
            "ff_apply_block_noalloc", "ff_last_error"]
 
@@ -45,7 +45,7 @@ class FFIrlsParams(C.Structure):
 
 class FFTuning(C.Structure):
     _fields_ = [("lg_G", C.c_int32), ("lg_GT", C.c_int32), ("row_tile", C.c_int32), ("batch", C.c_int32),
-                ("col_batched", C.c_int32), ("rsvd_qr", C.c_int32)]
+                ("col_batched", C.c_int32), ("rsvd_qr", C.c_int32), ("pair_fused", C.c_int32)]
 
 
 class FastFocusError(RuntimeError):
@@ -90,6 +90,7 @@ def load(path=None):
         "ff_multi_create": [i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
                             C.POINTER(vp)],
         "ff_multi_apply": [vp, vp],
+        "ff_multi_time_pass": [vp, i32, i32, vp],
         "ff_multi_free": [vp],
         "ff_spectra_save": [vp, C.c_char_p],
         "ff_spectra_load": [C.c_char_p, vp, C.POINTER(vp)],

@@ -27,6 +27,9 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # never emit packed FP32 arithmetic (v_pk_*_f32)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit contraction into fused multiply-adds: the kernels write their FMAs out, so that
+    # kernels sharing a transform or a product round it identically
+    "-ffp-contract=off",
     "-Wno-unused-result", "-Wno-unused-value", "-I", INCLUDE, "-I", CSRC,
 ]
 LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]

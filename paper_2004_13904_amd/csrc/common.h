@@ -26,12 +26,19 @@ template <typename T> __host__ __device__ __forceinline__ cplx<T> mk(T re, T im)
 }
 template <typename T> __device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
 template <typename T> __device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+// Complex products with the fused multiply-adds written out: every kernel then rounds a
+// product the same way (left to the compiler's contraction, the same expression could be
+// fused differently in different kernels, and paths that should agree bit for bit would not).
+__device__ __forceinline__ float ffma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double ffma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 template <typename T> __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
-  return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  const T yy = a.y * b.y, yx = a.y * b.x;
+  return mk<T>(ffma(a.x, b.x, -yy), ffma(a.x, b.y, yx));
 }
 // a * conj(b)
 template <typename T> __device__ __forceinline__ cplx<T> cmulc(cplx<T> a, cplx<T> b) {
-  return mk<T>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+  const T yy = a.y * b.y, xy = a.x * b.y;
+  return mk<T>(ffma(a.x, b.x, yy), ffma(a.y, b.x, -xy));
 }
 template <typename T> __device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return mk<T>(a.x, -a.y); }
 template <typename T> __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
@@ -103,6 +110,7 @@ struct ff_spectra_s {
   int row_tile = 0;                   // 0 auto, 1 one transform per row block, 2 largest tile
   int col_batched = 1;                // 4-vectors-per-block column passes for block applies
   int rsvd_qr = 0;                    // RSVD orthonormalization: 0 CholQR2 first, 1 Householder, 2 CholQR3 first
+  int pair_fused = 1;                 // grouped plans: G x and G^T d of this survey share one column pass
   void *ws_rows = nullptr;           // batch x nz x H x max(ny, sy) complex: row-pass <-> column-pass
   void *ws_cols = nullptr;           // batch x LG x H x max(sy, ...) complex: column-pass partials / D1
   size_t ws_rows_bytes = 0, ws_cols_bytes = 0;

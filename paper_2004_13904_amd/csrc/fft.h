@@ -30,17 +30,6 @@ template <> struct Consts<double> { static constexpr double r2 = 0.7071067811865
 template <bool INV, typename T> __device__ __forceinline__ cplx<T> mul_w4(cplx<T> a) {
   return INV ? mk<T>(-a.y, a.x) : mk<T>(a.y, -a.x);
 }
-// multiply by w8 = (1 -+ i)/sqrt2
-template <bool INV, typename T> __device__ __forceinline__ cplx<T> mul_w8(cplx<T> a) {
-  const T c = Consts<T>::r2;
-  return INV ? mk<T>((a.x - a.y) * c, (a.x + a.y) * c) : mk<T>((a.x + a.y) * c, (a.y - a.x) * c);
-}
-// multiply by w8^3 = (-1 -+ i)/sqrt2
-template <bool INV, typename T> __device__ __forceinline__ cplx<T> mul_w83(cplx<T> a) {
-  const T c = Consts<T>::r2;
-  return INV ? mk<T>((-a.x - a.y) * c, (a.x - a.y) * c) : mk<T>((a.y - a.x) * c, (-a.x - a.y) * c);
-}
-
 template <bool INV, typename T>
 __device__ __forceinline__ void dft2(cplx<T> &a0, cplx<T> &a1) {
   cplx<T> t = a0;
@@ -58,23 +47,35 @@ __device__ __forceinline__ void dft4(cplx<T> &a0, cplx<T> &a1, cplx<T> &a2, cplx
   a3 = csub<T>(t1, t3);
 }
 
+// e +- c (p, q): the butterfly of an odd term rotated by an eighth turn, c (p, q) with
+// c = 1/sqrt2 and p, q sums of its parts, as explicit fused multiply-adds
+template <typename T>
+__device__ __forceinline__ void bfly_c(cplx<T> e, T p, T q, cplx<T> &plus, cplx<T> &minus) {
+  const T c = Consts<T>::r2;
+  plus = mk<T>(ffma(c, p, e.x), ffma(c, q, e.y));
+  minus = mk<T>(ffma(-c, p, e.x), ffma(-c, q, e.y));
+}
+
 // in-place 8-point DFT of a[0..7]
 template <bool INV, typename T> __device__ __forceinline__ void dft8(cplx<T> *a) {
   cplx<T> e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
   cplx<T> o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
   dft4<INV, T>(e0, e1, e2, e3);
   dft4<INV, T>(o0, o1, o2, o3);
-  o1 = mul_w8<INV, T>(o1);
   o2 = mul_w4<INV, T>(o2);
-  o3 = mul_w83<INV, T>(o3);
   a[0] = cadd<T>(e0, o0);
   a[4] = csub<T>(e0, o0);
-  a[1] = cadd<T>(e1, o1);
-  a[5] = csub<T>(e1, o1);
   a[2] = cadd<T>(e2, o2);
   a[6] = csub<T>(e2, o2);
-  a[3] = cadd<T>(e3, o3);
-  a[7] = csub<T>(e3, o3);
+  // w8 o1 = c (x + y, y - x) forward, c (x - y, x + y) inverse;
+  // w8^3 o3 = c (y - x, -x - y) forward, c (-x - y, x - y) inverse
+  if (INV) {
+    bfly_c<T>(e1, o1.x - o1.y, o1.x + o1.y, a[1], a[5]);
+    bfly_c<T>(e3, -o3.x - o3.y, o3.x - o3.y, a[3], a[7]);
+  } else {
+    bfly_c<T>(e1, o1.x + o1.y, o1.y - o1.x, a[1], a[5]);
+    bfly_c<T>(e3, o3.y - o3.x, -o3.x - o3.y, a[3], a[7]);
+  }
 }
 
 template <bool INV, typename T>
@@ -243,5 +244,81 @@ template <typename T, int N, bool INV> struct FFT {
     if (used_lds) group_sync<TPF>();
   }
 };
+
+// Two independent transforms of the same length run interleaved by one FFT group: `a` in
+// direction INVA and `b` in direction INVB, each with its own exchange buffer, sharing the
+// register twiddles and the barriers of every exchange.  Each transform does exactly the
+// arithmetic of FFT::run_tw (same results bit for bit); the interleaving gives the scheduler a
+// second chain of work while the other waits on LDS.  Wave-level transforms only (N <= 512).
+template <typename T, int N, bool INVA, bool INVB>
+__device__ __forceinline__ void fft_dual(cplx<T> (&a)[8], cplx<T> (&b)[8], int j, cplx<T> *bufA, cplx<T> *bufB,
+                                         const typename FFT<T, N, false>::Tw &t) {
+  using F = FFT<T, N, false>;
+  static_assert(F::WAVE, "fft_dual: wave-level transforms only");
+  constexpr int TPF = F::TPF, L8 = F::L8, REM = F::REM;
+  auto mulA = [](cplx<T> v, cplx<T> w) { return INVA ? cmulc<T>(v, w) : cmul<T>(v, w); };
+  auto mulB = [](cplx<T> v, cplx<T> w) { return INVB ? cmulc<T>(v, w) : cmul<T>(v, w); };
+  int Ns = 1, q = 0;
+  bool used_lds = false;
+#pragma unroll
+  for (int st = 0; st < L8; ++st) {
+    const bool last = (st == L8 - 1) && REM == 1;
+    const int k = j % Ns;
+    if (st > 0) {
+#pragma unroll
+      for (int u = 1; u < 8; ++u) {
+        a[u] = mulA(a[u], t.w[q]);
+        b[u] = mulB(b[u], t.w[q]);
+        ++q;
+      }
+    }
+    dft8<INVA, T>(a);
+    dft8<INVB, T>(b);
+    if (!last) {
+      const int base = (j / Ns) * Ns * 8 + k;
+      group_sync<TPF>();
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        bufA[pad8(base + s * Ns)] = a[s];
+        bufB[pad8(base + s * Ns)] = b[s];
+      }
+      group_sync<TPF>();
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        a[u] = bufA[pad8(j + u * TPF)];
+        b[u] = bufB[pad8(j + u * TPF)];
+      }
+      used_lds = true;
+    }
+    Ns *= 8;
+  }
+  if (REM == 4) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (Ns > 1) {
+#pragma unroll
+        for (int u = 1; u < 4; ++u) {
+          a[c + 2 * u] = mulA(a[c + 2 * u], t.w[q]);
+          b[c + 2 * u] = mulB(b[c + 2 * u], t.w[q]);
+          ++q;
+        }
+      }
+      dft4<INVA, T>(a[c], a[c + 2], a[c + 4], a[c + 6]);
+      dft4<INVB, T>(b[c], b[c + 2], b[c + 4], b[c + 6]);
+    }
+  } else if (REM == 2) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (Ns > 1) {
+        a[c + 4] = mulA(a[c + 4], t.w[q]);
+        b[c + 4] = mulB(b[c + 4], t.w[q]);
+        ++q;
+      }
+      dft2<INVA, T>(a[c], a[c + 4]);
+      dft2<INVB, T>(b[c], b[c + 4]);
+    }
+  }
+  if (used_lds) group_sync<TPF>();
+}
 
 }  // namespace ff

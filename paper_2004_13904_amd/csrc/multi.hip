@@ -29,6 +29,7 @@ template <int NY> struct MultiCol {
   using CC = ColCfg<float, NY>;
   static_assert(CC::THREADS * CC::WPB == kMultiThreads, "grouped column blocks have 512 threads");
   static constexpr int SH = CC::WPB * CC::CPB * FFT<float, NY, false>::LDS;
+  static constexpr int SHP = SH > PairCfg<float, NY>::SH ? SH : PairCfg<float, NY>::SH;
 };
 
 constexpr int max3(int a, int b, int c) { return a > b ? (a > c ? a : c) : (b > c ? b : c); }
@@ -37,6 +38,10 @@ constexpr int kRowSH = max3(max3(MultiRow<8>::C::SH, MultiRow<16>::C::SH, MultiR
                             MultiRow<512>::C::SH);
 constexpr int kColSH = max3(max3(MultiCol<8>::SH, MultiCol<16>::SH, MultiCol<32>::SH),
                             max3(MultiCol<64>::SH, MultiCol<128>::SH, MultiCol<256>::SH), MultiCol<512>::SH);
+// the pair's column pass keeps two exchange buffers per wave group (about 104 KB at 512 points),
+// so its launches hold one block per CU; plans without pair tasks keep the smaller blocks
+constexpr int kColPairSH = max3(max3(MultiCol<8>::SHP, MultiCol<16>::SHP, MultiCol<32>::SHP),
+                                max3(MultiCol<64>::SHP, MultiCol<128>::SHP, MultiCol<256>::SHP), MultiCol<512>::SHP);
 
 // Row transforms of one product of one survey (pass 1), arguments as k_row_r2c's.
 struct R2CTask {
@@ -63,14 +68,17 @@ struct C2RTask {
   const float2 *tw;
 };
 
-// Column pass (pass 2) of G (op 0) or G^T (op 1), arguments as k_col_G's / k_col_GT's; the
-// task's blocks are nbx column blocks times LG layer groups.
+// Column pass (pass 2) of G (op 0), of G^T (op 1), or of both products of one survey with one
+// read of the spectra (op 2, col_pair_body), arguments as k_col_G's / k_col_GT's; the task's
+// blocks are nbx column blocks times LG layer groups.
 struct ColTask {
   int block0, NY, op, nbx;
-  const float2 *src;       // G: X1; G^T: D1
-  float2 *dst;             // G: partial sums; G^T: X1
+  const float2 *src;       // G and the pair: X1; G^T: D1
+  float2 *dst;             // G and the pair: partial sums; G^T: X1
   int ny, ldy, nz, HC, LG, sy, lds, pyl;
   const float2 *spec, *tw;
+  const float2 *src2;      // the pair: G^T's D1
+  float2 *dst2;            // the pair: G^T's X1
 };
 
 template <class Task> __device__ __forceinline__ int find_task(const Task *__restrict__ t, int nt) {
@@ -89,9 +97,12 @@ template <int N> __device__ __forceinline__ void c2r_task(float2 *sh, int lb, co
                                                  t.out, t.oi, nullptr, Idx3{0, 0, 0}, t.len, t.off, t.tw);
 }
 
-template <int NY> __device__ __forceinline__ void col_task(float2 *sh, int lb, const ColTask &t) {
+template <int NY, bool PAIR> __device__ __forceinline__ void col_task(float2 *sh, int lb, const ColTask &t) {
   const int bx = lb % t.nbx, by = lb / t.nbx;
-  if (t.op == 0)
+  if (PAIR && t.op == 2)
+    col_pair_body<float, NY>(sh, bx, by, t.src, t.ny, t.ldy, t.dst, t.src2, t.dst2, t.sy, t.lds, t.pyl, t.nz, t.HC,
+                             t.LG, t.spec, t.tw);
+  else if (t.op == 0)
     col_G_body<float, NY>(sh, bx, by, 0, t.src, t.ny, t.ldy, t.nz, t.HC, t.LG, t.spec, t.dst, t.sy, t.lds, t.pyl,
                           t.tw);
   else
@@ -124,7 +135,16 @@ __global__ void __launch_bounds__(kMultiThreads) k_multi_col(const ColTask *__re
   __shared__ float2 sh[kColSH];
   const ColTask &t = tasks[find_task(tasks, nt)];
   const int lb = (int)blockIdx.x - t.block0;
-#define FF_COL(NN) col_task<NN>(sh, lb, t)
+#define FF_COL(NN) col_task<NN, false>(sh, lb, t)
+  FF_MULTI_SWITCH(t.NY, FF_COL)
+#undef FF_COL
+}
+
+__global__ void __launch_bounds__(kMultiThreads) k_multi_col_pair(const ColTask *__restrict__ tasks, int nt) {
+  __shared__ float2 sh[kColPairSH];
+  const ColTask &t = tasks[find_task(tasks, nt)];
+  const int lb = (int)blockIdx.x - t.block0;
+#define FF_COL(NN) col_task<NN, true>(sh, lb, t)
   FF_MULTI_SWITCH(t.NY, FF_COL)
 #undef FF_COL
 }
@@ -153,12 +173,21 @@ struct ff_multi_s {
   int device = 0;
   int n_r2c = 0, n_col = 0, n_c2r = 0;          // tasks per launch
   int b_r2c = 0, b_col = 0, b_c2r = 0;          // blocks per launch
+  bool col_pair = false;                        // the column launch holds a pair task
   R2CTask *r2c = nullptr;
   ColTask *col = nullptr;
   C2RTask *c2r = nullptr;
 };
 
 namespace {
+
+void launch_col(ff_multi p, hipStream_t s) {
+  if (!p->n_col) return;
+  if (p->col_pair)
+    k_multi_col_pair<<<p->b_col, kMultiThreads, 0, s>>>(p->col, p->n_col);
+  else
+    k_multi_col<<<p->b_col, kMultiThreads, 0, s>>>(p->col, p->n_col);
+}
 
 void free_plan(ff_multi p) {
   if (!p) return;
@@ -192,6 +221,7 @@ ff_status ff_multi_create(int32_t count, const ff_spectra *handles, const void *
   std::vector<ColTask> col;
   std::vector<C2RTask> c2r;
   int b_r2c = 0, b_col = 0, b_c2r = 0;
+  bool any_pair = false;
   for (int i = 0; i < count; ++i) {
     const ff_spectra h = handles[i];
     if (!h) return fail(FF_EINVAL, "ff_multi_create: NULL handle");
@@ -217,14 +247,28 @@ ff_status ff_multi_create(int32_t count, const ff_spectra *handles, const void *
     const float2 *twx = (const float2 *)h->tw_x, *twy = (const float2 *)h->tw_y;
     const float2 *spec = (const float2 *)h->spec;
     const int rpb = rows_per_block(h->NX), nbx = col_blocks_x(h->NY, HC);
+    // a pair task halves the column blocks of the two products and holds one block per CU: it is
+    // used for a single survey whose pair alone fills the chip
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+    const bool pair = doG && doT && h->pair_fused && count == 1 && nbx * h->lg_G >= cus;
+    any_pair = any_pair || pair;
+    if (pair) {
+      // one column task for both products: each spectrum column is read once
+      ColTask c{b_col, h->NY, 2, nbx, X1, C2, ny, ldy, nz, HC, h->lg_G, sy, lds, h->pyl, spec, twy, C2t, X1t};
+      col.push_back(c);
+      b_col += nbx * h->lg_G;
+    }
     if (doG) {
       R2CTask a{b_r2c, h->NX, (const float *)x[i], Idx3{0, lay, nx}, ny, nz, nx, 0, X1, Idx3{0, (int64_t)HC * ldy, 1},
                 ldy, twx};
       r2c.push_back(a);
       b_r2c += (ny * nz + rpb - 1) / rpb;
-      ColTask c{b_col, h->NY, 0, nbx, X1, C2, ny, ldy, nz, HC, h->lg_G, sy, lds, h->pyl, spec, twy};
-      col.push_back(c);
-      b_col += nbx * h->lg_G;
+      if (!pair) {
+        ColTask c{b_col, h->NY, 0, nbx, X1, C2, ny, ldy, nz, HC, h->lg_G, sy, lds, h->pyl, spec, twy, nullptr, nullptr};
+        col.push_back(c);
+        b_col += nbx * h->lg_G;
+      }
       C2RTask e{b_c2r, h->NX, C2, Idx3{0, 0, 1}, lds, (int64_t)HC * lds, h->lg_G, sy, 1, (float *)gx[i],
                 Idx3{0, 0, sx}, sx, h->pxl, twx};
       c2r.push_back(e);
@@ -234,9 +278,12 @@ ff_status ff_multi_create(int32_t count, const ff_spectra *handles, const void *
       R2CTask a{b_r2c, h->NX, (const float *)d[i], Idx3{0, 0, sx}, sy, 1, sx, h->pxl, C2t, Idx3{0, 0, 1}, lds, twx};
       r2c.push_back(a);
       b_r2c += (sy + rpb - 1) / rpb;
-      ColTask c{b_col, h->NY, 1, nbx, C2t, X1t, ny, ldy, nz, HC, h->lg_GT, sy, lds, h->pyl, spec, twy};
-      col.push_back(c);
-      b_col += nbx * h->lg_GT;
+      if (!pair) {
+        ColTask c{b_col, h->NY, 1, nbx, C2t, X1t, ny, ldy, nz, HC, h->lg_GT, sy, lds, h->pyl, spec, twy, nullptr,
+                  nullptr};
+        col.push_back(c);
+        b_col += nbx * h->lg_GT;
+      }
       C2RTask e{b_c2r, h->NX, X1t, Idx3{0, (int64_t)HC * ldy, 1}, ldy, 0, 1, ny, nz, (float *)gtd[i],
                 Idx3{0, lay, nx}, nx, 0, twx};
       c2r.push_back(e);
@@ -252,6 +299,7 @@ ff_status ff_multi_create(int32_t count, const ff_spectra *handles, const void *
   p->b_r2c = b_r2c;
   p->b_col = b_col;
   p->b_c2r = b_c2r;
+  p->col_pair = any_pair;
   ff_status st = upload(r2c, &p->r2c);
   if (st == FF_OK) st = upload(col, &p->col);
   if (st == FF_OK) st = upload(c2r, &p->c2r);
@@ -271,10 +319,26 @@ ff_status ff_multi_apply(ff_multi p, ff_stream stream) {
   hipStream_t s = (hipStream_t)stream;
   if (p->n_r2c) k_multi_r2c<<<p->b_r2c, kMultiThreads, 0, s>>>(p->r2c, p->n_r2c);
   FF_LAUNCH_CHECK("grouped row transforms");
-  if (p->n_col) k_multi_col<<<p->b_col, kMultiThreads, 0, s>>>(p->col, p->n_col);
+  launch_col(p, s);
   FF_LAUNCH_CHECK("grouped column passes");
   if (p->n_c2r) k_multi_c2r<<<p->b_c2r, kMultiThreads, 0, s>>>(p->c2r, p->n_c2r);
   FF_LAUNCH_CHECK("grouped inverse row transforms");
+  return FF_OK;
+}
+
+ff_status ff_multi_time_pass(ff_multi p, int32_t pass, int32_t reps, ff_stream stream) {
+  if (!p) return fail(FF_EINVAL, "ff_multi_time_pass: NULL plan");
+  if (pass < 0 || pass > 2 || reps < 0) return fail(FF_EINVAL, "ff_multi_time_pass: pass in {0,1,2}, reps >= 0");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+    return fail(FF_EDEVICE, "ff_multi_time_pass: plan built on another device");
+  hipStream_t s = (hipStream_t)stream;
+  for (int r = 0; r < reps; ++r) {
+    if (pass == 0 && p->n_r2c) k_multi_r2c<<<p->b_r2c, kMultiThreads, 0, s>>>(p->r2c, p->n_r2c);
+    if (pass == 1) launch_col(p, s);
+    if (pass == 2 && p->n_c2r) k_multi_c2r<<<p->b_c2r, kMultiThreads, 0, s>>>(p->c2r, p->n_c2r);
+  }
+  FF_LAUNCH_CHECK("ff_multi_time_pass");
   return FF_OK;
 }
 

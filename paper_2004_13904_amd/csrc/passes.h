@@ -553,6 +553,198 @@ k_col_GT(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz, int H
   col_GT_body<T, NY>(sh, blockIdx.x, blockIdx.y, blockIdx.z, D1, sy, ldd, pyl, nz, HC, LG, spec, X1, ny, ldy, tw);
 }
 
+// Pass 2 of an independent pair G x, G^T d of one survey, in one launch: per column slot the
+// work of col_G_body and of col_GT_body, with each layer spectrum column read once for both
+// products.  Wave group w takes the layers L_i = r0 + w + i WPB of layer group `by` for both
+// products and runs its transforms two at a time (fft_dual), as a short software pipeline:
+//   step 0:          FFT_y(x_{L_0})  with  FFT_y(D)            (D: the data column of G^T)
+//   step i >= 1:     FFT_y(x_{L_i})  with  IFFT_y(conj(S_{L_{i-1}}) .* FFT_y(D))
+//   last:            IFFT_y of the last layer's G^T product, with (wave group 0) the inverse of
+//                    the G layer sum after the wave groups' sums are added up.
+// Each transform, product and sum is the one col_G_body / col_GT_body computes, in the same
+// order, so both results are bit for bit those of the separate passes.
+// LDS: per wave group two exchange buffers per column and a copy of FFT_y(D) (packed slot).
+// NY <= 512 (wave-level transforms).  Grid: (ceil(HC/CPB), LG).
+template <typename T, int NY> struct PairCfg {
+  using CC = ColCfg<T, NY>;
+  static constexpr int LDSF = FFT<T, NY, false>::LDS;
+  static constexpr int PER_W = CC::CPB * (2 * LDSF + NY);   // complex elements per wave group
+  static constexpr int SH = CC::WPB * PER_W;
+};
+
+template <typename T, int NY>
+__device__ __forceinline__ void
+col_pair_body(cplx<T> *__restrict__ sh, int bx, int by, const cplx<T> *__restrict__ X1, int ny, int ldy,
+              cplx<T> *__restrict__ outp, const cplx<T> *__restrict__ D1, cplx<T> *__restrict__ X1t, int sy,
+              int lds, int pyl, int nz, int HC, int LG, const cplx<T> *__restrict__ spec,
+              const cplx<T> *__restrict__ tw) {
+  using CC = ColCfg<T, NY>;
+  using PC = PairCfg<T, NY>;
+  using Ff = FFT<T, NY, false>;
+  using Fi = FFT<T, NY, true>;
+  constexpr int TPF = CC::TPF, WPB = CC::WPB, LDSF = PC::LDSF;
+  static_assert(TPF <= 64, "pair column pass: wave-level transforms only");
+  const int w = threadIdx.x / CC::THREADS, lt = threadIdx.x % CC::THREADS;
+  const int f = lt / TPF, j = lt % TPF;
+  const int kx = bx * CC::CPB + f;
+  const bool ok = kx < HC;
+  const int kxs = ok ? kx : 0;
+  const bool pk = bx == 0;            // block-uniform: slot 0 sits at f == 0 of block 0
+  const bool pk0 = pk && f == 0;
+  const int64_t SH = HC + 1;
+  const int g = by;
+  const int r0 = (int)((int64_t)g * nz / LG), r1 = (int)((int64_t)(g + 1) * nz / LG);
+  const int nl = r0 + w < r1 ? (r1 - r0 - w + WPB - 1) / WPB : 0;   // this wave group's layers
+  cplx<T> *wbase = sh + w * PC::PER_W;
+  cplx<T> *bufA = wbase + f * LDSF;                        // exchange buffers of this column
+  cplx<T> *bufB = wbase + (CC::CPB + f) * LDSF;
+  cplx<T> *dcopy = wbase + 2 * CC::CPB * LDSF + f * NY;     // FFT_y(D) of this column (packed slot)
+  typename Ff::Tw twr;
+  Ff::load_tw(twr, j, tw);
+  const typename Fi::Tw &twi = *reinterpret_cast<const typename Fi::Tw *>(&twr);
+  cplx<T> acc[8], accm[8], dh[8], xn[8], sn[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    acc[u] = mk<T>(0, 0);
+    accm[u] = mk<T>(0, 0);
+  }
+  auto layer = [&](int i) { return r0 + w + i * WPB; };
+  auto load = [&](int rr) {
+    const cplx<T> *src = X1 + ((int64_t)rr * HC + kxs) * (int64_t)ldy;
+    const cplx<T> *sp = spec + ((int64_t)rr * SH + kxs) * NY;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int y = j + u * TPF;
+      xn[u] = (ok && y < ny) ? src[y] : mk<T>(0, 0);
+      sn[u] = sp[y];
+    }
+  };
+  // M_r (packed slot only), read where it is used
+  auto mrow = [&](int rr, int u) { return spec[((int64_t)rr * SH + HC) * NY + j + u * TPF]; };
+  // G: add S_r .* X and (packed slot) M_r .* X to the layer sums
+  auto gsum = [&](const cplx<T> (&a)[8], const cplx<T> (&sc)[8], int rr) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = cadd<T>(acc[u], cmul<T>(a[u], sc[u]));
+    if (pk) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) accm[u] = cadd<T>(accm[u], cmul<T>(a[u], mrow(rr, u)));
+    }
+  };
+  // G^T: conj(S_r) .* D (+ conj(M_r) .* conj(D[-k]) in the packed slot)
+  auto gtprod = [&](cplx<T> (&b)[8], const cplx<T> (&sc)[8], int rr) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) b[u] = cmulc<T>(dh[u], sc[u]);
+    if (pk0) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const cplx<T> dr = cconj<T>(dcopy[(NY - j - u * TPF) & (NY - 1)]);
+        b[u] = cadd<T>(b[u], cmulc<T>(dr, mrow(rr, u)));
+      }
+    }
+  };
+  auto gtstore = [&](const cplx<T> (&b)[8], int rr) {
+    if (ok) {
+      cplx<T> *dst = X1t + ((int64_t)rr * HC + kx) * (int64_t)ldy;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int y = j + u * TPF;
+        if (y < ny) dst[y] = b[u];
+      }
+    }
+  };
+  if (nl > 0) load(layer(0));
+  {
+    const cplx<T> *src = D1 + (int64_t)kxs * lds;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int y = j + u * TPF - pyl;
+      dh[u] = (ok && y >= 0 && y < sy) ? src[y] : mk<T>(0, 0);
+    }
+  }
+  cplx<T> sc[8];   // spectrum column of the layer whose G^T product comes next
+  if (nl > 0) {
+    cplx<T> a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a[u] = xn[u];
+      sc[u] = sn[u];
+    }
+    if (nl > 1) load(layer(1));
+    fft_dual<T, NY, false, false>(a, dh, j, bufA, bufB, twr);
+    gsum(a, sc, layer(0));
+  } else {
+    Ff::run_tw(dh, j, bufB, twr);
+  }
+  if (pk) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) dcopy[j + u * TPF] = dh[u];
+    group_sync<TPF>();
+  }
+  for (int i = 1; i < nl; ++i) {
+    cplx<T> a[8], b[8];
+    gtprod(b, sc, layer(i - 1));
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a[u] = xn[u];
+      sc[u] = sn[u];
+    }
+    if (i + 1 < nl) load(layer(i + 1));
+    fft_dual<T, NY, false, true>(a, b, j, bufA, bufB, twr);
+    gsum(a, sc, layer(i));
+    gtstore(b, layer(i - 1));
+  }
+  if (pk) {
+    // each wave group folds its own M sum into its G sum: acc[k] += conj(accm[-k]) (slot 0)
+    group_sync<TPF>();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) bufA[pad8(j + u * TPF)] = accm[u];
+    group_sync<TPF>();
+    if (f == 0) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = cadd<T>(acc[u], cconj<T>(bufA[pad8((NY - j - u * TPF) & (NY - 1))]));
+    }
+  }
+  if constexpr (WPB > 1) {
+    // the wave groups' G sums meet in LDS (buffer A of each), added in wave-group order
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) bufA[j + u * TPF] = acc[u];
+    __syncthreads();
+    for (int u = w; u < 8; u += WPB) {
+      const int e = f * LDSF + j + u * TPF;
+      cplx<T> t = sh[e];
+      for (int w2 = 1; w2 < WPB; ++w2) t = cadd<T>(t, sh[w2 * PC::PER_W + e]);
+      sh[e] = t;
+    }
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = bufA[j + u * TPF];
+    }
+    group_sync<TPF>();
+  }
+  // the last G^T layer, and (wave group 0) the inverse of the G sum
+  cplx<T> b[8];
+  if (nl > 0) gtprod(b, sc, layer(nl - 1));
+  if (w == 0 && nl > 0) {
+    fft_dual<T, NY, true, true>(acc, b, j, bufA, bufB, twr);
+    gtstore(b, layer(nl - 1));
+  } else if (w == 0) {
+    Fi::run_tw(acc, j, bufA, twi);
+  } else if (nl > 0) {
+    Fi::run_tw(b, j, bufB, twi);
+    gtstore(b, layer(nl - 1));
+  }
+  if (w == 0 && ok) {
+    cplx<T> *dst = outp + ((int64_t)g * HC + kx) * (int64_t)lds;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int y = j + u * TPF - pyl;
+      if (y >= 0 && y < sy) dst[y] = acc[u];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------------------
 // Batched column passes (single precision, NY <= 512): V = 4 vectors per block.  The block's
 // WPB wave groups form GL = WPB/2 layer groups times 2 vector pairs: wave group w takes the

@@ -15,6 +15,19 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def agree(a, b, tol):
+    """Parity bar of an operator result a against the oracle's b: relative l2 error and the worst
+    element, relative to the largest reference element, both within tol (an error confined to a
+    few entries, such as a crop edge or a ragged tail, fails the second)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    assert np.isfinite(a).all()
+    e = rel(a, b)
+    m = float(np.abs(a - b).max() / np.abs(b).max())
+    assert e <= tol and m <= tol, (e, m, tol)
+    return e, m
+
+
 def same(a, b):
     """Batched against single-vector results: bit-identical in FP64 (same kernels); in FP32 the
     batched column passes add the layer terms in another order, so agreement is to rounding

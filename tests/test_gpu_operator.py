@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_common import announce, ogeom, otable, rel, same, to_dev, to_host
+from gpu_common import agree, announce, ogeom, otable, rel, same, to_dev, to_host
 from oracle import geometry, operator as op
 from paper_2004_13904_amd import workloads as W
 from paper_2004_13904_amd import _lib as L
@@ -50,8 +50,8 @@ def test_small_against_dense_G(name, dtype):
     A = Operator(s, dtype)
     dG = to_host(A.G(to_dev(x, dtype)))
     xT = to_host(A.GT(to_dev(d, dtype)))
-    assert rel(dG, G @ x) <= TOL[dtype]
-    assert rel(xT, G.T @ d) <= TOL[dtype]
+    agree(dG, G @ x, TOL[dtype])
+    agree(xT, G.T @ d, TOL[dtype])
     A.close()
 
 
@@ -87,7 +87,7 @@ def test_embedding_size_invariance(nfft):
     assert A.nfft == nfft and B.nfft == (32, 32)
     a = to_host(A.G(to_dev(x, F64)))
     b = to_host(B.G(to_dev(x, F64)))
-    assert rel(a, b) <= 1e-13
+    agree(a, b, 1e-13)
 
 
 @pytest.mark.parametrize("nfft", [(1024, 32), (32, 1024), (2048, 32), (32, 2048)])
@@ -106,13 +106,13 @@ def test_large_embeddings_against_dense_G(nfft, name, dtype):
     D = rng.standard_normal((3, g.m))
     A = Operator(s, dtype, nfft=nfft)
     assert A.nfft == nfft
-    assert rel(to_host(A.G(to_dev(X[0], dtype))), G @ X[0]) <= TOL[dtype]
-    assert rel(to_host(A.GT(to_dev(D[0], dtype))), G.T @ D[0]) <= TOL[dtype]
+    agree(to_host(A.G(to_dev(X[0], dtype))), G @ X[0], TOL[dtype])
+    agree(to_host(A.GT(to_dev(D[0], dtype))), G.T @ D[0], TOL[dtype])
     Y = to_host(A.G_block(to_dev(X, dtype)))
     Z = to_host(A.G_block(to_dev(D, dtype), transpose=True))
     for i in range(3):
-        assert rel(Y[i], G @ X[i]) <= TOL[dtype]
-        assert rel(Z[i], G.T @ D[i]) <= TOL[dtype]
+        agree(Y[i], G @ X[i], TOL[dtype])
+        agree(Z[i], G.T @ D[i], TOL[dtype])
     A.close()
 
 
@@ -135,8 +135,8 @@ def test_full_size_fp32_against_direct_sums(name):
     xT = to_host(A.GT(to_dev(d, F32)))
     ref_d = op.apply_G(g, x, T)
     ref_x = op.apply_GT(g, d, T)
-    assert rel(dG, ref_d) <= 1e-5
-    assert rel(xT, ref_x) <= 1e-5
+    agree(dG, ref_d, 1e-5)
+    agree(xT, ref_x, 1e-5)
     # the embedding size, the spectra and both FFT directions are exercised by the adjoint
     assert abs(dG @ d - x @ xT) <= 1e-5 * np.linalg.norm(dG) * np.linalg.norm(d)
 
@@ -151,9 +151,9 @@ def test_weighted_operator(dtype):
     wn, wm = 0.5 + rng.random(g.n), 0.5 + rng.random(g.m)
     A = Operator(s, dtype)
     out = to_host(A.G(to_dev(x, dtype), w_pre=to_dev(wn, dtype), w_post=to_dev(wm, dtype)))
-    assert rel(out, wm * (G @ (wn * x))) <= TOL[dtype]
+    agree(out, wm * (G @ (wn * x)), TOL[dtype])
     out = to_host(A.GT(to_dev(d, dtype), w_pre=to_dev(wm, dtype), w_post=to_dev(wn, dtype)))
-    assert rel(out, wn * (G.T @ (wm * d))) <= TOL[dtype]
+    agree(out, wn * (G.T @ (wm * d)), TOL[dtype])
 
 
 @pytest.mark.parametrize("dtype", [F64, F32])
@@ -173,8 +173,8 @@ def test_block_apply_equals_vector_loop(dtype, k):
         # column passes, whose layer sums are taken in another order
         same(GX[c], A.G(to_dev(X[c], dtype)))
         same(GTY[c], A.GT(to_dev(Y[c], dtype)))
-    assert rel(to_host(GX), X @ G.T) <= TOL[dtype]
-    assert rel(to_host(GTY), Y @ G) <= TOL[dtype]
+    agree(to_host(GX), X @ G.T, TOL[dtype])
+    agree(to_host(GTY), Y @ G, TOL[dtype])
 
 
 @pytest.mark.parametrize("k", [2, 6])
@@ -208,8 +208,8 @@ def test_rsvd_block_product_full_size_sampled_columns():
     Y = A.G_block(X)
     Z = A.G_block(D, transpose=True)
     for c in (0, 1877, k - 1):
-        assert rel(to_host(Y[c]), op.apply_G(g, to_host(X[c]), T)) <= 1e-5
-        assert rel(to_host(Z[c]), op.apply_GT(g, to_host(D[c]), T)) <= 1e-5
+        agree(to_host(Y[c]), op.apply_G(g, to_host(X[c]), T), 1e-5)
+        agree(to_host(Z[c]), op.apply_GT(g, to_host(D[c]), T), 1e-5)
     del X, D, Y, Z
     A.close()
     torch.cuda.empty_cache()
@@ -239,11 +239,11 @@ def test_zero_and_impulse_inputs():
     for st in (0, g.m - 1, 13):
         e = np.zeros(g.m)
         e[st] = 1.0
-        assert rel(to_host(A.GT(to_dev(e, F64))), G[st]) <= 1e-12
+        agree(to_host(A.GT(to_dev(e, F64))), G[st], 1e-12)
     for c in (0, g.n - 1, 77):
         e = np.zeros(g.n)
         e[c] = 1.0
-        assert rel(to_host(A.G(to_dev(e, F64))), G[:, c]) <= 1e-12
+        agree(to_host(A.G(to_dev(e, F64))), G[:, c], 1e-12)
 
 
 def test_deterministic_repeats():
@@ -299,8 +299,8 @@ def _full_size_check(s, seed):
     x = rng.random(g.n)
     d = rng.standard_normal(g.m)
     A = Operator(s, F32)
-    assert rel(to_host(A.G(to_dev(x, F32))), op.apply_G(g, x, T)) <= 1e-5
-    assert rel(to_host(A.GT(to_dev(d, F32))), op.apply_GT(g, d, T)) <= 1e-5
+    agree(to_host(A.G(to_dev(x, F32))), op.apply_G(g, x, T), 1e-5)
+    agree(to_host(A.GT(to_dev(d, F32))), op.apply_GT(g, d, T), 1e-5)
 
 
 @pytest.mark.parametrize("nz", [20, 239])

@@ -1,5 +1,6 @@
 """Parity of the HIP projected solvers and IRLS step with the oracle's Algorithms 1 and 2."""
 import math
+import time
 
 import numpy as np
 import pytest
@@ -387,3 +388,101 @@ def test_irls_step_rejects_non_finite_inputs(where):
     wd[3] = 1.0
     m0[3] = 0.0
     S.irls_step(A, p, 1, d, wd, m0)      # the same call with finite inputs succeeds
+
+
+# ---- the n = 1e6 magnetic inversion (t = m/20 = 2500, t_p = 2625) -----------------------------
+
+@pytest.fixture(scope="module")
+def c2_problem():
+    """The first IRLS step's weighted problem on the n = 1e6 magnetic survey: the cube + dike
+    model, 2 % noise (tau1 = 0.02, tau2 = 0.002, seed 2), depth weighting beta = 1.4, W_L = I,
+    r~ = W_d d_obs; products with G~ by the oracle's direct sums.  Also the largest singular
+    value of G~ by Lanczos iteration on G~^T G~ over those products."""
+    from scipy.sparse.linalg import LinearOperator, eigsh
+    s = W.SURVEYS["magnetic_1m"]
+    g = ogeom(s)
+    T = op.kernel_table(g)
+    m_true = W.block_model(s, W.MAGNETIC_1M_BLOCKS)
+    d_exact = op.apply_G(g, m_true, T)
+    eta, sd = W.noise(d_exact, 0.02, 0.002, 2)
+    d_obs = d_exact + eta
+    wd = 1.0 / sd
+    winv = 1.0 / oirls.depth_weights(g, 1.4)
+    r = wd * d_obs
+    count = [0]
+    t0 = time.perf_counter()
+
+    def tick(what):
+        # progress of the long host products (each about a second on many cores)
+        count[0] += 1
+        print(f"[c2 oracle] product {count[0]} ({what}) at {time.perf_counter() - t0:.1f} s", flush=True)
+
+    def Gt(v):
+        tick("G")
+        return wd * op.apply_G(g, winv * v, T)
+
+    def GtT(y):
+        tick("G^T")
+        return winv * op.apply_GT(g, wd * y, T)
+    v0 = GtT(r)
+    lo = LinearOperator((g.n, g.n), matvec=lambda v: GtT(Gt(np.asarray(v).ravel())), dtype=np.float64)
+    lam = eigsh(lo, k=1, which="LA", v0=v0, tol=1e-10, ncv=12, maxiter=40, return_eigenvectors=False)
+    return dict(s=s, g=g, T=T, d_obs=d_obs, wd=wd, winv=winv, r=r, Gt=Gt, GtT=GtT,
+                sigma1=float(math.sqrt(lam[0])))
+
+
+@pytest.mark.parametrize("basis", ["f64", "f32"])
+def test_gkb_c2_full_size_properties(c2_problem, basis):
+    # GKB at the metric's IRLS size (n = 1e6, t = 2500, t_p = 2625, FP32 operator; the n x t_p basis
+    # in FP64, 21 GB, or FP32): eq. (eq:alpha1) on the returned spectrum, sigma_1 against the
+    # oracle's Lanczos value, and the Galerkin conditions of the projected Tikhonov solution at a
+    # fixed alpha, with the oracle's direct sums (size-dependent indexing of the 2.6e9-element
+    # bases runs here)
+    P = c2_problem
+    g = P["g"]
+    announce("gkb c2", basis, 2500, 2625)
+    A = Operator(P["s"], F32)
+    t, tp = 2500, 2625
+    args = (to_dev(P["r"], F64), to_dev(P["wd"], F64), to_dev(P["winv"], F64), t, tp)
+    _, a1, sig = S.gkb_project(A, *args, alpha_mode="alpha1", basis=basis)
+    sig = to_host(sig)
+    assert np.all(np.diff(sig) <= 0) and sig[-1] > 0
+    assert abs(a1 - osol.alpha_one(g.n, g.m, sig)) <= 1e-12 * a1
+    assert abs(sig[0] - P["sigma1"]) <= 1e-5 * P["sigma1"], (sig[0], P["sigma1"])
+    alpha = float(sig[t // 2])
+    y, a, _ = S.gkb_project(A, *args, alpha_mode="fixed", alpha=alpha, basis=basis)
+    assert a == alpha
+    y = to_host(y)
+    assert np.isfinite(y).all()
+    assert galerkin_defects(P["Gt"], P["GtT"], P["r"], y, alpha, powers=2).max() <= 2e-5
+    A.close()
+    torch.cuda.empty_cache()
+
+
+def test_irls_step_c2(c2_problem):
+    # one IRLS step (k = 1, lambda = 1, GKB t = 2500, t_p = 2625, FP32 basis, alpha of
+    # eq. (eq:alpha1)) at n = 1e6: the step equals clip(W^{-1} y) for the projected solve of the same
+    # r~ (gkb_project), its scaled chi^2 equals eq. (scaledchi2) evaluated by the oracle on the
+    # returned model, and the bounds hold
+    P = c2_problem
+    g = P["g"]
+    announce("irls c2", 2500, 2625)
+    A = Operator(P["s"], F32)
+    p = S.IrlsParams(solver="gkb", t=2500, tp=2625, lam=1.0, eps2=1e-9, beta_depth=1.4, m_min=0.0,
+                     m_max=0.1, basis="f32")
+    d_obs = to_dev(P["d_obs"], F64)
+    wd = to_dev(P["wd"], F64)
+    m0 = torch.zeros(g.n, dtype=F64, device="cuda")
+    m1, alpha, chi2 = S.irls_step(A, p, 1, d_obs, wd, m0)
+    m1 = to_host(m1)
+    assert np.isfinite(m1).all() and m1.min() >= 0.0 and m1.max() <= 0.1
+    y, a1, _ = S.gkb_project(A, to_dev(P["r"], F64), wd, to_dev(P["winv"], F64), 2500, 2625,
+                             alpha_mode="alpha1", basis="f32")
+    # the same solve (the step's depth weights and r~ agree with the host's to rounding)
+    assert abs(alpha - a1) <= 1e-9 * a1
+    ref = np.clip(P["winv"] * to_host(y), 0.0, 0.1)
+    assert np.abs(m1 - ref).max() <= 1e-6 * 0.1
+    c_or = oirls.chi2_scaled(op.apply_G(g, m1, P["T"]), P["d_obs"], P["wd"])
+    assert abs(chi2 - c_or) <= 1e-4 * c_or, (chi2, c_or)
+    A.close()
+    torch.cuda.empty_cache()
