@@ -269,11 +269,13 @@ ff_status irls_step(ff_spectra h, const ff_irls_params *p, const double *d_obs, 
      rsvd_qr       orthonormalization inside rsvd_project: 0 = Cholesky QR with the fallbacks
                    described there, 1 = always Householder QR (geqrf + orgqr), 2 = start at the
                    shifted CholeskyQR3 (then Householder).
-     pair_fused    grouped plans (ff_multi_create) of this survey alone that bind both G x and
-                   G^T d: 1 = one column pass for both products, reading each layer spectrum once
-                   (it splits the layers of both over lg_G groups), used when its column blocks
-                   (nfft_x/2 slots, lg_G groups) at least fill the device's compute units;
-                   0 = separate column passes.  The results are the same bit for bit. */
+     pair_fused    grouped plans (ff_multi_create) that bind both G x and G^T d of this
+                   survey: one column pass for both products, reading each layer spectrum once (it
+                   splits the layers of both over lg_G groups), or separate column passes.
+                   1 (default) = the shared pass when the plan holds this survey alone and its
+                   column blocks (nfft_x/2 slots, lg_G groups) at least fill the device's compute
+                   units; 2 = the shared pass in every plan; 0 = never.  The results are the same
+                   bit for bit. */
 typedef struct {
     int32_t lg_G, lg_GT;
     int32_t row_tile;

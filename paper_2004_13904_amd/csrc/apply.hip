@@ -92,18 +92,26 @@ ff_status run_pass(ff_spectra h, const OpWs &ws, int transpose, int pass, int kb
                                                Idx3{(int64_t)nz * HC * ldy, (int64_t)HC * ldy, 1}, ldy, twx, s));
       FF_LAUNCH_CHECK("G pass 1 (row transforms)");
     } else if (pass == 1) {
+      const bool half = 2 * ny <= h->NY && 2 * (h->pyl + sy) <= h->NY;
       FF_SWITCH_N(h->NY, {
         using CC = ColCfg<T, NN>;
         if constexpr (BatchCfg<T, NN>::OK) {
           if (kb > 1 && h->col_batched) {
             dim3 g((HC + CC::CPB - 1) / CC::CPB, LG, (kb + BatchCfg<T, NN>::V - 1) / BatchCfg<T, NN>::V);
-            k_col_G_batch<T, NN><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, ldy, nz, HC, LG, kb, spec,
-                                                                                    C2, sy, lds, h->pyl, twy);
+            if (half)
+              k_col_G_batch<T, NN, true><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, ldy, nz, HC, LG, kb, spec,
+                                                                          C2, sy, lds, h->pyl, twy);
+            else
+              k_col_G_batch<T, NN, false><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, ldy, nz, HC, LG, kb, spec,
+                                                                           C2, sy, lds, h->pyl, twy);
             break;
           }
         }
         dim3 g((HC + CC::CPB - 1) / CC::CPB, LG, kb);
-        k_col_G<T, NN><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, ldy, nz, HC, LG, spec, C2, sy, lds, h->pyl, twy);
+        if (half)
+          k_col_G<T, NN, true><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, ldy, nz, HC, LG, spec, C2, sy, lds, h->pyl, twy);
+        else
+          k_col_G<T, NN, false><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, ldy, nz, HC, LG, spec, C2, sy, lds, h->pyl, twy);
       });
       FF_LAUNCH_CHECK("G pass 2 (column transforms and spectral products)");
     } else {
@@ -118,18 +126,26 @@ ff_status run_pass(ff_spectra h, const OpWs &ws, int transpose, int pass, int kb
                                                Idx3{(int64_t)HC * lds, 0, 1}, lds, twx, s));
       FF_LAUNCH_CHECK("G^T pass 1 (row transforms)");
     } else if (pass == 1) {
+      const bool half = 2 * ny <= h->NY && 2 * (h->pyl + sy) <= h->NY;
       FF_SWITCH_N(h->NY, {
         using CC = ColCfg<T, NN>;
         if constexpr (BatchCfg<T, NN>::OK) {
           if (kb > 1 && h->col_batched) {
             dim3 g((HC + CC::CPB - 1) / CC::CPB, LG, (kb + BatchCfg<T, NN>::V - 1) / BatchCfg<T, NN>::V);
-            k_col_GT_batch<T, NN><<<g, CC::THREADS * CC::WPB, 0, s>>>(C2, sy, lds, h->pyl, nz, HC, LG, kb,
-                                                                                     spec, X1, ny, ldy, twy);
+            if (half)
+              k_col_GT_batch<T, NN, true><<<g, CC::THREADS * CC::WPB, 0, s>>>(C2, sy, lds, h->pyl, nz, HC, LG, kb,
+                                                                           spec, X1, ny, ldy, twy);
+            else
+              k_col_GT_batch<T, NN, false><<<g, CC::THREADS * CC::WPB, 0, s>>>(C2, sy, lds, h->pyl, nz, HC, LG, kb,
+                                                                            spec, X1, ny, ldy, twy);
             break;
           }
         }
         dim3 g((HC + CC::CPB - 1) / CC::CPB, LG, kb);
-        k_col_GT<T, NN><<<g, CC::THREADS * CC::WPB, 0, s>>>(C2, sy, lds, h->pyl, nz, HC, LG, spec, X1, ny, ldy, twy);
+        if (half)
+          k_col_GT<T, NN, true><<<g, CC::THREADS * CC::WPB, 0, s>>>(C2, sy, lds, h->pyl, nz, HC, LG, spec, X1, ny, ldy, twy);
+        else
+          k_col_GT<T, NN, false><<<g, CC::THREADS * CC::WPB, 0, s>>>(C2, sy, lds, h->pyl, nz, HC, LG, spec, X1, ny, ldy, twy);
       });
       FF_LAUNCH_CHECK("G^T pass 2 (column transforms and spectral products)");
     } else {

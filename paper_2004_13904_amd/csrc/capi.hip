@@ -375,7 +375,7 @@ ff_status ff_set_tuning(ff_spectra h, const ff_tuning *t) {
     return fail(FF_EINVAL, "ff_set_tuning: batch must lie in [1, the handle's workspace batch]");
   if (t->col_batched != 0 && t->col_batched != 1) return fail(FF_EINVAL, "ff_set_tuning: col_batched must be 0 or 1");
   if (t->rsvd_qr < 0 || t->rsvd_qr > 2) return fail(FF_EINVAL, "ff_set_tuning: rsvd_qr must be 0, 1 or 2");
-  if (t->pair_fused != 0 && t->pair_fused != 1) return fail(FF_EINVAL, "ff_set_tuning: pair_fused must be 0 or 1");
+  if (t->pair_fused < 0 || t->pair_fused > 2) return fail(FF_EINVAL, "ff_set_tuning: pair_fused must be 0, 1 or 2");
   h->lg_G = t->lg_G;
   h->lg_GT = t->lg_GT;
   h->row_tile = t->row_tile;

@@ -78,6 +78,55 @@ template <bool INV, typename T> __device__ __forceinline__ void dft8(cplx<T> *a)
   }
 }
 
+// Pruned butterflies.  ZIN: the inputs a[4..7] of a first-stage 8-point DFT are zero (the
+// transform's input is zero from element N/2 on, so they need not be loaded or added); ZOUT:
+// only the outputs a[0..3] of a last-stage DFT are used (elements below N/2), the others are
+// left unspecified.  Both skip arithmetic only; the outputs computed are those of dft8 bit for bit.
+template <bool INV, typename T>
+__device__ __forceinline__ void dft4_zin(cplx<T> &a0, cplx<T> &a1, cplx<T> &a2, cplx<T> &a3) {
+  // a2 = a3 = 0 on input
+  const cplx<T> t3 = mul_w4<INV, T>(a1);
+  a2 = csub<T>(a0, a1);
+  a3 = csub<T>(a0, t3);
+  const cplx<T> x0 = a0;
+  a0 = cadd<T>(x0, a1);
+  a1 = cadd<T>(x0, t3);
+}
+template <bool INV, bool ZIN, bool ZOUT, typename T> __device__ __forceinline__ void dft8p(cplx<T> *a) {
+  if constexpr (!ZIN && !ZOUT) {
+    dft8<INV, T>(a);
+  } else {
+    cplx<T> e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
+    cplx<T> o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
+    if constexpr (ZIN) {
+      dft4_zin<INV, T>(e0, e1, e2, e3);
+      dft4_zin<INV, T>(o0, o1, o2, o3);
+    } else {
+      dft4<INV, T>(e0, e1, e2, e3);
+      dft4<INV, T>(o0, o1, o2, o3);
+    }
+    o2 = mul_w4<INV, T>(o2);
+    a[0] = cadd<T>(e0, o0);
+    a[2] = cadd<T>(e2, o2);
+    if constexpr (!ZOUT) {
+      a[4] = csub<T>(e0, o0);
+      a[6] = csub<T>(e2, o2);
+    }
+    cplx<T> m1, m3;
+    if (INV) {
+      bfly_c<T>(e1, o1.x - o1.y, o1.x + o1.y, a[1], m1);
+      bfly_c<T>(e3, -o3.x - o3.y, o3.x - o3.y, a[3], m3);
+    } else {
+      bfly_c<T>(e1, o1.x + o1.y, o1.y - o1.x, a[1], m1);
+      bfly_c<T>(e3, o3.y - o3.x, -o3.x - o3.y, a[3], m3);
+    }
+    if constexpr (!ZOUT) {
+      a[5] = m1;
+      a[7] = m3;
+    }
+  }
+}
+
 template <bool INV, typename T>
 __device__ __forceinline__ cplx<T> twiddle(cplx<T> v, const cplx<T> *__restrict__ tw, int e) {
   cplx<T> w = tw[e];
@@ -143,7 +192,10 @@ template <typename T, int N, bool INV> struct FFT {
   }
   __device__ static cplx<T> tmul(cplx<T> v, cplx<T> w) { return INV ? cmulc<T>(v, w) : cmul<T>(v, w); }
 
-  // Same transform as run(), with the twiddles taken from registers.
+  // Same transform as run(), with the twiddles taken from registers.  ZIN: the input is zero
+  // from element N/2 on (v[4..7] are not read); ZOUT: only the outputs below N/2 (v[0..3]) are
+  // produced.
+  template <bool ZIN = false, bool ZOUT = false>
   __device__ static void run_tw(cplx<T> (&v)[8], int j, cplx<T> *buf, const Tw &t) {
     int Ns = 1, q = 0;
     bool used_lds = false;
@@ -155,7 +207,10 @@ template <typename T, int N, bool INV> struct FFT {
 #pragma unroll
         for (int u = 1; u < 8; ++u) v[u] = tmul(v[u], t.w[q++]);
       }
-      dft8<INV, T>(v);
+      if (st == 0 && last) dft8p<INV, ZIN, ZOUT, T>(v);
+      else if (st == 0) dft8p<INV, ZIN, false, T>(v);
+      else if (last) dft8p<INV, false, ZOUT, T>(v);
+      else dft8<INV, T>(v);
       if (!last) {
         cplx<T> *dst = SINGLE ? buf : buf + (st & 1) * HALF;
         const int base = (j / Ns) * Ns * 8 + k;
@@ -169,6 +224,13 @@ template <typename T, int N, bool INV> struct FFT {
       }
       Ns *= 8;
     }
+    final_stage<ZOUT>(v, Ns, q, t);
+    if (used_lds) group_sync<TPF>();
+  }
+
+  // the radix-4 or radix-2 stage after the radix-8 ones (REM = 4 or 2), twiddles from registers
+  template <bool ZOUT>
+  __device__ static void final_stage(cplx<T> (&v)[8], int Ns, int q, const Tw &t) {
     if (REM == 4) {
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
@@ -176,19 +238,29 @@ template <typename T, int N, bool INV> struct FFT {
 #pragma unroll
           for (int u = 1; u < 4; ++u) v[c + 2 * u] = tmul(v[c + 2 * u], t.w[q++]);
         }
-        dft4<INV, T>(v[c], v[c + 2], v[c + 4], v[c + 6]);
+        if (ZOUT) {
+          // outputs c, c + 2 only (elements below N/2)
+          const cplx<T> t0 = cadd<T>(v[c], v[c + 4]), t1 = csub<T>(v[c], v[c + 4]);
+          const cplx<T> t2 = cadd<T>(v[c + 2], v[c + 6]), t3 = mul_w4<INV, T>(csub<T>(v[c + 2], v[c + 6]));
+          v[c] = cadd<T>(t0, t2);
+          v[c + 2] = cadd<T>(t1, t3);
+        } else {
+          dft4<INV, T>(v[c], v[c + 2], v[c + 4], v[c + 6]);
+        }
       }
     } else if (REM == 2) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         if (Ns > 1) v[c + 4] = tmul(v[c + 4], t.w[q++]);
-        dft2<INV, T>(v[c], v[c + 4]);
+        if (ZOUT) v[c] = cadd<T>(v[c], v[c + 4]);
+        else dft2<INV, T>(v[c], v[c + 4]);
       }
     }
-    if (used_lds) group_sync<TPF>();
   }
 
   // v[u] = x[j + u*TPF] on entry, X[j + u*TPF] on exit.  buf: this group's LDS elements.
+  // Twiddles read from the table; ZIN / ZOUT as for run_tw.
+  template <bool ZIN = false, bool ZOUT = false>
   __device__ static void run(cplx<T> (&v)[8], int j, cplx<T> *buf, const cplx<T> *__restrict__ tw) {
     int Ns = 1;
     bool used_lds = false;
@@ -202,7 +274,10 @@ template <typename T, int N, bool INV> struct FFT {
 #pragma unroll
         for (int t = 1; t < 8; ++t) v[t] = twiddle<INV, T>(v[t], tw, step * t);
       }
-      dft8<INV, T>(v);
+      if (st == 0 && last) dft8p<INV, ZIN, ZOUT, T>(v);
+      else if (st == 0) dft8p<INV, ZIN, false, T>(v);
+      else if (last) dft8p<INV, false, ZOUT, T>(v);
+      else dft8<INV, T>(v);
       if (!last) {
         cplx<T> *dst = SINGLE ? buf : buf + (st & 1) * HALF;
         const int base = (j / Ns) * Ns * 8 + k;
@@ -227,7 +302,14 @@ template <typename T, int N, bool INV> struct FFT {
 #pragma unroll
           for (int t = 1; t < 4; ++t) v[c + 2 * t] = twiddle<INV, T>(v[c + 2 * t], tw, step * t);
         }
-        dft4<INV, T>(v[c], v[c + 2], v[c + 4], v[c + 6]);
+        if (ZOUT) {
+          const cplx<T> t0 = cadd<T>(v[c], v[c + 4]), t1 = csub<T>(v[c], v[c + 4]);
+          const cplx<T> t2 = cadd<T>(v[c + 2], v[c + 6]), t3 = mul_w4<INV, T>(csub<T>(v[c + 2], v[c + 6]));
+          v[c] = cadd<T>(t0, t2);
+          v[c + 2] = cadd<T>(t1, t3);
+        } else {
+          dft4<INV, T>(v[c], v[c + 2], v[c + 4], v[c + 6]);
+        }
       }
     } else if (REM == 2) {
       // four radix-2 butterflies b = j + c*N/8 on slots c, c+4
@@ -237,7 +319,8 @@ template <typename T, int N, bool INV> struct FFT {
         const int k = b % Ns;
         const int step = k * (N / (Ns * 2));
         if (Ns > 1) v[c + 4] = twiddle<INV, T>(v[c + 4], tw, step);
-        dft2<INV, T>(v[c], v[c + 4]);
+        if (ZOUT) v[c] = cadd<T>(v[c], v[c + 4]);
+        else dft2<INV, T>(v[c], v[c + 4]);
       }
     }
     // A later call (or the caller's own LDS use) may overwrite the buffers this call read.
@@ -248,12 +331,16 @@ template <typename T, int N, bool INV> struct FFT {
 // Two independent transforms of the same length run interleaved by one FFT group: `a` in
 // direction INVA and `b` in direction INVB, each with its own exchange buffer, sharing the
 // register twiddles and the barriers of every exchange.  Each transform does exactly the
-// arithmetic of FFT::run_tw (same results bit for bit); the interleaving gives the scheduler a
-// second chain of work while the other waits on LDS.  Wave-level transforms only (N <= 512).
-template <typename T, int N, bool INVA, bool INVB>
+// arithmetic of FFT::run_tw with its own pruning flags (same results bit for bit); the
+// interleaving gives the scheduler a second chain of work while the other waits on LDS.
+// Wave-level transforms only (N <= 512).
+template <typename T, int N, bool INVA, bool INVB, bool ZINA = false, bool ZOUTA = false, bool ZINB = false,
+          bool ZOUTB = false>
 __device__ __forceinline__ void fft_dual(cplx<T> (&a)[8], cplx<T> (&b)[8], int j, cplx<T> *bufA, cplx<T> *bufB,
                                          const typename FFT<T, N, false>::Tw &t) {
   using F = FFT<T, N, false>;
+  using FA = FFT<T, N, INVA>;
+  using FB = FFT<T, N, INVB>;
   static_assert(F::WAVE, "fft_dual: wave-level transforms only");
   constexpr int TPF = F::TPF, L8 = F::L8, REM = F::REM;
   auto mulA = [](cplx<T> v, cplx<T> w) { return INVA ? cmulc<T>(v, w) : cmul<T>(v, w); };
@@ -272,8 +359,19 @@ __device__ __forceinline__ void fft_dual(cplx<T> (&a)[8], cplx<T> (&b)[8], int j
         ++q;
       }
     }
-    dft8<INVA, T>(a);
-    dft8<INVB, T>(b);
+    if (st == 0 && last) {
+      dft8p<INVA, ZINA, ZOUTA, T>(a);
+      dft8p<INVB, ZINB, ZOUTB, T>(b);
+    } else if (st == 0) {
+      dft8p<INVA, ZINA, false, T>(a);
+      dft8p<INVB, ZINB, false, T>(b);
+    } else if (last) {
+      dft8p<INVA, false, ZOUTA, T>(a);
+      dft8p<INVB, false, ZOUTB, T>(b);
+    } else {
+      dft8<INVA, T>(a);
+      dft8<INVB, T>(b);
+    }
     if (!last) {
       const int base = (j / Ns) * Ns * 8 + k;
       group_sync<TPF>();
@@ -292,31 +390,9 @@ __device__ __forceinline__ void fft_dual(cplx<T> (&a)[8], cplx<T> (&b)[8], int j
     }
     Ns *= 8;
   }
-  if (REM == 4) {
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      if (Ns > 1) {
-#pragma unroll
-        for (int u = 1; u < 4; ++u) {
-          a[c + 2 * u] = mulA(a[c + 2 * u], t.w[q]);
-          b[c + 2 * u] = mulB(b[c + 2 * u], t.w[q]);
-          ++q;
-        }
-      }
-      dft4<INVA, T>(a[c], a[c + 2], a[c + 4], a[c + 6]);
-      dft4<INVB, T>(b[c], b[c + 2], b[c + 4], b[c + 6]);
-    }
-  } else if (REM == 2) {
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      if (Ns > 1) {
-        a[c + 4] = mulA(a[c + 4], t.w[q]);
-        b[c + 4] = mulB(b[c + 4], t.w[q]);
-        ++q;
-      }
-      dft2<INVA, T>(a[c], a[c + 4]);
-      dft2<INVB, T>(b[c], b[c + 4]);
-    }
+  if (REM != 1) {
+    FA::template final_stage<ZOUTA>(a, Ns, q, *reinterpret_cast<const typename FA::Tw *>(&t));
+    FB::template final_stage<ZOUTB>(b, Ns, q, *reinterpret_cast<const typename FB::Tw *>(&t));
   }
   if (used_lds) group_sync<TPF>();
 }

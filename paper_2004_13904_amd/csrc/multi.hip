@@ -38,8 +38,8 @@ constexpr int kRowSH = max3(max3(MultiRow<8>::C::SH, MultiRow<16>::C::SH, MultiR
                             MultiRow<512>::C::SH);
 constexpr int kColSH = max3(max3(MultiCol<8>::SH, MultiCol<16>::SH, MultiCol<32>::SH),
                             max3(MultiCol<64>::SH, MultiCol<128>::SH, MultiCol<256>::SH), MultiCol<512>::SH);
-// the pair's column pass keeps two exchange buffers per wave group (about 104 KB at 512 points),
-// so its launches hold one block per CU; plans without pair tasks keep the smaller blocks
+// the pair's column pass keeps two exchange buffers per wave group and the shared transform of
+// the data column (about 76 KB at 512 points); plans without pair tasks keep the smaller blocks
 constexpr int kColPairSH = max3(max3(MultiCol<8>::SHP, MultiCol<16>::SHP, MultiCol<32>::SHP),
                                 max3(MultiCol<64>::SHP, MultiCol<128>::SHP, MultiCol<256>::SHP), MultiCol<512>::SHP);
 
@@ -99,15 +99,29 @@ template <int N> __device__ __forceinline__ void c2r_task(float2 *sh, int lb, co
 
 template <int NY, bool PAIR> __device__ __forceinline__ void col_task(float2 *sh, int lb, const ColTask &t) {
   const int bx = lb % t.nbx, by = lb / t.nbx;
-  if (PAIR && t.op == 2)
-    col_pair_body<float, NY>(sh, bx, by, t.src, t.ny, t.ldy, t.dst, t.src2, t.dst2, t.sy, t.lds, t.pyl, t.nz, t.HC,
-                             t.LG, t.spec, t.tw);
-  else if (t.op == 0)
-    col_G_body<float, NY>(sh, bx, by, 0, t.src, t.ny, t.ldy, t.nz, t.HC, t.LG, t.spec, t.dst, t.sy, t.lds, t.pyl,
-                          t.tw);
-  else
-    col_GT_body<float, NY>(sh, bx, by, 0, t.src, t.sy, t.lds, t.pyl, t.nz, t.HC, t.LG, t.spec, t.dst, t.ny, t.ldy,
-                           t.tw);
+  if (PAIR && t.op == 2) {
+    if (2 * t.ny <= NY && 2 * (t.pyl + t.sy) <= NY)
+      col_pair_body<float, NY, true>(sh, bx, by, t.src, t.ny, t.ldy, t.dst, t.src2, t.dst2, t.sy, t.lds, t.pyl,
+                                     t.nz, t.HC, t.LG, t.spec, t.tw);
+    else
+      col_pair_body<float, NY, false>(sh, bx, by, t.src, t.ny, t.ldy, t.dst, t.src2, t.dst2, t.sy, t.lds, t.pyl,
+                                      t.nz, t.HC, t.LG, t.spec, t.tw);
+  }
+  else if (t.op == 0) {
+    if (2 * t.ny <= NY && 2 * (t.pyl + t.sy) <= NY)
+      col_G_body<float, NY, true>(sh, bx, by, 0, t.src, t.ny, t.ldy, t.nz, t.HC, t.LG, t.spec, t.dst, t.sy, t.lds,
+                                  t.pyl, t.tw);
+    else
+      col_G_body<float, NY, false>(sh, bx, by, 0, t.src, t.ny, t.ldy, t.nz, t.HC, t.LG, t.spec, t.dst, t.sy, t.lds,
+                                   t.pyl, t.tw);
+  } else {
+    if (2 * t.ny <= NY && 2 * (t.pyl + t.sy) <= NY)
+      col_GT_body<float, NY, true>(sh, bx, by, 0, t.src, t.sy, t.lds, t.pyl, t.nz, t.HC, t.LG, t.spec, t.dst, t.ny,
+                                   t.ldy, t.tw);
+    else
+      col_GT_body<float, NY, false>(sh, bx, by, 0, t.src, t.sy, t.lds, t.pyl, t.nz, t.HC, t.LG, t.spec, t.dst, t.ny,
+                                    t.ldy, t.tw);
+  }
 }
 
 #define FF_MULTI_SWITCH(N, CALL)                                                                             \
@@ -247,11 +261,11 @@ ff_status ff_multi_create(int32_t count, const ff_spectra *handles, const void *
     const float2 *twx = (const float2 *)h->tw_x, *twy = (const float2 *)h->tw_y;
     const float2 *spec = (const float2 *)h->spec;
     const int rpb = rows_per_block(h->NX), nbx = col_blocks_x(h->NY, HC);
-    // a pair task halves the column blocks of the two products and holds one block per CU: it is
-    // used for a single survey whose pair alone fills the chip
+    // a pair task halves the column blocks of the two products and needs more LDS per block: by
+    // default (pair_fused = 1) it is used for a single survey whose pair alone fills the chip
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
-    const bool pair = doG && doT && h->pair_fused && count == 1 && nbx * h->lg_G >= cus;
+    const bool pair = doG && doT && (h->pair_fused == 2 || (h->pair_fused == 1 && count == 1 && nbx * h->lg_G >= cus));
     any_pair = any_pair || pair;
     if (pair) {
       // one column task for both products: each spectrum column is read once

@@ -89,9 +89,9 @@ template <class C> struct TileRow {
 // kx < N/2 + 1, or with PACK for the N/2 column slots of the column passes (slot 0 holds the
 // real DC and Nyquist bins as one complex value, DC + i Nyquist).  Rows are numbered across the nb batches (R = b*nrows + row), so a pass of nb*nrows rows
 // fills exactly ceil(nb*nrows/ROWS) blocks.  Grid: (ceil(nb*nrows/ROWS), 1, nvec).
-template <typename T, typename TI, int N, int NF, bool PACK = true>
+template <typename T, typename TI, int N, int NF, bool PACK = true, bool HALF = false>
 __device__ __forceinline__ void
-row_r2c_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const TI *__restrict__ in, Idx3 ii, const TI *__restrict__ pre, Idx3 pi, int nrows, int nb, int len,
+row_r2c_body_h(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const TI *__restrict__ in, Idx3 ii, const TI *__restrict__ pre, Idx3 pi, int nrows, int nb, int len,
           int off, cplx<T> *__restrict__ out, Idx3 oi, int64_t out_kx,
           const cplx<T> *__restrict__ tw) {
   using C = RowCfg<T, N, NF>;
@@ -107,7 +107,7 @@ row_r2c_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const TI *__r
   for (int u = 0; u < 8; ++u) {
     const int c = j + u * F::TPF - off;
     T a = 0, bv = 0;
-    if (c >= 0 && c < len) {
+    if ((!HALF || u < 4) && c >= 0 && c < len) {
       if (ra < total) {
         a = (T)in[ii.at(vec, ba, qa) + c];
         if (pre) a *= (T)pre[pi.at(0, ba, qa) + c];
@@ -119,7 +119,7 @@ row_r2c_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const TI *__r
     }
     v[u] = mk<T>(a, bv);
   }
-  F::run(v, j, sh + f * F::LDS, tw);
+  F::template run<HALF, false>(v, j, sh + f * F::LDS, tw);
   // separate the two packed real transforms: Xa = (Z_k + conj Z_{N-k})/2, Xb = (Z_k - conj Z_{N-k})/(2i)
   cplx<T> *z = sh + f * F::LDS;
 #pragma unroll
@@ -170,6 +170,19 @@ row_r2c_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const TI *__r
   }
 }
 
+// The row values sit at x = off .. off + len - 1: when that lies in the first half of the
+// embedding the transform skips the zero half of its input.
+template <typename T, typename TI, int N, int NF, bool PACK = true>
+__device__ __forceinline__ void
+row_r2c_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const TI *__restrict__ in, Idx3 ii, const TI *__restrict__ pre, Idx3 pi, int nrows, int nb, int len,
+          int off, cplx<T> *__restrict__ out, Idx3 oi, int64_t out_kx,
+          const cplx<T> *__restrict__ tw) {
+  if (2 * (off + len) <= N)
+    row_r2c_body_h<T, TI, N, NF, PACK, true>(sh, bx, by, bz, in, ii, pre, pi, nrows, nb, len, off, out, oi, out_kx, tw);
+  else
+    row_r2c_body_h<T, TI, N, NF, PACK, false>(sh, bx, by, bz, in, ii, pre, pi, nrows, nb, len, off, out, oi, out_kx, tw);
+}
+
 template <typename T, typename TI, int N, int NF, bool PACK = true>
 __global__ void __launch_bounds__((RowCfg<T, N, NF>::THREADS))
 k_row_r2c(const TI *__restrict__ in, Idx3 ii, const TI *__restrict__ pre, Idx3 pi, int nrows, int nb, int len,
@@ -185,9 +198,9 @@ k_row_r2c(const TI *__restrict__ in, Idx3 ii, const TI *__restrict__ pre, Idx3 p
 // real rows; keeps x = off .. off+len-1, multiplies by `post` (optional, indexed without the
 // vector stride).  Rows numbered across batches as in pass 1.
 // Grid: (ceil(nb*nrows/ROWS), 1, nvec).
-template <typename T, typename TO, int N, int NF>
+template <typename T, typename TO, int N, int NF, bool HALF>
 __device__ __forceinline__ void
-row_c2r_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<T> *__restrict__ in, Idx3 ii, int64_t in_kx, int64_t pstride, int P, int nrows, int nb,
+row_c2r_body_h(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<T> *__restrict__ in, Idx3 ii, int64_t in_kx, int64_t pstride, int P, int nrows, int nb,
           TO *__restrict__ out, Idx3 oi, const TO *__restrict__ post, Idx3 qi, int len, int off,
           const cplx<T> *__restrict__ tw) {
   using C = RowCfg<T, N, NF>;
@@ -249,11 +262,11 @@ row_c2r_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<T>
     v[u] = mk<T>(A.x - B.y, A.y + B.x);  // Z = A + i B
   }
   __syncthreads();
-  F::run(v, j, sh + f * F::LDS, tw);
+  F::template run<false, HALF>(v, j, sh + f * F::LDS, tw);
   const int ra = R0 + 2 * f, rb = ra + 1;
   const int ba = ra / nrows, qa = ra - ba * nrows, bb = rb / nrows, qb = rb - bb * nrows;
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
+  for (int u = 0; u < (HALF ? 4 : 8); ++u) {
     const int c = j + u * F::TPF - off;
     if (c >= 0 && c < len) {
       if (ra < total) {
@@ -268,6 +281,19 @@ row_c2r_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<T>
       }
     }
   }
+}
+
+// The kept values x = off .. off + len - 1: when they lie in the first half of the embedding
+// the transform skips the outputs of the other half.
+template <typename T, typename TO, int N, int NF>
+__device__ __forceinline__ void
+row_c2r_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<T> *__restrict__ in, Idx3 ii, int64_t in_kx, int64_t pstride, int P, int nrows, int nb,
+          TO *__restrict__ out, Idx3 oi, const TO *__restrict__ post, Idx3 qi, int len, int off,
+          const cplx<T> *__restrict__ tw) {
+  if (2 * (off + len) <= N)
+    row_c2r_body_h<T, TO, N, NF, true>(sh, bx, by, bz, in, ii, in_kx, pstride, P, nrows, nb, out, oi, post, qi, len, off, tw);
+  else
+    row_c2r_body_h<T, TO, N, NF, false>(sh, bx, by, bz, in, ii, in_kx, pstride, P, nrows, nb, out, oi, post, qi, len, off, tw);
 }
 
 template <typename T, typename TO, int N, int NF>
@@ -302,7 +328,7 @@ k_row_c2r(const cplx<T> *__restrict__ in, Idx3 ii, int64_t in_kx, int64_t pstrid
 // partial sums are added up in LDS, each wave group taking a share of the elements, and wave
 // group 0 does the inverse transform.
 // Grid: (ceil(HC/CPB), LG, nvec).
-template <typename T, int NY>
+template <typename T, int NY, bool HALF = false>
 __device__ __forceinline__ void
 col_G_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, int LG,
         const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ outp, int sy, int lds, int pyl,
@@ -333,7 +359,7 @@ col_G_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<T> *
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int y = j + u * TPF;
-      xn[u] = (ok && y < ny) ? src[y] : mk<T>(0, 0);
+      xn[u] = ((!HALF || u < 4) && ok && y < ny) ? src[y] : mk<T>(0, 0);
       sn[u] = sp[y];
     }
   };
@@ -350,7 +376,7 @@ col_G_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<T> *
         s[u] = sn[u];
       }
       if (r + WPB < r1) load(r + WPB);
-      Ff::run_tw(v, j, buf, twr);
+      Ff::template run_tw<HALF, false>(v, j, buf, twr);
 #pragma unroll
       for (int u = 0; u < 8; ++u) acc[u] = cadd<T>(acc[u], cmul<T>(v[u], s[u]));
     }
@@ -380,7 +406,7 @@ col_G_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<T> *
         load(r + WPB);
         loadm(r + WPB);
       }
-      Ff::run_tw(v, j, buf, twr);
+      Ff::template run_tw<HALF, false>(v, j, buf, twr);
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         acc[u] = cadd<T>(acc[u], cmul<T>(v[u], s[u]));
@@ -419,24 +445,27 @@ col_G_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<T> *
     group_sync<TPF>();
   }
   // the inverse transform uses the conjugate twiddles of the same table
-  Fi::run_tw(acc, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
+  Fi::template run_tw<false, HALF>(acc, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
   if (ok) {
     cplx<T> *dst = outp + ((vec * LG + g) * HC + kx) * (int64_t)lds;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < (HALF ? 4 : 8); ++u) {
       const int y = j + u * TPF - pyl;
       if (y >= 0 && y < sy) dst[y] = acc[u];
     }
   }
 }
 
-template <typename T, int NY>
+// HALF: the model rows (y < ny) and the kept station rows (pyl .. pyl + sy - 1) lie in the
+// first half of the embedding, so the forward transforms skip the zero half of their input and
+// the inverse one the discarded half of its output (same results for the values kept).
+template <typename T, int NY, bool HALF>
 __global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
 k_col_G(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, int LG,
         const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ outp, int sy, int lds, int pyl,
         const cplx<T> *__restrict__ tw) {
   __shared__ cplx<T> sh[ColCfg<T, NY>::WPB * ColCfg<T, NY>::CPB * FFT<T, NY, false>::LDS];
-  col_G_body<T, NY>(sh, blockIdx.x, blockIdx.y, blockIdx.z, X1, ny, ldy, nz, HC, LG, spec, outp, sy, lds, pyl, tw);
+  col_G_body<T, NY, HALF>(sh, blockIdx.x, blockIdx.y, blockIdx.z, X1, ny, ldy, nz, HC, LG, spec, outp, sy, lds, pyl, tw);
 }
 
 // Pass 2 of G^T: for each column slot c: D = FFT_y(D1[vec, c, :] placed at rows pyl..pyl+sy-1);
@@ -444,7 +473,7 @@ k_col_G(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, int LG,
 // (slot 0: conj(P_r) .* D + conj(M_r) .* conj(D[-k])).
 // Wave group w of a block takes every WPB-th layer of the group and transforms D itself.
 // Grid: (ceil(HC/CPB), LG, nvec).
-template <typename T, int NY>
+template <typename T, int NY, bool HALF = false>
 __device__ __forceinline__ void
 col_GT_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz, int HC, int LG,
          const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ X1, int ny, int ldy,
@@ -476,16 +505,16 @@ col_GT_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<T> 
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int y = j + u * TPF - pyl;
-      dh[u] = (ok && y >= 0 && y < sy) ? src[y] : mk<T>(0, 0);
+      dh[u] = ((!HALF || u < 4) && ok && y >= 0 && y < sy) ? src[y] : mk<T>(0, 0);
       sn[u] = sp[j + u * TPF];
     }
   }
-  Ff::run_tw(dh, j, buf, twr);
+  Ff::template run_tw<HALF, false>(dh, j, buf, twr);
   auto store = [&](int r, const cplx<T> *v) {
     if (ok) {
       cplx<T> *dst = X1 + ((vec * nz + r) * HC + kx) * (int64_t)ldy;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < (HALF ? 4 : 8); ++u) {
         const int y = j + u * TPF;
         if (y < ny) dst[y] = v[u];
       }
@@ -501,7 +530,7 @@ col_GT_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<T> 
 #pragma unroll
         for (int u = 0; u < 8; ++u) sn[u] = sp[j + u * TPF];
       }
-      Fi::run_tw(v, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
+      Fi::template run_tw<false, HALF>(v, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
       store(r, v);
     }
   } else {
@@ -538,41 +567,46 @@ col_GT_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<T> 
         for (int u = 0; u < 8; ++u) sn[u] = sp[j + u * TPF];
         if (PREFETCH) loadm(r + WPB);
       }
-      Fi::run_tw(v, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
+      Fi::template run_tw<false, HALF>(v, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
       store(r, v);
     }
   }
 }
 
-template <typename T, int NY>
+template <typename T, int NY, bool HALF>
 __global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
 k_col_GT(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz, int HC, int LG,
          const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ X1, int ny, int ldy,
          const cplx<T> *__restrict__ tw) {
   __shared__ cplx<T> sh[ColCfg<T, NY>::WPB * ColCfg<T, NY>::CPB * FFT<T, NY, false>::LDS];
-  col_GT_body<T, NY>(sh, blockIdx.x, blockIdx.y, blockIdx.z, D1, sy, ldd, pyl, nz, HC, LG, spec, X1, ny, ldy, tw);
+  col_GT_body<T, NY, HALF>(sh, blockIdx.x, blockIdx.y, blockIdx.z, D1, sy, ldd, pyl, nz, HC, LG, spec, X1, ny, ldy, tw);
 }
 
 // Pass 2 of an independent pair G x, G^T d of one survey, in one launch: per column slot the
 // work of col_G_body and of col_GT_body, with each layer spectrum column read once for both
-// products.  Wave group w takes the layers L_i = r0 + w + i WPB of layer group `by` for both
-// products and runs its transforms two at a time (fft_dual), as a short software pipeline:
-//   step 0:          FFT_y(x_{L_0})  with  FFT_y(D)            (D: the data column of G^T)
-//   step i >= 1:     FFT_y(x_{L_i})  with  IFFT_y(conj(S_{L_{i-1}}) .* FFT_y(D))
-//   last:            IFFT_y of the last layer's G^T product, with (wave group 0) the inverse of
-//                    the G layer sum after the wave groups' sums are added up.
-// Each transform, product and sum is the one col_G_body / col_GT_body computes, in the same
-// order, so both results are bit for bit those of the separate passes.
-// LDS: per wave group two exchange buffers per column and a copy of FFT_y(D) (packed slot).
+// products.  D^ = FFT_y(D), the transform of G^T's data column, is computed once per block by
+// wave group WD and shared through LDS.  Wave group w then takes the layers L_i = r0 + w + i WPB
+// of layer group `by`; per layer it transforms the model column, adds S_r .* FFT_y(x_r) to the
+// G sum and stores IFFT_y(conj(S_r) .* D^) as G^T's layer r, the two transforms interleaved
+// (fft_dual), while the next layer's columns (and, in the block of the packed slot 0, the
+// M_r column) are loaded.  After the wave groups' G sums are added up, wave group WI inverts
+// the sum.  Each transform, product and sum is the one col_G_body / col_GT_body computes, in
+// the same order, so both results are bit for bit those of the separate passes.  HALF: the
+// model and data rows sit in the first half of the embedding (ny <= NY/2 and pyl + sy <= NY/2,
+// which the smallest embedding of an unpadded survey always gives), so the forward transforms
+// skip the zero half of their input and the inverse ones the half of their output that is
+// discarded.
 // NY <= 512 (wave-level transforms).  Grid: (ceil(HC/CPB), LG).
 template <typename T, int NY> struct PairCfg {
   using CC = ColCfg<T, NY>;
   static constexpr int LDSF = FFT<T, NY, false>::LDS;
-  static constexpr int PER_W = CC::CPB * (2 * LDSF + NY);   // complex elements per wave group
-  static constexpr int SH = CC::WPB * PER_W;
+  static constexpr int PER_W = 2 * CC::CPB * LDSF;          // exchange buffers per wave group
+  static constexpr int SH = CC::WPB * PER_W + CC::CPB * NY;  // + the shared D^ of the columns
+  static constexpr int WD = CC::WPB >= 4 ? CC::WPB - 3 : CC::WPB - 1;   // computes D^
+  static constexpr int WI = CC::WPB >= 2 ? CC::WPB - 2 : 0;             // inverts the G sum
 };
 
-template <typename T, int NY>
+template <typename T, int NY, bool HALF>
 __device__ __forceinline__ void
 col_pair_body(cplx<T> *__restrict__ sh, int bx, int by, const cplx<T> *__restrict__ X1, int ny, int ldy,
               cplx<T> *__restrict__ outp, const cplx<T> *__restrict__ D1, cplx<T> *__restrict__ X1t, int sy,
@@ -582,7 +616,8 @@ col_pair_body(cplx<T> *__restrict__ sh, int bx, int by, const cplx<T> *__restric
   using PC = PairCfg<T, NY>;
   using Ff = FFT<T, NY, false>;
   using Fi = FFT<T, NY, true>;
-  constexpr int TPF = CC::TPF, WPB = CC::WPB, LDSF = PC::LDSF;
+  constexpr int TPF = CC::TPF, WPB = CC::WPB, LDSF = PC::LDSF, WD = PC::WD, WI = PC::WI;
+  constexpr int UH = HALF ? 4 : 8;   // register slots of a half-pruned transform's input / output
   static_assert(TPF <= 64, "pair column pass: wave-level transforms only");
   const int w = threadIdx.x / CC::THREADS, lt = threadIdx.x % CC::THREADS;
   const int f = lt / TPF, j = lt % TPF;
@@ -598,15 +633,15 @@ col_pair_body(cplx<T> *__restrict__ sh, int bx, int by, const cplx<T> *__restric
   cplx<T> *wbase = sh + w * PC::PER_W;
   cplx<T> *bufA = wbase + f * LDSF;                        // exchange buffers of this column
   cplx<T> *bufB = wbase + (CC::CPB + f) * LDSF;
-  cplx<T> *dcopy = wbase + 2 * CC::CPB * LDSF + f * NY;     // FFT_y(D) of this column (packed slot)
+  cplx<T> *dsh = sh + WPB * PC::PER_W + f * NY;             // D^ of this column, shared
   typename Ff::Tw twr;
   Ff::load_tw(twr, j, tw);
-  const typename Fi::Tw &twi = *reinterpret_cast<const typename Fi::Tw *>(&twr);
-  cplx<T> acc[8], accm[8], dh[8], xn[8], sn[8];
+  cplx<T> acc[8], accm[8], dh[8], xn[8], sn[8], mn[8];
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
     acc[u] = mk<T>(0, 0);
     accm[u] = mk<T>(0, 0);
+    xn[u] = mk<T>(0, 0);
   }
   auto layer = [&](int i) { return r0 + w + i * WPB; };
   auto load = [&](int rr) {
@@ -615,83 +650,67 @@ col_pair_body(cplx<T> *__restrict__ sh, int bx, int by, const cplx<T> *__restric
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int y = j + u * TPF;
-      xn[u] = (ok && y < ny) ? src[y] : mk<T>(0, 0);
+      if (u < UH) xn[u] = (ok && y < ny) ? src[y] : mk<T>(0, 0);
       sn[u] = sp[y];
     }
+    if (pk) {
+      const cplx<T> *mp = spec + ((int64_t)rr * SH + HC) * NY;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) mn[u] = mp[j + u * TPF];
+    }
   };
-  // M_r (packed slot only), read where it is used
-  auto mrow = [&](int rr, int u) { return spec[((int64_t)rr * SH + HC) * NY + j + u * TPF]; };
-  // G: add S_r .* X and (packed slot) M_r .* X to the layer sums
-  auto gsum = [&](const cplx<T> (&a)[8], const cplx<T> (&sc)[8], int rr) {
+  if (nl > 0) load(layer(0));
+  if (w == WD) {
+    // the data column of G^T, embedded at rows pyl .. pyl + sy - 1, and its transform, for all
+    const cplx<T> *src = D1 + (int64_t)kxs * lds;
+    cplx<T> d[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int y = j + u * TPF - pyl;
+      d[u] = (u < UH && ok && y >= 0 && y < sy) ? src[y] : mk<T>(0, 0);
+    }
+    Ff::template run_tw<HALF, false>(d, j, bufB, twr);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) dsh[j + u * TPF] = d[u];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 8; ++u) dh[u] = dsh[j + u * TPF];
+  for (int i = 0; i < nl; ++i) {
+    const int rr = layer(i);
+    cplx<T> a[8], b[8], sc[8], mc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a[u] = xn[u];
+      sc[u] = sn[u];
+      mc[u] = mn[u];
+      b[u] = cmulc<T>(dh[u], sn[u]);     // G^T: conj(S_r) .* D^
+    }
+    if (pk0) {
+      // + conj(M_r) .* conj(D^[-k]) in the packed slot
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const cplx<T> dr = cconj<T>(dsh[(NY - j - u * TPF) & (NY - 1)]);
+        b[u] = cadd<T>(b[u], cmulc<T>(dr, mn[u]));
+      }
+    }
+    if (i + 1 < nl) load(layer(i + 1));
+    fft_dual<T, NY, false, true, HALF, false, false, HALF>(a, b, j, bufA, bufB, twr);
+    // G: the layer sums of S_r .* X and (packed slot) M_r .* X
 #pragma unroll
     for (int u = 0; u < 8; ++u) acc[u] = cadd<T>(acc[u], cmul<T>(a[u], sc[u]));
     if (pk) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) accm[u] = cadd<T>(accm[u], cmul<T>(a[u], mrow(rr, u)));
+      for (int u = 0; u < 8; ++u) accm[u] = cadd<T>(accm[u], cmul<T>(a[u], mc[u]));
     }
-  };
-  // G^T: conj(S_r) .* D (+ conj(M_r) .* conj(D[-k]) in the packed slot)
-  auto gtprod = [&](cplx<T> (&b)[8], const cplx<T> (&sc)[8], int rr) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) b[u] = cmulc<T>(dh[u], sc[u]);
-    if (pk0) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const cplx<T> dr = cconj<T>(dcopy[(NY - j - u * TPF) & (NY - 1)]);
-        b[u] = cadd<T>(b[u], cmulc<T>(dr, mrow(rr, u)));
-      }
-    }
-  };
-  auto gtstore = [&](const cplx<T> (&b)[8], int rr) {
     if (ok) {
       cplx<T> *dst = X1t + ((int64_t)rr * HC + kx) * (int64_t)ldy;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < UH; ++u) {
         const int y = j + u * TPF;
         if (y < ny) dst[y] = b[u];
       }
     }
-  };
-  if (nl > 0) load(layer(0));
-  {
-    const cplx<T> *src = D1 + (int64_t)kxs * lds;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int y = j + u * TPF - pyl;
-      dh[u] = (ok && y >= 0 && y < sy) ? src[y] : mk<T>(0, 0);
-    }
-  }
-  cplx<T> sc[8];   // spectrum column of the layer whose G^T product comes next
-  if (nl > 0) {
-    cplx<T> a[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      a[u] = xn[u];
-      sc[u] = sn[u];
-    }
-    if (nl > 1) load(layer(1));
-    fft_dual<T, NY, false, false>(a, dh, j, bufA, bufB, twr);
-    gsum(a, sc, layer(0));
-  } else {
-    Ff::run_tw(dh, j, bufB, twr);
-  }
-  if (pk) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) dcopy[j + u * TPF] = dh[u];
-    group_sync<TPF>();
-  }
-  for (int i = 1; i < nl; ++i) {
-    cplx<T> a[8], b[8];
-    gtprod(b, sc, layer(i - 1));
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      a[u] = xn[u];
-      sc[u] = sn[u];
-    }
-    if (i + 1 < nl) load(layer(i + 1));
-    fft_dual<T, NY, false, true>(a, b, j, bufA, bufB, twr);
-    gsum(a, sc, layer(i));
-    gtstore(b, layer(i - 1));
   }
   if (pk) {
     // each wave group folds its own M sum into its G sum: acc[k] += conj(accm[-k]) (slot 0)
@@ -705,7 +724,8 @@ col_pair_body(cplx<T> *__restrict__ sh, int bx, int by, const cplx<T> *__restric
     }
   }
   if constexpr (WPB > 1) {
-    // the wave groups' G sums meet in LDS (buffer A of each), added in wave-group order
+    // the wave groups' G sums meet in LDS (buffer A of each), added in wave-group order; the
+    // sums end in wave group 0's buffer A
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < 8; ++u) bufA[j + u * TPF] = acc[u];
@@ -717,28 +737,16 @@ col_pair_body(cplx<T> *__restrict__ sh, int bx, int by, const cplx<T> *__restric
       sh[e] = t;
     }
     __syncthreads();
-    if (w == 0) {
+    if (w != WI) return;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc[u] = bufA[j + u * TPF];
-    }
+    for (int u = 0; u < 8; ++u) acc[u] = sh[f * LDSF + j + u * TPF];
     group_sync<TPF>();
   }
-  // the last G^T layer, and (wave group 0) the inverse of the G sum
-  cplx<T> b[8];
-  if (nl > 0) gtprod(b, sc, layer(nl - 1));
-  if (w == 0 && nl > 0) {
-    fft_dual<T, NY, true, true>(acc, b, j, bufA, bufB, twr);
-    gtstore(b, layer(nl - 1));
-  } else if (w == 0) {
-    Fi::run_tw(acc, j, bufA, twi);
-  } else if (nl > 0) {
-    Fi::run_tw(b, j, bufB, twi);
-    gtstore(b, layer(nl - 1));
-  }
-  if (w == 0 && ok) {
+  Fi::template run_tw<false, HALF>(acc, j, bufA, *reinterpret_cast<const typename Fi::Tw *>(&twr));
+  if (ok) {
     cplx<T> *dst = outp + ((int64_t)g * HC + kx) * (int64_t)lds;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < UH; ++u) {
       const int y = j + u * TPF - pyl;
       if (y >= 0 && y < sy) dst[y] = acc[u];
     }
@@ -765,7 +773,7 @@ template <typename T, int NY> struct BatchCfg {
 // The partial sums of vector 2p + i sit in the wave groups 2l + p (l < GL); wave group 2i + p
 // adds them up in layer-group order and does the vector's inverse transform.  Block 0 (slot 0
 // at f == 0) also sums the M_r products and folds them in per wave group before the reduction.
-template <typename T, int NY>
+template <typename T, int NY, bool HALF>
 __global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
 k_col_G_batch(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, int LG, int kb,
               const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ outp, int sy, int lds, int pyl,
@@ -818,9 +826,9 @@ k_col_G_batch(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, i
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int y = j + u * TPF;
-        xv[u] = (okv && y < ny) ? src[y] : mk<T>(0, 0);
+        xv[u] = ((!HALF || u < 4) && okv && y < ny) ? src[y] : mk<T>(0, 0);
       }
-      Ff::run_tw(xv, j, buf, twr);
+      Ff::template run_tw<HALF, false>(xv, j, buf, twr);
 #pragma unroll
       for (int u = 0; u < 8; ++u) acc[i][u] = cadd<T>(acc[i][u], cmul<T>(xv[u], sv[u]));
       if (pk) {
@@ -865,11 +873,11 @@ k_col_G_batch(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, i
   __syncthreads();
   const int64_t vo = vec0 + 2 * p + lgw;   // the vector this wave group finishes (lgw < 2)
   if (lgw >= 2 || vo >= kb) return;
-  Fi::run_tw(mine, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
+  Fi::template run_tw<false, HALF>(mine, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
   if (ok) {
     cplx<T> *dst = outp + ((vo * LG + g) * HC + kx) * (int64_t)lds;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < (HALF ? 4 : 8); ++u) {
       const int y = j + u * TPF - pyl;
       if (y >= 0 && y < sy) dst[y] = mine[u];
     }
@@ -880,7 +888,7 @@ k_col_G_batch(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, i
 // into LDS; then wave group w takes the vectors 2p, 2p+1 and the layers r0 + l + k GL as above,
 // loading each spectrum column once for its two products and inverse transforms.  Slot 0
 // reads the reversed transform conj(D[-k]) from the same LDS copy.
-template <typename T, int NY>
+template <typename T, int NY, bool HALF>
 __global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
 k_col_GT_batch(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz, int HC, int LG, int kb,
                const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ X1, int ny, int ldy,
@@ -915,9 +923,9 @@ k_col_GT_batch(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz,
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int y = j + u * TPF - pyl;
-      dv[u] = (okv && y >= 0 && y < sy) ? src[y] : mk<T>(0, 0);
+      dv[u] = ((!HALF || u < 4) && okv && y >= 0 && y < sy) ? src[y] : mk<T>(0, 0);
     }
-    Ff::run_tw(dv, j, buf, twr);
+    Ff::template run_tw<HALF, false>(dv, j, buf, twr);
 #pragma unroll
     for (int u = 0; u < 8; ++u) dsh[(w * CC::CPB + f) * NY + j + u * TPF] = dv[u];
   }
@@ -950,11 +958,11 @@ k_col_GT_batch(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz,
           xv[u] = cadd<T>(xv[u], cmulc<T>(dr, mv[u]));
         }
       }
-      Fi::run_tw(xv, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
+      Fi::template run_tw<false, HALF>(xv, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
       if (ok && vec < kb) {
         cplx<T> *dst = X1 + ((vec * nz + r) * HC + kx) * (int64_t)ldy;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < (HALF ? 4 : 8); ++u) {
           const int y = j + u * TPF;
           if (y < ny) dst[y] = xv[u];
         }

@@ -141,3 +141,42 @@ def test_tuning_variants_keep_results():
             A.set_tuning(**bad)
     A.set_tuning(**base)
     assert A.tuning == base
+
+
+@pytest.mark.parametrize("name", ["magnetic_1m", "padded_heavy", "many_layers", "tiny", "gravity_l4"])
+def test_pair_plan_equals_separate_calls(name):
+    # the grouped plan of one survey with both products, its column pass shared by G x and G^T d
+    # (forced with pair_fused = 2 where the default would not pick it): equal bit for bit to
+    # apply_G / apply_GT, and within the bars of the oracle.  The geometries cover the pruned
+    # transforms (rows in the first half of the embedding) and the unpruned ones (heavy padding:
+    # ny > NY/2), several columns per wave (NY < 512), fewer layers than wave groups (tiny), more
+    # layers than fit one wave group's pipeline (many_layers) and the packed DC/Nyquist slot.
+    import ctypes as C
+    from paper_2004_13904_amd import _lib as L
+    s = {"magnetic_1m": W.SURVEYS["magnetic_1m"], "tiny": W.SURVEYS["tiny"],
+         "gravity_l4": W.SURVEYS["gravity_l4"],
+         "padded_heavy": W.survey(20, 14, 5, 20.0, 20.0, 20.0, kernel="magnetic", incl=60.0, decl=-20.0,
+                                  pad=(30, 25, 31, 24)),
+         "many_layers": W.survey(23, 19, 33, 25.0, 25.0, 12.0, kernel="magnetic", incl=70.0, decl=10.0)}[name]
+    A = Operator(s, F32)
+    A.set_tuning(pair_fused=2)
+    g = torch.Generator(device="cuda").manual_seed(21)
+    x = torch.rand(A.n, device="cuda", generator=g)
+    d = torch.randn(A.m, device="cuda", generator=g)
+    gx = torch.full((A.m,), float("nan"), device="cuda")
+    gtd = torch.full((A.n,), float("nan"), device="cuda")
+    arr = C.c_void_p * 1
+    plan = C.c_void_p()
+    L.call("ff_multi_create", 1, arr(A.h.value), arr(x.data_ptr()), arr(gx.data_ptr()), arr(d.data_ptr()),
+           arr(gtd.data_ptr()), C.byref(plan))
+    for _ in range(2):
+        L.call("ff_multi_apply", plan, C.c_void_p(torch.cuda.current_stream().cuda_stream))
+        torch.cuda.synchronize()
+        assert torch.equal(gx, A.G(x))
+        assert torch.equal(gtd, A.GT(d))
+    L.load().ff_multi_free(plan)
+    gi = ogeom(s)
+    T = op.kernel_table(gi)
+    agree(to_host(gx), op.apply_G(gi, to_host(x), T), 1e-5)
+    agree(to_host(gtd), op.apply_GT(gi, to_host(d), T), 1e-5)
+    A.close()

@@ -426,7 +426,7 @@ def c2_problem():
         return winv * op.apply_GT(g, wd * y, T)
     v0 = GtT(r)
     lo = LinearOperator((g.n, g.n), matvec=lambda v: GtT(Gt(np.asarray(v).ravel())), dtype=np.float64)
-    lam = eigsh(lo, k=1, which="LA", v0=v0, tol=1e-10, ncv=12, maxiter=40, return_eigenvectors=False)
+    lam = eigsh(lo, k=1, which="LA", v0=v0, tol=1e-8, ncv=20, maxiter=40, return_eigenvectors=False)
     return dict(s=s, g=g, T=T, d_obs=d_obs, wd=wd, winv=winv, r=r, Gt=Gt, GtT=GtT,
                 sigma1=float(math.sqrt(lam[0])))
 
