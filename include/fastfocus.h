@@ -275,7 +275,13 @@ ff_status irls_step(ff_spectra h, const ff_irls_params *p, const double *d_obs, 
                    1 (default) = the shared pass when the plan holds this survey alone and its
                    column blocks (nfft_x/2 slots, lg_G groups) at least fill the device's compute
                    units; 2 = the shared pass in every plan; 0 = never.  The results are the same
-                   bit for bit. */
+                   bit for bit.
+     gkb_graph     gkb_project and irls_step with GKB: 1 = the iteration loop of Algorithm 1
+                   (about 24 launches per iteration, none waiting for the host) is captured into a
+                   graph on the handle's own stream at the first solve and replayed by later solves
+                   with the same workspace, t_p and basis type (not while the caller's stream is
+                   being captured or pass profiling is on); 0 (default) = launched one by one.  The
+                   results are the same bit for bit. */
 typedef struct {
     int32_t lg_G, lg_GT;
     int32_t row_tile;
@@ -283,6 +289,7 @@ typedef struct {
     int32_t col_batched;
     int32_t rsvd_qr;
     int32_t pair_fused;
+    int32_t gkb_graph;
 } ff_tuning;
 ff_status ff_get_tuning(ff_spectra h, ff_tuning *t);
 ff_status ff_set_tuning(ff_spectra h, const ff_tuning *t);

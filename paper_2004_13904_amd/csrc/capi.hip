@@ -55,6 +55,9 @@ void free_handle(ff_spectra h) {
   hipFree(h->z_dev);
   hipFree(h->ws_rows);
   hipFree(h->ws_cols);
+  if (h->gkb_exec) hipGraphExecDestroy((hipGraphExec_t)h->gkb_exec);
+  if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+  release_blas(h);
   hipSetDevice(cur);
   delete h;
 }
@@ -363,6 +366,7 @@ ff_status ff_get_tuning(ff_spectra h, ff_tuning *t) {
   t->col_batched = h->col_batched;
   t->rsvd_qr = h->rsvd_qr;
   t->pair_fused = h->pair_fused;
+  t->gkb_graph = h->gkb_graph;
   return FF_OK;
 }
 
@@ -376,6 +380,7 @@ ff_status ff_set_tuning(ff_spectra h, const ff_tuning *t) {
   if (t->col_batched != 0 && t->col_batched != 1) return fail(FF_EINVAL, "ff_set_tuning: col_batched must be 0 or 1");
   if (t->rsvd_qr < 0 || t->rsvd_qr > 2) return fail(FF_EINVAL, "ff_set_tuning: rsvd_qr must be 0, 1 or 2");
   if (t->pair_fused < 0 || t->pair_fused > 2) return fail(FF_EINVAL, "ff_set_tuning: pair_fused must be 0, 1 or 2");
+  if (t->gkb_graph != 0 && t->gkb_graph != 1) return fail(FF_EINVAL, "ff_set_tuning: gkb_graph must be 0 or 1");
   h->lg_G = t->lg_G;
   h->lg_GT = t->lg_GT;
   h->row_tile = t->row_tile;
@@ -383,6 +388,8 @@ ff_status ff_set_tuning(ff_spectra h, const ff_tuning *t) {
   h->col_batched = t->col_batched;
   h->rsvd_qr = t->rsvd_qr;
   h->pair_fused = t->pair_fused;
+  h->gkb_graph = t->gkb_graph;
+  ++h->tune_version;
   return FF_OK;
 }
 

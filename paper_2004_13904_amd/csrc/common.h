@@ -111,6 +111,16 @@ struct ff_spectra_s {
   int col_batched = 1;                // 4-vectors-per-block column passes for block applies
   int rsvd_qr = 0;                    // RSVD orthonormalization: 0 CholQR2 first, 1 Householder, 2 CholQR3 first
   int pair_fused = 1;                 // grouped plans: G x and G^T d of this survey share one column pass
+  int gkb_graph = 0;                  // replay the GKB iteration loop from a captured graph
+  uint64_t tune_version = 0;          // bumped by every ff_set_tuning (captured launches depend on it)
+  // the captured GKB iteration loop and what it was captured for
+  void *gkb_exec = nullptr;           // hipGraphExec_t
+  const void *gkb_ws = nullptr;
+  size_t gkb_ws_bytes = 0;
+  int gkb_tp = 0, gkb_tb = 0;
+  uint64_t gkb_tune = 0;
+  hipStream_t cap_stream = nullptr;   // the handle's own stream for captures
+  void *blas = nullptr;               // rocblas_handle of this handle's solver calls
   void *ws_rows = nullptr;           // batch x nz x H x max(ny, sy) complex: row-pass <-> column-pass
   void *ws_cols = nullptr;           // batch x LG x H x max(sy, ...) complex: column-pass partials / D1
   size_t ws_rows_bytes = 0, ws_cols_bytes = 0;
@@ -148,4 +158,6 @@ ff_status kernel_table(ff_spectra h, double *table, hipStream_t s);
 int col_wave_groups(int dtype, int NY);
 // records profiling event `slot` (0..3) of the current profiled call, if profiling is on
 void prof_mark(ff_spectra h, int slot, int transpose, hipStream_t s);
+// destroys the handle's rocBLAS handle, if it has one (solvers.hip)
+void release_blas(ff_spectra h);
 }  // namespace ff

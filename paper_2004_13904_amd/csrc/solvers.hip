@@ -691,28 +691,35 @@ int partials_for(int64_t nrows, int rpl) {
   return (int)((nrows + rows - 1) / rows);
 }
 
-// rocBLAS handle per device, created on first use
-rocblas_handle blas(hipStream_t s, ff_status *st) {
-  static std::mutex mu;
-  static std::map<int, rocblas_handle> handles;
-  int dev = 0;
-  hipGetDevice(&dev);
-  std::lock_guard<std::mutex> lk(mu);
-  auto it = handles.find(dev);
-  rocblas_handle h = nullptr;
-  if (it == handles.end()) {
+// The spectra handle's rocBLAS handle, created on first use on the handle's device and bound to
+// the caller's stream: solver calls on different spectra handles (and so on different streams)
+// never share one.
+rocblas_handle blas(ff_spectra sh, hipStream_t s, ff_status *st) {
+  if (!sh->blas) {
+    rocblas_handle h = nullptr;
     if (rocblas_create_handle(&h) != rocblas_status_success) {
       *st = fail(FF_EHIP, "rocblas_create_handle failed");
       return nullptr;
     }
-    handles[dev] = h;
-  } else {
-    h = it->second;
+    sh->blas = h;
   }
-  rocblas_set_stream(h, s);
+  rocblas_handle h = (rocblas_handle)sh->blas;
+  if (rocblas_set_stream(h, s) != rocblas_status_success) {
+    *st = fail(FF_EHIP, "rocblas_set_stream failed");
+    return nullptr;
+  }
   *st = FF_OK;
   return h;
 }
+
+}  // namespace
+
+void release_blas(ff_spectra sh) {
+  if (sh->blas) rocblas_destroy_handle((rocblas_handle)sh->blas);
+  sh->blas = nullptr;
+}
+
+namespace {
 
 #define FF_BLAS(call, what)                                                       \
   do {                                                                            \
@@ -834,6 +841,7 @@ template <typename TB> struct GkbWs {
   TB *A, *H;
   int64_t ldA, ldH;
   double *b, *c, *gamma, *beta, *ginv, *binv, *coef, *part, *dT, *eT, *C, *S, *V, *u0, *g, *w, *alpha, *sq0, *sq1;
+  double *wdc, *winvc;   // copies of the weights, so that a captured iteration loop reads fixed addresses
   int *flag;
   rocblas_int *info;
   void carve(Arena &a, int64_t n, int64_t m, int tp) {
@@ -863,6 +871,8 @@ template <typename TB> struct GkbWs {
     alpha = a.take<double>(2);
     sq0 = a.take<double>(kNormBlocks);
     sq1 = a.take<double>((size_t)Pn);
+    wdc = a.take<double>(m);
+    winvc = a.take<double>(n);
     flag = a.take<int>(1);
     info = a.take<rocblas_int>(4);
   }
@@ -959,6 +969,48 @@ ff_status choose_alpha(ff_spectra h, int mode, double fixed, UpreIn q, const dou
   return FF_OK;
 }
 
+// Runs `loop` (launches only, on the stream it is given) on stream s: eagerly, or, when the
+// handle allows it, from a graph captured on the handle's own stream the first time and replayed
+// while the key (workspace, t_p, basis type, tuning) stays the same.  Graphs are not used while
+// the caller's stream is itself being captured (the launches then join that capture) or while
+// pass profiling is on.
+template <class Loop>
+ff_status run_captured(ff_spectra h, hipStream_t s, const void *ws, size_t ws_bytes, int tp, int tb, Loop &&loop) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) cs = hipStreamCaptureStatusActive;
+  if (!h->gkb_graph || h->prof_cap > 0 || cs != hipStreamCaptureStatusNone) return loop(s);
+  const bool hit = h->gkb_exec && h->gkb_ws == ws && h->gkb_ws_bytes == ws_bytes && h->gkb_tp == tp &&
+                   h->gkb_tb == tb && h->gkb_tune == h->tune_version;
+  if (!hit) {
+    if (h->gkb_exec) {
+      FF_HIP(hipGraphExecDestroy((hipGraphExec_t)h->gkb_exec));
+      h->gkb_exec = nullptr;
+    }
+    if (!h->cap_stream) FF_HIP(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    FF_HIP(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    ff_status st = loop(h->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+    if (st != FF_OK) {
+      if (g) hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "gkb_project: capture of the iteration loop");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "gkb_project: instantiation of the iteration graph");
+    h->gkb_exec = ex;
+    h->gkb_ws = ws;
+    h->gkb_ws_bytes = ws_bytes;
+    h->gkb_tp = tp;
+    h->gkb_tb = tb;
+    h->gkb_tune = h->tune_version;
+  }
+  FF_HIP(hipGraphLaunch((hipGraphExec_t)h->gkb_exec, s));
+  return FF_OK;
+}
+
 template <typename TB>
 ff_status gkb_run(ff_spectra h, const double *rt, const double *wd, const double *winv, int t, int tp, int mode,
                   double *y, double *alpha, double *sigma, void *ws, size_t ws_bytes, hipStream_t s) {
@@ -974,11 +1026,19 @@ ff_status gkb_run(ff_spectra h, const double *rt, const double *wd, const double
   if ((st = norm2(rt, m, W.beta, W.binv, W.part, s))) return st;
   k_scale_from<TB><<<grid_for(m), kThreads, 0, s>>>(rt, W.binv, W.H, W.c, m);
   FF_HIP(hipMemsetAsync(W.b, 0, sizeof(double) * n, s));
+  FF_HIP(hipMemcpyAsync(W.wdc, wd, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
+  FF_HIP(hipMemcpyAsync(W.winvc, winv, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  // The t_p iterations: about 24 launches each, none of which waits for the host.  With the
+  // handle's gkb_graph tuning they are captured once into a graph per (handle, workspace, t_p,
+  // basis type, tuning) and replayed on later solves; the graph reads only the workspace (the
+  // weights are copied there above), the handle's spectra and its pass buffers.
+  auto iterate = [&](hipStream_t s) -> ff_status {
+  ff_status st;
   for (int i = 0; i < tp; ++i) {
     TB *ai = W.A + (int64_t)i * W.ldA;
     const TB *hi = W.H + (int64_t)i * W.ldH;
     // b = G~^T h_i - beta_i a_{i-1}, reorthogonalized; gamma_i = ||b||
-    if ((st = op_apply(h, 1, 1, W.c, m, W.b, n, wd, winv, FF_F64, s))) return st;
+    if ((st = op_apply(h, 1, 1, W.c, m, W.b, n, W.wdc, W.winvc, FF_F64, s))) return st;
     if (i > 0)
       k_axpy_sumsq<TB><<<kNormBlocks, kThreads, 0, s>>>(W.b, W.A + (int64_t)(i - 1) * W.ldA, W.beta + i, -1.0, n,
                                                         W.sq0);
@@ -991,7 +1051,7 @@ ff_status gkb_run(ff_spectra h, const double *rt, const double *wd, const double
     else
       k_scale_store<TB><<<grid_for(n), kThreads, 0, s>>>(W.b, W.ginv + i, ai, n);
     // c = G~ a_i - gamma_i h_i, reorthogonalized; beta_{i+1} = ||c||
-    if ((st = op_apply(h, 0, 1, W.b, n, W.c, m, winv, wd, FF_F64, s))) return st;
+    if ((st = op_apply(h, 0, 1, W.b, n, W.c, m, W.winvc, W.wdc, FF_F64, s))) return st;
     k_axpy_sumsq<TB><<<kNormBlocks, kThreads, 0, s>>>(W.c, hi, W.gamma + i, -1.0, m, W.sq0);
     if ((st = reorth_norm<TB>(W.H, W.ldH, m, i + 1, W.c, W.coef, W.part, W.sq0, true, W.sq1, W.flag,
                               W.beta + i + 1, W.binv + i + 1, s, &dn)))
@@ -1004,10 +1064,14 @@ ff_status gkb_run(ff_spectra h, const double *rt, const double *wd, const double
       k_scale_store<TB><<<grid_for(m), kThreads, 0, s>>>(W.c, W.binv + i + 1, hn, m);
   }
   FF_LAUNCH_CHECK("gkb iteration");
+  return FF_OK;
+  };
+  if ((st = run_captured(h, s, (const void *)ws, ws_bytes, tp, (int)sizeof(TB), iterate))) return st;
+
   // SVD of the (tp+1) x tp bidiagonal through its Golub-Kahan tridiagonal
   const int n2 = 2 * tp + 1;
   k_tgk_build<<<(n2 + 255) / 256, 256, 0, s>>>(W.gamma, W.beta, tp, W.dT, W.eT);
-  rocblas_handle bh = blas(s, &st);
+  rocblas_handle bh = blas(h, s, &st);
   if (st) return st;
   FF_BLAS(rocsolver_dstedc(bh, rocblas_evect_tridiagonal, n2, W.dT, W.eT, W.C, n2, W.info), "rocsolver_dstedc");
   k_tgk_extract<<<grid_for((int64_t)tp * tp, 256, 1 << 30), 256, 0, s>>>(W.dT, W.C, tp, W.S, W.V, W.u0);
@@ -1153,7 +1217,7 @@ ff_status rsvd_run(ff_spectra h, const double *rt, const double *wd, const doubl
   if (n > INT32_MAX) return fail(FF_ENOTIMPL, "rsvd_project: n exceeds the eigensolver's index range");
   const double fixed = *alpha;
   ff_status st;
-  rocblas_handle bh = blas(s, &st);
+  rocblas_handle bh = blas(h, s, &st);
   if (st) return st;
   // Omega from the counter-based generator when not given (its tp x m values fill Bm, which
   // is not needed before the first product has read them)

@@ -75,7 +75,7 @@ class Operator:
         op._attach(h, survey)
         return op
 
-    TUNING_KEYS = ("lg_G", "lg_GT", "row_tile", "batch", "col_batched", "rsvd_qr", "pair_fused")
+    TUNING_KEYS = ("lg_G", "lg_GT", "row_tile", "batch", "col_batched", "rsvd_qr", "pair_fused", "gkb_graph")
 
     @property
     def batch_max(self):

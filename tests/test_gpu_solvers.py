@@ -486,3 +486,37 @@ def test_irls_step_c2(c2_problem):
     assert abs(chi2 - c_or) <= 1e-4 * c_or, (chi2, c_or)
     A.close()
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("basis", ["f64", "f32"])
+def test_gkb_graph_replay_equals_launches(basis):
+    # The GKB iteration loop captured into a graph at the first solve and replayed by the next
+    # ones (gkb_graph = 1) gives the same y, sigma and alpha bit for bit as the same loop launched
+    # kernel by kernel (gkb_graph = 0); the replays see new r~ and weights through the workspace
+    s, g, G, wd, winv, Gt, r = problem("medium", "magnetic", seed=3)
+    A = Operator(s, F32)
+    t, tp = 40, 48
+    ws = S._workspace(A, "gkb", tp, 0, None, basis)
+    rng = np.random.default_rng(8)
+    cases = [(r, wd, winv), (rng.standard_normal(g.m), 1.0 / (0.1 + rng.random(g.m)), 0.5 + rng.random(g.n))]
+    for rr, ww, wi in cases + cases[::-1]:
+        args = (to_dev(rr, F64), to_dev(ww, F64), to_dev(wi, F64), t, tp)
+        out = {}
+        for graph in (0, 1):
+            A.set_tuning(gkb_graph=graph)
+            y, a, sig = S.gkb_project(A, *args, alpha_mode="upre", ws=ws, basis=basis)
+            torch.cuda.synchronize()
+            out[graph] = (y.clone(), a, sig.clone())
+        assert torch.equal(out[0][0], out[1][0])
+        assert torch.equal(out[0][2], out[1][2])
+        assert out[0][1] == out[1][1]
+        # and the result is the oracle's Algorithm 1 within the FP32-operator bar
+        Gt2 = ww[:, None] * G * wi[None, :]
+        z, a_o, s_o = osol.gkb(lambda v: Gt2 @ v, lambda v: Gt2.T @ v, rr, g.n, t, tp, "upre")
+        assert rel(to_host(out[1][2]), s_o) <= 1e-5
+    # replays after a tuning change recapture (the key holds the tuning version)
+    A.set_tuning(gkb_graph=1, lg_G=2)
+    y2, _, _ = S.gkb_project(A, to_dev(r, F64), to_dev(wd, F64), to_dev(winv, F64), t, tp, alpha_mode="upre", ws=ws,
+                             basis=basis)
+    assert torch.isfinite(y2).all()
+    A.close()
