@@ -7,9 +7,9 @@
  *     entry the prism integral of the gravity (g_z) or magnetic (total-field anomaly) kernel.
  *   Appendix A: every G^(r) is embedded in a BCCB matrix; G x and G^T y are computed with
  *     2-D FFTs of the precomputed kernel spectra.
- *   Sec. 2.3, Algorithms 1 and 2: GKB and RSVD projected solves of the normal equations
- *     eq. (normalequations) with the UPRE regularization parameter; Sec. 2.2-2.3 the IRLS
- *     focusing iteration.
+ *   Sec. 2.4, Algorithms 1 and 2: GKB and RSVD projected solves of the normal equations
+ *     eq. (normalequations) of Sec. 2.3 with the UPRE regularization parameter; Secs. 2.2-2.3
+ *     the IRLS focusing iteration.
  *
  * Conventions for every entry point
  *   - Model vectors (length n = nx*ny*nz) are ordered (layer r, row q, column p), p fastest;
@@ -74,7 +74,7 @@ typedef struct {
 
 typedef struct ff_spectra_s *ff_spectra;
 
-/* Appendix A ("the 2DFFT of T is precomputed"): evaluates the per-offset kernel table
+/* Appendix A (the kernel spectra are formed once, before any product): evaluates the per-offset kernel table
    t_r(u, v) of every layer from the prism formulas in FP64, places it in the circulant
    array of the embedding and stores its 2-D DFT (scaled by 1/(nfft_x*nfft_y)) on the
    current device, as complex64 (dtype FF_F32) or complex128 (FF_F64).  Also allocates the
@@ -128,7 +128,7 @@ ff_status apply_G(ff_spectra h, const void *x, void *d, const void *w_pre, const
 ff_status apply_GT(ff_spectra h, const void *d, void *x, const void *w_pre, const void *w_post,
                    ff_stream stream);
 
-/* Sec. 2.4 ("matrix products are loops over columns") and Appendix A (cost of G X):
+/* Sec. 2.5 (a product with a matrix of t_p columns is that many vector products) and Appendix A:
    Y = w_post .* G (w_pre .* X) for transpose = 0, Y = w_post .* G^T (w_pre .* X) for
    transpose = 1, for k column vectors.  X is column-major with leading dimension ldx
    (>= n, or >= m when transposed), Y likewise with ldy.  The weights apply to every column.
@@ -174,7 +174,7 @@ ff_status ff_focusing_grad(ff_spectra h, int64_t k, const void *m, const void *r
                            double eps2, const double *scale, void *grad, ff_stream stream);
 
 /* ---------------------------------------------------------------------------------------
-   Projected solvers and IRLS (Sec. 2.3).  All vectors below are FP64 device arrays; the
+   Projected solvers (Sec. 2.4) and IRLS (Secs. 2.2-2.3).  All vectors below are FP64 device arrays; the
    operator applications inside run in the handle's dtype.  `workspace` is a caller-owned
    device buffer of at least ff_workspace_size(...) bytes (it holds the n x t_p basis). */
 
@@ -312,7 +312,7 @@ ff_status ff_time_pass(ff_spectra h, int32_t transpose, int32_t pass, int32_t re
                        ff_stream stream);
 
 /* ---------------------------------------------------------------------------------------
-   Several surveys at once (Sec. 2.4: the products are independent per column; here the columns
+   Several surveys at once (Sec. 2.5: the products are independent per column; here the columns
    belong to different surveys).  A plan binds, for count single-precision handles of distinct
    surveys, device vectors x[i] (n_i floats) -> gx[i] = G_i x[i] (m_i floats) and d[i] (m_i) ->
    gtd[i] = G_i^T d[i] (n_i); either pair of a survey may be NULL to skip that product.

@@ -17,7 +17,7 @@ The oracle computes the *definitions*, never the fast method:
 * ``solvers``   Algorithm 1 (GKB with MGS reorthogonalization), Algorithm 2 (RSVD
                 with one power iteration), the truncated UPRE and the closed-form
                 Tikhonov solution eq. (constantWL).
-* ``irls``      the focusing IRLS step of Sec. 2.3, depth weighting, noise model
+* ``irls``      the focusing IRLS step of Secs. 2.2-2.3, depth weighting, noise model
                 eq. (noisydata), chi^2 test eq. (scaledchi2), SNR and RE.
 
 Functions whose result the tests cannot pin to anything independent of the oracle

@@ -138,7 +138,7 @@ def apply_GT(geom: Geometry, d, table=None):
 
 
 def apply_G_cols(geom: Geometry, X, table=None):
-    """G X for an n x k block, column by column (the paper's loop over columns, Sec. 2.4)."""
+    """G X for an n x k block, column by column (a block product is a loop over its columns, Sec. 2.5)."""
     X = np.asarray(X, dtype=np.float64)
     return np.stack([apply_G(geom, X[:, c], table) for c in range(X.shape[1])], axis=1)
 

@@ -1,6 +1,6 @@
 """Projected solvers of the normal equations (oracle; test infrastructure only).
 
-Written from Sec. 2.3 of the paper in its order and notation, in FP64 NumPy:
+Written from Sec. 2.4 of the paper (Algorithms 1 and 2) in its order and notation, in FP64 NumPy:
 
 * ``gkb``     Algorithm 1: Golub-Kahan bidiagonalization G~ A = H B with modified
               Gram-Schmidt reorthogonalization of both bases, SVD of the
@@ -40,7 +40,7 @@ GOLDEN_TOL = 1e-10
 
 
 def gamma_filter(alpha, s):
-    """Gamma(alpha, Sigma) = diag(s_i / (s_i^2 + alpha^2)) (Sec. 2.3)."""
+    """Gamma(alpha, Sigma) = diag(s_i / (s_i^2 + alpha^2)) (Sec. 2.4, Algorithms 1 and 2)."""
     s = np.asarray(s, dtype=np.float64)
     return s / (s * s + alpha * alpha)
 

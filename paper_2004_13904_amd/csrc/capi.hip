@@ -246,7 +246,6 @@ ff_status ff_spectra_save(ff_spectra h, const char *path) {
 }
 
 ff_status ff_spectra_load(const char *path, ff_stream stream, ff_spectra *out) {
-  (void)stream;
   if (!path || !out) return fail(FF_EINVAL, "ff_spectra_load: NULL argument");
   *out = nullptr;
   FILE *f = std::fopen(path, "rb");
@@ -285,7 +284,11 @@ ff_status ff_spectra_load(const char *path, ff_stream stream, ff_spectra *out) {
     free_handle(h);
     return fail(FF_EINVAL, "ff_spectra_load: spectra truncated or corrupted");
   }
-  if (hipMemcpy(h->spec, buf.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+  // the upload is ordered on the caller's stream; the call returns once it is done (buf is host
+  // memory of this call)
+  const hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(h->spec, buf.data(), bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
     free_handle(h);
     return fail(FF_EHIP, "ff_spectra_load: spectra upload failed");
   }

@@ -77,6 +77,21 @@ ff_status hip_fail(hipError_t e, const char *what);
   }
 
 
+// The same dispatch for code that must release resources first: an unsupported size sets `st`.
+#define FF_SWITCH_N_SET(N, st, ...)                            \
+  switch (N) {                                                 \
+    case 8: { constexpr int NN = 8; __VA_ARGS__; } break;             \
+    case 16: { constexpr int NN = 16; __VA_ARGS__; } break;           \
+    case 32: { constexpr int NN = 32; __VA_ARGS__; } break;           \
+    case 64: { constexpr int NN = 64; __VA_ARGS__; } break;           \
+    case 128: { constexpr int NN = 128; __VA_ARGS__; } break;         \
+    case 256: { constexpr int NN = 256; __VA_ARGS__; } break;         \
+    case 512: { constexpr int NN = 512; __VA_ARGS__; } break;         \
+    case 1024: { constexpr int NN = 1024; __VA_ARGS__; } break;       \
+    case 2048: { constexpr int NN = 2048; __VA_ARGS__; } break;       \
+    default: st = ::ff::fail(FF_ENOTIMPL, "unsupported embedding size"); \
+  }
+
 inline bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 // Vectors per batched operator launch: each handle picks a batch (a multiple of 4 within

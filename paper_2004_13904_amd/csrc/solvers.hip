@@ -1,4 +1,5 @@
-// Projected solvers of the normal equations (Sec. 2.3 of the paper) and the IRLS step.
+// Projected solvers of the normal equations (Algorithms 1 and 2, Sec. 2.4 of the paper) and the IRLS
+// step (Secs. 2.2-2.3).
 //
 //  gkb_project  -- Algorithm 1: Golub-Kahan bidiagonalization of G~ = diag(wd) G diag(winv)
 //                  with reorthogonalization of both bases in FP64, SVD of the bidiagonal B,

@@ -1,4 +1,5 @@
-// Kernel spectra of the BCCB embedding (Appendix A: "the 2DFFT of T is precomputed").
+// Kernel spectra of the BCCB embedding (Appendix A: the 2-D DFT of each layer's kernel array is
+// formed once, before any product).
 //
 // 1. Every layer's kernel table t_r(u, v) -- the prism integral of Sec. 2.1 for the prism at
 //    station-to-prism offset (u, v) -- is evaluated in FP64 and placed at
@@ -229,7 +230,7 @@ ff_status make_spectra(ff_spectra h, hipStream_t s) {
   }
   st = launch_table(h, nullptr, circ, s);
   if (st == FF_OK) {
-    FF_SWITCH_N(NX, st = rows_fp64<NN>(circ, nz, NY, tmp, twx, s));
+    FF_SWITCH_N_SET(NX, st, st = rows_fp64<NN>(circ, nz, NY, tmp, twx, s));
   }
   if (st == FF_OK) {
     k_pack_dc_nyquist<<<dim3((NY + 255) / 256, nz), 256, 0, s>>>(tmp, H, NY);
@@ -239,9 +240,9 @@ ff_status make_spectra(ff_spectra h, hipStream_t s) {
   if (st == FF_OK) {
     const double scale = 1.0 / ((double)NX * (double)NY);
     if (h->dtype == FF_F32) {
-      FF_SWITCH_N(NY, st = (cols_fp64<float, NN>(tmp, nz, H, scale, h->spec, twy, s)));
+      FF_SWITCH_N_SET(NY, st, st = (cols_fp64<float, NN>(tmp, nz, H, scale, h->spec, twy, s)));
     } else {
-      FF_SWITCH_N(NY, st = (cols_fp64<double, NN>(tmp, nz, H, scale, h->spec, twy, s)));
+      FF_SWITCH_N_SET(NY, st, st = (cols_fp64<double, NN>(tmp, nz, H, scale, h->spec, twy, s)));
     }
   }
   if (st == FF_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(FF_EHIP, "build_spectra: kernels failed");

@@ -152,7 +152,7 @@ def test_fused_focusing_loss_equals_unfused_and_gradchecks():
     L2 = (r * r).sum() + alpha * (m2 * m2 / (m2 * m2 + eps2)).sum()
     (3.0 * L1).backward()           # an upstream factor reaches the gradient
     (3.0 * L2).backward()
-    assert abs(float(L1) - float(L2)) <= 1e-12 * abs(float(L2))
+    assert abs(float(L1.detach()) - float(L2.detach())) <= 1e-12 * abs(float(L2.detach()))
     assert rel(to_host(m1.grad), to_host(m2.grad)) <= 1e-12
     x = to_dev(m0[0], F64).requires_grad_(True)
     assert torch.autograd.gradcheck(lambda v: FocusingLoss.apply(A, v, d_obs[0], wd[0], alpha, eps2), (x,),

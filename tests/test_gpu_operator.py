@@ -320,7 +320,7 @@ def test_padded_size_ladder(ell, kernel):
 
 @pytest.mark.parametrize("ell,kernel", [(11, "magnetic"), (12, "gravity")])
 def test_high_resolution_ladder(ell, kernel):
-    # the high-resolution sizes of Sec. 3.3.4 (n = 998250 and 1296000, unpadded): 1024-point rows
+    # the high-resolution sizes of Sec. 3.3.3 (n = 998250 and 1296000, unpadded): 1024-point rows
     announce("ladder", ell, kernel)
     s = W.ladder_survey(ell, kernel, pad_fraction=0.0)
     assert W.sizes(s)[4] == {11: 998250, 12: 1296000}[ell]
