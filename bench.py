@@ -328,6 +328,9 @@ def main(argv=None):
         if a.irls_c2_basis == "f64" and a.irls_c2_steps <= 2:
             result["irls_magnetic_1m_f32basis"] = irls_c2_leg(a.irls_c2_steps, "f32", a.irls_c2_lambda,
                                                              a.irls_c2_stop)
+            for b in ("f32", "f64"):
+                result[f"irls_magnetic_1m_rsvd_{b}basis"] = irls_c2_leg(a.irls_c2_steps, b, a.irls_c2_lambda,
+                                                                       a.irls_c2_stop, solver="rsvd")
     if "study" in legs:
         result["study"] = study_leg([int(v) for v in a.study_ells.split(",")],
                                     [int(v) for v in a.study_s.split(",")], a.study_kinds.split(","),
@@ -864,13 +867,15 @@ def irls_leg(steps, lam=0.0, stop=False, basis="f64"):
             "alpha_1": hist[0][1], "alpha_K": hist[-1][1], "RE": round(re, 4)}
 
 
-def irls_c2_leg(steps, basis="f64", lam=0.0, stop=False):
+def irls_c2_leg(steps, basis="f64", lam=0.0, stop=False, solver="gkb"):
     """IRLS on the n = 1e6 magnetic survey (250 x 200 x 20, TFA with I = D = 45 deg): a 0.1 SI cube
     and a 45-degree dipping dike, 2 % noise (tau1 = 0.02, tau2 = 0.002), minimum support
-    (lambda = 0, eps^2 = 1e-9), depth weighting beta = 1.4, bounds [0, 0.1], GKB with
-    t = m/20 = 2500, t_p = 2625 (the n x t_p FP64 basis is 21 GB), FP32 operator.  Each step is
-    timed; the time is dominated by the FP64 reorthogonalization (at least t_p^2 (n + m) doubles
-    read per step)."""
+    (lambda = 0, eps^2 = 1e-9), depth weighting beta = 1.4, bounds [0, 0.1], t = m/20 = 2500,
+    t_p = 2625, FP32 operator.  GKB: the n x t_p FP64 basis is 21 GB and the time is dominated by
+    the reorthogonalization (at least t_p^2 (n + m) doubles read per step).  RSVD (one power
+    iteration, Omega drawn on the device): Q and G~^T B in FP64 are 63 GB, in FP32 storage 21 GB;
+    the time is the 4 t_p operator products and the Gram products of the QR factorizations.
+    Each step is timed."""
     import torch
 
     from paper_2004_13904_amd import solvers as SV
@@ -883,8 +888,8 @@ def irls_c2_leg(steps, basis="f64", lam=0.0, stop=False):
     eta, sd = W.noise(d_exact, 0.02, 0.002, 2)
     d_obs = torch.tensor(d_exact + eta, dtype=torch.float64, device="cuda")
     wd = torch.tensor(1.0 / sd, dtype=torch.float64, device="cuda")
-    p = SV.IrlsParams(solver="gkb", t=2500, tp=2625, lam=lam, eps2=1e-9, beta_depth=1.4, m_min=0.0,
-                      m_max=0.1, basis=basis)
+    p = SV.IrlsParams(solver=solver, t=2500, tp=2625, lam=lam, eps2=1e-9, beta_depth=1.4, m_min=0.0,
+                      m_max=0.1, basis=basis, seed=7)
     times = []
     t_last = [0.0]
 
@@ -893,7 +898,7 @@ def irls_c2_leg(steps, basis="f64", lam=0.0, stop=False):
         now = time.perf_counter()
         times.append(now - t_last[0])
         t_last[0] = now
-        log(f"irls (magnetic_1m) step {k}: alpha {alpha:.4g} chi2 {chi2:.4f} ({times[-1]:.2f} s)")
+        log(f"irls (magnetic_1m, {solver}, {basis}) step {k}: alpha {alpha:.4g} chi2 {chi2:.4f} ({times[-1]:.2f} s)")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     t_last[0] = t0
@@ -901,19 +906,26 @@ def irls_c2_leg(steps, basis="f64", lam=0.0, stop=False):
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     tp, n, mm = p.tp, A.n, A.m
-    # one Gram-Schmidt pass (Q^T v, then v - Q c) over both bases per iteration; the second pass
-    # runs only when the first cancels most of the vector
-    reorth_bytes = 2 * (8 if basis == "f64" else 4) * (n + mm) * tp * (tp + 1) / 2
     mt = m_true.double()
     re = float(torch.linalg.norm(mt - m) / torch.linalg.norm(mt))
-    return {"workload": "magnetic_1m: 250x200 stations, nz=20, cube + dipping dike, 2% noise, GKB t=2500 "
-                        "t_p=2625, FP32 operator, FP64 solve",
-            "lambda": lam, "basis": basis, "steps": len(hist), "converged": hist[-1][2] <= 1.0, "RE": round(re, 4),
-            "seconds_per_step": [round(x, 3) for x in times],
-            "seconds_per_step_after_first": round(float(np.mean(times[1:])), 3) if len(times) > 1 else None,
-            "seconds_total": round(total, 3), "chi2_scaled": [round(h[2], 4) for h in hist],
-            "reorth_bytes_per_step": reorth_bytes,
-            "reorth_GBs_if_all_time": round(reorth_bytes / (total / len(hist)) / 1e9, 1)}
+    ws = SV.workspace_bytes(A, "irls", tp, 0 if solver == "gkb" else 1, basis)
+    out = {"workload": f"magnetic_1m: 250x200 stations, nz=20, cube + dipping dike, 2% noise, {solver.upper()} "
+                       "t=2500 t_p=2625, FP32 operator, FP64 solve",
+           "solver": solver, "lambda": lam, "basis": basis, "workspace_GB": round(ws / 1e9, 2),
+           "steps": len(hist), "converged": hist[-1][2] <= 1.0, "RE": round(re, 4),
+           "seconds_per_step": [round(x, 3) for x in times],
+           "seconds_per_step_after_first": round(float(np.mean(times[1:])), 3) if len(times) > 1 else None,
+           "seconds_total": round(total, 3), "chi2_scaled": [round(h[2], 4) for h in hist]}
+    if solver == "gkb":
+        # one Gram-Schmidt pass (Q^T v, then v - Q c) over both bases per iteration; the second
+        # pass runs only when the first cancels most of the vector
+        reorth_bytes = 2 * (8 if basis == "f64" else 4) * (n + mm) * tp * (tp + 1) / 2
+        out["reorth_bytes_per_step"] = reorth_bytes
+        out["reorth_GBs_if_all_time"] = round(reorth_bytes / (total / len(hist)) / 1e9, 1)
+    A.close()
+    del m, m_true, d_obs, wd
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(s, x_h, d_h, gx_dev, gtd_dev):

@@ -182,7 +182,7 @@ ff_status ff_focusing_grad(ff_spectra h, int64_t k, const void *m, const void *r
 #define FF_WS_RSVD 1
 #define FF_WS_IRLS 2
 /* which: FF_WS_GKB, FF_WS_RSVD or FF_WS_IRLS (then solver 0 = GKB, 1 = RSVD); basis_dtype:
-   FF_F64 or FF_F32 storage of the GKB bases (ignored for RSVD); 1 <= tp <= m. */
+   FF_F64 or FF_F32 storage of the GKB bases or of the RSVD n x t_p matrices; 1 <= tp <= m. */
 ff_status ff_workspace_size(ff_spectra h, int32_t which, int32_t solver, int32_t basis_dtype, int32_t tp,
                             size_t *bytes);
 
@@ -212,11 +212,18 @@ ff_status gkb_project(ff_spectra h, const double *r_tilde, const double *wd, con
    Gram product, Cholesky, triangular inverse and product): two plain passes (CholeskyQR2),
    else three passes with a shifted first one (shifted CholeskyQR3), else Householder QR
    (geqrf + orgqr); a Cholesky result is accepted when every factorization succeeded and
-   max |Q^T Q - I| <= 1e-8.  The call synchronizes `stream` after each attempt. */
+   max |Q^T Q - I| <= 1e-8.  The call synchronizes `stream` after each attempt.
+   basis_dtype: FF_F64 stores every matrix of the algorithm in double precision; FF_F32 (FP32
+   handles only) stores the n x t_p matrices (Q and the copy kept for a second attempt) in
+   single precision, about 8 (n + m) t_p bytes of workspace instead of 8 (3n + m) t_p: their
+   Gram products and products with R^-1 run over row chunks converted to double, so all
+   arithmetic stays FP64, Q is orthonormal to about 1e-7 (an attempt is accepted at
+   max |Q^T Q - I| <= 1e-6) and, with no FP64 copy of the n x t_p matrix to fall back on, the call
+   returns FF_ENOTIMPL when both Cholesky attempts fail (or rsvd_qr = 1). */
 ff_status rsvd_project(ff_spectra h, const double *r_tilde, const double *wd, const double *winv,
                        int32_t t, int32_t tp, const double *omega, uint64_t seed, int32_t power_iters,
-                       int32_t alpha_mode, double *y, double *alpha, double *sigma, void *workspace,
-                       size_t ws_bytes, ff_stream stream);
+                       int32_t alpha_mode, int32_t basis_dtype, double *y, double *alpha, double *sigma,
+                       void *workspace, size_t ws_bytes, ff_stream stream);
 
 /* Counts of the RSVD orthonormalizations done on handle h so far: by CholeskyQR2, by shifted
    CholeskyQR3 and by Householder QR (see rsvd_project). */
@@ -234,7 +241,7 @@ typedef struct {
     double alpha_fixed;  /* > 0: use this alpha; otherwise eq. (eq:alpha1) at k = 1, UPRE after */
     int32_t power_iters; /* RSVD power iterations (the paper: 1)                            */
     uint64_t seed;       /* RSVD with omega = NULL: Omega drawn from (seed, counter word 2 = k) */
-    int32_t basis_dtype; /* GKB basis storage: FF_F64 or FF_F32 (see gkb_project)           */
+    int32_t basis_dtype; /* FF_F64 or FF_F32 storage of the n x t_p matrices (see gkb_project, rsvd_project) */
 } ff_irls_params;
 
 /* One IRLS step: W = W_z W_L^(k) with (W_L^(k))_ii = ((m_prev - m_prev2)_i^2 + eps2)^((lambda-2)/4)

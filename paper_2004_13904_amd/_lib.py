@@ -80,7 +80,7 @@ def load(path=None):
         "ff_apply_block_noalloc": [vp, i32, i64, vp, i64, vp, i64, vp, vp, vp],
         "ff_workspace_size": [vp, i32, i32, i32, i32, C.POINTER(C.c_size_t)],
         "gkb_project": [vp, vp, vp, vp, i32, i32, i32, i32, vp, dp, vp, vp, C.c_size_t, vp],
-        "rsvd_project": [vp, vp, vp, vp, i32, i32, vp, C.c_uint64, i32, i32, vp, dp, vp, vp, C.c_size_t, vp],
+        "rsvd_project": [vp, vp, vp, vp, i32, i32, vp, C.c_uint64, i32, i32, i32, vp, dp, vp, vp, C.c_size_t, vp],
         "irls_step": [vp, C.POINTER(FFIrlsParams), vp, vp, vp, vp, vp, vp, dp, dp, vp, C.c_size_t,
                       vp],
         "ff_get_tuning": [vp, C.POINTER(FFTuning)],

@@ -169,16 +169,17 @@ ff_status run_op(ff_spectra h, const OpWs &ws, int transpose, int kb, const TI *
   return FF_OK;
 }
 
-template <typename T, typename TIO>
+// k vectors of type TI in, of type TO out (the pre-weights are TI values, the post-weights TO)
+template <typename T, typename TI, typename TO>
 ff_status run(ff_spectra h, const OpWs &ws, int transpose, int64_t k, const void *X, int64_t ldx, void *Y,
               int64_t ldy, const void *w_pre, const void *w_post, hipStream_t s) {
-  const TIO *x = (const TIO *)X;
-  TIO *y = (TIO *)Y;
+  const TI *x = (const TI *)X;
+  TO *y = (TO *)Y;
   const int B = ws.batch;
   for (int64_t c0 = 0; c0 < k; c0 += B) {
     const int kb = (int)((k - c0) < B ? (k - c0) : B);
-    ff_status st = run_op<T, TIO, TIO>(h, ws, transpose, kb, x + c0 * ldx, ldx, y + c0 * ldy, ldy,
-                                       (const TIO *)w_pre, (const TIO *)w_post, s);
+    ff_status st = run_op<T, TI, TO>(h, ws, transpose, kb, x + c0 * ldx, ldx, y + c0 * ldy, ldy,
+                                     (const TI *)w_pre, (const TO *)w_post, s);
     if (st != FF_OK) return st;
   }
   return FF_OK;
@@ -249,12 +250,23 @@ ff_status op_apply_ws(ff_spectra h, const OpWs &ws, int transpose, int64_t k, co
                       int64_t ldy, const void *w_pre, const void *w_post, int io_dtype, hipStream_t s) {
   if (ws.batch < 1 || !ws.rows || !ws.cols) return fail(FF_EINVAL, "operator workspace is empty");
   if (h->dtype == FF_F32 && io_dtype == FF_F32)
-    return run<float, float>(h, ws, transpose, k, X, ldx, Y, ldy, w_pre, w_post, s);
+    return run<float, float, float>(h, ws, transpose, k, X, ldx, Y, ldy, w_pre, w_post, s);
   if (h->dtype == FF_F32 && io_dtype == FF_F64)
-    return run<float, double>(h, ws, transpose, k, X, ldx, Y, ldy, w_pre, w_post, s);
+    return run<float, double, double>(h, ws, transpose, k, X, ldx, Y, ldy, w_pre, w_post, s);
   if (h->dtype == FF_F64 && io_dtype == FF_F64)
-    return run<double, double>(h, ws, transpose, k, X, ldx, Y, ldy, w_pre, w_post, s);
+    return run<double, double, double>(h, ws, transpose, k, X, ldx, Y, ldy, w_pre, w_post, s);
   return fail(FF_EDTYPE, "vector dtype not supported for this handle");
+}
+
+ff_status op_apply_io(ff_spectra h, int transpose, int64_t k, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                      const void *w_pre, const void *w_post, int in_dtype, int out_dtype, hipStream_t s) {
+  if (in_dtype == out_dtype) return op_apply(h, transpose, k, X, ldx, Y, ldy, w_pre, w_post, in_dtype, s);
+  const OpWs ws = handle_ws(h);
+  if (h->dtype == FF_F32 && in_dtype == FF_F64 && out_dtype == FF_F32)
+    return run<float, double, float>(h, ws, transpose, k, X, ldx, Y, ldy, w_pre, w_post, s);
+  if (h->dtype == FF_F32 && in_dtype == FF_F32 && out_dtype == FF_F64)
+    return run<float, float, double>(h, ws, transpose, k, X, ldx, Y, ldy, w_pre, w_post, s);
+  return fail(FF_EDTYPE, "vector dtypes not supported for this handle");
 }
 
 ff_status op_apply(ff_spectra h, int transpose, int64_t k, const void *X, int64_t ldx, void *Y, int64_t ldy,

@@ -165,6 +165,10 @@ ff_status op_apply(ff_spectra h, int transpose, int64_t k, const void *X, int64_
 ff_status op_apply_ws(ff_spectra h, const OpWs &ws, int transpose, int64_t k, const void *X, int64_t ldx,
                       void *Y, int64_t ldy, const void *w_pre, const void *w_post, int io_dtype, hipStream_t s);
 void op_ws_per_vector(ff_spectra h, int transpose, size_t *rows_bytes, size_t *cols_bytes);
+// vectors of one type in and another out (single-precision handles: FP64 in, FP32 out or the
+// reverse); w_pre has the input type, w_post the output type
+ff_status op_apply_io(ff_spectra h, int transpose, int64_t k, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                      const void *w_pre, const void *w_post, int in_dtype, int out_dtype, hipStream_t s);
 ff_status op_time_pass(ff_spectra h, int transpose, int pass, int reps, const void *X, void *Y, hipStream_t s);
 // spectra construction (spectra.hip)
 ff_status make_spectra(ff_spectra h, hipStream_t s);

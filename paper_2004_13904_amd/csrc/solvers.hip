@@ -592,6 +592,25 @@ __global__ void k_sum_slices(const double *__restrict__ Gs, int P, int64_t cc, d
 
 // zero the strictly lower triangle of the column-major cols x cols R^-1, so that a plain product
 // with it reads only the triangle
+// rows r0 .. r0 + rows - 1 of the column-major single-precision matrix Q (ld rows) to the
+// rows x cols double matrix C, and back
+__global__ void k_rows_to64(const float *__restrict__ Q, int64_t ld, int64_t r0, int64_t rows, int cols,
+                            double *__restrict__ C) {
+  for (int c = blockIdx.y; c < cols; c += gridDim.y)
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rows; r += (int64_t)gridDim.x * blockDim.x)
+      C[(int64_t)c * rows + r] = (double)Q[(int64_t)c * ld + r0 + r];
+}
+__global__ void k_rows_to32(const double *__restrict__ C, int64_t rows, int cols, float *__restrict__ Q, int64_t ld,
+                            int64_t r0) {
+  for (int c = blockIdx.y; c < cols; c += gridDim.y)
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rows; r += (int64_t)gridDim.x * blockDim.x)
+      Q[(int64_t)c * ld + r0 + r] = (float)C[(int64_t)c * rows + r];
+}
+__global__ void k_to_f32(const double *__restrict__ x, int64_t n, float *__restrict__ y) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+
 __global__ void k_zero_lower(double *__restrict__ A, int cols) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)cols * cols) return;
@@ -925,6 +944,52 @@ struct RsvdWs {
   }
 };
 
+// Algorithm 2 with the n x t_p matrices (Q and the copy kept for a second Cholesky QR attempt)
+// stored in single precision: they are streamed through FP64 row chunks (Ca, Cb) for the Gram
+// products and the products with R^-1, so every product and sum is still formed in double.
+// The m x t_p matrices and the projected problem stay FP64.
+int64_t lean_chunk_rows(int64_t n, int tp) {
+  int64_t r = ((int64_t)1 << 26) / (tp > 0 ? tp : 1);   // 512 MB of doubles per staging buffer
+  if (r < 4096) r = 4096;
+  return r > n ? n : r;
+}
+
+struct RsvdWs32 {
+  float *Q, *M, *winv32;
+  double *Bm, *T, *U, *Gs, *Ca, *Cb, *dev, *Y, *lam, *E, *S, *Vs, *btr, *c, *g, *w, *tau, *alpha, *part;
+  int *perm;
+  rocblas_int *info;
+  int64_t CH;
+  void carve(Arena &a, int64_t n, int64_t m, int tp) {
+    const int64_t P = ((n > m ? n : m) + kRowsMin - 1) / kRowsMin + 1;
+    CH = lean_chunk_rows(n, tp);
+    Q = a.take<float>((size_t)n * tp);
+    M = a.take<float>((size_t)n * tp);
+    winv32 = a.take<float>(n);
+    Bm = a.take<double>((size_t)m * tp);     // G~ Q, and Omega when drawn here
+    T = a.take<double>((size_t)m * tp);      // QR scratch of the m x t_p factors
+    U = a.take<double>((size_t)m * tp);
+    Gs = a.take<double>(gram_scratch(m, tp));
+    Ca = a.take<double>((size_t)CH * tp);
+    Cb = a.take<double>((size_t)CH * tp);
+    dev = a.take<double>(1);
+    Y = a.take<double>((size_t)tp * tp);
+    lam = a.take<double>(tp);
+    E = a.take<double>(tp);
+    S = a.take<double>(tp);
+    Vs = a.take<double>((size_t)tp * tp);
+    btr = a.take<double>(tp);
+    c = a.take<double>(tp);
+    g = a.take<double>(tp);
+    w = a.take<double>(tp);
+    tau = a.take<double>(tp);
+    alpha = a.take<double>(2);
+    part = a.take<double>((size_t)((P > 256 ? P : 256) + 1) * (tp + 2));
+    perm = a.take<int>(tp);
+    info = a.take<rocblas_int>(8);
+  }
+};
+
 struct IrlsWs {
   double *winv, *r, *gm, *y, *zw, *sig, *part, *nrm;
   void carve(Arena &a, int64_t n, int64_t m, int nz, int tp) {
@@ -1207,6 +1272,161 @@ ff_status qr_inplace(ff_spectra h, rocblas_handle bh, double *M, int64_t rows, i
   return householder_qr(bh, M, rows, cols, tau);
 }
 
+// ---- Cholesky QR of the single-precision basis --------------------------------------------
+dim3 chunk_grid(int64_t rows, int cols) {
+  const int64_t bx = (rows + kThreads - 1) / kThreads;
+  return dim3((unsigned)(bx < 64 ? bx : 64), (unsigned)(cols < 65535 ? cols : 65535));
+}
+
+// G = Q^T Q over row chunks staged in FP64 (the chunks' products accumulated in order)
+ff_status gram32(rocblas_handle bh, const float *Q, int64_t n, int tp, RsvdWs32 &W, double *G, hipStream_t s) {
+  const double one = 1.0, zero = 0.0;
+  for (int64_t r0 = 0; r0 < n; r0 += W.CH) {
+    const int64_t rows = n - r0 < W.CH ? n - r0 : W.CH;
+    k_rows_to64<<<chunk_grid(rows, tp), kThreads, 0, s>>>(Q, n, r0, rows, tp, W.Ca);
+    FF_LAUNCH_CHECK("basis chunk to FP64");
+    FF_BLAS(rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, tp, tp, (rocblas_int)rows, &one,
+                          W.Ca, (rocblas_int)rows, W.Ca, (rocblas_int)rows, r0 == 0 ? &zero : &one, G, tp),
+            "rocblas_dgemm (chunked Gram)");
+  }
+  return FF_OK;
+}
+
+// Q <- Q Rinv over row chunks (Rinv upper triangular, lower part zero)
+ff_status right_mult32(rocblas_handle bh, float *Q, int64_t n, int tp, const double *Rinv, RsvdWs32 &W,
+                       hipStream_t s) {
+  const double one = 1.0, zero = 0.0;
+  for (int64_t r0 = 0; r0 < n; r0 += W.CH) {
+    const int64_t rows = n - r0 < W.CH ? n - r0 : W.CH;
+    k_rows_to64<<<chunk_grid(rows, tp), kThreads, 0, s>>>(Q, n, r0, rows, tp, W.Ca);
+    FF_LAUNCH_CHECK("basis chunk to FP64");
+    FF_BLAS(rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_none, (rocblas_int)rows, tp, tp, &one, W.Ca,
+                          (rocblas_int)rows, Rinv, tp, &zero, W.Cb, (rocblas_int)rows),
+            "rocblas_dgemm (chunked Q R^-1)");
+    k_rows_to32<<<chunk_grid(rows, tp), kThreads, 0, s>>>(W.Cb, rows, tp, Q, n, r0);
+    FF_LAUNCH_CHECK("basis chunk to FP32");
+  }
+  return FF_OK;
+}
+
+// The stored single-precision Q is orthonormal to about its own rounding; an attempt is
+// accepted at max |Q^T Q - I| <= this bound.
+constexpr double kDefect32 = 1e-6;
+
+// One Cholesky QR attempt in place on the single-precision W.Q (as cholesky_qr, chunked).
+ff_status cholesky_qr32(rocblas_handle bh, int64_t n, int tp, int passes, bool shift, RsvdWs32 &W, hipStream_t s,
+                        bool *ok) {
+  const rocblas_int c = tp;
+  FF_HIP(hipMemsetAsync(W.info, 0, 8 * sizeof(rocblas_int), s));
+  for (int p = 0; p < passes; ++p) {
+    ff_status st = gram32(bh, W.Q, n, tp, W, W.Y, s);
+    if (st) return st;
+    if (p == 0 && shift) {
+      k_gram_shift<<<1, kThreads, 0, s>>>(W.Y, c, n);
+      FF_LAUNCH_CHECK("gram shift");
+    }
+    FF_BLAS(rocsolver_dpotrf(bh, rocblas_fill_upper, c, W.Y, c, W.info + 2 * p), "rocsolver_dpotrf");
+    FF_BLAS(rocsolver_dtrtri(bh, rocblas_fill_upper, rocblas_diagonal_non_unit, c, W.Y, c, W.info + 2 * p + 1),
+            "rocsolver_dtrtri");
+    k_zero_lower<<<grid_for((int64_t)c * c, 256, 1 << 30), 256, 0, s>>>(W.Y, c);
+    FF_LAUNCH_CHECK("zero lower");
+    if ((st = right_mult32(bh, W.Q, n, tp, W.Y, W, s))) return st;
+  }
+  ff_status st = gram32(bh, W.Q, n, tp, W, W.Y, s);
+  if (st) return st;
+  FF_HIP(hipMemsetAsync(W.dev, 0, sizeof(double), s));
+  k_orth_defect<<<c < 1024 ? c : 1024, kThreads, 0, s>>>(W.Y, c, (unsigned long long *)W.dev);
+  FF_LAUNCH_CHECK("orthogonality check");
+  struct {
+    rocblas_int info[8];
+    double defect;
+  } hs;
+  FF_HIP(hipMemcpyAsync(hs.info, W.info, sizeof(hs.info), hipMemcpyDeviceToHost, s));
+  FF_HIP(hipMemcpyAsync(&hs.defect, W.dev, sizeof(double), hipMemcpyDeviceToHost, s));
+  FF_HIP(hipStreamSynchronize(s));
+  bool good = hs.defect <= kDefect32;
+  for (int i = 0; i < 2 * passes; ++i) good = good && hs.info[i] == 0;
+  *ok = good;
+  return FF_OK;
+}
+
+// Orthonormal basis of the columns of the single-precision n x tp matrix W.Q, in place:
+// CholeskyQR2, then shifted CholeskyQR3 on the kept input (as qr_inplace).  Householder QR, the
+// last resort of the double-precision path, would need the FP64 matrix this variant avoids: if
+// both Cholesky attempts fail the call fails (FF_ENOTIMPL).
+ff_status qr32(ff_spectra h, rocblas_handle bh, int64_t n, int tp, RsvdWs32 &W, hipStream_t s) {
+  if (h->rsvd_qr == 1)
+    return fail(FF_ENOTIMPL, "rsvd_project: Householder QR needs FP64 basis storage (rsvd_qr = 1)");
+  FF_HIP(hipMemcpyAsync(W.M, W.Q, sizeof(float) * n * tp, hipMemcpyDeviceToDevice, s));
+  for (int attempt = h->rsvd_qr == 2 ? 1 : 0; attempt < 2; ++attempt) {
+    if (attempt == 1) FF_HIP(hipMemcpyAsync(W.Q, W.M, sizeof(float) * n * tp, hipMemcpyDeviceToDevice, s));
+    bool ok = false;
+    ff_status st = cholesky_qr32(bh, n, tp, attempt == 0 ? 2 : 3, attempt == 1, W, s, &ok);
+    if (st) return st;
+    if (ok) {
+      (attempt == 0 ? h->qr_cholesky2 : h->qr_cholesky3) += 1;
+      return FF_OK;
+    }
+  }
+  return fail(FF_ENOTIMPL, "rsvd_project: Cholesky QR of the single-precision basis failed; use FP64 storage");
+}
+
+// Algorithm 2 with the n x t_p matrices stored in single precision (see RsvdWs32); the steps
+// are those of rsvd_run.
+ff_status rsvd_run32(ff_spectra h, const double *rt, const double *wd, const double *winv, int t, int tp,
+                     const double *omega, uint64_t seed, uint32_t stream, int power_iters, int mode, double *y,
+                     double *alpha, double *sigma, void *ws, size_t ws_bytes, hipStream_t s) {
+  const int64_t n = h->n, m = h->m;
+  if (h->dtype != FF_F32) return fail(FF_EDTYPE, "rsvd_project: FP32 basis storage needs an FP32 handle");
+  Arena ar{(char *)ws, ws_bytes, 0, false};
+  RsvdWs32 W;
+  W.carve(ar, n, m, tp);
+  if (ar.used > ws_bytes) return fail(FF_ENOMEM, "rsvd_project: workspace too small");
+  if (n > INT32_MAX) return fail(FF_ENOTIMPL, "rsvd_project: n exceeds the eigensolver's index range");
+  const double fixed = *alpha;
+  ff_status st;
+  rocblas_handle bh = blas(h, s, &st);
+  if (st) return st;
+  // W^-1 as the post-weights of the products that produce the single-precision n x tp matrices
+  k_to_f32<<<grid_for(n), kThreads, 0, s>>>(winv, n, W.winv32);
+  if (!omega) {
+    k_gaussian<<<grid_for((int64_t)tp * m), kThreads, 0, s>>>(W.Bm, (int64_t)tp * m, seed, stream);
+    omega = W.Bm;
+  }
+  FF_LAUNCH_CHECK("rsvd setup");
+  // Y^T = G~^T Omega^T (n x tp, stored FP32), Q = qr(Y^T)
+  if ((st = op_apply_io(h, 1, tp, omega, m, W.Q, n, wd, W.winv32, FF_F64, FF_F32, s))) return st;
+  if ((st = qr32(h, bh, n, tp, W, s))) return st;
+  for (int q = 0; q < power_iters; ++q) {
+    if ((st = op_apply_io(h, 0, tp, W.Q, n, W.Bm, m, W.winv32, wd, FF_F32, FF_F64, s))) return st;
+    if ((st = qr_inplace(h, bh, W.Bm, m, tp, W.tau, W.T, W.U, W.Y, W.Gs, W.dev, W.info, s))) return st;
+    if ((st = op_apply_io(h, 1, tp, W.Bm, m, W.Q, n, wd, W.winv32, FF_F64, FF_F32, s))) return st;
+    if ((st = qr32(h, bh, n, tp, W, s))) return st;
+  }
+  // B = G~ Q
+  if ((st = op_apply_io(h, 0, tp, W.Q, n, W.Bm, m, W.winv32, wd, FF_F32, FF_F64, s))) return st;
+  const double one = 1.0, zero = 0.0;
+  FF_BLAS(rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, tp, tp, (rocblas_int)m, &one, W.Bm,
+                        (rocblas_int)m, W.Bm, (rocblas_int)m, &zero, W.Y, tp),
+          "rocblas_dgemm");
+  FF_BLAS(rocsolver_dsyevd(bh, rocblas_evect_original, rocblas_fill_lower, tp, W.Y, tp, W.lam, W.E, W.info),
+          "rocsolver_dsyevd");
+  k_rsvd_sort<<<(tp + 255) / 256, 256, 0, s>>>(W.lam, tp, W.S, W.perm);
+  k_gather_cols<<<grid_for((int64_t)tp * t, 256, 1 << 30), 256, 0, s>>>(W.Y, tp, tp, W.perm, t, W.Vs);
+  if ((st = gemv_t(W.Bm, m, m, tp, rt, W.btr, W.part, s))) return st;
+  k_rsvd_coef<<<(t + 255) / 256, 256, 0, s>>>(W.Vs, tp, W.btr, W.S, t, W.c);
+  UpreIn q{W.S, W.c, nullptr, 0, nullptr, t};
+  if ((st = choose_alpha(h, mode, fixed, q, W.S, tp, W.alpha, s))) return st;
+  k_filter<<<(t + 255) / 256, 256, 0, s>>>(W.S, W.alpha, q, t, W.g);
+  if ((st = gemv_n(W.Vs, tp, tp, t, W.g, W.w, 1.0, s))) return st;
+  launch_gemv_n<float>(W.Q, n, n, tp, W.w, y, 1.0, 0.0, s);
+  FF_LAUNCH_CHECK("rsvd solution");
+  FF_HIP(hipMemcpyAsync(sigma, W.S, sizeof(double) * tp, hipMemcpyDeviceToDevice, s));
+  FF_HIP(hipMemcpyAsync(alpha, W.alpha, sizeof(double), hipMemcpyDeviceToHost, s));
+  FF_HIP(hipStreamSynchronize(s));
+  return FF_OK;
+}
+
 ff_status rsvd_run(ff_spectra h, const double *rt, const double *wd, const double *winv, int t, int tp,
                    const double *omega, uint64_t seed, uint32_t stream, int power_iters, int mode, double *y,
                    double *alpha, double *sigma, void *ws, size_t ws_bytes, hipStream_t s) {
@@ -1276,7 +1496,10 @@ size_t irls_own_bytes(ff_spectra h, int tp) {
 size_t solver_bytes(ff_spectra h, int which, int solver, int basis, int tp) {
   Arena ar{nullptr, 0, 0, true};
   const int sol = which == FF_WS_IRLS ? solver : (which == FF_WS_RSVD ? 1 : 0);
-  if (sol == 1) {
+  if (sol == 1 && basis == FF_F32) {
+    RsvdWs32 W;
+    W.carve(ar, h->n, h->m, tp);
+  } else if (sol == 1) {
     RsvdWs W;
     W.carve(ar, h->n, h->m, tp);
   } else if (basis == FF_F32) {
@@ -1334,12 +1557,18 @@ ff_status ff_solver_stats(ff_spectra h, int64_t *qr_cholesky2, int64_t *qr_chole
 
 ff_status rsvd_project(ff_spectra h, const double *r_tilde, const double *wd, const double *winv, int32_t t,
                        int32_t tp, const double *omega, uint64_t seed, int32_t power_iters, int32_t alpha_mode,
-                       double *y, double *alpha, double *sigma, void *workspace, size_t ws_bytes, ff_stream stream) {
+                       int32_t basis_dtype, double *y, double *alpha, double *sigma, void *workspace, size_t ws_bytes,
+                       ff_stream stream) {
   ff_status st = check_solver_args("rsvd_project", h, t, tp, r_tilde, wd, winv, y, alpha, sigma, workspace);
   if (st) return st;
   if (power_iters < 0 || power_iters > kMaxPowerIters)
     return fail(FF_EINVAL, "rsvd_project: power_iters must lie in [0, 8]");
   if (alpha_mode < 0 || alpha_mode > 2) return fail(FF_EINVAL, "rsvd_project: alpha_mode must be 0, 1 or 2");
+  if (basis_dtype != FF_F64 && basis_dtype != FF_F32)
+    return fail(FF_EDTYPE, "rsvd_project: basis_dtype must be FF_F64 or FF_F32");
+  if (basis_dtype == FF_F32)
+    return rsvd_run32(h, r_tilde, wd, winv, t, tp, omega, seed, 0u, power_iters, alpha_mode, y, alpha, sigma,
+                      workspace, ws_bytes, (hipStream_t)stream);
   return rsvd_run(h, r_tilde, wd, winv, t, tp, omega, seed, 0u, power_iters, alpha_mode, y, alpha, sigma, workspace,
                   ws_bytes, (hipStream_t)stream);
 }
@@ -1396,6 +1625,9 @@ ff_status irls_step(ff_spectra h, const ff_irls_params *p, const double *d_obs, 
   if (p->solver == 0)
     st = p->basis_dtype == FF_F32 ? gkb_run<float>(h, I.r, wd, I.winv, p->t, p->tp, mode, I.y, &a, I.sig, workspace, sol, s)
                                   : gkb_run<double>(h, I.r, wd, I.winv, p->t, p->tp, mode, I.y, &a, I.sig, workspace, sol, s);
+  else if (p->basis_dtype == FF_F32)
+    st = rsvd_run32(h, I.r, wd, I.winv, p->t, p->tp, omega, p->seed, (uint32_t)p->k, p->power_iters, mode, I.y, &a,
+                    I.sig, workspace, sol, s);
   else
     st = rsvd_run(h, I.r, wd, I.winv, p->t, p->tp, omega, p->seed, (uint32_t)p->k, p->power_iters, mode, I.y, &a,
                   I.sig, workspace, sol, s);

@@ -59,20 +59,21 @@ def gkb_project(op, r_tilde, wd, winv, t, tp, alpha_mode="upre", alpha=None, ws=
 
 
 def rsvd_project(op, r_tilde, wd, winv, t, tp, omega=None, alpha_mode="upre", alpha=None, ws=None,
-                 stream=None, seed=0, power_iters=1):
+                 stream=None, seed=0, power_iters=1, basis="f64"):
     """omega: (tp, m) float64 Gaussian matrix, or None to draw it on the device from `seed`
-    (Philox4x32-10, see rsvd_project in include/fastfocus.h).  Returns (y, alpha, sigma)."""
+    (Philox4x32-10, see rsvd_project in include/fastfocus.h).  basis: "f64" (default) or "f32"
+    storage of the n x t_p matrices.  Returns (y, alpha, sigma)."""
     _f64(op, r_tilde, op.m, "rsvd_project")
     _f64(op, wd, op.m, "rsvd_project")
     _f64(op, winv, op.n, "rsvd_project")
     if omega is not None:
         _f64(op, omega, tp * op.m, "rsvd_project")
-    ws = _workspace(op, "rsvd", tp, 1, ws)
+    ws = _workspace(op, "rsvd", tp, 1, ws, basis)
     y = torch.empty(op.n, dtype=torch.float64, device=op.device)
     sigma = torch.empty(tp, dtype=torch.float64, device=op.device)
     a = C.c_double(float(alpha) if alpha is not None else 0.0)
     L.call("rsvd_project", op.h, _ptr(r_tilde), _ptr(wd), _ptr(winv), int(t), int(tp), _ptr(omega),
-           int(seed), int(power_iters), ALPHA_MODES[alpha_mode], _ptr(y), C.byref(a), _ptr(sigma), _ptr(ws),
+           int(seed), int(power_iters), ALPHA_MODES[alpha_mode], BASIS[basis], _ptr(y), C.byref(a), _ptr(sigma), _ptr(ws),
            ws.numel(), _stream(stream))
     return y, a.value, sigma
 

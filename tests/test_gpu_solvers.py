@@ -520,3 +520,87 @@ def test_gkb_graph_replay_equals_launches(basis):
                              basis=basis)
     assert torch.isfinite(y2).all()
     A.close()
+
+
+@pytest.mark.parametrize("mode", ["fixed", "upre", "alpha1"])
+@pytest.mark.parametrize("qr,power", [(0, 1), (2, 1), (0, 0), (0, 2)])
+def test_rsvd_single_precision_basis(mode, qr, power):
+    # Algorithm 2 with the n x t_p matrices stored in FP32 (chunked FP64 Gram products and R^-1
+    # products, FP64 projected problem) against the oracle's Algorithm 2 at the FP32-operator bar
+    s, g, G, wd, winv, Gt, r = problem("mid", kernel="gravity", seed=2)
+    t, tp = 60, 63
+    announce("rsvd f32 basis", mode, "qr", qr, "power", power)
+    omega = np.random.default_rng(4).standard_normal((tp, g.m))
+    y0, a0, s0, F = osol.rsvd(*dense_ops(Gt), r, g.n, t, tp, omega, mode, 2.0, return_factors=True,
+                              power_iters=power)
+    A = Operator(s, F32)
+    A.set_tuning(rsvd_qr=qr)
+    args = (to_dev(r, F64), to_dev(wd, F64), to_dev(winv, F64), t, tp, to_dev(omega, F64))
+    y, a, sig = S.rsvd_project(A, *args, mode, 2.0, power_iters=power, basis="f32")
+    assert rel(to_host(sig)[:t], s0[:t]) <= 2e-5
+    c0 = F["U"].T @ (F["B"].T @ r)
+    check_alpha(mode, a, a0, s0[:t], c0, F32)
+    ya = S.rsvd_project(A, *args, "fixed", a0, power_iters=power, basis="f32")[0]
+    assert rel(to_host(ya), y0) <= 1e-4
+    # the same problem with FP64 storage agrees to the FP32 storage's rounding
+    yd = S.rsvd_project(A, *args, "fixed", a0, power_iters=power, basis="f64")[0]
+    assert rel(to_host(ya), to_host(yd)) <= 1e-5
+
+
+
+def test_rsvd_single_precision_basis_workspace_and_errors():
+    # at the n = 1e6 magnetic survey with t_p = 2625 the FP32 storage keeps the workspace of
+    # Algorithm 2 (and of the IRLS step around it) under 32 GB, against over 60 GB with the n x t_p
+    # matrices in FP64; Householder QR (rsvd_qr = 1) needs FP64 storage, and an FP64 handle
+    # rejects FP32 storage
+    A = Operator(W.SURVEYS["magnetic_1m"], F32)
+    tp = 2625
+    b64 = S.workspace_bytes(A, "rsvd", tp, 1, "f64")
+    b32 = S.workspace_bytes(A, "rsvd", tp, 1, "f32")
+    i32 = S.workspace_bytes(A, "irls", tp, 1, "f32")
+    announce("rsvd workspace", b64 / 1e9, b32 / 1e9, i32 / 1e9)
+    assert b64 > 60e9 and b32 <= 32e9 and i32 <= 32e9
+    assert b32 >= 8 * A.n * tp       # the two n x t_p FP32 matrices
+    A.close()
+    s, g, G, wd, winv, Gt, r = problem("mid", kernel="gravity", seed=2)
+    A = Operator(s, F32)
+    A.set_tuning(rsvd_qr=1)
+    args = (to_dev(r, F64), to_dev(wd, F64), to_dev(winv, F64), 20, 21)
+    with pytest.raises(L.FastFocusError) as e:
+        S.rsvd_project(A, *args, None, "fixed", 2.0, basis="f32")
+    assert e.value.code == L.FF_ENOTIMPL
+    B = Operator(s, F64)
+    with pytest.raises(L.FastFocusError) as e:
+        S.rsvd_project(B, *args, None, "fixed", 2.0, basis="f32")
+    assert e.value.code == L.FF_EDTYPE
+
+
+def test_irls_rsvd_single_precision_basis_matches_oracle():
+    # two IRLS steps with RSVD and FP32 storage of the n x t_p matrices against the oracle's steps
+    s = W.survey(16, 12, 5, 25, 25, 25)
+    g = ogeom(s)
+    G = op.dense_G(g)
+    rng = np.random.default_rng(3)
+    m_true = np.zeros(g.n)
+    m_true[rng.choice(g.n, 20, replace=False)] = 1.0
+    d_exact = G @ m_true
+    eta, sd = W.noise(d_exact, 0.02, 0.002, 5)
+    d_obs = d_exact + eta
+    wd = 1.0 / sd
+    t, tp = 40, 42
+    omega = rng.standard_normal((tp, g.m))
+    A = Operator(s, F32)
+    po = oirls.IrlsParams(solver="rsvd", t=t, tp=tp, lam=0.0, beta_depth=0.8, m_min=0.0, m_max=1.0)
+    pg = S.IrlsParams(solver="rsvd", t=t, tp=tp, lam=0.0, beta_depth=0.8, m_min=0.0, m_max=1.0, basis="f32")
+    m1o, a1o, c1o, _ = oirls.irls_step(g, po, 1, d_obs, wd, np.zeros(g.n), None, omega, G_dense=G)
+    m1, a1, c1 = S.irls_step(A, pg, 1, to_dev(d_obs, F64), to_dev(wd, F64),
+                             torch.zeros(g.n, dtype=F64, device="cuda"), None, to_dev(omega, F64))
+    assert abs(a1 - a1o) <= 1e-5 * a1o
+    assert rel(to_host(m1), m1o) <= 1e-4
+    assert abs(c1 - c1o) <= 1e-4 * c1o
+    m2o, a2o, c2o, _ = oirls.irls_step(g, po, 2, d_obs, wd, m1o, np.zeros(g.n), omega, G_dense=G)
+    m2, a2, c2 = S.irls_step(A, pg, 2, to_dev(d_obs, F64), to_dev(wd, F64), to_dev(m1o, F64),
+                             torch.zeros(g.n, dtype=F64, device="cuda"), to_dev(omega, F64))
+    assert abs(a2 - a2o) <= 1e-3 * a2o
+    assert rel(to_host(m2), m2o) <= 1e-4 + 2 * abs(a2 - a2o) / a2o
+    assert abs(c2 - c2o) <= (1e-4 + 4 * abs(a2 - a2o) / a2o) * c2o
