@@ -111,9 +111,10 @@ ff_status ff_kernel_table(ff_spectra h, double *table, ff_stream stream);
    transforms of length n (a power of two in [8, 2048]), out[b] = sum_k in[b][k] exp(-+2 pi i j k / n)
    (minus for inverse = 0, plus and unnormalized for inverse = 1).  in, out: count x n complex
    values (interleaved re, im) of dtype FF_F32 or FF_F64; twiddles: device scratch of n complex
-   values of the same dtype (filled here).  Asynchronous on `stream`. */
-ff_status ff_fft_1d(int32_t n, int32_t dtype, int32_t inverse, int64_t count, const void *in, void *out,
-                    void *twiddles, ff_stream stream);
+   values of the same dtype (filled here).  plan: the stage plan (0, 1 or 2, as fft_plan_x of
+   ff_tuning).  Asynchronous on `stream`. */
+ff_status ff_fft_1d(int32_t n, int32_t dtype, int32_t inverse, int32_t plan, int64_t count, const void *in,
+                    void *out, void *twiddles, ff_stream stream);
 
 /* Appendix A, eq. (costGx): d = w_post .* G (w_pre .* x).  x: n values, d: m values, both of
    the handle's dtype (float or double).  w_pre (n) and w_post (m) are optional diagonal
@@ -257,10 +258,16 @@ ff_status irls_step(ff_spectra h, const ff_irls_params *p, const double *d_obs, 
                     double *m_new, double *alpha, double *chi2_scaled, void *workspace,
                     size_t ws_bytes, ff_stream stream);
 
-/* Launch tuning of a handle (tile shapes and batch schedule; the FFT radices follow from the
-   embedding sizes: radix-8 passes with one radix-4 or radix-2 pass when log2 N is not a
-   multiple of 3).  build_spectra picks values that fill the chip; an autotuner may change them.
-   Results do not depend on them beyond rounding order.
+/* Launch tuning of a handle (FFT stage plans, tile shapes and batch schedule).  build_spectra
+   picks values that fill the chip; an autotuner may change them.  Results do not depend on them
+   beyond rounding order (Appendix A: the 2-D DFT as 1-D transforms along x, then along y).
+     fft_plan_x    stage plan of the NX-point row transforms, fft_plan_y of the NY-point column
+                   transforms (eight elements per thread, stages of radix 8, 4 and 2):
+                   0 (default) = radix-8 stages, then one radix-4 or radix-2 stage when log2 N is
+                   not a multiple of 3; 1 = that radix-4 or radix-2 stage first (the same as 0 when
+                   log2 N is a multiple of 3); 2 = radix-4 stages, then one radix-2 stage when
+                   log2 N is odd.  They apply to apply_G, apply_GT, apply_G_block and the solvers;
+                   grouped plans (ff_multi_create) use plan 0.
      lg_G, lg_GT   the layers of every column are split over this many groups of column-pass
                    blocks (1 <= lg <= nz); the G partial sums of the groups are added in the
                    inverse row pass.
@@ -297,6 +304,7 @@ typedef struct {
     int32_t rsvd_qr;
     int32_t pair_fused;
     int32_t gkb_graph;
+    int32_t fft_plan_x, fft_plan_y;
 } ff_tuning;
 ff_status ff_get_tuning(ff_spectra h, ff_tuning *t);
 ff_status ff_set_tuning(ff_spectra h, const ff_tuning *t);

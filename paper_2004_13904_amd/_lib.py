@@ -46,7 +46,7 @@ class FFIrlsParams(C.Structure):
 class FFTuning(C.Structure):
     _fields_ = [("lg_G", C.c_int32), ("lg_GT", C.c_int32), ("row_tile", C.c_int32), ("batch", C.c_int32),
                 ("col_batched", C.c_int32), ("rsvd_qr", C.c_int32), ("pair_fused", C.c_int32),
-                ("gkb_graph", C.c_int32)]
+                ("gkb_graph", C.c_int32), ("fft_plan_x", C.c_int32), ("fft_plan_y", C.c_int32)]
 
 
 class FastFocusError(RuntimeError):
@@ -99,7 +99,7 @@ def load(path=None):
         "ff_solver_stats": [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)],
         "ff_focusing_loss": [vp, i64, vp, vp, vp, C.c_double, C.c_double, vp, vp, vp],
         "ff_focusing_grad": [vp, i64, vp, vp, C.c_double, C.c_double, vp, vp, vp],
-        "ff_fft_1d": [i32, i32, i32, i64, vp, vp, vp, vp],
+        "ff_fft_1d": [i32, i32, i32, i32, i64, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

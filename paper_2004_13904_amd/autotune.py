@@ -1,18 +1,20 @@
-"""Launch autotuner of a handle: tile shapes and batch schedule.
+"""Launch autotuner of a handle: FFT stage plans, tile shapes and batch schedule.
 
-The free launch parameters of a handle (``ff_set_tuning``; the FFT radices are fixed by the
-embedding sizes) are:
+The free launch parameters of a handle (``ff_set_tuning``) are:
 
+* ``fft_plan_x``, ``fft_plan_y``: stage plans of the row (NX-point) and column (NY-point)
+  transforms of the 2-D DFT taken as 1-D transforms (Appendix A of the paper): radix-8 stages with
+  the radix-4 or radix-2 stage last (0) or first (1), or radix-4 stages (2); only the plans that
+  differ for the size are tried;
 * ``lg_G``, ``lg_GT``: layer groups of the two column passes (more groups give more waves but more
   partial sums for G, more forward transforms for G^T);
 * ``row_tile``: transforms per row-pass block (automatic, one, two, four, or the largest that fits LDS);
-* ``batch`` and ``col_batched`` (block applies only): vectors per launch, and whether the column
-  passes take 4 vectors per block.
+* ``batch`` and ``col_batched`` (block applies only): vectors per launch, and the column-pass
+  tile (4 vectors per block, or one).
 
 ``autotune`` times candidates on the caller's own vectors with HIP events (one G plus one G^T
 per trial), by coordinate descent over the parameters in that order, keeps the fastest, and
-caches the choice in a JSON file keyed by the embedding, layer count, survey size, dtype and
-batch width.
+caches the choice in a JSON file keyed by (NX, NY, nz, k, dtype).
 """
 from __future__ import annotations
 
@@ -26,8 +28,13 @@ CACHE = os.environ.get("FASTFOCUS_TUNE_CACHE",
 
 
 def _key(op, k):
-    s = op.survey
-    return f"{op.nfft[0]}x{op.nfft[1]}:nz{op.nz}:s{s['sx']}x{s['sy']}:n{op.nx}x{op.ny}:{op.dtype}:k{k}"
+    return f"NX{op.nfft[0]}:NY{op.nfft[1]}:nz{op.nz}:k{k}:{op.dtype}"
+
+
+def fft_plans(n):
+    """The stage plans that differ for an n-point transform: plan 1 is plan 0 when n is a power
+    of 8 (no radix-4 or radix-2 stage to move)."""
+    return [0, 2] if n.bit_length() % 3 == 1 else [0, 1, 2]
 
 
 def _lg_candidates(nz):
@@ -49,7 +56,8 @@ def _time(fn, reps=20):
 
 def candidates(op, batched):
     """The values tried for each tuning key (dict key -> list), in search order."""
-    c = {"lg_G": _lg_candidates(op.nz), "lg_GT": _lg_candidates(op.nz), "row_tile": [0, 1, 2, 3, 4]}
+    c = {"fft_plan_x": fft_plans(op.nfft[0]), "fft_plan_y": fft_plans(op.nfft[1]),
+         "lg_G": _lg_candidates(op.nz), "lg_GT": _lg_candidates(op.nz), "row_tile": [0, 1, 2, 3, 4]}
     if batched:
         bmax = op.batch_max
         c["batch"] = sorted({b for b in (4, 8, 16, 32, 64, bmax) if b <= bmax})

@@ -20,7 +20,8 @@ OUT_DIR = os.path.join(HERE, "lib")
 OUT = os.path.join(OUT_DIR, "libfastfocus.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["capi.hip", "spectra.hip", "apply.hip", "solvers.hip", "multi.hip", "objective.hip", "fft1d.hip", "noalloc.hip"]
+SOURCES = ["capi.hip", "spectra.hip", "apply.hip", "plan0.hip", "plan1.hip", "plan2.hip", "solvers.hip", "multi.hip",
+           "objective.hip", "fft1d.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -3,158 +3,38 @@
 // last passes.  Launches are asynchronous on the caller's stream and allocate nothing.
 #include <type_traits>
 
-#include "passes.h"
+#include "plan_passes.h"
 
 namespace ff {
 namespace {
 
 
-// Row-pass tile: transforms per block (a block of NF transforms writes 2*NF-row contiguous
-// segments).  `tile` is the handle's row_tile: 1 = one transform, 2 = the largest that fits LDS,
-// 3 = four, 4 = two (capped by the largest); 0 = automatic by the rows of the pass (measured on
-// 512- and 256-point rows): one transform below 512 rows and two below 1024, so that small passes
-// still spread over the chip; four for larger forward passes; four for inverse passes below 2048
-// rows and the largest above (its 2*NF-row write segments fetch fewer partial cache lines).
-inline int row_nf(int tile, int64_t rows, int nfm, bool inverse) {
-  int nf;
-  if (tile == 1) nf = 1;
-  else if (tile == 2) nf = nfm;
-  else if (tile == 3) nf = 4;
-  else if (tile == 4) nf = 2;
-  else nf = rows < 512 ? 1 : rows < 1024 ? 2 : (inverse && rows >= 2048) ? nfm : 4;
-  return nf < nfm ? nf : nfm;
-}
-
-template <typename T, typename TI, int N, int NF>
-void launch_r2c_nf(int nrows, int nb, int kb, const TI *in, Idx3 ii, const TI *pre, Idx3 pi, int len, int off,
-                   cplx<T> *out, Idx3 oi, int64_t out_kx, const cplx<T> *tw, hipStream_t s) {
-  using C = RowCfg<T, N, NF>;
-  dim3 g((nrows * nb + C::ROWS - 1) / C::ROWS, 1, kb);
-  k_row_r2c<T, TI, N, NF><<<g, C::THREADS, 0, s>>>(in, ii, pre, pi, nrows, nb, len, off, out, oi, out_kx, tw);
-}
-
-template <typename T, typename TI, int N>
-void launch_r2c(int tile, int nrows, int nb, int kb, const TI *in, Idx3 ii, const TI *pre, Idx3 pi, int len, int off,
-                cplx<T> *out, Idx3 oi, int64_t out_kx, const cplx<T> *tw, hipStream_t s) {
-  constexpr int NFM = RowMax<T, N>::NF;
-  constexpr int NF4 = NFM < 4 ? NFM : 4, NF2 = NFM < 2 ? NFM : 2;
-  const int nf = row_nf(tile, (int64_t)nrows * nb * kb, NFM, false);
-  if (nf == NFM)
-    launch_r2c_nf<T, TI, N, NFM>(nrows, nb, kb, in, ii, pre, pi, len, off, out, oi, out_kx, tw, s);
-  else if (nf == NF4)
-    launch_r2c_nf<T, TI, N, NF4>(nrows, nb, kb, in, ii, pre, pi, len, off, out, oi, out_kx, tw, s);
-  else if (nf == NF2)
-    launch_r2c_nf<T, TI, N, NF2>(nrows, nb, kb, in, ii, pre, pi, len, off, out, oi, out_kx, tw, s);
-  else
-    launch_r2c_nf<T, TI, N, 1>(nrows, nb, kb, in, ii, pre, pi, len, off, out, oi, out_kx, tw, s);
-}
-
-template <typename T, typename TO, int N, int NF>
-void launch_c2r_nf(int nrows, int nb, int kb, const cplx<T> *in, Idx3 ii, int64_t in_kx, int64_t pstride, int P,
-                   TO *out, Idx3 oi, const TO *post, Idx3 qi, int len, int off, const cplx<T> *tw, hipStream_t s) {
-  using C = RowCfg<T, N, NF>;
-  dim3 g((nrows * nb + C::ROWS - 1) / C::ROWS, 1, kb);
-  k_row_c2r<T, TO, N, NF><<<g, C::THREADS, 0, s>>>(in, ii, in_kx, pstride, P, nrows, nb, out, oi, post, qi, len, off, tw);
-}
-
-template <typename T, typename TO, int N>
-void launch_c2r(int tile, int nrows, int nb, int kb, const cplx<T> *in, Idx3 ii, int64_t in_kx, int64_t pstride,
-                int P, TO *out, Idx3 oi, const TO *post, Idx3 qi, int len, int off, const cplx<T> *tw, hipStream_t s) {
-  constexpr int NFM = RowMax<T, N>::NF;
-  constexpr int NF4 = NFM < 4 ? NFM : 4, NF2 = NFM < 2 ? NFM : 2;
-  const int nf = row_nf(tile, (int64_t)nrows * nb * kb, NFM, true);
-  if (nf == NFM)
-    launch_c2r_nf<T, TO, N, NFM>(nrows, nb, kb, in, ii, in_kx, pstride, P, out, oi, post, qi, len, off, tw, s);
-  else if (nf == NF4)
-    launch_c2r_nf<T, TO, N, NF4>(nrows, nb, kb, in, ii, in_kx, pstride, P, out, oi, post, qi, len, off, tw, s);
-  else if (nf == NF2)
-    launch_c2r_nf<T, TO, N, NF2>(nrows, nb, kb, in, ii, in_kx, pstride, P, out, oi, post, qi, len, off, tw, s);
-  else
-    launch_c2r_nf<T, TO, N, 1>(nrows, nb, kb, in, ii, in_kx, pstride, P, out, oi, post, qi, len, off, tw, s);
-}
-
 // One pass of G (transpose = 0) or G^T (transpose = 1) for kb vectors: pass 0 = row
-// transforms, 1 = column transforms with the spectral products, 2 = inverse row transforms.
+// transforms, 1 = column transforms with the spectral products, 2 = inverse row transforms,
+// each with the handle's stage plan of its transforms.
 template <typename T, typename TI, typename TO>
 ff_status run_pass(ff_spectra h, const OpWs &ws, int transpose, int pass, int kb, const TI *X, int64_t ldx, TO *Y,
                    int64_t ldy_out, const TI *pre, const TO *post, hipStream_t s) {
-  const int HC = h->NX / 2, nz = h->nz, nx = h->nx, ny = h->ny, sx = h->sx, sy = h->sy;
-  const int ldy = h->ldy, lds = h->lds;
-  cplx<T> *X1 = (cplx<T> *)ws.rows;   // [vec][r][c][row] (ld ldy), HC column slots
-  cplx<T> *C2 = (cplx<T> *)ws.cols;   // G: partial sums [vec][g][c][j]; G^T: D1 [vec][c][j] (ld lds)
-  const cplx<T> *spec = (const cplx<T> *)h->spec;
-  const cplx<T> *twx = (const cplx<T> *)h->tw_x, *twy = (const cplx<T> *)h->tw_y;
-  const int64_t lay = (int64_t)ny * nx;
-  if (!transpose) {
-    const int LG = h->lg_G;
-    if (pass == 0) {
-      FF_SWITCH_N(h->NX, launch_r2c<T, TI, NN>(h->row_tile, ny, nz, kb, X, Idx3{ldx, lay, nx}, pre, Idx3{0, lay, nx}, nx, 0, X1,
-                                               Idx3{(int64_t)nz * HC * ldy, (int64_t)HC * ldy, 1}, ldy, twx, s));
-      FF_LAUNCH_CHECK("G pass 1 (row transforms)");
-    } else if (pass == 1) {
-      const bool half = 2 * ny <= h->NY && 2 * (h->pyl + sy) <= h->NY;
-      FF_SWITCH_N(h->NY, {
-        using CC = ColCfg<T, NN>;
-        if constexpr (BatchCfg<T, NN>::OK) {
-          if (kb > 1 && h->col_batched) {
-            dim3 g((HC + CC::CPB - 1) / CC::CPB, LG, (kb + BatchCfg<T, NN>::V - 1) / BatchCfg<T, NN>::V);
-            if (half)
-              k_col_G_batch<T, NN, true><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, ldy, nz, HC, LG, kb, spec,
-                                                                          C2, sy, lds, h->pyl, twy);
-            else
-              k_col_G_batch<T, NN, false><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, ldy, nz, HC, LG, kb, spec,
-                                                                           C2, sy, lds, h->pyl, twy);
-            break;
-          }
-        }
-        dim3 g((HC + CC::CPB - 1) / CC::CPB, LG, kb);
-        if (half)
-          k_col_G<T, NN, true><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, ldy, nz, HC, LG, spec, C2, sy, lds, h->pyl, twy);
-        else
-          k_col_G<T, NN, false><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, ldy, nz, HC, LG, spec, C2, sy, lds, h->pyl, twy);
-      });
-      FF_LAUNCH_CHECK("G pass 2 (column transforms and spectral products)");
-    } else {
-      FF_SWITCH_N(h->NX, launch_c2r<T, TO, NN>(h->row_tile, sy, 1, kb, C2, Idx3{(int64_t)LG * HC * lds, 0, 1}, lds, (int64_t)HC * lds,
-                                               LG, Y, Idx3{ldy_out, 0, sx}, post, Idx3{0, 0, sx}, sx, h->pxl, twx, s));
-      FF_LAUNCH_CHECK("G pass 3 (inverse row transforms)");
-    }
-  } else {
-    const int LG = h->lg_GT;
-    if (pass == 0) {
-      FF_SWITCH_N(h->NX, launch_r2c<T, TI, NN>(h->row_tile, sy, 1, kb, X, Idx3{ldx, 0, sx}, pre, Idx3{0, 0, sx}, sx, h->pxl, C2,
-                                               Idx3{(int64_t)HC * lds, 0, 1}, lds, twx, s));
-      FF_LAUNCH_CHECK("G^T pass 1 (row transforms)");
-    } else if (pass == 1) {
-      const bool half = 2 * ny <= h->NY && 2 * (h->pyl + sy) <= h->NY;
-      FF_SWITCH_N(h->NY, {
-        using CC = ColCfg<T, NN>;
-        if constexpr (BatchCfg<T, NN>::OK) {
-          if (kb > 1 && h->col_batched) {
-            dim3 g((HC + CC::CPB - 1) / CC::CPB, LG, (kb + BatchCfg<T, NN>::V - 1) / BatchCfg<T, NN>::V);
-            if (half)
-              k_col_GT_batch<T, NN, true><<<g, CC::THREADS * CC::WPB, 0, s>>>(C2, sy, lds, h->pyl, nz, HC, LG, kb,
-                                                                           spec, X1, ny, ldy, twy);
-            else
-              k_col_GT_batch<T, NN, false><<<g, CC::THREADS * CC::WPB, 0, s>>>(C2, sy, lds, h->pyl, nz, HC, LG, kb,
-                                                                            spec, X1, ny, ldy, twy);
-            break;
-          }
-        }
-        dim3 g((HC + CC::CPB - 1) / CC::CPB, LG, kb);
-        if (half)
-          k_col_GT<T, NN, true><<<g, CC::THREADS * CC::WPB, 0, s>>>(C2, sy, lds, h->pyl, nz, HC, LG, spec, X1, ny, ldy, twy);
-        else
-          k_col_GT<T, NN, false><<<g, CC::THREADS * CC::WPB, 0, s>>>(C2, sy, lds, h->pyl, nz, HC, LG, spec, X1, ny, ldy, twy);
-      });
-      FF_LAUNCH_CHECK("G^T pass 2 (column transforms and spectral products)");
-    } else {
-      FF_SWITCH_N(h->NX, launch_c2r<T, TO, NN>(h->row_tile, ny, nz, kb, X1, Idx3{(int64_t)nz * HC * ldy, (int64_t)HC * ldy, 1}, ldy, 0,
-                                               1, Y, Idx3{ldy_out, lay, nx}, post, Idx3{0, lay, nx}, nx, 0, twx, s));
-      FF_LAUNCH_CHECK("G^T pass 3 (inverse row transforms)");
+  if (pass == 1) {
+    switch (plan_canon(h->NY, h->fft_plan_y)) {
+      case 0: return col_pass<0, T>(h, ws, transpose, kb, s);
+      case 1: return col_pass<1, T>(h, ws, transpose, kb, s);
+      default: return col_pass<2, T>(h, ws, transpose, kb, s);
     }
   }
-  return FF_OK;
+  const int px = plan_canon(h->NX, h->fft_plan_x);
+  if (pass == 0) {
+    switch (px) {
+      case 0: return r2c_pass<0, T, TI>(h, ws, transpose, kb, X, ldx, pre, s);
+      case 1: return r2c_pass<1, T, TI>(h, ws, transpose, kb, X, ldx, pre, s);
+      default: return r2c_pass<2, T, TI>(h, ws, transpose, kb, X, ldx, pre, s);
+    }
+  }
+  switch (px) {
+    case 0: return c2r_pass<0, T, TO>(h, ws, transpose, kb, Y, ldy_out, post, s);
+    case 1: return c2r_pass<1, T, TO>(h, ws, transpose, kb, Y, ldy_out, post, s);
+    default: return c2r_pass<2, T, TO>(h, ws, transpose, kb, Y, ldy_out, post, s);
+  }
 }
 
 template <typename T, typename TI, typename TO>

@@ -92,6 +92,9 @@ ff_status hip_fail(hipError_t e, const char *what);
     default: st = ::ff::fail(FF_ENOTIMPL, "unsupported embedding size"); \
   }
 
+// stage plans of the device FFT (fft.h)
+constexpr int kFftPlans = 3;
+
 inline bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 // Vectors per batched operator launch: each handle picks a batch (a multiple of 4 within
@@ -127,6 +130,7 @@ struct ff_spectra_s {
   int rsvd_qr = 0;                    // RSVD orthonormalization: 0 CholQR2 first, 1 Householder, 2 CholQR3 first
   int pair_fused = 1;                 // grouped plans: G x and G^T d of this survey share one column pass
   int gkb_graph = 0;                  // replay the GKB iteration loop from a captured graph
+  int fft_plan_x = 0, fft_plan_y = 0; // stage plans of the row and column transforms (fft.h)
   uint64_t tune_version = 0;          // bumped by every ff_set_tuning (captured launches depend on it)
   // the captured GKB iteration loop and what it was captured for
   void *gkb_exec = nullptr;           // hipGraphExec_t

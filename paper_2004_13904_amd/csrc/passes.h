@@ -89,13 +89,13 @@ template <class C> struct TileRow {
 // kx < N/2 + 1, or with PACK for the N/2 column slots of the column passes (slot 0 holds the
 // real DC and Nyquist bins as one complex value, DC + i Nyquist).  Rows are numbered across the nb batches (R = b*nrows + row), so a pass of nb*nrows rows
 // fills exactly ceil(nb*nrows/ROWS) blocks.  Grid: (ceil(nb*nrows/ROWS), 1, nvec).
-template <typename T, typename TI, int N, int NF, bool PACK = true, bool HALF = false>
+template <typename T, typename TI, int N, int NF, bool PACK = true, bool HALF = false, int FP = 0>
 __device__ __forceinline__ void
 row_r2c_body_h(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const TI *__restrict__ in, Idx3 ii, const TI *__restrict__ pre, Idx3 pi, int nrows, int nb, int len,
           int off, cplx<T> *__restrict__ out, Idx3 oi, int64_t out_kx,
           const cplx<T> *__restrict__ tw) {
   using C = RowCfg<T, N, NF>;
-  using F = FFT<T, N, false>;
+  using F = FFT<T, N, false, FP>;
   const int f = threadIdx.x / F::TPF, j = threadIdx.x % F::TPF;
   const int64_t vec = bz;
   const int total = nrows * nb;
@@ -172,24 +172,24 @@ row_r2c_body_h(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const TI *_
 
 // The row values sit at x = off .. off + len - 1: when that lies in the first half of the
 // embedding the transform skips the zero half of its input.
-template <typename T, typename TI, int N, int NF, bool PACK = true>
+template <typename T, typename TI, int N, int NF, bool PACK = true, int FP = 0>
 __device__ __forceinline__ void
 row_r2c_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const TI *__restrict__ in, Idx3 ii, const TI *__restrict__ pre, Idx3 pi, int nrows, int nb, int len,
           int off, cplx<T> *__restrict__ out, Idx3 oi, int64_t out_kx,
           const cplx<T> *__restrict__ tw) {
   if (2 * (off + len) <= N)
-    row_r2c_body_h<T, TI, N, NF, PACK, true>(sh, bx, by, bz, in, ii, pre, pi, nrows, nb, len, off, out, oi, out_kx, tw);
+    row_r2c_body_h<T, TI, N, NF, PACK, true, FP>(sh, bx, by, bz, in, ii, pre, pi, nrows, nb, len, off, out, oi, out_kx, tw);
   else
-    row_r2c_body_h<T, TI, N, NF, PACK, false>(sh, bx, by, bz, in, ii, pre, pi, nrows, nb, len, off, out, oi, out_kx, tw);
+    row_r2c_body_h<T, TI, N, NF, PACK, false, FP>(sh, bx, by, bz, in, ii, pre, pi, nrows, nb, len, off, out, oi, out_kx, tw);
 }
 
-template <typename T, typename TI, int N, int NF, bool PACK = true>
+template <typename T, typename TI, int N, int NF, bool PACK = true, int FP = 0>
 __global__ void __launch_bounds__((RowCfg<T, N, NF>::THREADS))
 k_row_r2c(const TI *__restrict__ in, Idx3 ii, const TI *__restrict__ pre, Idx3 pi, int nrows, int nb, int len,
           int off, cplx<T> *__restrict__ out, Idx3 oi, int64_t out_kx,
           const cplx<T> *__restrict__ tw) {
   __shared__ cplx<T> sh[RowCfg<T, N, NF>::SH];
-  row_r2c_body<T, TI, N, NF, PACK>(sh, blockIdx.x, blockIdx.y, blockIdx.z, in, ii, pre, pi, nrows, nb, len, off, out, oi, out_kx, tw);
+  row_r2c_body<T, TI, N, NF, PACK, FP>(sh, blockIdx.x, blockIdx.y, blockIdx.z, in, ii, pre, pi, nrows, nb, len, off, out, oi, out_kx, tw);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -198,13 +198,13 @@ k_row_r2c(const TI *__restrict__ in, Idx3 ii, const TI *__restrict__ pre, Idx3 p
 // real rows; keeps x = off .. off+len-1, multiplies by `post` (optional, indexed without the
 // vector stride).  Rows numbered across batches as in pass 1.
 // Grid: (ceil(nb*nrows/ROWS), 1, nvec).
-template <typename T, typename TO, int N, int NF, bool HALF>
+template <typename T, typename TO, int N, int NF, bool HALF, int FP = 0>
 __device__ __forceinline__ void
 row_c2r_body_h(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<T> *__restrict__ in, Idx3 ii, int64_t in_kx, int64_t pstride, int P, int nrows, int nb,
           TO *__restrict__ out, Idx3 oi, const TO *__restrict__ post, Idx3 qi, int len, int off,
           const cplx<T> *__restrict__ tw) {
   using C = RowCfg<T, N, NF>;
-  using F = FFT<T, N, true>;
+  using F = FFT<T, N, true, FP>;
   const int f = threadIdx.x / F::TPF, j = threadIdx.x % F::TPF;
   const int64_t vec = bz;
   const int total = nrows * nb;
@@ -285,24 +285,24 @@ row_c2r_body_h(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<
 
 // The kept values x = off .. off + len - 1: when they lie in the first half of the embedding
 // the transform skips the outputs of the other half.
-template <typename T, typename TO, int N, int NF>
+template <typename T, typename TO, int N, int NF, int FP = 0>
 __device__ __forceinline__ void
 row_c2r_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<T> *__restrict__ in, Idx3 ii, int64_t in_kx, int64_t pstride, int P, int nrows, int nb,
           TO *__restrict__ out, Idx3 oi, const TO *__restrict__ post, Idx3 qi, int len, int off,
           const cplx<T> *__restrict__ tw) {
   if (2 * (off + len) <= N)
-    row_c2r_body_h<T, TO, N, NF, true>(sh, bx, by, bz, in, ii, in_kx, pstride, P, nrows, nb, out, oi, post, qi, len, off, tw);
+    row_c2r_body_h<T, TO, N, NF, true, FP>(sh, bx, by, bz, in, ii, in_kx, pstride, P, nrows, nb, out, oi, post, qi, len, off, tw);
   else
-    row_c2r_body_h<T, TO, N, NF, false>(sh, bx, by, bz, in, ii, in_kx, pstride, P, nrows, nb, out, oi, post, qi, len, off, tw);
+    row_c2r_body_h<T, TO, N, NF, false, FP>(sh, bx, by, bz, in, ii, in_kx, pstride, P, nrows, nb, out, oi, post, qi, len, off, tw);
 }
 
-template <typename T, typename TO, int N, int NF>
+template <typename T, typename TO, int N, int NF, int FP = 0>
 __global__ void __launch_bounds__((RowCfg<T, N, NF>::THREADS))
 k_row_c2r(const cplx<T> *__restrict__ in, Idx3 ii, int64_t in_kx, int64_t pstride, int P, int nrows, int nb,
           TO *__restrict__ out, Idx3 oi, const TO *__restrict__ post, Idx3 qi, int len, int off,
           const cplx<T> *__restrict__ tw) {
   __shared__ cplx<T> sh[RowCfg<T, N, NF>::SH];
-  row_c2r_body<T, TO, N, NF>(sh, blockIdx.x, blockIdx.y, blockIdx.z, in, ii, in_kx, pstride, P, nrows, nb, out, oi, post, qi, len, off, tw);
+  row_c2r_body<T, TO, N, NF, FP>(sh, blockIdx.x, blockIdx.y, blockIdx.z, in, ii, in_kx, pstride, P, nrows, nb, out, oi, post, qi, len, off, tw);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -328,14 +328,14 @@ k_row_c2r(const cplx<T> *__restrict__ in, Idx3 ii, int64_t in_kx, int64_t pstrid
 // partial sums are added up in LDS, each wave group taking a share of the elements, and wave
 // group 0 does the inverse transform.
 // Grid: (ceil(HC/CPB), LG, nvec).
-template <typename T, int NY, bool HALF = false>
+template <typename T, int NY, bool HALF = false, int FP = 0>
 __device__ __forceinline__ void
 col_G_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, int LG,
         const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ outp, int sy, int lds, int pyl,
         const cplx<T> *__restrict__ tw) {
   using CC = ColCfg<T, NY>;
-  using Ff = FFT<T, NY, false>;
-  using Fi = FFT<T, NY, true>;
+  using Ff = FFT<T, NY, false, FP>;
+  using Fi = FFT<T, NY, true, FP>;
   constexpr int TPF = CC::TPF, WPB = CC::WPB;
   const int w = threadIdx.x / CC::THREADS, lt = threadIdx.x % CC::THREADS;
   const int f = lt / TPF, j = lt % TPF;
@@ -459,13 +459,13 @@ col_G_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<T> *
 // HALF: the model rows (y < ny) and the kept station rows (pyl .. pyl + sy - 1) lie in the
 // first half of the embedding, so the forward transforms skip the zero half of their input and
 // the inverse one the discarded half of its output (same results for the values kept).
-template <typename T, int NY, bool HALF>
+template <typename T, int NY, bool HALF, int FP = 0>
 __global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
 k_col_G(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, int LG,
         const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ outp, int sy, int lds, int pyl,
         const cplx<T> *__restrict__ tw) {
   __shared__ cplx<T> sh[ColCfg<T, NY>::WPB * ColCfg<T, NY>::CPB * FFT<T, NY, false>::LDS];
-  col_G_body<T, NY, HALF>(sh, blockIdx.x, blockIdx.y, blockIdx.z, X1, ny, ldy, nz, HC, LG, spec, outp, sy, lds, pyl, tw);
+  col_G_body<T, NY, HALF, FP>(sh, blockIdx.x, blockIdx.y, blockIdx.z, X1, ny, ldy, nz, HC, LG, spec, outp, sy, lds, pyl, tw);
 }
 
 // Pass 2 of G^T: for each column slot c: D = FFT_y(D1[vec, c, :] placed at rows pyl..pyl+sy-1);
@@ -473,14 +473,14 @@ k_col_G(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, int LG,
 // (slot 0: conj(P_r) .* D + conj(M_r) .* conj(D[-k])).
 // Wave group w of a block takes every WPB-th layer of the group and transforms D itself.
 // Grid: (ceil(HC/CPB), LG, nvec).
-template <typename T, int NY, bool HALF = false>
+template <typename T, int NY, bool HALF = false, int FP = 0>
 __device__ __forceinline__ void
 col_GT_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz, int HC, int LG,
          const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ X1, int ny, int ldy,
          const cplx<T> *__restrict__ tw) {
   using CC = ColCfg<T, NY>;
-  using Ff = FFT<T, NY, false>;
-  using Fi = FFT<T, NY, true>;
+  using Ff = FFT<T, NY, false, FP>;
+  using Fi = FFT<T, NY, true, FP>;
   constexpr int TPF = CC::TPF, WPB = CC::WPB;
   const int w = threadIdx.x / CC::THREADS, lt = threadIdx.x % CC::THREADS;
   const int f = lt / TPF, j = lt % TPF;
@@ -573,13 +573,13 @@ col_GT_body(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<T> 
   }
 }
 
-template <typename T, int NY, bool HALF>
+template <typename T, int NY, bool HALF, int FP = 0>
 __global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
 k_col_GT(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz, int HC, int LG,
          const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ X1, int ny, int ldy,
          const cplx<T> *__restrict__ tw) {
   __shared__ cplx<T> sh[ColCfg<T, NY>::WPB * ColCfg<T, NY>::CPB * FFT<T, NY, false>::LDS];
-  col_GT_body<T, NY, HALF>(sh, blockIdx.x, blockIdx.y, blockIdx.z, D1, sy, ldd, pyl, nz, HC, LG, spec, X1, ny, ldy, tw);
+  col_GT_body<T, NY, HALF, FP>(sh, blockIdx.x, blockIdx.y, blockIdx.z, D1, sy, ldd, pyl, nz, HC, LG, spec, X1, ny, ldy, tw);
 }
 
 // Pass 2 of an independent pair G x, G^T d of one survey, in one launch: per column slot the
@@ -606,7 +606,7 @@ template <typename T, int NY> struct PairCfg {
   static constexpr int WI = CC::WPB >= 2 ? CC::WPB - 2 : 0;             // inverts the G sum
 };
 
-template <typename T, int NY, bool HALF>
+template <typename T, int NY, bool HALF, int FP = 0>
 __device__ __forceinline__ void
 col_pair_body(cplx<T> *__restrict__ sh, int bx, int by, const cplx<T> *__restrict__ X1, int ny, int ldy,
               cplx<T> *__restrict__ outp, const cplx<T> *__restrict__ D1, cplx<T> *__restrict__ X1t, int sy,
@@ -614,8 +614,8 @@ col_pair_body(cplx<T> *__restrict__ sh, int bx, int by, const cplx<T> *__restric
               const cplx<T> *__restrict__ tw) {
   using CC = ColCfg<T, NY>;
   using PC = PairCfg<T, NY>;
-  using Ff = FFT<T, NY, false>;
-  using Fi = FFT<T, NY, true>;
+  using Ff = FFT<T, NY, false, FP>;
+  using Fi = FFT<T, NY, true, FP>;
   constexpr int TPF = CC::TPF, WPB = CC::WPB, LDSF = PC::LDSF, WD = PC::WD, WI = PC::WI;
   constexpr int UH = HALF ? 4 : 8;   // register slots of a half-pruned transform's input / output
   static_assert(TPF <= 64, "pair column pass: wave-level transforms only");
@@ -695,7 +695,7 @@ col_pair_body(cplx<T> *__restrict__ sh, int bx, int by, const cplx<T> *__restric
       }
     }
     if (i + 1 < nl) load(layer(i + 1));
-    fft_dual<T, NY, false, true, HALF, false, false, HALF>(a, b, j, bufA, bufB, twr);
+    fft_dual<T, NY, false, true, HALF, false, false, HALF, FP>(a, b, j, bufA, bufB, twr);
     // G: the layer sums of S_r .* X and (packed slot) M_r .* X
 #pragma unroll
     for (int u = 0; u < 8; ++u) acc[u] = cadd<T>(acc[u], cmul<T>(a[u], sc[u]));
@@ -773,15 +773,15 @@ template <typename T, int NY> struct BatchCfg {
 // The partial sums of vector 2p + i sit in the wave groups 2l + p (l < GL); wave group 2i + p
 // adds them up in layer-group order and does the vector's inverse transform.  Block 0 (slot 0
 // at f == 0) also sums the M_r products and folds them in per wave group before the reduction.
-template <typename T, int NY, bool HALF>
+template <typename T, int NY, bool HALF, int FP = 0>
 __global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
 k_col_G_batch(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, int LG, int kb,
               const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ outp, int sy, int lds, int pyl,
               const cplx<T> *__restrict__ tw) {
   using CC = ColCfg<T, NY>;
   using BC = BatchCfg<T, NY>;
-  using Ff = FFT<T, NY, false>;
-  using Fi = FFT<T, NY, true>;
+  using Ff = FFT<T, NY, false, FP>;
+  using Fi = FFT<T, NY, true, FP>;
   constexpr int TPF = CC::TPF, GL = BC::GL;
   static_assert(BC::OK, "batched column pass configuration");
   __shared__ cplx<T> sh[CC::WPB * CC::CPB * Ff::LDS];
@@ -888,15 +888,15 @@ k_col_G_batch(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, i
 // into LDS; then wave group w takes the vectors 2p, 2p+1 and the layers r0 + l + k GL as above,
 // loading each spectrum column once for its two products and inverse transforms.  Slot 0
 // reads the reversed transform conj(D[-k]) from the same LDS copy.
-template <typename T, int NY, bool HALF>
+template <typename T, int NY, bool HALF, int FP = 0>
 __global__ void __launch_bounds__((ColCfg<T, NY>::THREADS * ColCfg<T, NY>::WPB))
 k_col_GT_batch(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz, int HC, int LG, int kb,
                const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ X1, int ny, int ldy,
                const cplx<T> *__restrict__ tw) {
   using CC = ColCfg<T, NY>;
   using BC = BatchCfg<T, NY>;
-  using Ff = FFT<T, NY, false>;
-  using Fi = FFT<T, NY, true>;
+  using Ff = FFT<T, NY, false, FP>;
+  using Fi = FFT<T, NY, true, FP>;
   constexpr int TPF = CC::TPF, GL = BC::GL;
   static_assert(BC::OK, "batched column pass configuration");
   __shared__ cplx<T> sh[CC::WPB * CC::CPB * Ff::LDS];

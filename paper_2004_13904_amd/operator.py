@@ -75,7 +75,8 @@ class Operator:
         op._attach(h, survey)
         return op
 
-    TUNING_KEYS = ("lg_G", "lg_GT", "row_tile", "batch", "col_batched", "rsvd_qr", "pair_fused", "gkb_graph")
+    TUNING_KEYS = ("lg_G", "lg_GT", "row_tile", "batch", "col_batched", "rsvd_qr", "pair_fused", "gkb_graph",
+                   "fft_plan_x", "fft_plan_y")
 
     @property
     def batch_max(self):

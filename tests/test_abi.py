@@ -107,8 +107,10 @@ def test_spectra_load_rejects_foreign_and_missing_files(tmp_path):
 def test_fft_1d_rejects_bad_arguments_before_launching(n, dtype, inverse, count, code):
     L, lib = _lib()
     p = C.c_void_p(16)        # never dereferenced: validation precedes any device work
-    assert lib.ff_fft_1d(n, dtype, inverse, count, p, p, p, None) == code
-    assert lib.ff_fft_1d(64, 0, 0, 1, None, p, p, None) == -1
+    assert lib.ff_fft_1d(n, dtype, inverse, 0, count, p, p, p, None) == code
+    assert lib.ff_fft_1d(64, 0, 0, 0, 1, None, p, p, None) == -1
+    for plan in (-1, 3):      # stage plans 0, 1 and 2 only
+        assert lib.ff_fft_1d(64, 0, 0, plan, 1, p, p, p, None) == -1
 
 
 @pytest.mark.parametrize("compiler,lang", [("gcc", "c"), ("g++", "c++")])

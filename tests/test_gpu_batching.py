@@ -1,14 +1,15 @@
 """Uneven multi-survey batch in one HIP graph, and the launch autotuner."""
+import json
 import os
 
 import numpy as np
 import pytest
 import torch
 
-from gpu_common import agree, ogeom, otable, rel, to_dev, to_host
+from gpu_common import agree, announce, ogeom, otable, rel, to_dev, to_host
 from oracle import operator as op
 from paper_2004_13904_amd import workloads as W
-from paper_2004_13904_amd.autotune import autotune
+from paper_2004_13904_amd.autotune import autotune, candidates, fft_plans
 from paper_2004_13904_amd.operator import Operator, SurveyBatch
 
 pytestmark = pytest.mark.gpu
@@ -101,18 +102,63 @@ def test_autotune_picks_valid_tuning_and_keeps_results(tmp_path):
     A = Operator(s, F32)
     x = to_dev(W.uniform_model(s, 0), F32)
     d = to_dev(W.gaussian_data(s, 1), F32)
-    ref_g, ref_t = A.G(x).clone(), A.GT(d).clone()
     cache = str(tmp_path / "tune.json")
     choice = autotune(A, x, d, cache=cache, reps=5)
     assert 1 <= choice["lg_G"] <= A.nz and 1 <= choice["lg_GT"] <= A.nz
     assert choice["row_tile"] in (0, 1, 2, 3, 4)
+    assert choice["fft_plan_x"] in fft_plans(A.nfft[0]) and choice["fft_plan_y"] in fft_plans(A.nfft[1])
     assert os.path.exists(cache)
-    # the tuning changes only the summation order of the layer groups
-    assert rel(to_host(A.G(x)), to_host(ref_g)) <= 1e-6
-    assert rel(to_host(A.GT(d)), to_host(ref_t)) <= 1e-6
+    with open(cache) as f:
+        assert list(json.load(f)) == [f"NX{A.nfft[0]}:NY{A.nfft[1]}:nz{A.nz}:k1:{A.dtype}"]
+    # the chosen tuning against the oracle's direct sums
+    g = ogeom(s)
+    agree(to_host(A.G(x)), op.apply_G(g, to_host(x), otable("gravity_l4")), 1e-5)
+    agree(to_host(A.GT(d)), op.apply_GT(g, to_host(d), otable("gravity_l4")), 1e-5)
     B = Operator(s, F32)
     assert autotune(B, x, d, cache=cache) == choice     # cache hit
     assert B.tuning == choice
+
+
+# embeddings 32 x 32 (pruned transforms), 128 x 128 (pruned, three plans on both axes) and
+# 64 x 64 (unpruned: the data rows and model rows reach past the half of the embedding; plans 0
+# and 2 only, 64 being a power of 8)
+CANDIDATE_SURVEYS = {
+    "tiny": W.SURVEYS["tiny"],
+    "s40x33": W.survey(40, 33, 5, 20, 20, 20, kernel="magnetic", incl=60.0, decl=-20.0),
+    "padded64": W.survey(20, 20, 4, 20, 20, 20, pad=(14, 0, 14, 0)),
+}
+
+
+@pytest.mark.parametrize("name", list(CANDIDATE_SURVEYS))
+def test_every_tuning_candidate_matches_oracle(name):
+    # every value the autotuner may try, one key at a time from the default tuning, and every
+    # pair of row and column stage plans, for single and block products (5 vectors: the batched
+    # column passes), against the oracle's direct sums at the FP32 bar
+    s = CANDIDATE_SURVEYS[name]
+    A = Operator(s, F32)
+    g = ogeom(s)
+    T = op.kernel_table(g)
+    rng = np.random.default_rng(12)
+    X = rng.random((5, g.n))
+    D = rng.standard_normal((5, g.m))
+    GX = np.stack([op.apply_G(g, v, T) for v in X])
+    GTD = np.stack([op.apply_GT(g, v, T) for v in D])
+    Xd, Dd = to_dev(X, F32), to_dev(D, F32)
+    base = A.tuning
+    cand = candidates(A, batched=True)
+    configs = [dict(base, **{k: v}) for k, vals in cand.items() for v in vals]
+    configs += [dict(base, fft_plan_x=px, fft_plan_y=py) for px in cand["fft_plan_x"] for py in cand["fft_plan_y"]]
+    if name == "tiny":
+        assert cand["fft_plan_x"] == cand["fft_plan_y"] == [0, 1, 2]
+    if name == "padded64":
+        assert A.nfft == (64, 64) and cand["fft_plan_y"] == [0, 2]
+    for cfg in configs:
+        A.set_tuning(**cfg)
+        announce("tuning candidate", name, cfg)
+        agree(to_host(A.G(Xd[0])), GX[0], 1e-5)
+        agree(to_host(A.GT(Dd[0])), GTD[0], 1e-5)
+        agree(to_host(A.G_block(Xd)), GX, 1e-5)
+        agree(to_host(A.G_block(Dd, transpose=True)), GTD, 1e-5)
 
 
 def test_tuning_variants_keep_results():
