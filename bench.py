@@ -431,7 +431,8 @@ def study_leg(ells, s_list, kinds, solvers, basis="f64", pad=0.0, kmax=25):
 
 
 # the sources that define the operator's pass kernels and their launches
-PASS_SOURCES = ("apply.hip", "common.h", "fft.h", "passes.h")
+# the sources of the pass kernels the counters cover (per-survey passes with FFT plan 0, grouped passes)
+PASS_SOURCES = ("apply.hip", "plan_passes.h", "plan0.hip", "multi.hip", "common.h", "fft.h", "passes.h")
 
 
 def pass_sources_sha256():
