@@ -154,7 +154,8 @@ def main(argv=None):
     # ---- timed region: K pairs replayed from a hipGraph (R pairs per graph) -----------
     # The library launches on torch's current stream, so a torch CUDA graph captures its
     # kernels; replaying it removes the host launch cost from the loop.
-    R = 20
+    # pairs per graph: the largest divisor of the step count up to 20, so that exactly K pairs are timed
+    R = max(r for r in range(1, 21) if a.steps % r == 0)
 
     def capture(fn):
         g_ = torch.cuda.CUDAGraph()
@@ -303,7 +304,7 @@ def main(argv=None):
         "pair_separate_calls": {"ms_per_pair": round(ms_sep, 6), "pairs_per_s": round(1e3 / ms_sep, 1),
                                 "results_equal_plan": same, "passes": passes,
                                 "how": "apply_G then apply_GT, three launches each, hipGraph replay"},
-        "launch": "hipGraph replay of 20 pairs per graph (torch CUDA graph capture of the library's launches)",
+        "launch": f"hipGraph replay of {R} pairs per graph (torch CUDA graph capture of the library's launches)",
     }
     result["hbm_copy"] = copy_bandwidth()
     result["path_roofline"]["frac_of_copy"] = round(path_gbs / result["hbm_copy"]["GBs"], 4)
