@@ -277,7 +277,7 @@ ff_status ff_multi_create(int32_t count, const ff_spectra *handles, const void *
       R2CTask a{b_r2c, h->NX, (const float *)x[i], Idx3{0, lay, nx}, ny, nz, nx, 0, X1, Idx3{0, (int64_t)HC * ldy, 1},
                 ldy, twx};
       r2c.push_back(a);
-      b_r2c += (ny * nz + rpb - 1) / rpb;
+      b_r2c += row_blocks(ny, nz, rpb);
       if (!pair) {
         ColTask c{b_col, h->NY, 0, nbx, X1, C2, ny, ldy, nz, HC, h->lg_G, sy, lds, h->pyl, spec, twy, nullptr, nullptr};
         col.push_back(c);
@@ -286,12 +286,12 @@ ff_status ff_multi_create(int32_t count, const ff_spectra *handles, const void *
       C2RTask e{b_c2r, h->NX, C2, Idx3{0, 0, 1}, lds, (int64_t)HC * lds, h->lg_G, sy, 1, (float *)gx[i],
                 Idx3{0, 0, sx}, sx, h->pxl, twx};
       c2r.push_back(e);
-      b_c2r += (sy + rpb - 1) / rpb;
+      b_c2r += row_blocks(sy, 1, rpb);
     }
     if (doT) {
       R2CTask a{b_r2c, h->NX, (const float *)d[i], Idx3{0, 0, sx}, sy, 1, sx, h->pxl, C2t, Idx3{0, 0, 1}, lds, twx};
       r2c.push_back(a);
-      b_r2c += (sy + rpb - 1) / rpb;
+      b_r2c += row_blocks(sy, 1, rpb);
       if (!pair) {
         ColTask c{b_col, h->NY, 1, nbx, C2t, X1t, ny, ldy, nz, HC, h->lg_GT, sy, lds, h->pyl, spec, twy, nullptr,
                   nullptr};
@@ -301,7 +301,7 @@ ff_status ff_multi_create(int32_t count, const ff_spectra *handles, const void *
       C2RTask e{b_c2r, h->NX, X1t, Idx3{0, (int64_t)HC * ldy, 1}, ldy, 0, 1, ny, nz, (float *)gtd[i],
                 Idx3{0, lay, nx}, nx, 0, twx};
       c2r.push_back(e);
-      b_c2r += (ny * nz + rpb - 1) / rpb;
+      b_c2r += row_blocks(ny, nz, rpb);
     }
   }
   ff_multi p = new (std::nothrow) ff_multi_s();

@@ -51,6 +51,9 @@ template <typename T, int NY> struct ColCfg {
   static constexpr int WPB = TPF > 64 ? 1 : (byLds < 8 ? byLds : 8);
 };
 
+// Blocks of a row pass over nb batches of nrows rows, ROWS rows per block (RowMap).
+inline int row_blocks(int nrows, int nb, int rows) { return nb * ((nrows + rows - 1) / rows); }
+
 // Strides of a 3-level index (vector v, batch b within the vector, row) -> element offset.
 struct Idx3 {
   int64_t v, b, row;
@@ -59,25 +62,36 @@ struct Idx3 {
   }
 };
 
+// Rows of a row pass: each of the nb batches (layers) takes its nrows rows padded to a multiple
+// of ROWS, so that a block's ROWS rows lie in one batch and start on a multiple of ROWS (whole
+// cache lines of the column-major intermediates, whose row strides are multiples of 16
+// elements).  Block bx holds rows row0 .. row0 + ROWS - 1 of batch b; the padding rows are
+// neither read nor written.  A pass fills nb * ceil(nrows / ROWS) blocks (row_blocks).
+template <class C> struct RowMap {
+  int b, row0, nrows;
+  bool ok;   // the block lies inside the pass
+  __device__ __forceinline__ RowMap(int bx, int nrows_, int nb) : nrows(nrows_) {
+    const int per = (nrows + C::ROWS - 1) / C::ROWS;   // blocks per batch
+    b = bx / per;
+    row0 = (bx - b * per) * C::ROWS;
+    ok = b < nb;
+  }
+  __device__ __forceinline__ bool valid(int row) const { return ok && row < nrows; }
+};
+
 // Row of a transposed tile element: tile element idx belongs to tile row idx % ROWS, i.e. to
-// flat row R = R0 + idx % ROWS = b*nrows + row.  When THREADS is a multiple of ROWS each
-// thread always meets the same tile row, and the division by nrows is done once.
+// row row0 + idx % ROWS of the block's batch.  When THREADS is a multiple of ROWS each thread
+// always meets the same tile row.
 template <class C> struct TileRow {
   static constexpr bool FIXED = C::THREADS % C::ROWS == 0;
-  int R0, total, nrows, R, b;
-  __device__ __forceinline__ TileRow(int R0_, int total_, int nrows_) : R0(R0_), total(total_), nrows(nrows_) {
-    R = R0 + (int)threadIdx.x % C::ROWS;
-    b = R / nrows;
-  }
-  // false when the row lies past the last one; else o = ix.at(vec, b, row)
+  RowMap<C> m;
+  int row;
+  __device__ __forceinline__ TileRow(const RowMap<C> &m_) : m(m_) { row = m.row0 + (int)threadIdx.x % C::ROWS; }
+  // false for a padding row or a block past the pass; else o = ix.at(vec, b, row)
   __device__ __forceinline__ bool get(int idx, const Idx3 &ix, int64_t vec, int64_t &o) const {
-    int r = R, bb = b;
-    if (!FIXED) {
-      r = R0 + idx % C::ROWS;
-      bb = r / nrows;
-    }
-    o = ix.at(vec, bb, r - bb * nrows);
-    return r < total;
+    const int r = FIXED ? row : m.row0 + idx % C::ROWS;
+    o = ix.at(vec, m.b, r);
+    return m.valid(r);
   }
 };
 
@@ -87,8 +101,8 @@ template <class C> struct TileRow {
 // embedding (zero elsewhere); `pre` (optional) multiplies them (indexed without the vector
 // stride).  Output element (vec, b, kx, row) at out[o.at(vec, b, row) + kx*out_kx], for
 // kx < N/2 + 1, or with PACK for the N/2 column slots of the column passes (slot 0 holds the
-// real DC and Nyquist bins as one complex value, DC + i Nyquist).  Rows are numbered across the nb batches (R = b*nrows + row), so a pass of nb*nrows rows
-// fills exactly ceil(nb*nrows/ROWS) blocks.  Grid: (ceil(nb*nrows/ROWS), 1, nvec).
+// real DC and Nyquist bins as one complex value, DC + i Nyquist).  Rows as RowMap numbers them.
+// Grid: (row_blocks(nrows, nb, ROWS), 1, nvec).
 template <typename T, typename TI, int N, int NF, bool PACK = true, bool HALF = false, int FP = 0>
 __device__ __forceinline__ void
 row_r2c_body_h(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const TI *__restrict__ in, Idx3 ii, const TI *__restrict__ pre, Idx3 pi, int nrows, int nb, int len,
@@ -98,23 +112,22 @@ row_r2c_body_h(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const TI *_
   using F = FFT<T, N, false, FP>;
   const int f = threadIdx.x / F::TPF, j = threadIdx.x % F::TPF;
   const int64_t vec = bz;
-  const int total = nrows * nb;
-  const int R0 = bx * C::ROWS;
-  const int ra = R0 + 2 * f, rb = ra + 1;
-  const int ba = ra / nrows, qa = ra - ba * nrows, bb = rb / nrows, qb = rb - bb * nrows;
+  const RowMap<C> rm(bx, nrows, nb);
+  const int qa = rm.row0 + 2 * f, qb = qa + 1, bq = rm.b;
+  const bool va = rm.valid(qa), vb = rm.valid(qb);
   cplx<T> v[8];
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
     const int c = j + u * F::TPF - off;
     T a = 0, bv = 0;
     if ((!HALF || u < 4) && c >= 0 && c < len) {
-      if (ra < total) {
-        a = (T)in[ii.at(vec, ba, qa) + c];
-        if (pre) a *= (T)pre[pi.at(0, ba, qa) + c];
+      if (va) {
+        a = (T)in[ii.at(vec, bq, qa) + c];
+        if (pre) a *= (T)pre[pi.at(0, bq, qa) + c];
       }
-      if (rb < total) {
-        bv = (T)in[ii.at(vec, bb, qb) + c];
-        if (pre) bv *= (T)pre[pi.at(0, bb, qb) + c];
+      if (vb) {
+        bv = (T)in[ii.at(vec, bq, qb) + c];
+        if (pre) bv *= (T)pre[pi.at(0, bq, qb) + c];
       }
     }
     v[u] = mk<T>(a, bv);
@@ -160,7 +173,7 @@ row_r2c_body_h(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const TI *_
     const int k = idx / C::ROWS, rr = idx - k * C::ROWS;
     tv[q] = tile[k * C::TS + rr];
   }
-  TileRow<C> tr(R0, total, nrows);
+  TileRow<C> tr(rm);
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int idx = threadIdx.x + q * C::THREADS;
@@ -196,8 +209,8 @@ k_row_r2c(const TI *__restrict__ in, Idx3 ii, const TI *__restrict__ pre, Idx3 p
 // Pass 3: half spectra (vec, b, c, row) in the N/2 packed column slots of pass 1, summed over
 // P partial buffers `pstride` apart, ->
 // real rows; keeps x = off .. off+len-1, multiplies by `post` (optional, indexed without the
-// vector stride).  Rows numbered across batches as in pass 1.
-// Grid: (ceil(nb*nrows/ROWS), 1, nvec).
+// vector stride).  Rows as RowMap numbers them.
+// Grid: (row_blocks(nrows, nb, ROWS), 1, nvec).
 template <typename T, typename TO, int N, int NF, bool HALF, int FP = 0>
 __device__ __forceinline__ void
 row_c2r_body_h(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<T> *__restrict__ in, Idx3 ii, int64_t in_kx, int64_t pstride, int P, int nrows, int nb,
@@ -207,15 +220,14 @@ row_c2r_body_h(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<
   using F = FFT<T, N, true, FP>;
   const int f = threadIdx.x / F::TPF, j = threadIdx.x % F::TPF;
   const int64_t vec = bz;
-  const int total = nrows * nb;
-  const int R0 = bx * C::ROWS;
+  const RowMap<C> rm(bx, nrows, nb);
   cplx<T> *tile = sh;
   // every thread issues all of its tile loads before the first LDS write, so the global
   // load latencies overlap instead of adding up
   constexpr int HI = N / 2;   // input column slots (slot 0 = DC + i Nyquist)
   constexpr int PER = (HI * C::ROWS + C::THREADS - 1) / C::THREADS;
   cplx<T> tv[PER];
-  TileRow<C> tr(R0, total, nrows);
+  TileRow<C> tr(rm);
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int idx = threadIdx.x + q * C::THREADS;
@@ -263,21 +275,21 @@ row_c2r_body_h(cplx<T> *__restrict__ sh, int bx, int by, int64_t bz, const cplx<
   }
   __syncthreads();
   F::template run<false, HALF>(v, j, sh + f * F::LDS, tw);
-  const int ra = R0 + 2 * f, rb = ra + 1;
-  const int ba = ra / nrows, qa = ra - ba * nrows, bb = rb / nrows, qb = rb - bb * nrows;
+  const int qa = rm.row0 + 2 * f, qb = qa + 1, bq = rm.b;
+  const bool va = rm.valid(qa), vb = rm.valid(qb);
 #pragma unroll
   for (int u = 0; u < (HALF ? 4 : 8); ++u) {
     const int c = j + u * F::TPF - off;
     if (c >= 0 && c < len) {
-      if (ra < total) {
+      if (va) {
         T a = v[u].x;
-        if (post) a *= (T)post[qi.at(0, ba, qa) + c];
-        out[oi.at(vec, ba, qa) + c] = (TO)a;
+        if (post) a *= (T)post[qi.at(0, bq, qa) + c];
+        out[oi.at(vec, bq, qa) + c] = (TO)a;
       }
-      if (rb < total) {
+      if (vb) {
         T bv = v[u].y;
-        if (post) bv *= (T)post[qi.at(0, bb, qb) + c];
-        out[oi.at(vec, bb, qb) + c] = (TO)bv;
+        if (post) bv *= (T)post[qi.at(0, bq, qb) + c];
+        out[oi.at(vec, bq, qb) + c] = (TO)bv;
       }
     }
   }

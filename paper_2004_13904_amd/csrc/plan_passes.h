@@ -45,7 +45,7 @@ template <typename T, typename TI, int N, int NF, int FP>
 void launch_r2c_nf(int nrows, int nb, int kb, const TI *in, Idx3 ii, const TI *pre, Idx3 pi, int len, int off,
                    cplx<T> *out, Idx3 oi, int64_t out_kx, const cplx<T> *tw, hipStream_t s) {
   using C = RowCfg<T, N, NF>;
-  dim3 g((nrows * nb + C::ROWS - 1) / C::ROWS, 1, kb);
+  dim3 g(row_blocks(nrows, nb, C::ROWS), 1, kb);
   k_row_r2c<T, TI, N, NF, true, FP><<<g, C::THREADS, 0, s>>>(in, ii, pre, pi, nrows, nb, len, off, out, oi, out_kx, tw);
 }
 
@@ -69,7 +69,7 @@ template <typename T, typename TO, int N, int NF, int FP>
 void launch_c2r_nf(int nrows, int nb, int kb, const cplx<T> *in, Idx3 ii, int64_t in_kx, int64_t pstride, int P,
                    TO *out, Idx3 oi, const TO *post, Idx3 qi, int len, int off, const cplx<T> *tw, hipStream_t s) {
   using C = RowCfg<T, N, NF>;
-  dim3 g((nrows * nb + C::ROWS - 1) / C::ROWS, 1, kb);
+  dim3 g(row_blocks(nrows, nb, C::ROWS), 1, kb);
   k_row_c2r<T, TO, N, NF, FP><<<g, C::THREADS, 0, s>>>(in, ii, in_kx, pstride, P, nrows, nb, out, oi, post, qi, len, off, tw);
 }
 

@@ -150,7 +150,7 @@ ff_status rows_fp64(const double *circ, int nz, int NY, double2 *tmp, const doub
   using C = RowCfg<double, NX, NF>;
   const int H = NX / 2 + 1;
   Idx3 ii{0, (int64_t)NY * NX, NX}, pi{0, 0, 0}, oi{0, (int64_t)H * NY, 1};
-  dim3 grid((NY * nz + C::ROWS - 1) / C::ROWS, 1, 1);
+  dim3 grid(row_blocks(NY, nz, C::ROWS), 1, 1);
   k_row_r2c<double, double, NX, NF, false><<<grid, C::THREADS, 0, s>>>(circ, ii, nullptr, pi, NY, nz, NX, 0, tmp, oi,
                                                              (int64_t)NY, tw);
   FF_LAUNCH_CHECK("row transform of the kernel generator");
