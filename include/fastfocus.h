@@ -278,8 +278,11 @@ ff_status irls_step(ff_spectra h, const ff_irls_params *p, const double *d_obs, 
                    transforms (3 and 4 capped by the largest tile).
      batch         vectors per launch of apply_G_block, 1 <= batch <= the batch the handle's
                    workspace was sized for (the value build_spectra sets).
-     col_batched   1 = block applies use the 4-vectors-per-block column passes (single
-                   precision), 0 = one vector per column block.
+     col_batched   column passes of block applies (single precision, nfft_y <= 512): 1 = four
+                   vectors per block, the layers split over its wave groups; 2 (default) = the
+                   same for G^T, and for G eight vectors per block, each wave group one whole
+                   vector, the layer spectra staged in LDS once per block; 0 = one vector per
+                   column block.
      rsvd_qr       orthonormalization inside rsvd_project: 0 = Cholesky QR with the fallbacks
                    described there, 1 = always Householder QR (geqrf + orgqr), 2 = start at the
                    shifted CholeskyQR3 (then Householder).

@@ -10,7 +10,8 @@ The free launch parameters of a handle (``ff_set_tuning``) are:
   partial sums for G, more forward transforms for G^T);
 * ``row_tile``: transforms per row-pass block (automatic, one, two, four, or the largest that fits LDS);
 * ``batch`` and ``col_batched`` (block applies only): vectors per launch, and the column-pass
-  tile (4 vectors per block, or one).
+  tile (G: 8 vectors per block with one whole vector per wave group, or 4 vectors per block with
+  the layers split over its wave groups, or one vector per block).
 
 ``autotune`` times candidates on the caller's own vectors with HIP events (one G plus one G^T
 per trial), by coordinate descent over the parameters in that order, keeps the fastest, and
@@ -61,7 +62,7 @@ def candidates(op, batched):
     if batched:
         bmax = op.batch_max
         c["batch"] = sorted({b for b in (4, 8, 16, 32, 64, bmax) if b <= bmax})
-        c["col_batched"] = [1, 0]
+        c["col_batched"] = [2, 1, 0]
     return c
 
 

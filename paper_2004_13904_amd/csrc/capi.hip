@@ -382,7 +382,7 @@ ff_status ff_set_tuning(ff_spectra h, const ff_tuning *t) {
   if (t->row_tile < 0 || t->row_tile > 4) return fail(FF_EINVAL, "ff_set_tuning: row_tile must lie in [0, 4]");
   if (t->batch < 1 || t->batch > h->batch_max)
     return fail(FF_EINVAL, "ff_set_tuning: batch must lie in [1, the handle's workspace batch]");
-  if (t->col_batched != 0 && t->col_batched != 1) return fail(FF_EINVAL, "ff_set_tuning: col_batched must be 0 or 1");
+  if (t->col_batched < 0 || t->col_batched > 2) return fail(FF_EINVAL, "ff_set_tuning: col_batched must be 0, 1 or 2");
   if (t->rsvd_qr < 0 || t->rsvd_qr > 2) return fail(FF_EINVAL, "ff_set_tuning: rsvd_qr must be 0, 1 or 2");
   if (t->pair_fused < 0 || t->pair_fused > 2) return fail(FF_EINVAL, "ff_set_tuning: pair_fused must be 0, 1 or 2");
   if (t->gkb_graph != 0 && t->gkb_graph != 1) return fail(FF_EINVAL, "ff_set_tuning: gkb_graph must be 0 or 1");

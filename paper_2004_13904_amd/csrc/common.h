@@ -126,7 +126,7 @@ struct ff_spectra_s {
   int batch = ff::kMinBatch;          // vectors per batched launch (tunable, <= batch_max)
   int batch_max = ff::kMinBatch;      // vectors the pass workspace holds
   int row_tile = 0;                   // 0 auto, 1 one transform per row block, 2 largest tile
-  int col_batched = 1;                // 4-vectors-per-block column passes for block applies
+  int col_batched = 2;                // column passes of block applies (ff_tuning)
   int rsvd_qr = 0;                    // RSVD orthonormalization: 0 CholQR2 first, 1 Householder, 2 CholQR3 first
   int pair_fused = 1;                 // grouped plans: G x and G^T d of this survey share one column pass
   int gkb_graph = 0;                  // replay the GKB iteration loop from a captured graph

@@ -983,4 +983,131 @@ k_col_GT_batch(const cplx<T> *__restrict__ D1, int sy, int ldd, int pyl, int nz,
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// Vector-parallel column pass of G for block products (single precision, NY <= 512): a block
+// takes CPB column slots and VV = 8 vectors, one vector per wave group, and every wave group
+// runs its vector's whole column chain on its own (every layer's forward transform and
+// product, the layer sum and the inverse), the next layer's column loaded while the current
+// one is transformed.  The wave groups of a block wait for each other only while the block
+// stages the layer spectra of its columns in LDS, LC layers at a time: each spectrum column is
+// read from memory once per 8 vectors (the 4-vector pass reads it once per 2).  The layers are
+// summed in order, so the result agrees with the single-vector pass to rounding.  (The same
+// structure for G^T, one forward and nz inverse transforms per vector, was no faster than the
+// 4-vector pass.)
+template <typename T, int NY> struct VecCfg {
+  using CC = ColCfg<T, NY>;
+  static constexpr int VV = 8;                       // vectors (wave groups) per block
+  static constexpr int THREADS = VV * CC::THREADS;   // 512
+  static constexpr int LC = 8;                       // layers of spectra staged per round
+  static constexpr int SPL = CC::CPB * NY;           // spectrum elements per layer (512)
+  static constexpr int XL = CC::CPB * FFT<T, NY, false>::LDS;   // exchange elements per wave group
+  static constexpr int SH = VV * XL + LC * SPL;
+  static constexpr bool OK = std::is_same<T, float>::value && CC::TPF <= 64 && CC::THREADS == 64;
+};
+
+// stages the spectra of layers r0 .. r0 + lc - 1 of the block's CPB columns (kx0 ..) in LDS:
+// dst[l * SPL + f * NY + y]; columns past HC read column HC - 1 (their results are not stored)
+template <typename T, int NY>
+__device__ __forceinline__ void stage_spectra(cplx<T> *__restrict__ dst, const cplx<T> *__restrict__ spec, int r0,
+                                              int lc, int kx0, int HC) {
+  using VC = VecCfg<T, NY>;
+  const int64_t SH = HC + 1;
+  for (int e = threadIdx.x; e < lc * VC::SPL; e += VC::THREADS) {
+    const int l = e / VC::SPL, w = e - l * VC::SPL, fc = w / NY, y = w - fc * NY;
+    const int kx = min(kx0 + fc, HC - 1);
+    dst[e] = spec[((int64_t)(r0 + l) * SH + kx) * NY + y];
+  }
+}
+
+// Pass 2 of G for vectors 8 blockIdx.y + w: out[vec, 0, c, j] (the single layer-group partial).
+template <typename T, int NY, bool HALF, int FP = 0>
+__global__ void __launch_bounds__((VecCfg<T, NY>::THREADS))
+k_col_G_vec(const cplx<T> *__restrict__ X1, int ny, int ldy, int nz, int HC, int kb, int64_t vstride,
+            const cplx<T> *__restrict__ spec, cplx<T> *__restrict__ outp, int64_t ostride, int sy, int lds, int pyl,
+            const cplx<T> *__restrict__ tw) {
+  using CC = ColCfg<T, NY>;
+  using VC = VecCfg<T, NY>;
+  using Ff = FFT<T, NY, false, FP>;
+  using Fi = FFT<T, NY, true, FP>;
+  constexpr int TPF = CC::TPF, UH = HALF ? 4 : 8;
+  static_assert(VC::OK, "vector-parallel column pass configuration");
+  __shared__ cplx<T> sh[VC::SH];
+  const int w = threadIdx.x / CC::THREADS, lt = threadIdx.x % CC::THREADS;
+  const int f = lt / TPF, j = lt % TPF;
+  const int kx0 = blockIdx.x * CC::CPB, kx = kx0 + f;
+  const bool ok = kx < HC;
+  const int kxs = ok ? kx : 0;
+  const bool pk = blockIdx.x == 0;   // block-uniform: slot 0 sits at f == 0 of block 0
+  const int64_t vec = (int64_t)blockIdx.y * VC::VV + w;
+  const bool live = vec < kb;         // wave-uniform
+  const int64_t SH = HC + 1;
+  cplx<T> *buf = sh + w * VC::XL + f * Fi::LDS;
+  cplx<T> *sp = sh + VC::VV * VC::XL;
+  typename Ff::Tw twr;
+  Ff::load_tw(twr, j, tw);
+  cplx<T> acc[8], accm[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    acc[u] = mk<T>(0, 0);
+    accm[u] = mk<T>(0, 0);
+  }
+  const cplx<T> *src = X1 + vec * vstride + (int64_t)kxs * ldy;
+  cplx<T> xn[UH];   // the next layer's column, loaded while the current one is transformed
+  auto load = [&](int rr) {
+    const cplx<T> *xr = src + (int64_t)rr * HC * ldy;
+#pragma unroll
+    for (int u = 0; u < UH; ++u) {
+      const int y = j + u * TPF;
+      xn[u] = (ok && y < ny) ? xr[y] : mk<T>(0, 0);
+    }
+  };
+  if (live) load(0);
+  for (int r0 = 0; r0 < nz; r0 += VC::LC) {
+    const int lc = min(VC::LC, nz - r0);
+    __syncthreads();   // the previous round's spectra are no longer read
+    stage_spectra<T, NY>(sp, spec, r0, lc, kx0, HC);
+    __syncthreads();
+    if (live) {
+      for (int l = 0; l < lc; ++l) {
+        const int rr = r0 + l;
+        cplx<T> v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = u < UH ? xn[u] : mk<T>(0, 0);
+        if (rr + 1 < nz) load(rr + 1);
+        Ff::template run_tw<HALF, false>(v, j, buf, twr);
+        const cplx<T> *s = sp + l * VC::SPL + f * NY;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] = cadd<T>(acc[u], cmul<T>(v[u], s[j + u * TPF]));
+        if (pk) {
+          const cplx<T> *mp = spec + ((int64_t)rr * SH + HC) * NY;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) accm[u] = cadd<T>(accm[u], cmul<T>(v[u], mp[j + u * TPF]));
+        }
+      }
+    }
+  }
+  if (!live) return;
+  if (pk) {
+    // acc[k] += conj(accm[-k]) in the packed slot (f == 0)
+    group_sync<TPF>();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) buf[pad8(j + u * TPF)] = accm[u];
+    group_sync<TPF>();
+    if (f == 0) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = cadd<T>(acc[u], cconj<T>(buf[pad8((NY - j - u * TPF) & (NY - 1))]));
+    }
+    group_sync<TPF>();
+  }
+  Fi::template run_tw<false, HALF>(acc, j, buf, *reinterpret_cast<const typename Fi::Tw *>(&twr));
+  if (ok) {
+    cplx<T> *dst = outp + vec * ostride + (int64_t)kx * lds;
+#pragma unroll
+    for (int u = 0; u < UH; ++u) {
+      const int y = j + u * TPF - pyl;
+      if (y >= 0 && y < sy) dst[y] = acc[u];
+    }
+  }
+}
+
 }  // namespace ff

@@ -22,6 +22,12 @@ template <int FP, typename T, typename TO>
 ff_status c2r_pass(ff_spectra h, const OpWs &ws, int transpose, int kb, TO *Y, int64_t ldy_out, const TO *post,
                    hipStream_t s);
 
+// block products whose G column pass is the vector-parallel one (k_col_G_vec), which leaves
+// one layer-group partial per vector (G^T keeps the 4-vector pass)
+inline bool vec_cols(ff_spectra h, int kb) {
+  return kb > 1 && h->col_batched == 2 && h->dtype == FF_F32 && h->NY <= 512;
+}
+
 #ifdef FF_PLAN_UNIT
 namespace {
 
@@ -126,8 +132,8 @@ ff_status c2r_pass(ff_spectra h, const OpWs &ws, int transpose, int kb, TO *Y, i
     if constexpr (plan_canon(NN, FP) != FP) return fail(FF_EINVAL, "stage plan is not canonical for the row size");
     else if (!transpose)
       launch_c2r<T, TO, NN, FP>(h->row_tile, sy, 1, kb, C2, Idx3{(int64_t)h->lg_G * HC * lds, 0, 1}, lds,
-                                (int64_t)HC * lds, h->lg_G, Y, Idx3{ldy_out, 0, sx}, post, Idx3{0, 0, sx}, sx, h->pxl,
-                                twx, s);
+                                (int64_t)HC * lds, vec_cols(h, kb) ? 1 : h->lg_G, Y, Idx3{ldy_out, 0, sx}, post,
+                                Idx3{0, 0, sx}, sx, h->pxl, twx, s);
     else
       launch_c2r<T, TO, NN, FP>(h->row_tile, ny, nz, kb, X1, Idx3{(int64_t)nz * HC * ldy, (int64_t)HC * ldy, 1}, ldy,
                                 0, 1, Y, Idx3{ldy_out, lay, nx}, post, Idx3{0, lay, nx}, nx, 0, twx, s);
@@ -152,8 +158,22 @@ ff_status col_pass(ff_spectra h, const OpWs &ws, int transpose, int kb, hipStrea
       return fail(FF_EINVAL, "stage plan is not canonical for the column size");
     } else {
       bool done = false;
+      if constexpr (VecCfg<T, NN>::OK) {
+        if (!transpose && vec_cols(h, kb)) {
+          using VC = VecCfg<T, NN>;
+          dim3 g((HC + CC::CPB - 1) / CC::CPB, (kb + VC::VV - 1) / VC::VV);
+          const int64_t xs = (int64_t)nz * HC * ldy;
+          if (half)
+            k_col_G_vec<T, NN, true, FP><<<g, VC::THREADS, 0, s>>>(X1, ny, ldy, nz, HC, kb, xs, spec, C2,
+                                                                  (int64_t)h->lg_G * HC * lds, sy, lds, h->pyl, twy);
+          else
+            k_col_G_vec<T, NN, false, FP><<<g, VC::THREADS, 0, s>>>(X1, ny, ldy, nz, HC, kb, xs, spec, C2,
+                                                                   (int64_t)h->lg_G * HC * lds, sy, lds, h->pyl, twy);
+          done = true;
+        }
+      }
       if constexpr (BatchCfg<T, NN>::OK) {
-        if (kb > 1 && h->col_batched) {
+        if (!done && kb > 1 && h->col_batched) {
           dim3 g((HC + CC::CPB - 1) / CC::CPB, LG, (kb + BatchCfg<T, NN>::V - 1) / BatchCfg<T, NN>::V);
           if (!transpose && half)
             k_col_G_batch<T, NN, true, FP><<<g, CC::THREADS * CC::WPB, 0, s>>>(X1, ny, ldy, nz, HC, LG, kb, spec, C2,

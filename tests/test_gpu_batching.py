@@ -169,19 +169,20 @@ def test_tuning_variants_keep_results():
     D = torch.randn(6, A.m, device="cuda", generator=g)
     ref_g, ref_t = A.G_block(X).clone(), A.G_block(D, transpose=True).clone()
     base = A.tuning
-    assert base["batch"] == A.batch_max >= 16 and base["col_batched"] == 1
+    assert base["batch"] == A.batch_max >= 16 and base["col_batched"] == 2
     # the row tile changes only which block runs a row transform: bit-identical
     for tile in (1, 2, 3, 4, 0):
         A.set_tuning(row_tile=tile)
         assert torch.equal(A.G_block(X), ref_g)
         assert torch.equal(A.G_block(D, transpose=True), ref_t)
     # batch schedule and per-vector column blocks: the same sums in another order
-    for kw in ({"batch": 1}, {"batch": 4}, {"batch": 5}, {"batch": A.batch_max, "col_batched": 0}):
+    for kw in ({"batch": 1}, {"batch": 4}, {"batch": 5}, {"batch": A.batch_max, "col_batched": 0},
+               {"col_batched": 1}, {"batch": 5, "col_batched": 1}, {"batch": 5, "col_batched": 2}):
         A.set_tuning(**kw)
         assert rel(to_host(A.G_block(X)), to_host(ref_g)) <= 2e-6
         assert rel(to_host(A.G_block(D, transpose=True)), to_host(ref_t)) <= 2e-6
     from paper_2004_13904_amd import _lib as L
-    for bad in ({"row_tile": 5}, {"batch": 0}, {"batch": A.batch_max + 1}, {"col_batched": 2}, {"rsvd_qr": 3},
+    for bad in ({"row_tile": 5}, {"batch": 0}, {"batch": A.batch_max + 1}, {"col_batched": 3}, {"rsvd_qr": 3},
                 {"lg_G": 0}, {"lg_GT": A.nz + 1}):
         with pytest.raises(L.FastFocusError):
             A.set_tuning(**bad)
