@@ -3,10 +3,10 @@
 // launches per survey.  A survey alone is a chain of small, latency-bound kernels; grouped, the
 // chains of all surveys share each launch's ramp and fill the chip together.
 //
-// Each launch has 512-thread blocks; block b finds its task (survey and product) in a table of
-// first-block indices and runs the same pass body as the per-survey kernels for that task's
-// transform length.  The row passes take 4096/N transforms per block (512 threads for every N
-// up to 512); the column passes have 8 wave groups of 64 threads for every NY up to 512.
+// Block b of a launch finds its task (survey and product) in a table of first-block indices and
+// runs the same pass body as the per-survey kernels for that task's transform length.  The row
+// passes take 2048/N transforms per 256-thread block for every N up to 512; the column passes
+// have 8 wave groups of 64 threads (512 threads) for every NY up to 512.
 #include <algorithm>
 #include <new>
 #include <vector>
@@ -16,13 +16,14 @@
 namespace ff {
 namespace {
 
-constexpr int kMultiThreads = 512;
+constexpr int kMultiThreads = 512;      // column blocks
+constexpr int kMultiRowThreads = 256;   // row blocks
 constexpr int kMultiMaxN = 512;     // largest embedding side of a grouped survey
 
 template <int N> struct MultiRow {
-  static constexpr int NF = 4096 / N;
+  static constexpr int NF = 8 * kMultiRowThreads / N;
   using C = RowCfg<float, N, NF>;
-  static_assert(C::THREADS == kMultiThreads, "grouped row blocks have 512 threads");
+  static_assert(C::THREADS == kMultiRowThreads, "grouped row blocks have kMultiRowThreads threads");
 };
 
 template <int NY> struct MultiCol {
@@ -136,7 +137,7 @@ template <int NY, bool PAIR> __device__ __forceinline__ void col_task(float2 *sh
     default: break;                                                                                          \
   }
 
-__global__ void __launch_bounds__(kMultiThreads) k_multi_r2c(const R2CTask *__restrict__ tasks, int nt) {
+__global__ void __launch_bounds__(kMultiRowThreads) k_multi_r2c(const R2CTask *__restrict__ tasks, int nt) {
   __shared__ float2 sh[kRowSH];
   const R2CTask &t = tasks[find_task(tasks, nt)];
   const int lb = (int)blockIdx.x - t.block0;
@@ -163,7 +164,7 @@ __global__ void __launch_bounds__(kMultiThreads) k_multi_col_pair(const ColTask 
 #undef FF_COL
 }
 
-__global__ void __launch_bounds__(kMultiThreads) k_multi_c2r(const C2RTask *__restrict__ tasks, int nt) {
+__global__ void __launch_bounds__(kMultiRowThreads) k_multi_c2r(const C2RTask *__restrict__ tasks, int nt) {
   __shared__ float2 sh[kRowSH];
   const C2RTask &t = tasks[find_task(tasks, nt)];
   const int lb = (int)blockIdx.x - t.block0;
@@ -172,7 +173,8 @@ __global__ void __launch_bounds__(kMultiThreads) k_multi_c2r(const C2RTask *__re
 #undef FF_C2R
 }
 
-int rows_per_block(int N) { return 2 * (4096 / N); }
+constexpr int MultiRowNF(int N) { return 8 * kMultiRowThreads / N; }
+int rows_per_block(int N) { return 2 * MultiRowNF(N); }
 int col_blocks_x(int NY, int HC) {
   const int tpf = NY / 8, cpb = tpf >= 64 ? 1 : 64 / tpf;
   return (HC + cpb - 1) / cpb;
@@ -331,11 +333,11 @@ ff_status ff_multi_apply(ff_multi p, ff_stream stream) {
   if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
     return fail(FF_EDEVICE, "ff_multi_apply: plan built on another device");
   hipStream_t s = (hipStream_t)stream;
-  if (p->n_r2c) k_multi_r2c<<<p->b_r2c, kMultiThreads, 0, s>>>(p->r2c, p->n_r2c);
+  if (p->n_r2c) k_multi_r2c<<<p->b_r2c, kMultiRowThreads, 0, s>>>(p->r2c, p->n_r2c);
   FF_LAUNCH_CHECK("grouped row transforms");
   launch_col(p, s);
   FF_LAUNCH_CHECK("grouped column passes");
-  if (p->n_c2r) k_multi_c2r<<<p->b_c2r, kMultiThreads, 0, s>>>(p->c2r, p->n_c2r);
+  if (p->n_c2r) k_multi_c2r<<<p->b_c2r, kMultiRowThreads, 0, s>>>(p->c2r, p->n_c2r);
   FF_LAUNCH_CHECK("grouped inverse row transforms");
   return FF_OK;
 }
@@ -348,9 +350,9 @@ ff_status ff_multi_time_pass(ff_multi p, int32_t pass, int32_t reps, ff_stream s
     return fail(FF_EDEVICE, "ff_multi_time_pass: plan built on another device");
   hipStream_t s = (hipStream_t)stream;
   for (int r = 0; r < reps; ++r) {
-    if (pass == 0 && p->n_r2c) k_multi_r2c<<<p->b_r2c, kMultiThreads, 0, s>>>(p->r2c, p->n_r2c);
+    if (pass == 0 && p->n_r2c) k_multi_r2c<<<p->b_r2c, kMultiRowThreads, 0, s>>>(p->r2c, p->n_r2c);
     if (pass == 1) launch_col(p, s);
-    if (pass == 2 && p->n_c2r) k_multi_c2r<<<p->b_c2r, kMultiThreads, 0, s>>>(p->c2r, p->n_c2r);
+    if (pass == 2 && p->n_c2r) k_multi_c2r<<<p->b_c2r, kMultiRowThreads, 0, s>>>(p->c2r, p->n_c2r);
   }
   FF_LAUNCH_CHECK("ff_multi_time_pass");
   return FF_OK;
