@@ -4,9 +4,9 @@ Sec. 2.1 and Fig. 1 of the paper: stations s_ij on the surface at the centres of
 unpadded surface cells, prisms c_pqr on a uniform grid with optional padding cells
 (no stations over them), m = s_x s_y data and n = n_x n_y n_z unknowns.
 
-Vector layouts (the paper only says "reshaped"; this reading is fixed for the whole
-project): the model vector is ordered (layer r, row q, column p) with p fastest,
-the data vector (row j, column i) with i fastest.
+Vector layouts (the paper does not fix the order in which its 2-D arrays become vectors;
+this reading is fixed for the whole project): the model vector is ordered (layer r, row q,
+column p) with p fastest, the data vector (row j, column i) with i fastest.
 """
 from __future__ import annotations
 
