@@ -273,7 +273,8 @@ ff_status irls_step(ff_spectra h, const ff_irls_params *p, const double *d_obs, 
                    inverse row pass.
      row_tile      transforms per row-pass block: 0 = automatic by the rows of the pass (one
                    transform below 512 rows, two below 1024, else four; inverse passes of at
-                   least 2048 rows take the largest tile that fits 64 KB of LDS), 1 = always one
+                   least 2048 rows and every pass of at least 16384 rows take the largest tile
+                   that fits 64 KB of LDS), 1 = always one
                    transform (two rows), 2 = always the largest tile, 3 = four transforms, 4 = two
                    transforms (3 and 4 capped by the largest tile).
      batch         vectors per launch of apply_G_block, 1 <= batch <= the batch the handle's
