@@ -604,3 +604,44 @@ def test_irls_rsvd_single_precision_basis_matches_oracle():
     assert abs(a2 - a2o) <= 1e-3 * a2o
     assert rel(to_host(m2), m2o) <= 1e-4 + 2 * abs(a2 - a2o) / a2o
     assert abs(c2 - c2o) <= (1e-4 + 4 * abs(a2 - a2o) / a2o) * c2o
+
+
+@pytest.mark.parametrize("solver", ["gkb", "rsvd"])
+def test_irls_trajectory_matches_oracle(solver):
+    # six free-running IRLS steps (Secs. 2.2-2.3, the paper's lambda = 1) on the FP64 operator
+    # against the oracle's own loop from m^(0) = 0: every step's alpha, model and scaled chi^2.
+    # Step 1 (eq. (eq:alpha1)) agrees to rounding; from step 2 on alpha is the UPRE minimizer, whose
+    # flat minimum rounding moves by about 1e-7 relative, and each step feeds the next: the
+    # trajectories stay within 2e-6 (measured: at most 5e-7 in alpha, 6e-8 in the model).
+    s = W.survey(16, 12, 5, 25, 25, 25)
+    g = ogeom(s)
+    G = op.dense_G(g)
+    rng = np.random.default_rng(3)
+    m_true = np.zeros(g.n)
+    m_true[rng.choice(g.n, 20, replace=False)] = 1.0
+    d_exact = G @ m_true
+    eta, sd = W.noise(d_exact, 0.02, 0.002, 5)
+    d_obs = d_exact + eta
+    wd = 1.0 / sd
+    t, tp, K = 40, 42, 6
+    omegas = {k: np.random.default_rng(100 + k).standard_normal((tp, g.m)) for k in range(1, K + 1)}
+    po = oirls.IrlsParams(solver=solver, t=t, tp=tp, lam=1.0, beta_depth=0.8, m_min=0.0, m_max=1.0)
+    pg = S.IrlsParams(solver=solver, t=t, tp=tp, lam=1.0, beta_depth=0.8, m_min=0.0, m_max=1.0)
+    ref = []
+    m_prev, m_prev2 = np.zeros(g.n), None
+    for k in range(1, K + 1):
+        m_new, a, c, _ = oirls.irls_step(g, po, k, d_obs, wd, m_prev, m_prev2, omegas[k], G_dense=G)
+        ref.append((m_new, a, c))
+        m_prev2, m_prev = m_prev, m_new
+    got = []
+    A = Operator(s, F64)
+    S.irls(A, pg, to_dev(d_obs, F64), to_dev(wd, F64), k_max=K, stop_at_chi2=False,
+           omega_fn=lambda k: to_dev(omegas[k], F64),
+           callback=lambda k, m, a, c: got.append((to_host(m), a, c)))
+    assert len(got) == K
+    for k, ((mg, ag, cg), (mo, ao, co)) in enumerate(zip(got, ref), start=1):
+        tol = 1e-11 if k == 1 else 2e-6
+        announce("irls trajectory", solver, k, abs(ag - ao) / ao, rel(mg, mo), abs(cg - co) / co)
+        assert abs(ag - ao) <= tol * ao
+        assert rel(mg, mo) <= tol
+        assert abs(cg - co) <= tol * co
