@@ -949,7 +949,7 @@ struct RsvdWs {
 // products and the products with R^-1, so every product and sum is still formed in double.
 // The m x t_p matrices and the projected problem stay FP64.
 int64_t lean_chunk_rows(int64_t n, int tp) {
-  int64_t r = ((int64_t)1 << 26) / (tp > 0 ? tp : 1);   // 512 MB of doubles per staging buffer
+  int64_t r = ((int64_t)1 << 27) / (tp > 0 ? tp : 1);   // 1 GB of doubles per staging buffer
   if (r < 4096) r = 4096;
   return r > n ? n : r;
 }
@@ -969,7 +969,7 @@ struct RsvdWs32 {
     Bm = a.take<double>((size_t)m * tp);     // G~ Q, and Omega when drawn here
     T = a.take<double>((size_t)m * tp);      // QR scratch of the m x t_p factors
     U = a.take<double>((size_t)m * tp);
-    Gs = a.take<double>(gram_scratch(m, tp));
+    Gs = a.take<double>(gram_scratch(m > CH ? m : CH, tp));
     Ca = a.take<double>((size_t)CH * tp);
     Cb = a.take<double>((size_t)CH * tp);
     dev = a.take<double>(1);
@@ -1280,14 +1280,42 @@ dim3 chunk_grid(int64_t rows, int cols) {
 
 // G = Q^T Q over row chunks staged in FP64 (the chunks' products accumulated in order)
 ff_status gram32(rocblas_handle bh, const float *Q, int64_t n, int tp, RsvdWs32 &W, double *G, hipStream_t s) {
+  // Each staging round converts S row blocks of R rows (S R <= CH) to FP64 side by side, and one
+  // strided-batched product adds their Gram matrices to S partial sums (as gram() splits the
+  // rows, so that the product has S times the output tiles); the partials are summed in order at
+  // the end.  A last round of fewer rows adds its product to the first partial.
   const double one = 1.0, zero = 0.0;
-  for (int64_t r0 = 0; r0 < n; r0 += W.CH) {
-    const int64_t rows = n - r0 < W.CH ? n - r0 : W.CH;
-    k_rows_to64<<<chunk_grid(rows, tp), kThreads, 0, s>>>(Q, n, r0, rows, tp, W.Ca);
-    FF_LAUNCH_CHECK("basis chunk to FP64");
-    FF_BLAS(rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, tp, tp, (rocblas_int)rows, &one,
-                          W.Ca, (rocblas_int)rows, W.Ca, (rocblas_int)rows, r0 == 0 ? &zero : &one, G, tp),
-            "rocblas_dgemm (chunked Gram)");
+  const int S = gram_chunks(W.CH, tp);
+  const int64_t R = W.CH / S, cc = (int64_t)tp * tp;
+  double *Gp = S > 1 ? W.Gs : G;
+  bool first = true;
+  for (int64_t r0 = 0; r0 < n;) {
+    const int64_t left = n - r0;
+    if (left >= (int64_t)S * R) {
+      for (int p = 0; p < S; ++p)
+        k_rows_to64<<<chunk_grid(R, tp), kThreads, 0, s>>>(Q, n, r0 + p * R, R, tp, W.Ca + p * R * tp);
+      FF_LAUNCH_CHECK("basis chunk to FP64");
+      FF_BLAS(rocblas_dgemm_strided_batched(bh, rocblas_operation_transpose, rocblas_operation_none, tp, tp,
+                                            (rocblas_int)R, &one, W.Ca, (rocblas_int)R, R * tp, W.Ca, (rocblas_int)R,
+                                            R * tp, first ? &zero : &one, Gp, tp, cc, S),
+              "rocblas_dgemm_strided_batched (chunked Gram)");
+      r0 += (int64_t)S * R;
+    } else {
+      if (first && S > 1) {   // fewer rows than one round: the partials are not used
+        Gp = G;
+      }
+      k_rows_to64<<<chunk_grid(left, tp), kThreads, 0, s>>>(Q, n, r0, left, tp, W.Ca);
+      FF_LAUNCH_CHECK("basis chunk to FP64");
+      FF_BLAS(rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, tp, tp, (rocblas_int)left, &one,
+                            W.Ca, (rocblas_int)left, W.Ca, (rocblas_int)left, first ? &zero : &one, Gp, tp),
+              "rocblas_dgemm (chunked Gram)");
+      r0 = n;
+    }
+    first = false;
+  }
+  if (Gp != G) {
+    k_sum_slices<<<grid_for(cc), kThreads, 0, s>>>(Gp, S, cc, G);
+    FF_LAUNCH_CHECK("Gram sum");
   }
   return FF_OK;
 }
