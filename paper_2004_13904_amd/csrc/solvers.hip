@@ -901,8 +901,8 @@ template <typename TB> struct GkbWs {
 // Row chunks of a split Gram product Y^T Y (rows x cols Y): a single product has only
 // (cols / tile)^2 output tiles, too few for the chip when cols is small, so the rows are cut into
 // S chunks of at least 4 max(cols, 256) rows whose Gram matrices come from one batched product;
-// at most 64 chunks and 2^25 doubles of partial matrices.
-constexpr int64_t kGramScratch = (int64_t)1 << 25;
+// at most 64 chunks and 2^26 doubles (512 MB) of partial matrices.
+constexpr int64_t kGramScratch = (int64_t)1 << 26;
 int gram_chunks(int64_t rows, int cols) {
   int64_t S = rows / (4 * (int64_t)(cols > 256 ? cols : 256));
   if (S > 64) S = 64;
