@@ -300,25 +300,28 @@ k_gemv_t_partial(const TB *__restrict__ A, int64_t lda, int64_t nrows, int ncols
   }
 }
 
-// out[j] = scale * sum_p part[p][j]: 64 columns per block, the row-block range split over
-// the block's four waves, then summed in LDS in wave order.
+// out[j] = scale * sum_p part[p][j]: kCSumCols columns per block, the row-block range split over
+// the block's kThreads / kCSumCols groups of threads (consecutive threads of a group read
+// consecutive columns), then the groups' sums added in LDS in group order.  Narrow blocks and
+// short per-thread chains: at a few hundred columns the sums take a few dozen blocks.
+constexpr int kCSumCols = 16;
 __global__ void __launch_bounds__(kThreads)
 k_colsum(const double *__restrict__ part, int P, int ncols, double *__restrict__ out, double scale,
          const int *__restrict__ run) {
   if (run && *run == 0) return;
   __shared__ double red[kThreads];
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int j = blockIdx.x * 64 + l;
-  const int nw = kThreads / 64;
-  const int p0 = (int)((int64_t)P * w / nw), p1 = (int)((int64_t)P * (w + 1) / nw);
+  constexpr int NG = kThreads / kCSumCols;
+  const int c = threadIdx.x % kCSumCols, g = threadIdx.x / kCSumCols;
+  const int j = blockIdx.x * kCSumCols + c;
+  const int p0 = (int)((int64_t)P * g / NG), p1 = (int)((int64_t)P * (g + 1) / NG);
   double s = 0.0;
   if (j < ncols)
     for (int p = p0; p < p1; ++p) s += part[(int64_t)p * ncols + j];
   red[threadIdx.x] = s;
   __syncthreads();
-  if (w == 0 && j < ncols) {
-    double t = red[l];
-    for (int q = 1; q < nw; ++q) t += red[q * 64 + l];
+  if (g == 0 && j < ncols) {
+    double t = red[c];
+    for (int q = 1; q < NG; ++q) t += red[q * kCSumCols + c];
     out[j] = scale * t;
   }
 }
@@ -774,7 +777,7 @@ void launch_gemv_t(const TB *Q, int64_t ld, int64_t nrows, int ncols, const doub
     k_gemv_t_partial<R, TB><<<gt, kThreads, 0, s>>>(Q, ld, nrows, ncols, v, part, run);
   else
     k_gemv_t_partial<1, TB><<<gt, kThreads, 0, s>>>(Q, ld, nrows, ncols, v, part, run);
-  k_colsum<<<(ncols + 63) / 64, kThreads, 0, s>>>(part, P, ncols, out, 1.0, run);
+  k_colsum<<<(ncols + kCSumCols - 1) / kCSumCols, kThreads, 0, s>>>(part, P, ncols, out, 1.0, run);
 }
 
 // Returns the number of blocks (= partial sums written to sq, if given).
