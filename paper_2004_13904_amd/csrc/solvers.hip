@@ -326,20 +326,20 @@ k_colsum(const double *__restrict__ part, int P, int ncols, double *__restrict__
   }
 }
 
-// y = beta * y + alpha * A c   (A column-major nrows x ncols, ld lda).  A block of kNWaves waves
+// y = beta * y + alpha * A c   (A column-major nrows x ncols, ld lda).  A block of NW waves
 // covers 64 * RPL rows (RPL consecutive rows per lane, 16-byte loads when RPL = 2); wave w takes
-// the columns [w ncols / kNWaves, (w + 1) ncols / kNWaves), so that many column loads of a lane
-// are in flight; the waves' sums meet in LDS and are added in wave order.
-// Grid: ceil(nrows / (64 * RPL)) blocks of 64 * kNWaves threads.
-template <int RPL, typename TB>
-__global__ void __launch_bounds__(64 * kNWaves)
+// the columns [w ncols / NW, (w + 1) ncols / NW), so that many column loads of a lane are in
+// flight; the waves' sums meet in LDS and are added in wave order.
+// Grid: ceil(nrows / (64 * RPL)) blocks of 64 * NW threads.
+template <int RPL, typename TB, int NW = kNWaves>
+__global__ void __launch_bounds__(64 * NW)
 k_gemv_n(const TB *__restrict__ A, int64_t lda, int64_t nrows, int ncols, const double *__restrict__ c,
          double *__restrict__ y, double alpha, double beta, const int *__restrict__ run, double *__restrict__ sq) {
   if (run && *run == 0) return;
-  __shared__ double red[kNWaves][64 * RPL];
+  __shared__ double red[NW][64 * RPL];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t r = ((int64_t)blockIdx.x * 64 + l) * RPL;
-  const int j0 = (int)((int64_t)ncols * w / kNWaves), j1 = (int)((int64_t)ncols * (w + 1) / kNWaves);
+  const int j0 = (int)((int64_t)ncols * w / NW), j1 = (int)((int64_t)ncols * (w + 1) / NW);
   double s[RPL];
 #pragma unroll
   for (int q = 0; q < RPL; ++q) s[q] = 0.0;
@@ -374,11 +374,11 @@ k_gemv_n(const TB *__restrict__ A, int64_t lda, int64_t nrows, int ncols, const 
   for (int q = 0; q < RPL; ++q) red[w][l * RPL + q] = s[q];
   __syncthreads();
   double ss = 0.0;
-  for (int e = threadIdx.x; e < 64 * RPL; e += 64 * kNWaves) {
+  for (int e = threadIdx.x; e < 64 * RPL; e += 64 * NW) {
     const int64_t rr = (int64_t)blockIdx.x * 64 * RPL + e;
     if (rr < nrows) {
       double t = red[0][e];
-      for (int q = 1; q < kNWaves; ++q) t += red[q][e];
+      for (int q = 1; q < NW; ++q) t += red[q][e];
       const double v = (beta == 0.0 ? 0.0 : beta * y[rr]) + alpha * t;
       y[rr] = v;
       ss += v * v;
@@ -791,8 +791,9 @@ int launch_gemv_n(const TB *Q, int64_t ld, int64_t nrows, int ncols, const doubl
     k_gemv_n<R, TB><<<nb, 64 * kNWaves, 0, s>>>(Q, ld, nrows, ncols, c, y, alpha, beta, run, sq);
     return (int)nb;
   }
+  // shorter bases: twice the waves per block, half the columns per wave
   const unsigned nb = (unsigned)((nrows + 63) / 64);
-  k_gemv_n<1, TB><<<nb, 64 * kNWaves, 0, s>>>(Q, ld, nrows, ncols, c, y, alpha, beta, run, sq);
+  k_gemv_n<1, TB, 2 * kNWaves><<<nb, 128 * kNWaves, 0, s>>>(Q, ld, nrows, ncols, c, y, alpha, beta, run, sq);
   return (int)nb;
 }
 
