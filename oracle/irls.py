@@ -11,8 +11,11 @@ Sec. 2.2-2.3 of the paper:
   m^(k) = clip(m^(k-1) + W^{-1} z, m_min, m_max),
 * alpha^(1) by eq. (eq:alpha1), UPRE for k > 1,
 * the chi^2 test eq. (scaledchi2) on the clipped iterate.
-Whole multi-step trajectories: parity unpinned (alpha choices and clipping amplify
-rounding); single steps are pinned against the dense closed form.
+Whole multi-step trajectories are pinned only where they have a closed form: with lambda = 2
+(every focusing weight 1), alpha fixed, the bounds inactive and the full projected space, the
+iterates follow iterated Tikhonov (tests/test_oracle_solvers.py).  With the focusing weights,
+the UPRE alpha and active bounds: parity unpinned (single steps are pinned against the dense
+closed form; a trajectory feeds rounding in alpha and the clipping into the next step).
 """
 from __future__ import annotations
 

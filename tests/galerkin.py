@@ -43,3 +43,14 @@ def rsvd_galerkin_defects(apply_Gt, apply_GtT, r_tilde, y, alpha, omega, power_i
             v = apply_GtT(apply_Gt(v))
         out.append(abs(v @ g) / (np.linalg.norm(v) * scale))
     return np.array(out)
+
+
+def iterated_tikhonov(A, b, alpha, K):
+    """The iterates y^(1..K) of y^(k) = y^(k-1) + (A^T A + alpha^2 I)^{-1} A^T (b - A y^(k-1)),
+    y^(0) = 0, in closed form: along the right singular vector v_i (singular value s_i, data
+    coefficient c_i = u_i^T b) the error c_i / s_i - y_i shrinks by alpha^2 / (s_i^2 + alpha^2)
+    per step, so y^(k)_i = (c_i / s_i) (1 - (alpha^2 / (s_i^2 + alpha^2))^k)."""
+    U, s, Vt = np.linalg.svd(np.asarray(A, dtype=np.float64), full_matrices=False)
+    c = U.T @ np.asarray(b, dtype=np.float64)
+    q = alpha * alpha / (s * s + alpha * alpha)
+    return [Vt.T @ ((c / s) * (1.0 - q ** k)) for k in range(1, K + 1)]

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 import torch
 
-from galerkin import galerkin_defects, rsvd_galerkin_defects
+from galerkin import galerkin_defects, iterated_tikhonov, rsvd_galerkin_defects
 from gpu_common import announce, ogeom, rel, to_dev, to_host
 from oracle import irls as oirls, operator as op, philox, solvers as osol
 from paper_2004_13904_amd import _lib as L
@@ -645,3 +645,38 @@ def test_irls_trajectory_matches_oracle(solver):
         assert abs(ag - ao) <= tol * ao
         assert rel(mg, mo) <= tol
         assert abs(cg - co) <= tol * co
+
+
+@pytest.mark.parametrize("solver", ["gkb", "rsvd"])
+def test_irls_trajectory_is_iterated_tikhonov(solver):
+    # six chained IRLS steps of the device loop against a closed form (Secs. 2.2-2.3): with
+    # lambda = 2 every focusing weight of eq. (WLdefn) is 1, with alpha fixed, the bounds inactive
+    # and t = t_p = m each step adds the exact Tikhonov update of the current residual, so y = W m
+    # follows iterated Tikhonov from y^(0) = 0 (tests/galerkin.py).  FP64 operator.
+    s = W.survey(8, 8, 2, 25, 25, 25)
+    g = ogeom(s)
+    G = op.dense_G(g)
+    rng = np.random.default_rng(4)
+    d_obs = G @ rng.random(g.n) + 0.01 * rng.standard_normal(g.m)
+    wd = 1.0 / (0.05 + rng.random(g.m))
+    w = oirls.depth_weights(g, 0.8)
+    Gt = wd[:, None] * G / w[None, :]
+    alpha = 0.3 * np.linalg.svd(Gt, compute_uv=False)[5]
+    K = 6
+    ref = iterated_tikhonov(Gt, wd * d_obs, alpha, K)
+    p = S.IrlsParams(solver=solver, t=g.m, tp=g.m, lam=2.0, beta_depth=0.8, m_min=-1e300, m_max=1e300,
+                     alpha_fixed=alpha)
+    got = []
+    A = Operator(s, F64)
+    S.irls(A, p, to_dev(d_obs, F64), to_dev(wd, F64), k_max=K, stop_at_chi2=False,
+           omega_fn=lambda k: to_dev(np.random.default_rng(50 + k).standard_normal((g.m, g.m)), F64),
+           callback=lambda k, m, a, c: got.append((to_host(m), a, c)))
+    assert len(got) == K
+    for k, (m_k, a, c) in enumerate(got, start=1):
+        y = w * m_k
+        r = wd * d_obs - Gt @ ref[k - 1]
+        c_ref = (r @ r) / (g.m + math.sqrt(2.0 * g.m))
+        announce("iterated tikhonov", solver, k, rel(y, ref[k - 1]), abs(c - c_ref) / c_ref)
+        assert a == alpha
+        assert rel(y, ref[k - 1]) <= 1e-10   # measured 2e-14
+        assert abs(c - c_ref) <= 1e-10 * c_ref

@@ -4,7 +4,7 @@ import math
 import numpy as np
 import pytest
 
-from galerkin import galerkin_defects, rsvd_galerkin_defects
+from galerkin import galerkin_defects, iterated_tikhonov, rsvd_galerkin_defects
 from oracle import geometry, irls, operator as op, solvers
 
 
@@ -257,3 +257,39 @@ def test_scaled_chi2_of_pure_noise():
     assert abs(num.var(ddof=1) / (2.0 * m) - 1.0) < 0.25
     # a noise-free model gives zero
     assert irls.chi2_scaled(d_exact, d_exact, np.ones(m)) == 0.0
+
+
+@pytest.mark.parametrize("solver", ["gkb", "rsvd"])
+def test_irls_trajectory_is_iterated_tikhonov(solver):
+    # A whole multi-step trajectory of the oracle's IRLS (Secs. 2.2-2.3) in the regime where it has
+    # a closed form: lambda = 2 makes every focusing weight of eq. (WLdefn) 1, so W = W_z is the
+    # same at every step; with alpha fixed, no bounds active and the full projected space
+    # (t = t_p = m) each step adds the exact Tikhonov update of the current residual, and y = W m
+    # follows iterated Tikhonov from y^(0) = 0.  A slip in how the steps chain (the residual of
+    # the previous model, the W^{-1} of the update, the accumulation) breaks this at step 2.
+    g = geometry.uniform_geometry(8, 8, 2, 25.0, 25.0, 25.0)
+    G = op.dense_G(g)
+    rng = np.random.default_rng(4)
+    d_obs = G @ rng.random(g.n) + 0.01 * rng.standard_normal(g.m)
+    wd = 1.0 / (0.05 + rng.random(g.m))
+    w = irls.depth_weights(g, 0.8)
+    A = wd[:, None] * G / w[None, :]
+    alpha = 0.3 * np.linalg.svd(A, compute_uv=False)[5]
+    K = 6
+    ref = iterated_tikhonov(A, wd * d_obs, alpha, K)
+    p = irls.IrlsParams(solver=solver, t=g.m, tp=g.m, lam=2.0, beta_depth=0.8, m_min=-1e300, m_max=1e300,
+                        alpha_fixed=alpha)
+    m_prev, m_prev2 = np.zeros(g.n), None
+    steps = []
+    for k in range(1, K + 1):
+        omega = np.random.default_rng(50 + k).standard_normal((g.m, g.m))
+        m_new, a, chi2, _ = irls.irls_step(g, p, k, d_obs, wd, m_prev, m_prev2, omega, G_dense=G)
+        assert a == alpha
+        y = w * m_new
+        assert np.linalg.norm(y - ref[k - 1]) <= 1e-10 * np.linalg.norm(ref[k - 1])   # measured 4e-15
+        r = wd * d_obs - A @ ref[k - 1]
+        assert abs(chi2 - (r @ r) / (g.m + math.sqrt(2.0 * g.m))) <= 1e-10 * chi2
+        steps.append(y)
+        m_prev2, m_prev = m_prev, m_new
+    # the steps move: the closed form separates them by far more than the tolerance
+    assert np.linalg.norm(steps[-1] - steps[0]) >= 1e-2 * np.linalg.norm(steps[-1])
