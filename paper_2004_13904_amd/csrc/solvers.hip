@@ -701,8 +701,6 @@ unsigned grid_for(int64_t n, int threads = kThreads, int64_t cap = 4096) {
   return (unsigned)g;
 }
 
-// Rows per lane load of the basis products: two (16-byte loads) when every column start of the
-// basis is 16-byte aligned.
 // Rows per lane load of a basis: 16 bytes (2 doubles or 4 floats) when every column start is
 // 16-byte aligned, else 1.
 template <typename TB> int rows_per_load(const TB *Q, int64_t ld) {
