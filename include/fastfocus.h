@@ -78,7 +78,9 @@ typedef struct ff_spectra_s *ff_spectra;
    t_r(u, v) of every layer from the prism formulas in FP64, places it in the circulant
    array of the embedding and stores its 2-D DFT (scaled by 1/(nfft_x*nfft_y)) on the
    current device, as complex64 (dtype FF_F32) or complex128 (FF_F64).  Also allocates the
-   handle's pass workspace.  Blocks until the spectra are built.  *out receives the handle;
+   handle's pass workspace: the intermediates of one batched launch, about twice its row-pass
+   intermediates (the batch is the largest multiple of 4 in 16..128 vectors whose row-pass
+   intermediates fit in 512 MiB, else 16).  Blocks until the spectra are built.  *out receives the handle;
    free it with ff_free_spectra. */
 ff_status build_spectra(const ff_geometry *geom, int32_t dtype, ff_stream stream, ff_spectra *out);
 ff_status ff_free_spectra(ff_spectra h);
@@ -133,9 +135,9 @@ ff_status apply_GT(ff_spectra h, const void *d, void *x, const void *w_pre, cons
    Y = w_post .* G (w_pre .* X) for transpose = 0, Y = w_post .* G^T (w_pre .* X) for
    transpose = 1, for k column vectors.  X is column-major with leading dimension ldx
    (>= n, or >= m when transposed), Y likewise with ldy.  The weights apply to every column.
-   Vectors are processed in launches of up to the handle's batch (16 to 64 vectors, chosen at
-   build_spectra from the intermediates' size); in single precision the column passes take 4
-   vectors per block, which agree with the one-vector launches to rounding. */
+   Vectors are processed in launches of up to the handle's batch (16 to 128 vectors, chosen at
+   build_spectra from the intermediates' size); in single precision G's column pass takes 8
+   vectors per block and G^T's 4, which agree with the one-vector launches to rounding. */
 ff_status apply_G_block(ff_spectra h, int32_t transpose, int64_t k, const void *X, int64_t ldx,
                         void *Y, int64_t ldy, const void *w_pre, const void *w_post,
                         ff_stream stream);
