@@ -96,6 +96,9 @@ def main(argv=None):
     ap.add_argument("--irls-c2-lambda", type=float, default=0.0,
                     help="stabilizer of the n = 1e6 leg: 0 = minimum support, 1 = the paper's L1 choice")
     ap.add_argument("--irls-c2-stop", action="store_true", help="stop the n = 1e6 leg at the chi^2 test")
+    ap.add_argument("--irls-c2-onesided", type=int, default=0, choices=(0, 1, 2),
+                    help="gkb_onesided of the n = 1e6 leg's handle (0 both bases, 1 the data side, 2 as 1 with "
+                         "the model-side basis rebuilt)")
     ap.add_argument("--irls-steps", type=int, default=25)
     ap.add_argument("--study-ells", default="4", help="ladder sizes l of the study leg")
     ap.add_argument("--study-s", default="40,25,20,8,6,4,3", help="t = floor(m/s) of the study leg")
@@ -324,14 +327,21 @@ def main(argv=None):
         result["irls"] = irls_leg(a.irls_steps, lam=0.0)
         result["irls_l1"] = irls_leg(a.irls_steps, lam=1.0, stop=True)
         result["irls_l1_f32basis"] = irls_leg(a.irls_steps, lam=1.0, stop=True, basis="f32")
+        result["irls_l1_onesided"] = irls_leg(a.irls_steps, lam=1.0, stop=True, onesided=1)
+        result["irls_l1_lean"] = irls_leg(a.irls_steps, lam=1.0, stop=True, onesided=2)
     if "irls_c2" in legs:
-        result["irls_magnetic_1m"] = irls_c2_leg(a.irls_c2_steps, a.irls_c2_basis, a.irls_c2_lambda, a.irls_c2_stop)
-        if a.irls_c2_basis == "f64" and a.irls_c2_steps <= 2:
+        result["irls_magnetic_1m"] = irls_c2_leg(a.irls_c2_steps, a.irls_c2_basis, a.irls_c2_lambda, a.irls_c2_stop,
+                                                 onesided=a.irls_c2_onesided)
+        if a.irls_c2_basis == "f64" and a.irls_c2_steps <= 2 and a.irls_c2_onesided == 0:
             result["irls_magnetic_1m_f32basis"] = irls_c2_leg(a.irls_c2_steps, "f32", a.irls_c2_lambda,
                                                              a.irls_c2_stop)
             for b in ("f32", "f64"):
                 result[f"irls_magnetic_1m_rsvd_{b}basis"] = irls_c2_leg(a.irls_c2_steps, b, a.irls_c2_lambda,
                                                                        a.irls_c2_stop, solver="rsvd")
+            result["irls_magnetic_1m_onesided"] = irls_c2_leg(a.irls_c2_steps, "f64", a.irls_c2_lambda,
+                                                              a.irls_c2_stop, onesided=1)
+            result["irls_magnetic_1m_lean"] = irls_c2_leg(a.irls_c2_steps, "f64", a.irls_c2_lambda,
+                                                          a.irls_c2_stop, onesided=2)
     if "study" in legs:
         result["study"] = study_leg([int(v) for v in a.study_ells.split(",")],
                                     [int(v) for v in a.study_s.split(",")], a.study_kinds.split(","),
@@ -823,11 +833,13 @@ def multi_survey_leg():
     return out
 
 
-def irls_leg(steps, lam=0.0, stop=False, basis="f64"):
+def irls_leg(steps, lam=0.0, stop=False, basis="f64", onesided=0):
     """IRLS time on the gravity 100 x 60 x 10 survey (m = 6000, n = 60000): two 1 g/cc blocks,
     1 % noise (tau1 = 0.01, tau2 = 0.001), stabilizer lambda (0 = minimum support, timed over a
     fixed number of steps; 1 = the paper's L1 choice, run to the chi^2 test), depth weighting
-    beta = 0.8, bounds [0, 1], GKB with t = m/8 = 750, t_p = 787, FP32 operator."""
+    beta = 0.8, bounds [0, 1], GKB with t = m/8 = 750, t_p = 787, FP32 operator.  onesided: the
+    handle's gkb_onesided (0 both bases reorthogonalized, 1 the data-side basis only, 2 as 1 with
+    the model-side basis rebuilt instead of stored)."""
     import torch
 
     from paper_2004_13904_amd import solvers as SV
@@ -835,6 +847,7 @@ def irls_leg(steps, lam=0.0, stop=False, basis="f64"):
     from paper_2004_13904_amd.operator import Operator
     s = W.SURVEYS["gravity_l4"]
     A = Operator(s, torch.float32)
+    A.set_tuning(gkb_onesided=onesided)
     m_true = torch.tensor(W.block_model(s, W.GRAVITY_L4_BLOCKS), dtype=torch.float32, device="cuda")
     d_exact = A.G(m_true).double().cpu().numpy()
     eta, sd = W.noise(d_exact, 0.01, 0.001, 2)
@@ -863,13 +876,13 @@ def irls_leg(steps, lam=0.0, stop=False, basis="f64"):
             "the GPU and in the oracle alike: a fixed number of steps is timed and the chi^2 test is not met; "
             "the converged IRLS time is the lambda = 1 run") if lam == 0.0 else "run to the chi^2 test"
     return {"workload": "gravity_l4: 100x60 stations, nz=10, GKB t=750 t_p=787, FP32 operator, FP64 solve",
-            "lambda": lam, "basis": basis, "note": note,
+            "lambda": lam, "basis": basis, "gkb_onesided": onesided, "note": note,
             "steps": len(hist), "converged": hist[-1][2] <= 1.0, "seconds_total": round(total, 3),
             "seconds_per_step": round(total / len(hist), 4), "final_chi2_scaled": round(hist[-1][2], 4),
             "alpha_1": hist[0][1], "alpha_K": hist[-1][1], "RE": round(re, 4)}
 
 
-def irls_c2_leg(steps, basis="f64", lam=0.0, stop=False, solver="gkb"):
+def irls_c2_leg(steps, basis="f64", lam=0.0, stop=False, solver="gkb", onesided=0):
     """IRLS on the n = 1e6 magnetic survey (250 x 200 x 20, TFA with I = D = 45 deg): a 0.1 SI cube
     and a 45-degree dipping dike, 2 % noise (tau1 = 0.02, tau2 = 0.002), minimum support
     (lambda = 0, eps^2 = 1e-9), depth weighting beta = 1.4, bounds [0, 0.1], t = m/20 = 2500,
@@ -877,7 +890,9 @@ def irls_c2_leg(steps, basis="f64", lam=0.0, stop=False, solver="gkb"):
     the reorthogonalization (at least t_p^2 (n + m) doubles read per step).  RSVD (one power
     iteration, Omega drawn on the device): Q and G~^T B in FP64 are 63 GB, in FP32 storage 21 GB;
     the time is the 4 t_p operator products and the Gram products of the QR factorizations.
-    Each step is timed."""
+    onesided: the handle's gkb_onesided (1: only the m x t_p data-side basis is reorthogonalized;
+    2: besides, the model-side basis is rebuilt in a second pass instead of stored).  Each step is
+    timed."""
     import torch
 
     from paper_2004_13904_amd import solvers as SV
@@ -885,6 +900,7 @@ def irls_c2_leg(steps, basis="f64", lam=0.0, stop=False, solver="gkb"):
     from paper_2004_13904_amd.operator import Operator
     s = W.SURVEYS["magnetic_1m"]
     A = Operator(s, torch.float32)
+    A.set_tuning(gkb_onesided=onesided)
     m_true = torch.tensor(W.block_model(s, W.MAGNETIC_1M_BLOCKS), dtype=torch.float32, device="cuda")
     d_exact = A.G(m_true).double().cpu().numpy()
     eta, sd = W.noise(d_exact, 0.02, 0.002, 2)
@@ -900,7 +916,8 @@ def irls_c2_leg(steps, basis="f64", lam=0.0, stop=False, solver="gkb"):
         now = time.perf_counter()
         times.append(now - t_last[0])
         t_last[0] = now
-        log(f"irls (magnetic_1m, {solver}, {basis}) step {k}: alpha {alpha:.4g} chi2 {chi2:.4f} ({times[-1]:.2f} s)")
+        log(f"irls (magnetic_1m, {solver}, {basis}, onesided {onesided}) step {k}: alpha {alpha:.4g} chi2 {chi2:.4f} "
+            f"({times[-1]:.2f} s)")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     t_last[0] = t0
@@ -914,14 +931,16 @@ def irls_c2_leg(steps, basis="f64", lam=0.0, stop=False, solver="gkb"):
     out = {"workload": f"magnetic_1m: 250x200 stations, nz=20, cube + dipping dike, 2% noise, {solver.upper()} "
                        "t=2500 t_p=2625, FP32 operator, FP64 solve",
            "solver": solver, "lambda": lam, "basis": basis, "workspace_GB": round(ws / 1e9, 2),
+           "gkb_onesided": onesided if solver == "gkb" else None,
            "steps": len(hist), "converged": hist[-1][2] <= 1.0, "RE": round(re, 4),
            "seconds_per_step": [round(x, 3) for x in times],
            "seconds_per_step_after_first": round(float(np.mean(times[1:])), 3) if len(times) > 1 else None,
            "seconds_total": round(total, 3), "chi2_scaled": [round(h[2], 4) for h in hist]}
     if solver == "gkb":
-        # one Gram-Schmidt pass (Q^T v, then v - Q c) over both bases per iteration; the second
-        # pass runs only when the first cancels most of the vector
-        reorth_bytes = 2 * (8 if basis == "f64" else 4) * (n + mm) * tp * (tp + 1) / 2
+        # one Gram-Schmidt pass (Q^T v, then v - Q c) over both bases per iteration (over the
+        # data-side basis only when one-sided); the second pass runs only when the first cancels
+        # most of the vector
+        reorth_bytes = 2 * (8 if basis == "f64" else 4) * ((mm if onesided else n + mm)) * tp * (tp + 1) / 2
         out["reorth_bytes_per_step"] = reorth_bytes
         out["reorth_GBs_if_all_time"] = round(reorth_bytes / (total / len(hist)) / 1e9, 1)
     A.close()

@@ -301,7 +301,18 @@ ff_status irls_step(ff_spectra h, const ff_irls_params *p, const double *d_obs, 
                    graph on the handle's own stream at the first solve and replayed by later solves
                    with the same workspace, t_p and basis type (not while the caller's stream is
                    being captured or pass profiling is on); 0 (default) = launched one by one.  The
-                   results are the same bit for bit. */
+                   results are the same bit for bit.
+     gkb_onesided  reorthogonalization in gkb_project and irls_step with GKB (Algorithm 1 takes
+                   both bases): 0 (default) = both bases, the model-side A (n x t_p) and the
+                   data-side H (m x (t_p + 1)); 1 = the data-side basis H only: the model-side
+                   vectors stay orthogonal through the recurrence when one side of the
+                   Golub-Kahan process is kept orthogonal (Simon and Zha, SIAM J. Sci. Comput. 21,
+                   2000), which removes the n-length streams over A; 2 = as 1, and A is not stored:
+                   the solution y = A w is formed in a second pass that rebuilds every a_i from H
+                   and the stored coefficients with the same launches (bit for bit the first pass's
+                   vectors), at t_p more G^T applications; the workspace then holds two columns of
+                   A instead of t_p (ff_workspace_size reads this setting).  Modes 1 and 2 give the
+                   same B, sigma and alpha bit for bit; their y agree to rounding. */
 typedef struct {
     int32_t lg_G, lg_GT;
     int32_t row_tile;
@@ -311,6 +322,7 @@ typedef struct {
     int32_t pair_fused;
     int32_t gkb_graph;
     int32_t fft_plan_x, fft_plan_y;
+    int32_t gkb_onesided;
 } ff_tuning;
 ff_status ff_get_tuning(ff_spectra h, ff_tuning *t);
 ff_status ff_set_tuning(ff_spectra h, const ff_tuning *t);

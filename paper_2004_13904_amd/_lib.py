@@ -46,7 +46,8 @@ class FFIrlsParams(C.Structure):
 class FFTuning(C.Structure):
     _fields_ = [("lg_G", C.c_int32), ("lg_GT", C.c_int32), ("row_tile", C.c_int32), ("batch", C.c_int32),
                 ("col_batched", C.c_int32), ("rsvd_qr", C.c_int32), ("pair_fused", C.c_int32),
-                ("gkb_graph", C.c_int32), ("fft_plan_x", C.c_int32), ("fft_plan_y", C.c_int32)]
+                ("gkb_graph", C.c_int32), ("fft_plan_x", C.c_int32), ("fft_plan_y", C.c_int32),
+                ("gkb_onesided", C.c_int32)]
 
 
 class FastFocusError(RuntimeError):

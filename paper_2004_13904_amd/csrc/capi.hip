@@ -370,6 +370,7 @@ ff_status ff_get_tuning(ff_spectra h, ff_tuning *t) {
   t->rsvd_qr = h->rsvd_qr;
   t->pair_fused = h->pair_fused;
   t->gkb_graph = h->gkb_graph;
+  t->gkb_onesided = h->gkb_onesided;
   t->fft_plan_x = h->fft_plan_x;
   t->fft_plan_y = h->fft_plan_y;
   return FF_OK;
@@ -386,6 +387,8 @@ ff_status ff_set_tuning(ff_spectra h, const ff_tuning *t) {
   if (t->rsvd_qr < 0 || t->rsvd_qr > 2) return fail(FF_EINVAL, "ff_set_tuning: rsvd_qr must be 0, 1 or 2");
   if (t->pair_fused < 0 || t->pair_fused > 2) return fail(FF_EINVAL, "ff_set_tuning: pair_fused must be 0, 1 or 2");
   if (t->gkb_graph != 0 && t->gkb_graph != 1) return fail(FF_EINVAL, "ff_set_tuning: gkb_graph must be 0 or 1");
+  if (t->gkb_onesided < 0 || t->gkb_onesided > 2)
+    return fail(FF_EINVAL, "ff_set_tuning: gkb_onesided must be 0, 1 or 2");
   if (t->fft_plan_x < 0 || t->fft_plan_x >= kFftPlans || t->fft_plan_y < 0 || t->fft_plan_y >= kFftPlans)
     return fail(FF_EINVAL, "ff_set_tuning: FFT stage plans must be 0, 1 or 2");
   h->lg_G = t->lg_G;
@@ -396,6 +399,7 @@ ff_status ff_set_tuning(ff_spectra h, const ff_tuning *t) {
   h->rsvd_qr = t->rsvd_qr;
   h->pair_fused = t->pair_fused;
   h->gkb_graph = t->gkb_graph;
+  h->gkb_onesided = t->gkb_onesided;
   h->fft_plan_x = t->fft_plan_x;
   h->fft_plan_y = t->fft_plan_y;
   ++h->tune_version;

@@ -134,6 +134,7 @@ struct ff_spectra_s {
   int rsvd_qr = 0;                    // RSVD orthonormalization: 0 CholQR2 first, 1 Householder, 2 CholQR3 first
   int pair_fused = 1;                 // grouped plans: G x and G^T d of this survey share one column pass
   int gkb_graph = 0;                  // replay the GKB iteration loop from a captured graph
+  int gkb_onesided = 0;               // GKB: 0 both bases reorthogonalized, 1 the data side only, 2 as 1 with A recomputed
   int fft_plan_x = 0, fft_plan_y = 0; // stage plans of the row and column transforms (fft.h)
   uint64_t tune_version = 0;          // bumped by every ff_set_tuning (captured launches depend on it)
   // the captured GKB iteration loop and what it was captured for

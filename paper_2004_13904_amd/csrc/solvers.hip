@@ -180,6 +180,21 @@ __global__ void k_scale_from(const double *__restrict__ x, const double *__restr
   }
 }
 
+// dbl = (double) col
+template <typename TB>
+__global__ void k_widen(const TB *__restrict__ col, double *__restrict__ dbl, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dbl[i] = (double)col[i];
+}
+
+// y = (*sc) * x
+template <typename TB>
+__global__ void k_scaled(const TB *__restrict__ x, const double *__restrict__ sc, double *__restrict__ y, int64_t n) {
+  const double a = *sc;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * (double)x[i];
+}
+
 // After the first Gram-Schmidt pass: n0 = ||v0|| (before the pass) and n1 = ||v1|| (after it)
 // from their partial sums of squares, the second-pass test flag = n1 < n0 / sqrt 2
 // (Daniel-Gragg-Kaufman-Stewart), and the norm and its inverse as they stand if the second
@@ -859,6 +874,10 @@ ff_status norm2(const double *x, int64_t n, double *nrm, double *inv, double *pa
 // starts on a 256-byte boundary and the products use 16-byte loads for any n and m.
 inline int64_t basis_ld(int64_t rows) { return (rows + 63) / 64 * 64; }
 
+// Columns of the model-side basis A kept by gkb_run: all t_p, or a ring of two when the handle's
+// gkb_onesided tuning is 2 (A is then recomputed in a second pass instead of stored).
+inline int gkb_acols(ff_spectra h, int tp) { return h->gkb_onesided == 2 ? (tp < 2 ? tp : 2) : tp; }
+
 template <typename TB> struct GkbWs {
   TB *A, *H;
   int64_t ldA, ldH;
@@ -866,13 +885,13 @@ template <typename TB> struct GkbWs {
   double *wdc, *winvc;   // copies of the weights, so that a captured iteration loop reads fixed addresses
   int *flag;
   rocblas_int *info;
-  void carve(Arena &a, int64_t n, int64_t m, int tp) {
+  void carve(Arena &a, int64_t n, int64_t m, int tp, int acols) {
     const int64_t P = ((n > m ? n : m) + kRowsMin - 1) / kRowsMin + 1;   // partial rows at one row per load
     const int64_t Pn = ((n > m ? n : m) + 63) / 64 + 1;                  // blocks of the A c products
     const int64_t npart = ((P > 256 ? P : 256) + 1) * (tp + 2);
     ldA = basis_ld(n);
     ldH = basis_ld(m);
-    A = a.take<TB>((size_t)ldA * tp);
+    A = a.take<TB>((size_t)ldA * acols);
     H = a.take<TB>((size_t)ldH * (tp + 1));
     b = a.take<double>(n);
     c = a.take<double>(m);
@@ -1085,8 +1104,15 @@ ff_status gkb_run(ff_spectra h, const double *rt, const double *wd, const double
   const int64_t n = h->n, m = h->m;
   Arena ar{(char *)ws, ws_bytes, 0, false};
   GkbWs<TB> W;
-  W.carve(ar, n, m, tp);
+  // gkb_onesided: 0 = both bases reorthogonalized (Algorithm 1); 1 = only the data-side basis H,
+  // the model-side basis A kept orthogonal by the recurrence itself (one-sided reorthogonalization
+  // of the Golub-Kahan process, Simon and Zha 2000); 2 = as 1, with A recomputed in a second pass
+  // instead of stored
+  const int onesided = h->gkb_onesided;
+  const bool ring = onesided == 2 && tp >= 2;
+  W.carve(ar, n, m, tp, gkb_acols(h, tp));
   if (ar.used > ws_bytes) return fail(FF_ENOMEM, "gkb_project: workspace too small");
+  auto acol = [&](int i) { return W.A + (int64_t)(ring ? (i & 1) : i) * W.ldA; };
   const double fixed = *alpha;
   ff_status st;
   // beta_1 = ||r~||, h_1 = r~ / beta_1 (stored in H; c holds the same values in double, the
@@ -1103,16 +1129,15 @@ ff_status gkb_run(ff_spectra h, const double *rt, const double *wd, const double
   auto iterate = [&](hipStream_t s) -> ff_status {
   ff_status st;
   for (int i = 0; i < tp; ++i) {
-    TB *ai = W.A + (int64_t)i * W.ldA;
+    TB *ai = acol(i);
     const TB *hi = W.H + (int64_t)i * W.ldH;
-    // b = G~^T h_i - beta_i a_{i-1}, reorthogonalized; gamma_i = ||b||
+    // b = G~^T h_i - beta_i a_{i-1}, reorthogonalized (both-sided); gamma_i = ||b||
     if ((st = op_apply(h, 1, 1, W.c, m, W.b, n, W.wdc, W.winvc, FF_F64, s))) return st;
     if (i > 0)
-      k_axpy_sumsq<TB><<<kNormBlocks, kThreads, 0, s>>>(W.b, W.A + (int64_t)(i - 1) * W.ldA, W.beta + i, -1.0, n,
-                                                        W.sq0);
+      k_axpy_sumsq<TB><<<kNormBlocks, kThreads, 0, s>>>(W.b, acol(i - 1), W.beta + i, -1.0, n, W.sq0);
     int dn = 0;
-    if ((st = reorth_norm<TB>(W.A, W.ldA, n, i, W.b, W.coef, W.part, W.sq0, i > 0, W.sq1, W.flag, W.gamma + i,
-                              W.ginv + i, s, &dn)))
+    if ((st = reorth_norm<TB>(W.A, W.ldA, n, onesided ? 0 : i, W.b, W.coef, W.part, W.sq0, i > 0, W.sq1, W.flag,
+                              W.gamma + i, W.ginv + i, s, &dn)))
       return st;
     if (dn > 0)     // b = a_i as stored
       k_scale_store_cond<TB><<<grid_for(n), kThreads, 0, s>>>(W.b, ai, n, W.sq1, dn, W.flag, W.gamma + i, W.ginv + i);
@@ -1152,7 +1177,24 @@ ff_status gkb_run(ff_spectra h, const double *rt, const double *wd, const double
   qa.t = tp;
   k_filter<<<(tp + 255) / 256, 256, 0, s>>>(W.S, W.alpha, qa, tp, W.g);
   if ((st = gemv_n(W.V, tp, tp, tp, W.g, W.w, 1.0, s))) return st;
-  launch_gemv_n<TB>(W.A, W.ldA, n, tp, W.w, y, 1.0, 0.0, s);
+  if (onesided == 2) {
+    // y = sum_i w_i a_i with a_i rebuilt by the same launches, on the same values, as in the
+    // first pass (h_i from H exactly as the operator saw it, gamma_i and beta_i as computed
+    // there), so every a_i is the first pass's bit for bit
+    for (int i = 0; i < tp; ++i) {
+      k_widen<TB><<<grid_for(m), kThreads, 0, s>>>(W.H + (int64_t)i * W.ldH, W.c, m);
+      if ((st = op_apply(h, 1, 1, W.c, m, W.b, n, W.wdc, W.winvc, FF_F64, s))) return st;
+      if (i > 0)
+        k_axpy_sumsq<TB><<<kNormBlocks, kThreads, 0, s>>>(W.b, acol(i - 1), W.beta + i, -1.0, n, W.sq0);
+      k_scale_store<TB><<<grid_for(n), kThreads, 0, s>>>(W.b, W.ginv + i, acol(i), n);
+      if (i == 0)
+        k_scaled<TB><<<grid_for(n), kThreads, 0, s>>>(acol(0), W.w, y, n);
+      else
+        k_axpy_sumsq<TB><<<kNormBlocks, kThreads, 0, s>>>(y, acol(i), W.w + i, 1.0, n, W.sq0);
+    }
+  } else {
+    launch_gemv_n<TB>(W.A, W.ldA, n, tp, W.w, y, 1.0, 0.0, s);
+  }
   FF_LAUNCH_CHECK("gkb solution");
   FF_HIP(hipMemcpyAsync(sigma, W.S, sizeof(double) * tp, hipMemcpyDeviceToDevice, s));
   FF_HIP(hipMemcpyAsync(alpha, W.alpha, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1534,10 +1576,10 @@ size_t solver_bytes(ff_spectra h, int which, int solver, int basis, int tp) {
     W.carve(ar, h->n, h->m, tp);
   } else if (basis == FF_F32) {
     GkbWs<float> W;
-    W.carve(ar, h->n, h->m, tp);
+    W.carve(ar, h->n, h->m, tp, gkb_acols(h, tp));
   } else {
     GkbWs<double> W;
-    W.carve(ar, h->n, h->m, tp);
+    W.carve(ar, h->n, h->m, tp, gkb_acols(h, tp));
   }
   size_t b = ar.used + 256;
   if (which == FF_WS_IRLS) b += irls_own_bytes(h, tp);

@@ -76,7 +76,7 @@ class Operator:
         return op
 
     TUNING_KEYS = ("lg_G", "lg_GT", "row_tile", "batch", "col_batched", "rsvd_qr", "pair_fused", "gkb_graph",
-                   "fft_plan_x", "fft_plan_y")
+                   "fft_plan_x", "fft_plan_y", "gkb_onesided")
 
     @property
     def batch_max(self):

@@ -146,3 +146,27 @@ def test_every_entry_point_rejects_null_arguments():
         assert fn(*args) == -1, name
         assert lib.ff_last_error().decode().startswith(name + ":"), name
     assert lib.ff_multi_free(None) == 0
+
+
+def _header_struct_fields(name):
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\}\s*" + name + r";", text).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        names = decl.split(None, 1)[1] if not decl.startswith("const") else decl.split("*", 1)[1]
+        fields += [v.strip().lstrip("*") for v in names.split(",")]
+    return fields
+
+
+@pytest.mark.parametrize("c_name,py_name", [("ff_tuning", "FFTuning"), ("ff_irls_params", "FFIrlsParams"),
+                                            ("ff_geometry", "FFGeometry")])
+def test_binding_structs_match_the_header(c_name, py_name):
+    # the ctypes mirrors of the ABI structs list the header's fields in the header's order
+    from paper_2004_13904_amd import _lib as L
+    py = [f[0] for f in getattr(L, py_name)._fields_]
+    hdr = _header_struct_fields(c_name)
+    # Python cannot name a field "lambda"
+    assert [("lam" if f == "lambda" else f) for f in hdr] == py

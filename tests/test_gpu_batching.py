@@ -183,7 +183,7 @@ def test_tuning_variants_keep_results():
         assert rel(to_host(A.G_block(D, transpose=True)), to_host(ref_t)) <= 2e-6
     from paper_2004_13904_amd import _lib as L
     for bad in ({"row_tile": 5}, {"batch": 0}, {"batch": A.batch_max + 1}, {"col_batched": 3}, {"rsvd_qr": 3},
-                {"lg_G": 0}, {"lg_GT": A.nz + 1}):
+                {"lg_G": 0}, {"lg_GT": A.nz + 1}, {"gkb_onesided": 3}, {"gkb_onesided": -1}):
         with pytest.raises(L.FastFocusError):
             A.set_tuning(**bad)
     A.set_tuning(**base)

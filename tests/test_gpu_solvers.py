@@ -190,6 +190,39 @@ def test_gkb_single_precision_basis(kernel):
     assert S.workspace_bytes(A, "gkb", tp, basis="f32") < 0.75 * S.workspace_bytes(A, "gkb", tp)
 
 
+@pytest.mark.parametrize("onesided", [1, 2])
+@pytest.mark.parametrize("basis", ["f64", "f32"])
+@pytest.mark.parametrize("kernel", ["gravity", "magnetic"])
+def test_gkb_onesided_matches_oracle(onesided, basis, kernel):
+    # gkb_onesided = 1: only the data-side basis H is reorthogonalized; = 2: besides, the model-side
+    # basis is not stored but rebuilt in a second pass to form y.  Against the oracle's Algorithm 1
+    # (both bases reorthogonalized by MGS): the same projected problem to rounding, at the bars of
+    # the both-sided GPU solve; modes 1 and 2 share the first pass, so sigma and alpha agree bit for
+    # bit and y to rounding; mode 2's workspace drops t_p - 2 columns of A.
+    s, g, G, wd, winv, Gt, r = problem("mid", kernel=kernel, seed=1)
+    t, tp = 60, 63
+    announce("gkb onesided", onesided, basis, kernel)
+    y0, a0, s0, F = osol.gkb(*dense_ops(Gt), r, g.n, t, tp, "upre", 2.0, return_factors=True)
+    A = Operator(s, F64)
+    args = (to_dev(r, F64), to_dev(wd, F64), to_dev(winv, F64), t, tp)
+    ws0 = S.workspace_bytes(A, "gkb", tp, basis=basis)
+    A.set_tuning(gkb_onesided=1)
+    y1, a1, s1 = S.gkb_project(A, *args, "upre", basis=basis)
+    A.set_tuning(gkb_onesided=onesided)
+    y, a, sig = S.gkb_project(A, *args, "upre", basis=basis)
+    ya = S.gkb_project(A, *args, "fixed", a0, basis=basis)[0]
+    tol_s, tol_y = (1e-9, 1e-8) if basis == "f64" else (1e-6, 2e-5)
+    assert rel(to_host(sig), s0) <= tol_s
+    check_alpha("upre", a, a0, s0[:t], np.linalg.norm(r) * F["U"][0, :t], F64 if basis == "f64" else F32)
+    assert rel(to_host(ya), y0) <= tol_y
+    assert torch.equal(sig, s1) and a == a1
+    assert rel(to_host(y), to_host(y1)) <= 1e-13
+    if onesided == 2:
+        lda = (g.n + 63) // 64 * 64
+        per = 8 if basis == "f64" else 4
+        assert S.workspace_bytes(A, "gkb", tp, basis=basis) <= ws0 - (tp - 2) * lda * per
+
+
 @pytest.mark.parametrize("q", [0, 2])
 def test_rsvd_power_iterations_and_device_omega(q):
     # Omega drawn on the device from a seed (Philox4x32-10) and q power iterations, against the
@@ -240,8 +273,12 @@ def test_irls_rsvd_with_device_omega_matches_oracle():
     assert abs(c1 - c1o) <= 1e-8 * c1o
 
 
-@pytest.mark.parametrize("solver", ["gkb", "rsvd"])
+@pytest.mark.parametrize("solver", ["gkb", "rsvd", "gkb_onesided"])
 def test_irls_step_matches_oracle(solver):
+    # gkb_onesided: GKB reorthogonalizing the data-side basis only, the model-side basis rebuilt
+    # in a second pass (gkb_onesided = 2), against the oracle's Algorithm 1
+    onesided = solver == "gkb_onesided"
+    solver = "gkb" if onesided else solver
     s = W.survey(16, 12, 5, 25, 25, 25)
     g = ogeom(s)
     G = op.dense_G(g)
@@ -255,6 +292,8 @@ def test_irls_step_matches_oracle(solver):
     t, tp = 40, 42
     omega = rng.standard_normal((tp, g.m))
     A = Operator(s, F64)
+    if onesided:
+        A.set_tuning(gkb_onesided=2)
     po = oirls.IrlsParams(solver=solver, t=t, tp=tp, lam=0.0, beta_depth=0.8, m_min=0.0, m_max=1.0)
     pg = S.IrlsParams(solver=solver, t=t, tp=tp, lam=0.0, beta_depth=0.8, m_min=0.0, m_max=1.0)
     m1o, a1o, c1o, _ = oirls.irls_step(g, po, 1, d_obs, wd, np.zeros(g.n), None, omega, G_dense=G)
@@ -431,17 +470,23 @@ def c2_problem():
                 sigma1=float(math.sqrt(lam[0])))
 
 
-@pytest.mark.parametrize("basis", ["f64", "f32"])
+@pytest.mark.parametrize("basis", ["f64", "f32", "lean"])
 def test_gkb_c2_full_size_properties(c2_problem, basis):
     # GKB at the metric's IRLS size (n = 1e6, t = 2500, t_p = 2625, FP32 operator; the n x t_p basis
     # in FP64, 21 GB, or FP32): eq. (eq:alpha1) on the returned spectrum, sigma_1 against the
     # oracle's Lanczos value, and the Galerkin conditions of the projected Tikhonov solution at a
     # fixed alpha, with the oracle's direct sums (size-dependent indexing of the 2.6e9-element
     # bases runs here)
+    # "lean": FP64 bases with only the data-side basis reorthogonalized and the model-side basis
+    # rebuilt in a second pass instead of stored (gkb_onesided = 2: a 1 GB workspace, not 22 GB)
     P = c2_problem
     g = P["g"]
     announce("gkb c2", basis, 2500, 2625)
     A = Operator(P["s"], F32)
+    if basis == "lean":
+        A.set_tuning(gkb_onesided=2)
+        basis = "f64"
+        assert S.workspace_bytes(A, "gkb", 2625) < 2e9
     t, tp = 2500, 2625
     args = (to_dev(P["r"], F64), to_dev(P["wd"], F64), to_dev(P["winv"], F64), t, tp)
     _, a1, sig = S.gkb_project(A, *args, alpha_mode="alpha1", basis=basis)
