@@ -312,7 +312,10 @@ ff_status irls_step(ff_spectra h, const ff_irls_params *p, const double *d_obs, 
                    and the stored coefficients with the same launches (bit for bit the first pass's
                    vectors), at t_p more G^T applications; the workspace then holds two columns of
                    A instead of t_p (ff_workspace_size reads this setting).  Modes 1 and 2 give the
-                   same B, sigma and alpha bit for bit; their y agree to rounding. */
+                   same B, sigma and alpha bit for bit; their y agree to rounding.  Against mode 0:
+                   to rounding with an FP64 operator; with an FP32 operator the model-side basis
+                   stays orthogonal to about the operator's rounding (4e-8 at n = 1e6, t_p = 2625)
+                   and y moves by about 2e-7 at a fixed alpha. */
 typedef struct {
     int32_t lg_G, lg_GT;
     int32_t row_tile;
