@@ -369,6 +369,7 @@ def study_leg(ells, s_list, kinds, solvers, basis="f64", pad=0.0, kmax=25):
     [0, 1] / [0, 0.1], RSVD with one power iteration and a device-drawn Omega, stopped by the scaled
     chi^2 test or after kmax steps.  Data: the ladder structure through the FP64 operator, noise of
     eq. (noisydata) with tau1 = 0.02 and the paper's tau2 for l.  FP32 operator, FP64 solves.
+    Solver "gkb1" is GKB with only the data-side basis reorthogonalized (gkb_onesided = 1).
     Returns one record per run (K, seconds, RE, final scaled chi^2, alpha)."""
     import torch
 
@@ -394,7 +395,8 @@ def study_leg(ells, s_list, kinds, solvers, basis="f64", pad=0.0, kmax=25):
             log(f"study l={ell} {kind}: m {m} n {A.n} NX x NY {A.nfft} SNR {snr:.2f} dB")
 
             def params(solver, t, tp, sdiv):
-                return SV.IrlsParams(solver=solver, t=t, tp=tp, lam=1.0, eps2=1e-9,
+                A.set_tuning(gkb_onesided=1 if solver == "gkb1" else 0)
+                return SV.IrlsParams(solver="gkb" if solver == "gkb1" else solver, t=t, tp=tp, lam=1.0, eps2=1e-9,
                                      beta_depth=0.8 if grav else 1.4, m_min=0.0,
                                      m_max=1.0 if grav else 0.1, basis=basis, power_iters=1,
                                      seed=1000 * ell + sdiv)
