@@ -540,13 +540,16 @@ def test_irls_step_c2(c2_problem):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("basis", ["f64", "f32"])
-def test_gkb_graph_replay_equals_launches(basis):
+@pytest.mark.parametrize("basis,onesided", [("f64", 0), ("f32", 0), ("f64", 1), ("f64", 2)])
+def test_gkb_graph_replay_equals_launches(basis, onesided):
     # The GKB iteration loop captured into a graph at the first solve and replayed by the next
     # ones (gkb_graph = 1) gives the same y, sigma and alpha bit for bit as the same loop launched
-    # kernel by kernel (gkb_graph = 0); the replays see new r~ and weights through the workspace
+    # kernel by kernel (gkb_graph = 0); the replays see new r~ and weights through the workspace.
+    # Also with one-sided reorthogonalization (gkb_onesided = 1, 2; mode 2's second pass runs
+    # launched after the replayed loop)
     s, g, G, wd, winv, Gt, r = problem("medium", "magnetic", seed=3)
     A = Operator(s, F32)
+    A.set_tuning(gkb_onesided=onesided)
     t, tp = 40, 48
     ws = S._workspace(A, "gkb", tp, 0, None, basis)
     rng = np.random.default_rng(8)
