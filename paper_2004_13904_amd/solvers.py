@@ -44,7 +44,9 @@ def _workspace(op, which, tp, solver=0, ws=None, basis="f64"):
 def gkb_project(op, r_tilde, wd, winv, t, tp, alpha_mode="upre", alpha=None, ws=None, stream=None,
                 basis="f64"):
     """Returns (y, alpha, sigma): y standard-form (model update winv * y), sigma (tp,).
-    basis: "f64" (default) or "f32" storage of the GKB bases."""
+    basis: "f64" (default) or "f32" storage of the GKB bases.  The handle's gkb_onesided tuning
+    picks the reorthogonalization: both bases (0, Algorithm 1), the data-side basis only (1), or
+    that with the model-side basis rebuilt instead of stored (2); see ff_tuning."""
     _f64(op, r_tilde, op.m, "gkb_project")
     _f64(op, wd, op.m, "gkb_project")
     _f64(op, winv, op.n, "gkb_project")
