@@ -133,17 +133,17 @@ __global__ void k_scale_store(double *__restrict__ b, const double *__restrict__
   }
 }
 
-// k_norm_cond fused into k_scale_store: when the second Gram-Schmidt pass ran (*flag), every
-// block forms the norm from the pass's P partial sums (the same order as k_norm_cond) and block 0
-// writes *nrm and *inv; otherwise the blocks take *inv as k_norm_flag left it.  Then as
-// k_scale_store with that inverse norm.
+// k_norm_cond fused into k_scale_store: when the second Gram-Schmidt pass ran (*flag), or
+// always when flag is NULL, every block forms the norm from the P partial sums (the order of
+// k_norm_cond and k_norm_finalize) and block 0 writes *nrm and *inv; otherwise the blocks take
+// *inv as k_norm_flag left it.  Then as k_scale_store with that inverse norm.
 template <typename TB>
 __global__ void __launch_bounds__(kThreads)
 k_scale_store_cond(double *__restrict__ b, TB *__restrict__ col, int64_t n, const double *__restrict__ part, int P,
                    const int *__restrict__ flag, double *__restrict__ nrm, double *__restrict__ inv) {
   __shared__ double red[16];
   __shared__ double a_sh;
-  if (*flag) {
+  if (!flag || *flag) {
     double s = 0.0;
     for (int i = threadIdx.x; i < P; i += blockDim.x) s += part[i];
     s = block_sum(s, red);
@@ -1136,10 +1136,15 @@ ff_status gkb_run(ff_spectra h, const double *rt, const double *wd, const double
     if (i > 0)
       k_axpy_sumsq<TB><<<kNormBlocks, kThreads, 0, s>>>(W.b, acol(i - 1), W.beta + i, -1.0, n, W.sq0);
     int dn = 0;
-    if ((st = reorth_norm<TB>(W.A, W.ldA, n, onesided ? 0 : i, W.b, W.coef, W.part, W.sq0, i > 0, W.sq1, W.flag,
-                              W.gamma + i, W.ginv + i, s, &dn)))
+    if (onesided) {
+      // no reorthogonalization against A: gamma_i from the partial sums of b, fused into the scaling
+      if (i == 0) k_sumsq_partial<<<kNormBlocks, kThreads, 0, s>>>(W.b, n, W.sq0);
+      k_scale_store_cond<TB><<<grid_for(n), kThreads, 0, s>>>(W.b, ai, n, W.sq0, kNormBlocks, nullptr, W.gamma + i,
+                                                              W.ginv + i);
+    } else if ((st = reorth_norm<TB>(W.A, W.ldA, n, i, W.b, W.coef, W.part, W.sq0, i > 0, W.sq1, W.flag,
+                                     W.gamma + i, W.ginv + i, s, &dn))) {
       return st;
-    if (dn > 0)     // b = a_i as stored
+    } else if (dn > 0)     // b = a_i as stored
       k_scale_store_cond<TB><<<grid_for(n), kThreads, 0, s>>>(W.b, ai, n, W.sq1, dn, W.flag, W.gamma + i, W.ginv + i);
     else
       k_scale_store<TB><<<grid_for(n), kThreads, 0, s>>>(W.b, W.ginv + i, ai, n);
