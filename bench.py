@@ -325,6 +325,7 @@ def main(argv=None):
         result["table3"] = [geometry_leg(f"table3_nz{nz}", W.table3_survey(nz), check=check) for nz in (20, 239)]
     if "irls" in legs:
         result["irls"] = irls_leg(a.irls_steps, lam=0.0)
+        result["irls_onesided"] = irls_leg(a.irls_steps, lam=0.0, onesided=1)
         result["irls_l1"] = irls_leg(a.irls_steps, lam=1.0, stop=True)
         result["irls_l1_f32basis"] = irls_leg(a.irls_steps, lam=1.0, stop=True, basis="f32")
         result["irls_l1_onesided"] = irls_leg(a.irls_steps, lam=1.0, stop=True, onesided=1)
