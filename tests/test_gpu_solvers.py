@@ -82,15 +82,19 @@ def test_gkb_matches_oracle_algorithm(mode, dtype):
     assert rel(to_host(y), y0) <= (1e-8 if dtype == F64 else 1e-4) + 2 * abs(a - a0) / a0
 
 
-@pytest.mark.parametrize("solver", ["gkb", "rsvd"])
-@pytest.mark.parametrize("t,tp", [(1, 1), (1, 2), (2, 2)])
+@pytest.mark.parametrize("solver", ["gkb", "rsvd", "gkb_lean"])
+@pytest.mark.parametrize("t,tp", [(1, 1), (1, 2), (2, 2), (2, 3)])
 @pytest.mark.parametrize("mode", ["fixed", "alpha1"])
 def test_smallest_projected_sizes(solver, t, tp, mode):
-    # the degenerate projected problems: one or two basis vectors (a 2 x 1 or 3 x 2 bidiagonal
-    # for GKB, a 1 x 1 or 2 x 2 Gram matrix for RSVD), FP64 against the oracle's algorithms
+    # the degenerate projected problems: one to three basis vectors (a 2 x 1 to 4 x 3 bidiagonal
+    # for GKB, a 1 x 1 to 3 x 3 Gram matrix for RSVD), FP64 against the oracle's algorithms;
+    # gkb_lean: GKB with the model-side basis rebuilt from its two-column ring (gkb_onesided = 2)
     s, g, G, wd, winv, Gt, r = problem("mid", kernel="gravity", seed=3)
     announce("smallest", solver, t, tp, mode)
     A = Operator(s, F64)
+    if solver == "gkb_lean":
+        A.set_tuning(gkb_onesided=2)
+        solver = "gkb"
     args = (to_dev(r, F64), to_dev(wd, F64), to_dev(winv, F64), t, tp)
     if solver == "gkb":
         y0, a0, s0 = osol.gkb(*dense_ops(Gt), r, g.n, t, tp, mode, 2.0)
