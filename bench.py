@@ -149,15 +149,9 @@ def main(argv=None):
     def step():
         L.call("ff_multi_apply", plan, cur())
 
-    log("warmup", a.warmup)
-    for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
-
-    # ---- timed region: K pairs replayed from a hipGraph (R pairs per graph) -----------
-    # The library launches on torch's current stream, so a torch CUDA graph captures its
-    # kernels; replaying it removes the host launch cost from the loop.
-    # pairs per graph: the largest divisor of the step count up to 20, so that exactly K pairs are timed
+    # The same pairs replayed from a hipGraph (R pairs per graph, captured by torch from the
+    # library's launches on the current stream): not the headline, since the replayed kernels
+    # run about 2 % slower than the launched ones here and the host keeps ahead of the GPU.
     R = max(r for r in range(1, 21) if a.steps % r == 0)
 
     def capture(fn):
@@ -173,20 +167,7 @@ def main(argv=None):
         return g_
     graph = capture(step)
     reps = max(1, a.steps // R)
-    for _ in range(2):
-        graph.replay()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record()
-    for _ in range(reps):
-        graph.replay()
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    steps_done = reps * R
-    ms_step = ev0.elapsed_time(ev1) / steps_done
-    log(f"timed {steps_done} graph-replayed pairs: {ms_step * 1e3:.2f} us/pair (wall {wall:.3f} s)")
+    ms_graph = timed(graph.replay, reps) / R
 
     # spread of the replays (each replay of R pairs between its own events; not the headline)
     per_replay = []
@@ -198,7 +179,6 @@ def main(argv=None):
         torch.cuda.synchronize()
         per_replay.append(r0.elapsed_time(r1) / R * 1e3)
     pct = {f"p{q}": round(float(np.percentile(per_replay, q)), 3) for q in (10, 50, 90)}
-    ms_eager = timed(step, steps_done)
 
     # ---- the dominant kernel: each grouped kernel launched alone, back to back, between
     # HIP events on the stream the plan launches on (ff_multi_time_pass) ------------------
@@ -221,7 +201,6 @@ def main(argv=None):
     b_alg_pair = 2 * b_alg_op
     # one launch of any of the plan's kernels serves both products of the pair: two units
     achieved = 2 * b_alg_op / (kern_us[dom] * 1e-6) / 1e9
-    path_gbs = b_alg_pair / (ms_step * 1e-3) / 1e9
     pm = pass_model_bytes(A)
     pass_model = {k: {"us": round(kern_us[k], 3), "bytes": pm[k],
                       "GBs": round(pm[k] / (kern_us[k] * 1e-6) / 1e9, 1)} for k in kern_names}
@@ -275,6 +254,29 @@ def main(argv=None):
     del flush
     cold_ms = float(np.median(cold))
 
+    # ---- W warm-up pairs, then the timed region: K pairs, one call of the survey's plan each
+    # (three launches).  It runs after the other pair measurements above, so that the device is
+    # in its steady state under this load when the K pairs start.
+    log("warmup", a.warmup)
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(a.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    steps_done = a.steps
+    ms_step = ev0.elapsed_time(ev1) / steps_done
+    log(f"timed {steps_done} pairs: {ms_step * 1e3:.2f} us/pair (wall {wall:.3f} s)")
+
+    path_gbs = b_alg_pair / (ms_step * 1e-3) / 1e9
+
     result = {
         "metric": "G·m+G^T·d pairs/sec at n≈1M (FP32, ≤1e-5 rel err) + % HBM peak; IRLS time",
         "value": round(1e3 / ms_step, 1),
@@ -302,12 +304,12 @@ def main(argv=None):
                           "cold_ms_per_pair": round(cold_ms, 5),
                           "cold_frac": round(b_alg_pair / (cold_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "pass_model": pass_model,
-        "pair_us_spread": dict(pct, replays=len(per_replay), pairs_per_replay=R),
-        "eager_ms_per_step": round(ms_eager, 6),
+        "graph_ms_per_step": round(ms_graph, 6),
+        "graph_pair_us_spread": dict(pct, replays=len(per_replay), pairs_per_replay=R),
         "pair_separate_calls": {"ms_per_pair": round(ms_sep, 6), "pairs_per_s": round(1e3 / ms_sep, 1),
                                 "results_equal_plan": same, "passes": passes,
                                 "how": "apply_G then apply_GT, three launches each, hipGraph replay"},
-        "launch": f"hipGraph replay of {R} pairs per graph (torch CUDA graph capture of the library's launches)",
+        "launch": "one ff_multi_apply call per pair (three kernel launches), issued back to back on the stream",
     }
     result["hbm_copy"] = copy_bandwidth()
     result["path_roofline"]["frac_of_copy"] = round(path_gbs / result["hbm_copy"]["GBs"], 4)
