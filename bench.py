@@ -146,8 +146,14 @@ def main(argv=None):
     L.call("ff_multi_create", 1, arr(A.h.value), arr(x.data_ptr()), arr(gx.data_ptr()), arr(d.data_ptr()),
            arr(gtd.data_ptr()), C.byref(plan))
 
+    multi_apply = lib.ff_multi_apply
+    stream_h = cur()     # the launch stream of the timed pairs
+
     def step():
-        L.call("ff_multi_apply", plan, cur())
+        L.check("ff_multi_apply", multi_apply(plan, stream_h))
+
+    def step_on_current():    # the same call on whatever stream is current (graph capture)
+        L.check("ff_multi_apply", multi_apply(plan, cur()))
 
     # The same pairs replayed from a hipGraph (R pairs per graph, captured by torch from the
     # library's launches on the current stream): not the headline, since the replayed kernels
@@ -165,7 +171,7 @@ def main(argv=None):
             for _ in range(R):
                 fn()
         return g_
-    graph = capture(step)
+    graph = capture(step_on_current)
     reps = max(1, a.steps // R)
     ms_graph = timed(graph.replay, reps) / R
 
