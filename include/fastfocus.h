@@ -179,7 +179,8 @@ ff_status ff_focusing_grad(ff_spectra h, int64_t k, const void *m, const void *r
 /* ---------------------------------------------------------------------------------------
    Projected solvers (Sec. 2.4) and IRLS (Secs. 2.2-2.3).  All vectors below are FP64 device arrays; the
    operator applications inside run in the handle's dtype.  `workspace` is a caller-owned
-   device buffer of at least ff_workspace_size(...) bytes (it holds the n x t_p basis). */
+   device buffer of at least ff_workspace_size(...) bytes (it holds the n x t_p basis, or for GKB
+   with the handle's gkb_onesided = 2 only the m x t_p one). */
 
 #define FF_WS_GKB  0
 #define FF_WS_RSVD 1
@@ -190,7 +191,8 @@ ff_status ff_workspace_size(ff_spectra h, int32_t which, int32_t solver, int32_t
                             size_t *bytes);
 
 /* Algorithm 1: GKB factorization G~ A = H B of G~ = diag(wd) G diag(winv) with
-   reorthogonalization of A and H, SVD of the (tp+1) x tp bidiagonal B, and the solution
+   reorthogonalization of A and H (of H only, and A possibly rebuilt instead of stored, under the
+   handle's gkb_onesided tuning), SVD of the (tp+1) x tp bidiagonal B, and the solution
    y = ||r~|| A V Gamma(alpha, Sigma) U(1,:)^T.  Inputs r_tilde (m), wd (m), winv (n).
    alpha_mode: 0 = UPRE over the first t singular values, 1 = alpha^(1) of eq. (eq:alpha1),
    2 = fixed (*alpha on input).  basis_dtype: FF_F64 stores A and H in double precision (the
