@@ -293,3 +293,40 @@ def test_irls_trajectory_is_iterated_tikhonov(solver):
         m_prev2, m_prev = m_prev, m_new
     # the steps move: the closed form separates them by far more than the tolerance
     assert np.linalg.norm(steps[-1] - steps[0]) >= 1e-2 * np.linalg.norm(steps[-1])
+
+
+@pytest.mark.parametrize("kernel,sdiv", [("gravity", 8), ("magnetic", 4), ("gravity", 1)])
+def test_one_sided_reorthogonalization_matches_algorithm_1(kernel, sdiv):
+    # The device's gkb_onesided modes rest on a property of the Golub-Kahan process (Simon and Zha,
+    # SIAM J. Sci. Comput. 21, 2000): when the data-side vectors h are kept orthogonal, the
+    # model-side vectors a produced by the recurrence alone stay orthogonal to the level of the
+    # products' rounding.  Here with the dense FP64 operator: a one-sided run of the recurrence
+    # (written out below, MGS against H twice, no reorthogonalization of A) against the oracle's
+    # Algorithm 1, up to t_p = m.
+    g, G, wd, winv, Gt, r = small_problem(kernel, seed=2)
+    tp = g.m // sdiv
+    y0, a0, S0, F0 = solvers.gkb(*ops(Gt), r, g.n, tp, tp, "fixed", 0.05 * np.linalg.norm(Gt, 2),
+                                  return_factors=True)
+    A = np.zeros((g.n, tp))
+    H = np.zeros((g.m, tp + 1))
+    B = np.zeros((tp + 1, tp))
+    beta = np.linalg.norm(r)
+    H[:, 0] = r / beta
+    a = np.zeros(g.n)
+    for i in range(tp):
+        b = Gt.T @ H[:, i] - beta * a
+        gamma = np.linalg.norm(b)
+        a = b / gamma
+        A[:, i], B[i, i] = a, gamma
+        c = Gt @ a - gamma * H[:, i]
+        for _ in range(2):
+            for j in range(i + 1):
+                c = c - (H[:, j] @ c) * H[:, j]
+        beta = np.linalg.norm(c)
+        H[:, i + 1], B[i + 1, i] = c / beta, beta
+    assert np.abs(A.T @ A - np.eye(tp)).max() <= 1e-12
+    U, S, Vt = np.linalg.svd(B, full_matrices=False)
+    assert np.allclose(S, S0, rtol=1e-10, atol=1e-12 * S0[0])
+    alpha = 0.05 * np.linalg.norm(Gt, 2)
+    y = np.linalg.norm(r) * (A @ (Vt.T @ (solvers.gamma_filter(alpha, S) * U[0, :])))
+    assert np.linalg.norm(y - y0) <= 1e-10 * np.linalg.norm(y0)
